@@ -1,0 +1,205 @@
+/*
+ * discord_ref.c -- plain, slow, obviously correct FP64 reference for time-series
+ * discord search.  TEST INFRASTRUCTURE ONLY: it is called by the tests, by the
+ * smoke check and by the CPU-baseline leg of the benchmark, never by the
+ * product library, and it shares no code with it.
+ *
+ * Definitions followed (the paper's section 2.1, "formal definitions"):
+ *   - series T = (t_0 .. t_{m-1}); subsequence T_{i,n} = (t_i .. t_{i+n-1}),
+ *     N = m - n + 1 subsequences (indices are 0-based here, 1-based in the paper);
+ *   - T_{i,n} and T_{j,n} are non-self matches iff |i - j| >= n;
+ *   - Euclidean distance, eq. (1); comparisons are made on its square, as the
+ *     PotentialDiscord/RefineDiscord algorithms do, and the square root is taken
+ *     once at the end;
+ *   - the discord is the subsequence whose nearest non-self match is farthest.
+ *   - z-normalisation, eq. (2): one mean and one standard deviation for the whole
+ *     series.  It is an affine map, so every squared distance on the normalised
+ *     series equals the raw one divided by sigma^2; the search is done on raw
+ *     values and the reported distance is divided by sigma.
+ *
+ * Readings where the paper is silent:
+ *   - ties: the lowest index among maximal nearest-neighbour distances wins, and
+ *     the nearest neighbour reported is the lowest j among minimisers;
+ *   - rows that have no non-self match at all (possible only when 2n <= m <= 3n-2)
+ *     take no part in the argmax;
+ *   - sigma^2 is computed two-pass (same real number as eq. (2)'s one-pass form).
+ *
+ * Arithmetic: every float32 input is promoted to double exactly; each squared
+ * distance is the sequential sum over k = 0..n-1 of (a_k - b_k)^2 with separately
+ * rounded multiply and add (built with -ffp-contract=off).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_OK 0
+#define ORC_EINVAL -1
+#define ORC_ECONST -2
+
+/* Sum over k of (t[i+k] - t[j+k])^2, eq. (1) squared. */
+double orc_pair_d2(const float *T, int64_t m, int32_t n, int64_t i, int64_t j)
+{
+    (void)m;
+    double s = 0.0;
+    for (int32_t k = 0; k < n; ++k) {
+        double d = (double)T[i + k] - (double)T[j + k];
+        s = s + d * d;
+    }
+    return s;
+}
+
+/* Mean and standard deviation of the whole series, eq. (2), two-pass. */
+int orc_stats(const float *T, int64_t m, double *mu, double *sigma)
+{
+    if (!T || m < 1) return ORC_EINVAL;
+    double s = 0.0;
+    for (int64_t i = 0; i < m; ++i) {
+        if (!isfinite(T[i])) return ORC_EINVAL;
+        s += (double)T[i];
+    }
+    double mean = s / (double)m;
+    double v = 0.0;
+    for (int64_t i = 0; i < m; ++i) {
+        double d = (double)T[i] - mean;
+        v += d * d;
+    }
+    *mu = mean;
+    *sigma = sqrt(v / (double)m);
+    return *sigma > 0.0 ? ORC_OK : ORC_ECONST;
+}
+
+/* Nearest non-self match of one row: min over j with |i-j| >= n.  Returns 0 and
+ * sets *jout = -1 when the row has no non-self match. */
+static int row_nn(const float *T, int64_t m, int32_t n, int64_t i, double *dout, int64_t *jout)
+{
+    int64_t N = m - n + 1;
+    double best = INFINITY;
+    int64_t bj = -1;
+    for (int64_t j = 0; j < N; ++j) {
+        if (llabs(i - j) < n) continue;
+        double d = orc_pair_d2(T, m, n, i, j);
+        if (d < best) { best = d; bj = j; }
+    }
+    *dout = best;
+    *jout = bj;
+    return bj >= 0;
+}
+
+/* Exact nearest non-self match for a list of rows. */
+int orc_rows_nn(const float *T, int64_t m, int32_t n, const int64_t *rows, int64_t count,
+                double *nn_d2, int64_t *nn_j, int threads)
+{
+    if (!T || n < 1 || m < n) return ORC_EINVAL;
+    if (threads < 1) threads = 1;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(threads)
+    for (int64_t r = 0; r < count; ++r)
+        row_nn(T, m, n, rows[r], &nn_d2[r], &nn_j[r]);
+    return ORC_OK;
+}
+
+/* Brute-force discord: NN profile of every row, then the argmax (lowest index on
+ * ties).  profile / profile_j may be NULL. */
+int orc_discord(const float *T, int64_t m, int32_t n, int threads,
+                int64_t *idx, int64_t *nn_idx, double *d2, double *mu, double *sigma,
+                double *profile, int64_t *profile_j)
+{
+    if (!T || n < 1 || m < 2 * (int64_t)n) return ORC_EINVAL;
+    int st = orc_stats(T, m, mu, sigma);
+    if (st != ORC_OK) return st;
+    int64_t N = m - n + 1;
+    double *prof = profile ? profile : (double *)malloc(sizeof(double) * N);
+    int64_t *pj = profile_j ? profile_j : (int64_t *)malloc(sizeof(int64_t) * N);
+    if (threads < 1) threads = 1;
+#pragma omp parallel for schedule(dynamic, 16) num_threads(threads)
+    for (int64_t i = 0; i < N; ++i)
+        row_nn(T, m, n, i, &prof[i], &pj[i]);
+    int64_t bi = -1;
+    for (int64_t i = 0; i < N; ++i) {
+        if (pj[i] < 0) continue;
+        if (bi < 0 || prof[i] > prof[bi]) bi = i;
+    }
+    *idx = bi;
+    *nn_idx = pj[bi];
+    *d2 = prof[bi];
+    if (!profile) free(prof);
+    if (!profile_j) free(pj);
+    return ORC_OK;
+}
+
+/* Witness certificate for a claimed discord (idx, d2):
+ *  (i)  the exact NN of idx equals d2;
+ *  (ii) every other row i that has a non-self match carries a witness j_i with
+ *       |i - j_i| >= n and d(i, j_i) < d2, or d(i, j_i) <= d2 when i > idx.
+ * Then no row can beat idx under the lowest-index rule.  Returns the number of
+ * rows that fail (ii) and the first of them in *first_bad (-1 if none), or a
+ * negative status.  *nn_of_idx receives the exact NN of idx, which is also the
+ * threshold used for (ii); the caller checks (i) against it. */
+int64_t orc_witness_check(const float *T, int64_t m, int32_t n, int64_t idx, double d2,
+                          const int64_t *wit, int threads, int64_t *first_bad, double *nn_of_idx)
+{
+    if (!T || n < 1 || m < 2 * (int64_t)n) return ORC_EINVAL;
+    int64_t N = m - n + 1;
+    if (idx < 0 || idx >= N) return ORC_EINVAL;
+    double dd; int64_t jj;
+    if (!row_nn(T, m, n, idx, &dd, &jj)) return ORC_EINVAL;
+    *nn_of_idx = dd;
+    (void)d2;
+    d2 = dd;  /* part (ii) is checked against the exact NN of idx; the caller
+                 compares its claimed distance with *nn_of_idx */
+    int64_t bad = 0, first = -1;
+    if (threads < 1) threads = 1;
+#pragma omp parallel for schedule(static) num_threads(threads) reduction(+:bad)
+    for (int64_t i = 0; i < N; ++i) {
+        if (i == idx) continue;
+        /* rows with no non-self match at all need no witness */
+        int has = (i - n >= 0) || (i + n <= N - 1);
+        if (!has) continue;
+        int64_t j = wit[i];
+        int ok = 0;
+        if (j >= 0 && j < N && llabs(i - j) >= n) {
+            double e = orc_pair_d2(T, m, n, i, j);
+            ok = (e < d2) || (e == d2 && i > idx);
+        }
+        if (!ok) {
+            bad += 1;
+#pragma omp critical
+            if (first < 0 || i < first) first = i;
+        }
+    }
+    *first_bad = first;
+    return bad;
+}
+
+/* PAA, eq. (3), then SAX, eq. (4), then the word hash, eq. (9), of every row,
+ * on the z-normalised series of eq. (2).
+ *   - segment s of a row covers offsets [floor(s*n/w), floor((s+1)*n/w)); for
+ *     n divisible by w these are the paper's equal blocks of n/w points;
+ *   - the PAA value is the mean of the normalised points of the segment;
+ *   - the symbol is the k (0-based) with beta_{k} <= value < beta_{k+1}, where
+ *     beta_0 = -inf, beta_alpha = +inf and bp[0..alpha-2] are the inner points;
+ *   - the word id is sum_s sym_s * alpha^(w-1-s): lexicographic rank of the word,
+ *     first segment most significant. */
+int orc_sax_words(const float *T, int64_t m, int32_t n, int32_t w, int32_t alpha,
+                  const double *bp, double mu, double sigma, int32_t *words, int threads)
+{
+    if (!T || n < 1 || w < 1 || w > n || alpha < 2 || m < n) return ORC_EINVAL;
+    int64_t N = m - n + 1;
+    if (threads < 1) threads = 1;
+#pragma omp parallel for schedule(static) num_threads(threads)
+    for (int64_t i = 0; i < N; ++i) {
+        int32_t code = 0;
+        for (int32_t s = 0; s < w; ++s) {
+            int64_t a = ((int64_t)s * n) / w, b = ((int64_t)(s + 1) * n) / w;
+            double acc = 0.0;
+            for (int64_t k = a; k < b; ++k)
+                acc += ((double)T[i + k] - mu) / sigma;
+            double paa = acc / (double)(b - a);
+            int32_t sym = 0;
+            while (sym < alpha - 1 && paa >= bp[sym]) ++sym;
+            code = code * alpha + sym;
+        }
+        words[i] = code;
+    }
+    return ORC_OK;
+}

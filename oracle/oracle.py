@@ -1,0 +1,408 @@
+"""CPU oracle for discord search -- TEST INFRASTRUCTURE, not part of the product.
+
+Plain FP64 implementations written from the paper (Polyakov & Zymbler, PhiDD):
+the brute force of the definitions in section 2.1 (in C, see discord_ref.c),
+and, in Python, independent companions used to pin it: a NumPy all-pairs brute
+force, an exact-integer enumerator, Algorithm 1 (HOTSAX DiscordDiscovery) with
+any visiting order, Algorithms 2-4 (PhiDD) and the SAX preparation structures of
+section 3.1 (eqs. (3)-(10)).
+
+Readings of the paper that this oracle takes (the paper is silent or garbled):
+  * z-normalisation is global, eq. (2); it is affine, so the argmax is taken on
+    raw-value squared distances and the distance is reported divided by sigma;
+  * the lowest index wins ties in the argmax; the lowest j wins ties in the NN;
+  * rows with no non-self match take no part in the argmax;
+  * Algorithm 3's second inner loop updates ``min`` like Algorithm 4's does;
+  * dist_bsf starts at 0 and pos_bsf at "none";
+  * eq. (3) segments are [floor(s n / w), floor((s+1) n / w)); eq. (4) symbols are
+    left-closed quantile intervals of N(0,1); eq. (9) is the lexicographic rank
+    sum_s sym_s * |A|^(w-1-s) of the 0-based symbols.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import statistics
+
+import numpy as np
+
+__all__ = [
+    "load", "stats", "pair_d2", "rows_nn", "discord", "witness_check", "sax_words",
+    "np_sax_words", "breakpoints", "freq_cand", "index_word", "np_discord",
+    "int_discord", "alg1", "phidd", "pair_count", "OracleError",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIBPATH = os.path.join(_HERE, "lib", "liboracle.so")
+_lib = None
+
+
+class OracleError(ValueError):
+    """Raised for inputs the definitions do not cover (status < 0)."""
+
+
+def load():
+    """Load the compiled C oracle, compiling it with gcc first if it is absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIBPATH):
+        from . import build as _b
+        _b.build()
+    lib = ctypes.CDLL(_LIBPATH)
+    f64p = ctypes.POINTER(ctypes.c_double)
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    f32p = ctypes.POINTER(ctypes.c_float)
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    lib.orc_pair_d2.restype = ctypes.c_double
+    lib.orc_pair_d2.argtypes = [f32p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64]
+    lib.orc_stats.restype = ctypes.c_int
+    lib.orc_stats.argtypes = [f32p, ctypes.c_int64, f64p, f64p]
+    lib.orc_rows_nn.restype = ctypes.c_int
+    lib.orc_rows_nn.argtypes = [f32p, ctypes.c_int64, ctypes.c_int32, i64p, ctypes.c_int64,
+                                f64p, i64p, ctypes.c_int]
+    lib.orc_discord.restype = ctypes.c_int
+    lib.orc_discord.argtypes = [f32p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int,
+                                i64p, i64p, f64p, f64p, f64p, f64p, i64p]
+    lib.orc_witness_check.restype = ctypes.c_int64
+    lib.orc_witness_check.argtypes = [f32p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64,
+                                      ctypes.c_double, i64p, ctypes.c_int, i64p, f64p]
+    lib.orc_sax_words.restype = ctypes.c_int
+    lib.orc_sax_words.argtypes = [f32p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                  ctypes.c_int32, f64p, ctypes.c_double, ctypes.c_double,
+                                  i32p, ctypes.c_int]
+    _lib = lib
+    return lib
+
+
+def _f32(T) -> np.ndarray:
+    a = np.ascontiguousarray(T, dtype=np.float32)
+    if a.ndim != 1:
+        raise OracleError("series must be one-dimensional")
+    return a
+
+
+def _ptr(a, ct):
+    return a.ctypes.data_as(ctypes.POINTER(ct))
+
+
+def _threads(threads):
+    return int(threads) if threads else (os.cpu_count() or 1)
+
+
+def pair_count(N: int, n: int) -> int:
+    """Number of ordered pairs (i, j), 0 <= i, j < N, with |i - j| >= n."""
+    if N - n <= 0:
+        return 0
+    return (N - n) * (N - n + 1)
+
+
+def stats(T):
+    """Mean and standard deviation of the series, eq. (2) (two-pass FP64)."""
+    T = _f32(T)
+    mu, sd = ctypes.c_double(), ctypes.c_double()
+    st = load().orc_stats(_ptr(T, ctypes.c_float), T.size, ctypes.byref(mu), ctypes.byref(sd))
+    if st == -2:
+        raise OracleError("sigma == 0: eq. (2) is undefined for a constant series")
+    if st != 0:
+        raise OracleError("invalid series (empty or non-finite)")
+    return mu.value, sd.value
+
+
+def pair_d2(T, n: int, i: int, j: int) -> float:
+    """Squared Euclidean distance of eq. (1) between T_{i,n} and T_{j,n}."""
+    T = _f32(T)
+    N = T.size - n + 1
+    if not (0 <= i < N and 0 <= j < N):
+        raise OracleError("row out of range")
+    return load().orc_pair_d2(_ptr(T, ctypes.c_float), T.size, n, i, j)
+
+
+def rows_nn(T, n: int, rows, threads=None):
+    """Exact nearest non-self match (d^2, j) of each listed row; j = -1 if none."""
+    T = _f32(T)
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    N = T.size - n + 1
+    if rows.size and (rows.min() < 0 or rows.max() >= N):
+        raise OracleError("row out of range")
+    d = np.empty(rows.size, dtype=np.float64)
+    j = np.empty(rows.size, dtype=np.int64)
+    st = load().orc_rows_nn(_ptr(T, ctypes.c_float), T.size, n, _ptr(rows, ctypes.c_int64),
+                            rows.size, _ptr(d, ctypes.c_double), _ptr(j, ctypes.c_int64),
+                            _threads(threads))
+    if st != 0:
+        raise OracleError("invalid arguments")
+    return d, j
+
+
+def discord(T, n: int, threads=None, profile: bool = False) -> dict:
+    """Brute-force discord of section 2.1 in FP64 (C).  Returns index, nn_index,
+    d2 (raw squared NN distance), distance_raw, distance (z-normalised units,
+    eq. (2)), mu, sigma and, if asked, the NN profile and its argmins."""
+    T = _f32(T)
+    m = T.size
+    if n < 1 or m < 2 * n:
+        raise OracleError("need n >= 1 and m >= 2n")
+    N = m - n + 1
+    idx, nnj = ctypes.c_int64(), ctypes.c_int64()
+    d2, mu, sd = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    prof = np.empty(N, dtype=np.float64) if profile else None
+    pj = np.empty(N, dtype=np.int64) if profile else None
+    st = load().orc_discord(_ptr(T, ctypes.c_float), m, n, _threads(threads),
+                            ctypes.byref(idx), ctypes.byref(nnj), ctypes.byref(d2),
+                            ctypes.byref(mu), ctypes.byref(sd),
+                            _ptr(prof, ctypes.c_double) if profile else None,
+                            _ptr(pj, ctypes.c_int64) if profile else None)
+    if st == -2:
+        raise OracleError("sigma == 0: eq. (2) is undefined for a constant series")
+    if st != 0:
+        raise OracleError("invalid series")
+    out = dict(index=idx.value, nn_index=nnj.value, d2=d2.value,
+               distance_raw=math.sqrt(d2.value), distance=math.sqrt(d2.value) / sd.value,
+               mu=mu.value, sigma=sd.value)
+    if profile:
+        out["profile"] = prof
+        out["profile_j"] = pj
+    return out
+
+
+def witness_check(T, n: int, idx: int, d2: float, wit, threads=None):
+    """FP64 certificate (see discord_ref.c).  Returns (bad_rows, first_bad,
+    exact NN d^2 of idx)."""
+    T = _f32(T)
+    wit = np.ascontiguousarray(wit, dtype=np.int64)
+    N = T.size - n + 1
+    if wit.size != N:
+        raise OracleError("one witness per row expected")
+    fb, nn = ctypes.c_int64(), ctypes.c_double()
+    bad = load().orc_witness_check(_ptr(T, ctypes.c_float), T.size, n, int(idx), float(d2),
+                                   _ptr(wit, ctypes.c_int64), _threads(threads),
+                                   ctypes.byref(fb), ctypes.byref(nn))
+    if bad < 0:
+        raise OracleError("invalid arguments")
+    return int(bad), int(fb.value), nn.value
+
+
+# ----------------------------------------------------------------------------
+# SAX preparation (section 3.1)
+# ----------------------------------------------------------------------------
+
+def breakpoints(alpha: int = 4) -> np.ndarray:
+    """Inner breakpoints beta_1..beta_{alpha-1} of eq. (4): the N(0,1) quantiles
+    that cut the real line into alpha equiprobable intervals."""
+    nd = statistics.NormalDist(0.0, 1.0)
+    return np.array([nd.inv_cdf(k / alpha) for k in range(1, alpha)], dtype=np.float64)
+
+
+def sax_words(T, n: int, w: int = 4, alpha: int = 4, threads=None) -> np.ndarray:
+    """Word id of every row: PAA (eq. 3) -> SAX (eq. 4) -> hash (eq. 9), on the
+    z-normalised series of eq. (2).  C, sequential sums."""
+    T = _f32(T)
+    mu, sd = stats(T)
+    N = T.size - n + 1
+    bp = breakpoints(alpha)
+    words = np.empty(N, dtype=np.int32)
+    st = load().orc_sax_words(_ptr(T, ctypes.c_float), T.size, n, w, alpha,
+                              _ptr(bp, ctypes.c_double), mu, sd,
+                              _ptr(words, ctypes.c_int32), _threads(threads))
+    if st != 0:
+        raise OracleError("invalid SAX arguments")
+    return words
+
+
+def np_sax_words(T, n: int, w: int = 4, alpha: int = 4) -> np.ndarray:
+    """Independent NumPy version of ``sax_words`` (same definitions)."""
+    t = np.asarray(T, dtype=np.float32).astype(np.float64)
+    mu = t.mean()
+    sd = math.sqrt(((t - mu) ** 2).mean())
+    z = (t - mu) / sd
+    W = np.lib.stride_tricks.sliding_window_view(z, n)
+    bp = breakpoints(alpha)
+    code = np.zeros(W.shape[0], dtype=np.int64)
+    for s in range(w):
+        a, b = (s * n) // w, ((s + 1) * n) // w
+        paa = W[:, a:b].sum(axis=1) / (b - a)
+        sym = np.searchsorted(bp, paa, side="right")   # beta_{k} <= v < beta_{k+1}
+        code = code * alpha + sym
+    return code.astype(np.int32)
+
+
+def freq_cand(words, dict_size: int = 256):
+    """Eqs. (7)-(8): histogram of word ids, and Cand = ascending rows whose word
+    has the minimum frequency among the words that occur."""
+    words = np.asarray(words)
+    hist = np.bincount(words, minlength=dict_size).astype(np.int64)
+    freq = hist[words]
+    cand = np.flatnonzero(freq == freq.min()).astype(np.int64)
+    return hist, cand
+
+
+def index_word(words, dict_size: int = 256):
+    """Eq. (10) as a CSR inverted index: offsets[dict_size+1] and members[N],
+    members of each word in ascending row order."""
+    words = np.asarray(words)
+    hist = np.bincount(words, minlength=dict_size)
+    offsets = np.zeros(dict_size + 1, dtype=np.int64)
+    offsets[1:] = np.cumsum(hist)
+    members = np.argsort(words, kind="stable").astype(np.int64)
+    return offsets, members
+
+
+# ----------------------------------------------------------------------------
+# Independent companions used to pin the C brute force
+# ----------------------------------------------------------------------------
+
+def np_discord(T, n: int, block: int = 64) -> dict:
+    """NumPy all-pairs brute force (independent of the C code)."""
+    t = np.asarray(T, dtype=np.float32).astype(np.float64)
+    m = t.size
+    if n < 1 or m < 2 * n:
+        raise OracleError("need n >= 1 and m >= 2n")
+    W = np.lib.stride_tricks.sliding_window_view(t, n)
+    N = W.shape[0]
+    prof = np.full(N, np.inf)
+    pj = np.full(N, -1, dtype=np.int64)
+    cols = np.arange(N)
+    for r0 in range(0, N, block):
+        R = W[r0:r0 + block]
+        D = ((R[:, None, :] - W[None, :, :]) ** 2).sum(axis=2)
+        rows = np.arange(r0, r0 + R.shape[0])
+        D[np.abs(rows[:, None] - cols[None, :]) < n] = np.inf
+        pj[r0:r0 + R.shape[0]] = np.argmin(D, axis=1)
+        prof[r0:r0 + R.shape[0]] = D[np.arange(R.shape[0]), pj[r0:r0 + R.shape[0]]]
+    has = np.isfinite(prof)
+    pj[~has] = -1
+    best = np.max(prof[has])
+    idx = int(np.flatnonzero(has & (prof == best))[0])
+    sd = math.sqrt(((t - t.mean()) ** 2).mean())
+    return dict(index=idx, nn_index=int(pj[idx]), d2=float(best), profile=prof,
+                profile_j=pj, distance=math.sqrt(best) / sd)
+
+
+def int_discord(values, n: int):
+    """Exact enumerator over Python integers: every squared distance is an exact
+    integer, so ties are exact.  Returns (index, nn_index, d2, profile)."""
+    vals = [int(v) for v in values]
+    m = len(vals)
+    if n < 1 or m < 2 * n:
+        raise OracleError("need n >= 1 and m >= 2n")
+    N = m - n + 1
+    prof = [None] * N
+    pj = [-1] * N
+    for i in range(N):
+        for j in range(N):
+            if abs(i - j) < n:
+                continue
+            d = 0
+            for k in range(n):
+                e = vals[i + k] - vals[j + k]
+                d += e * e
+            if prof[i] is None or d < prof[i]:
+                prof[i], pj[i] = d, j
+    best_i = None
+    for i in range(N):
+        if prof[i] is None:
+            continue
+        if best_i is None or prof[i] > prof[best_i]:
+            best_i = i
+    return best_i, pj[best_i], prof[best_i], prof
+
+
+def _d2_seq(t, n, i, j):
+    """eq. (1) squared, sequential Python-float sum (same order as the C code)."""
+    s = 0.0
+    for k in range(n):
+        d = t[i + k] - t[j + k]
+        s = s + d * d
+    return s
+
+
+def _better(mn, i, bsf, pos):
+    """Lowest-index tie rule applied to Algorithm 1's bsf update."""
+    return pos < 0 or mn > bsf or (mn == bsf and i < pos)
+
+
+def alg1(T, n: int, outer=None, inner=None, count: list | None = None):
+    """Algorithm 1 (HOTSAX DiscordDiscovery, section 2.2) on raw values with
+    squared distances: for each row i in the ``outer`` order scan the non-self j
+    in the ``inner(i)`` order, leave the row as soon as a distance below the
+    best-so-far appears, otherwise update the best-so-far with the row's NN.
+    Returns (index, d2).  ``count`` (a one-element list) receives the number of
+    distances evaluated."""
+    t = [float(v) for v in np.asarray(T, dtype=np.float32)]
+    m = len(t)
+    N = m - n + 1
+    outer = range(N) if outer is None else outer
+    bsf, pos, evals = 0.0, -1, 0
+    for i in outer:
+        mn = math.inf
+        abandoned = False
+        for j in (inner(i) if inner else range(N)):
+            if abs(i - j) < n:
+                continue
+            d = _d2_seq(t, n, i, j)
+            evals += 1
+            if d < bsf:
+                abandoned = True
+                break
+            if d < mn:
+                mn = d
+        if abandoned or mn == math.inf:
+            continue
+        if _better(mn, i, bsf, pos):
+            bsf, pos = mn, i
+    if count is not None:
+        count.append(evals)
+    return pos, bsf
+
+
+def phidd(T, n: int, w: int = 4, alpha: int = 4, count: list | None = None):
+    """Algorithms 2-4 (PhiDD, section 3.2), sequential, on raw values.
+    Preparation: SAX words, Cand (eq. 7), Index_Word (eq. 10).  Search:
+    PotentialDiscord over Cand, then RefineDiscord over the other rows; each row
+    scans its own word's members first (Index_Word order), then every other row
+    in matrix order, leaving the row on a distance below the best-so-far.
+    Returns (index, d2)."""
+    t = [float(v) for v in np.asarray(T, dtype=np.float32)]
+    m = len(t)
+    N = m - n + 1
+    words = sax_words(T, n, w, alpha)
+    hist, cand = freq_cand(words, alpha ** w)
+    offsets, members = index_word(words, alpha ** w)
+    bsf, pos, evals = 0.0, -1, 0
+
+    def scan(i):
+        nonlocal evals
+        wd = words[i]
+        bucket = members[offsets[wd]:offsets[wd + 1]]
+        mn = math.inf
+        for j in bucket:                      # same-word subsequences first
+            if abs(i - j) < n:
+                continue
+            d = _d2_seq(t, n, i, int(j))
+            evals += 1
+            if d < bsf:
+                return None
+            mn = min(mn, d)
+        for j in range(N):                    # then the rest, matrix order
+            if words[j] == wd or abs(i - j) < n:
+                continue
+            d = _d2_seq(t, n, i, j)
+            evals += 1
+            if d < bsf:
+                return None
+            mn = min(mn, d)
+        return mn
+
+    in_cand = np.zeros(N, dtype=bool)
+    in_cand[cand] = True
+    for i in list(cand) + [r for r in range(N) if not in_cand[r]]:
+        mn = scan(int(i))
+        if mn is None or mn == math.inf:
+            continue
+        if _better(mn, int(i), bsf, pos):
+            bsf, pos = mn, int(i)
+    if count is not None:
+        count.append(evals)
+    return pos, bsf

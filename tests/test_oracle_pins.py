@@ -1,0 +1,384 @@
+"""Pins for the CPU oracle (CPU only).
+
+The paper prints no worked example and no discord positions, so the oracle is
+pinned to the mathematics instead: exhaustive integer enumeration, closed forms
+(n = 1 reduces to sorting, m = 2n, a periodic series with one spike),
+invariants of the definitions in section 2.1 (symmetry, non-self rule, affine
+invariance of eq. (2), time reversal, planting a copy), Algorithm 1 and
+Algorithms 2-4 with pruning (which must reach the same argmax), and the SAX
+structures of section 3.1 against the statistical table and a hand-worked case.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1901_00155_amd import workloads
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rand_int_series(rng, m, lo=-6, hi=7):
+    return rng.integers(lo, hi, size=m).astype(np.float32)
+
+
+# --------------------------------------------------------------------------- P1
+@pytest.mark.parametrize("seed", range(12))
+def test_exhaustive_integer_enumeration(seed):
+    """C brute force == NumPy brute force == pure-integer enumerator, for every
+    window length 1 <= n <= m/2 of tiny integer series (exact ties included)."""
+    rng = np.random.default_rng(100 + seed)
+    m = int(rng.integers(6, 34))
+    T = _rand_int_series(rng, m, -4 if seed % 2 else -9, 5 if seed % 2 else 10)
+    if np.all(T == T[0]):
+        T[0] += 1
+    for n in range(1, m // 2 + 1):
+        i_idx, i_nn, i_d2, i_prof = oracle.int_discord(T.astype(int).tolist(), n)
+        c = oracle.discord(T, n, threads=2, profile=True)
+        assert c["index"] == i_idx, (m, n)
+        assert c["nn_index"] == i_nn, (m, n)
+        assert c["d2"] == float(i_d2)
+        N = m - n + 1
+        for i in range(N):
+            if i_prof[i] is None:
+                assert c["profile_j"][i] == -1
+            else:
+                assert c["profile"][i] == float(i_prof[i])
+        npo = oracle.np_discord(T, n)
+        assert npo["index"] == i_idx and npo["d2"] == float(i_d2)
+
+
+# --------------------------------------------------------------------------- P2
+@pytest.mark.parametrize("seed", range(6))
+def test_window_one_reduces_to_sorting(seed):
+    """n = 1: NN(i) is the gap from t_i to the closest other value, found here by
+    sorting; the discord is the value with the widest such gap."""
+    rng = np.random.default_rng(200 + seed)
+    m = int(rng.integers(20, 400))
+    T = rng.standard_normal(m).astype(np.float32)
+    if seed % 3 == 0:
+        T[rng.integers(0, m, 5)] = T[0]             # duplicates -> NN 0
+    v = T.astype(np.float64)
+    order = np.argsort(v, kind="stable")
+    s = v[order]
+    gap = np.full(m, np.inf)
+    gap[:-1] = np.minimum(gap[:-1], s[1:] - s[:-1])
+    gap[1:] = np.minimum(gap[1:], s[1:] - s[:-1])
+    nn = np.empty(m)
+    nn[order] = gap ** 2
+    expect_idx = int(np.flatnonzero(nn == nn.max())[0])
+    c = oracle.discord(T, 1, threads=2, profile=True)
+    assert c["index"] == expect_idx
+    np.testing.assert_allclose(c["profile"], nn, rtol=1e-15, atol=0)
+
+
+# --------------------------------------------------------------------------- P3
+@pytest.mark.parametrize("n", [1, 2, 5, 16, 33])
+def test_m_equals_2n_closed_form(n):
+    """m = 2n: only rows 0 and n are non-self matches of each other, so the
+    discord is row 0 and its NN distance is ED(T_0, T_n)."""
+    rng = np.random.default_rng(n)
+    T = rng.integers(-50, 50, 2 * n).astype(np.float32)
+    expect = sum((int(T[k]) - int(T[n + k])) ** 2 for k in range(n))
+    c = oracle.discord(T, n, profile=True)
+    assert c["index"] == 0 and c["nn_index"] == n
+    assert c["d2"] == float(expect)
+    assert all(c["profile_j"][i] == -1 for i in range(1, n))
+
+
+# --------------------------------------------------------------------------- P4
+def _periodic_spike(rng, n):
+    """Integer pattern of period P >= n tiled over >= 8 periods plus one spike h
+    at p; returns (T, p, h) such that the closed form below holds."""
+    while True:
+        P = int(rng.integers(n, n + 6))
+        pat = rng.integers(-20, 21, P).astype(np.int64)
+        ext = np.concatenate([pat, pat, pat])
+        dmin = min(int(((ext[a:a + n] - ext[b:b + n]) ** 2).sum())
+                   for a in range(P) for b in range(P) if a != b) if P > 1 else 0
+        h = int(math.floor(math.sqrt(dmin / 6.0)))
+        if h >= 1 and 6 * h * h < dmin:
+            break
+    reps = int(rng.integers(8, 12))
+    x = np.tile(pat, reps)
+    p = int(rng.integers(2 * P, x.size - 2 * P))
+    x[p] += h if rng.random() < 0.5 else -h
+    return x.astype(np.float32), p, h
+
+
+@pytest.mark.parametrize("seed", range(20))
+def test_periodic_plus_spike_closed_form(seed):
+    """Every spike-free window has an exact copy a period away (NN = 0); every
+    window holding the spike is h^2 from its copy and farther from anything
+    else, so the discord is the first window holding the spike, at distance |h|
+    (exact ties across n windows: the lowest index must win)."""
+    rng = np.random.default_rng(300 + seed)
+    n = int(rng.integers(2, 9))
+    T, p, h = _periodic_spike(rng, n)
+    c = oracle.discord(T, n, profile=True)
+    assert c["index"] == max(0, p - n + 1)
+    assert c["d2"] == float(h * h)
+    prof = c["profile"]
+    N = T.size - n + 1
+    spike_rows = set(range(max(0, p - n + 1), min(N, p + 1)))
+    for i in range(N):
+        assert prof[i] == (float(h * h) if i in spike_rows else 0.0)
+
+
+# --------------------------------------------------------------------------- P5
+def test_symmetry_and_identity():
+    """Dist axioms of section 2.1: d(i, i) = 0 and d(i, j) = d(j, i)."""
+    T = workloads.random_walk(300, seed=5)
+    rng = np.random.default_rng(5)
+    for _ in range(200):
+        i, j = (int(v) for v in rng.integers(0, 300 - 16 + 1, 2))
+        assert oracle.pair_d2(T, 16, i, i) == 0.0
+        assert oracle.pair_d2(T, 16, i, j) == oracle.pair_d2(T, 16, j, i)
+
+
+def test_pair_distance_matches_definition():
+    """eq. (1) squared for one pair, against an exact rational sum."""
+    from fractions import Fraction
+    T = workloads.random_walk(200, seed=6)
+    for (i, j, n) in [(0, 50, 16), (10, 120, 33), (3, 170, 7)]:
+        exact = sum((Fraction(float(T[i + k])) - Fraction(float(T[j + k]))) ** 2 for k in range(n))
+        assert abs(oracle.pair_d2(T, n, i, j) - float(exact)) <= 1e-13 * float(exact)
+
+
+@pytest.mark.parametrize("scale,shift", [(2.0, 0.0), (0.25, 64.0), (-4.0, 8.0)])
+def test_affine_invariance_exact(scale, shift):
+    """eq. (2) makes the result invariant under T -> aT + b (a != 0).  With a a
+    power of two and b an integer, the float32 values stay exact, so the index
+    is identical and the normalised distance agrees to rounding."""
+    rng = np.random.default_rng(7)
+    T = rng.integers(-30, 30, 180).astype(np.float32)
+    a = oracle.discord(T, 12)
+    b = oracle.discord((T * scale + shift).astype(np.float32), 12)
+    assert a["index"] == b["index"]
+    assert b["d2"] == a["d2"] * scale * scale
+    assert math.isclose(a["distance"], b["distance"], rel_tol=1e-12)
+
+
+def test_affine_invariance_random_walk():
+    T = workloads.random_walk(1500, seed=8)
+    a = oracle.discord(T, 32)
+    b = oracle.discord((T * 3.7 + 1000.0).astype(np.float32), 32)
+    assert a["index"] == b["index"]
+    assert math.isclose(a["distance"], b["distance"], rel_tol=1e-5)
+
+
+def test_time_reversal():
+    """Reversing the series maps row i to row N-1-i with the same NN distance."""
+    T = workloads.random_walk(900, seed=9)
+    n = 24
+    a = oracle.discord(T, n, profile=True)
+    prof = a["profile"]
+    assert np.sum(prof == prof.max()) == 1           # unique maximum
+    b = oracle.discord(T[::-1].copy(), n, profile=True)
+    N = T.size - n + 1
+    assert b["index"] == N - 1 - a["index"]
+    np.testing.assert_allclose(b["profile"][::-1], prof, rtol=1e-12)
+
+
+def test_planting_a_copy_moves_the_discord():
+    """Copying the discord window elsewhere gives it an exact non-self match,
+    so its NN becomes 0 and another row becomes the discord."""
+    T = workloads.random_walk(1200, seed=10)
+    n = 32
+    a = oracle.discord(T, n)
+    i = a["index"]
+    U = T.copy()
+    dst = 100 if i > 600 else 1000
+    U[dst:dst + n] = T[i:i + n]
+    b = oracle.discord(U, n, profile=True)
+    assert b["profile"][i] == 0.0 or abs(i - dst) < n
+    assert b["index"] != i
+
+
+# --------------------------------------------------------------------------- P6
+@pytest.mark.parametrize("n", [3, 8, 17])
+def test_non_self_match_boundary(n):
+    """An exact repeat at offset n-1 overlaps (|i-j| < n) and must be ignored;
+    the same repeat at offset n is a non-self match and must count."""
+    rng = np.random.default_rng(40 + n)
+    base = rng.standard_normal(12 * n).astype(np.float32) * 100
+    s = 4 * n
+    for period, expect_zero in [(n - 1, False), (n, True)]:
+        T = base.copy()
+        for k in range(period, period + n):
+            T[s + k] = T[s + k - period]
+        assert np.array_equal(T[s:s + n], T[s + period:s + period + n])
+        c = oracle.discord(T, n, profile=True)
+        assert (c["profile"][s] == 0.0) == expect_zero
+
+
+# --------------------------------------------------------------------------- P7
+@pytest.mark.parametrize("seed", range(8))
+def test_alg1_random_orders_equal_brute_force(seed):
+    """Algorithm 1 with early abandon reaches the brute-force argmax for any
+    outer and inner visiting order (pruning changes the work, not the result)."""
+    rng = np.random.default_rng(500 + seed)
+    m, n = int(rng.integers(40, 120)), int(rng.integers(2, 10))
+    T = (rng.integers(-3, 4, m) if seed % 2 else rng.standard_normal(m)).astype(np.float32)
+    N = m - n + 1
+    ref = oracle.discord(T, n)
+    full = oracle.pair_count(N, n)
+    for trial in range(3):
+        outer = list(rng.permutation(N))
+        perms = {i: list(rng.permutation(N)) for i in range(N)}
+        cnt = []
+        idx, d2 = oracle.alg1(T, n, outer=outer, inner=lambda i: perms[i], count=cnt)
+        assert idx == ref["index"] and d2 == ref["d2"]
+        assert cnt[0] <= full
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_phidd_algorithms_equal_brute_force(seed):
+    """Algorithms 2-4 (PotentialDiscord over Cand, then RefineDiscord, same-word
+    rows first) reach the brute-force argmax."""
+    rng = np.random.default_rng(600 + seed)
+    m, n = int(rng.integers(60, 200)), int(rng.choice([4, 8, 12, 16]))
+    T = np.cumsum(rng.standard_normal(m)).astype(np.float32)
+    if seed % 3 == 0:
+        T = np.round(T).astype(np.float32)        # integer values: exact ties possible
+    ref = oracle.discord(T, n)
+    cnt = []
+    idx, d2 = oracle.phidd(T, n, count=cnt)
+    assert idx == ref["index"] and d2 == ref["d2"]
+    assert cnt[0] < oracle.pair_count(m - n + 1, n)
+
+
+# --------------------------------------------------------------------------- P8
+def test_small_workload_recovers_injected_anomaly():
+    """The m=4096 walk with a sine planted over t[2000:2064] (n = 64): the
+    discord window overlaps the planted window."""
+    w = workloads.small()
+    c = oracle.discord(w.series, w.n)
+    assert 2000 - w.n < c["index"] < 2064
+    assert math.isclose(c["distance"], c["distance_raw"] / c["sigma"], rel_tol=1e-15)
+
+
+# --------------------------------------------------------------------------- P9
+def test_witness_certificate():
+    """The certificate accepts the brute-force argmax with its NN witnesses and
+    rejects a claim with a broken witness or a wrong argmax."""
+    T = workloads.random_walk(700, seed=11)
+    n = 20
+    c = oracle.discord(T, n, profile=True)
+    wit = c["profile_j"].copy()
+    bad, first, nn = oracle.witness_check(T, n, c["index"], c["d2"], wit)
+    assert bad == 0 and first == -1 and nn == c["d2"]
+    # a witness inside the exclusion zone is rejected
+    r = (c["index"] + 300) % (T.size - n + 1)
+    wit2 = wit.copy()
+    wit2[r] = r
+    bad, first, _ = oracle.witness_check(T, n, c["index"], c["d2"], wit2)
+    assert bad == 1 and first == r
+    # claiming the runner-up as the discord fails at the true discord's row
+    prof = c["profile"].copy()
+    prof[c["index"]] = -1
+    runner = int(np.argmax(prof))
+    bad, first, nn = oracle.witness_check(T, n, runner, c["profile"][runner], wit)
+    assert bad >= 1 and first == c["index"]
+
+
+# --------------------------------------------------------------------------- stats
+def test_stats_closed_form():
+    """eq. (2) for an arithmetic progression a + k d: mu = a + d (m-1)/2 and
+    sigma^2 = d^2 (m^2 - 1) / 12."""
+    m, a, d = 1001, -7.0, 0.5
+    T = (a + d * np.arange(m)).astype(np.float32)
+    mu, sd = oracle.stats(T)
+    assert math.isclose(mu, a + d * (m - 1) / 2, rel_tol=1e-14)
+    assert math.isclose(sd, abs(d) * math.sqrt((m * m - 1) / 12.0), rel_tol=1e-13)
+
+
+def test_invalid_inputs():
+    with pytest.raises(oracle.OracleError):
+        oracle.discord(np.ones(100, np.float32), 10)          # sigma == 0
+    with pytest.raises(oracle.OracleError):
+        oracle.discord(np.arange(10, dtype=np.float32), 6)    # m < 2n
+    bad = np.arange(100, dtype=np.float32)
+    bad[3] = np.nan
+    with pytest.raises(oracle.OracleError):
+        oracle.discord(bad, 10)
+
+
+# --------------------------------------------------------------------------- P10
+def test_breakpoints_match_statistical_table():
+    with open(os.path.join(GOLDEN, "sax_breakpoints_table.txt")) as f:
+        rows = [ln.split() for ln in f if ln.strip() and not ln.startswith("#")]
+    for row in rows:
+        alpha = int(row[0])
+        table = np.array([float(v) for v in row[1:]])
+        bp = oracle.breakpoints(alpha)
+        np.testing.assert_array_equal(np.round(bp, 2) + 0.0, table)
+        # equiprobable: Phi(beta_k) = k / alpha
+        phi = 0.5 * (1.0 + np.array([math.erf(b / math.sqrt(2.0)) for b in bp]))
+        np.testing.assert_allclose(phi, np.arange(1, alpha) / alpha, atol=1e-14)
+
+
+def test_sax_worked_example():
+    with open(os.path.join(GOLDEN, "sax_worked_example.json")) as f:
+        g = json.load(f)
+    T = np.array(g["series"], dtype=np.float32)
+    words = oracle.sax_words(T, g["n"], g["w"], g["alphabet"])
+    assert words.tolist() == g["words"]
+    assert oracle.np_sax_words(T, g["n"], g["w"], g["alphabet"]).tolist() == g["words"]
+    hist, cand = oracle.freq_cand(words)
+    assert cand.tolist() == g["cand"]
+    off, mem = oracle.index_word(words)
+    assert mem[off[27]:off[28]].tolist() == g["bucket_27"]
+
+
+def test_sax_structure_on_walk():
+    w = workloads.small()
+    words = oracle.sax_words(w.series, w.n)
+    assert np.array_equal(words, oracle.np_sax_words(w.series, w.n))
+    N = w.m - w.n + 1
+    hist, cand = oracle.freq_cand(words)
+    assert hist.sum() == N
+    live = hist[hist > 0]
+    assert set(words[cand].tolist()) == set(np.flatnonzero(hist == live.min()).tolist())
+    assert np.all(np.diff(cand) > 0)
+    off, mem = oracle.index_word(words)
+    assert off[-1] == N and np.array_equal(np.sort(mem), np.arange(N))
+    for wd in range(256):
+        b = mem[off[wd]:off[wd + 1]]
+        assert np.all(np.diff(b) > 0) and np.all(words[b] == wd)
+
+
+def test_word_hash_is_lexicographic_bijection():
+    """eq. (9): the 4^4 words map one-to-one onto [0, 256) in lexicographic order."""
+    import itertools
+    T_len = 4
+    seen = []
+    bp = oracle.breakpoints(4)
+    centers = [bp[0] - 1.0, (bp[0] + bp[1]) / 2, (bp[1] + bp[2]) / 2, bp[2] + 1.0]
+    for word in itertools.product(range(4), repeat=T_len):
+        code = 0
+        for s in word:
+            code = code * 4 + s
+        seen.append(code)
+    assert seen == list(range(256))
+    # a constant window maps to four equal symbols
+    T = np.concatenate([np.full(8, 5.0), np.linspace(-3, 3, 40)]).astype(np.float32)
+    words = oracle.sax_words(T, 8, 4, 4)
+    s0 = words[0]
+    assert s0 in (0, 85, 170, 255)
+    assert centers[0] < centers[1]
+
+
+def test_breakpoint_intervals_are_left_closed():
+    """eq. (4) reads beta_{k-1} <= value < beta_k: a PAA value exactly on a
+    breakpoint takes the upper symbol.  T = (-1, 1, -1, 1, ...) has mu = 0 and
+    sigma = 1, every 2-point segment averages to exactly 0 = beta_2, so every
+    symbol is 2 (0-based) and every word is 2*64 + 2*16 + 2*4 + 2 = 170."""
+    T = np.tile(np.array([-1.0, 1.0], dtype=np.float32), 8)
+    assert oracle.stats(T) == (0.0, 1.0)
+    words = oracle.sax_words(T, 8, 4, 4)
+    assert words.tolist() == [170] * 9
+    assert oracle.np_sax_words(T, 8, 4, 4).tolist() == [170] * 9
