@@ -1,0 +1,167 @@
+/*
+ * discord.h -- C ABI of the MI355X (gfx950) discord-search library libdiscord.so.
+ *
+ * Problem (the paper's section 2.1): for a series T of m values and a window n,
+ * the subsequences T_{i,n} = (t_i .. t_{i+n-1}), 0 <= i < N = m - n + 1, are
+ * compared with the Euclidean distance of eq. (1); T_{j,n} is a non-self match
+ * of T_{i,n} when |i - j| >= n.  The discord is the subsequence whose nearest
+ * non-self match is farthest away.  The search follows PhiDD (Algorithm 2):
+ * a preparation stage (z-normalisation statistics of eq. (2), PAA/SAX words of
+ * eqs. (3)-(4), the word hash of eq. (9), Cand of eq. (7) and Index_Word of
+ * eq. (10)) and a search stage (PotentialDiscord over Cand, Algorithm 3, then
+ * RefineDiscord over the other rows, Algorithm 4) with early abandon against a
+ * best-so-far.  Distances are compared squared and the root is taken once.
+ *
+ * Conventions
+ *   - Indices are 0-based (the paper counts from 1).
+ *   - Ties: the lowest index wins among maximal nearest-neighbour distances, and
+ *     the lowest j among nearest neighbours.  Rows with no non-self match at all
+ *     (possible only when 2n <= m <= 3n-2) take no part in the argmax.
+ *   - z-normalisation is global (eq. (2)); it is affine, so the argmax is taken on
+ *     raw squared distances and `distance` = sqrt(d2) / sigma.
+ *   - The result is exact: every approximate (FP32 or split-BF16) decision is
+ *     certified or redone in FP64 on the GPU before it is returned.
+ *   - A negative status means no output was written.  No C++ exception crosses
+ *     this boundary.  All functions are thread-safe for distinct plans; a plan
+ *     must not be used from two threads at once.
+ */
+#ifndef DISCORD_H
+#define DISCORD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DISCORD_ABI_VERSION 1
+
+/* ---- status codes ------------------------------------------------------- */
+#define DISCORD_OK        0
+#define DISCORD_EINVAL   -1  /* NULL series, n < 1, m < 2n, NaN/Inf in T, bad option */
+#define DISCORD_ECONST   -2  /* sigma == 0: eq. (2) is undefined for a constant series */
+#define DISCORD_ENOMEM   -3  /* device memory (or the caller's workspace) too small */
+#define DISCORD_EDEVICE  -4  /* HIP runtime error; text in discord_plan_error() */
+#define DISCORD_EBUSY    -5  /* server full or request not finished */
+#define DISCORD_ERANGE   -6  /* size beyond a documented limit */
+
+/* ---- options ------------------------------------------------------------- */
+typedef enum {
+    DISCORD_PREC_FP32   = 0,  /* FP32 direct form sum (a-b)^2 on the vector ALUs */
+    DISCORD_PREC_BF16X3 = 1   /* centred split-BF16 hi/lo products on MFMA, FP32 accumulate */
+} discord_precision;
+
+typedef struct {
+    int32_t precision;  /* discord_precision                                         */
+    int32_t abandon;    /* 1: leave a row once a distance below the best-so-far appears
+                           (Algorithms 1, 3, 4); 0: scan every pair (full scan)      */
+    int32_t order;      /* 1: PhiDD visiting order (Cand rows first, same-word rows
+                           first, Algorithms 3-4); 0: matrix order only              */
+    int32_t topk;       /* approximate candidates per finalist row rescored in FP64
+                           (mixed precision; 1..32)                                  */
+    int32_t paa_w;      /* PAA segments w of eq. (3) (1..8; min(w, n) is used)       */
+    int32_t alphabet;   /* SAX alphabet size |A| of eq. (4) (2..8, |A|^w <= 256)      */
+    int32_t reserved[2];
+} discord_opts;
+
+/* Defaults: FP32, abandon on, PhiDD order, topk 16, w = |A| = 4 (section 3.1). */
+void discord_default_opts(discord_opts* opts);
+
+/* ---- result -------------------------------------------------------------- */
+typedef struct {
+    int64_t  index;           /* discord row i (0-based)                            */
+    int64_t  nn_index;        /* its nearest non-self match j (lowest j on ties)     */
+    double   d2;              /* squared raw distance to it, FP64 (sequential sum)   */
+    double   distance_raw;    /* sqrt(d2)                                           */
+    double   distance;        /* sqrt(d2) / sigma: distance on the series of eq. (2) */
+    double   mu, sigma;       /* eq. (2) statistics (FP64, two-pass)                 */
+    double   max_rel_err;     /* largest relative error of an approximate NN value
+                                 that was checked in FP64 during certification       */
+    int32_t  certified;       /* 1: FP64 certificate complete (always, on success)   */
+    int32_t  precision;       /* discord_precision used by the scan                  */
+    uint64_t pairs_evaluated; /* pair distances computed by the approximate scan      */
+    uint64_t rows_rescored;   /* rows whose exact NN was recomputed in FP64           */
+    uint64_t rows_abandoned;  /* rows left early against the best-so-far              */
+    uint64_t cand_rows;       /* |Cand| (eq. 7)                                       */
+    double   ms_prepare;      /* device time of discord_prepare (HIP events)         */
+    double   ms_search;       /* device time of discord_search (HIP events)          */
+    double   ms_scan;         /* of which: approximate scan kernels                  */
+} discord_result;
+
+typedef struct discord_plan_s* discord_plan;
+
+/* Device bytes a plan for (m, n, opts) needs.  This is what discord_prepare
+ * allocates (workspace == NULL) or requires of a caller workspace.  0 on
+ * invalid arguments. */
+size_t discord_workspace_bytes(int64_t m, int32_t n, const discord_opts* opts);
+
+/* Preparation stage (Algorithm 2, first six steps).
+ *   T          series of m float32 values, host or device pointer (detected with
+ *              hipPointerGetAttributes); borrowed for the call and copied.
+ *   opts       NULL for defaults.
+ *   workspace  NULL: the plan allocates and owns its device memory.  Otherwise a
+ *              device buffer of ws_bytes >= discord_workspace_bytes(), 256-byte
+ *              aligned, owned by the caller and kept alive until release.
+ *   stream     hipStream_t to run on, or NULL for a stream owned by the plan.
+ *   out        receives the plan.
+ * Errors: EINVAL, ECONST, ENOMEM, EDEVICE (see above). */
+int discord_prepare(const float* T, int64_t m, int32_t n, const discord_opts* opts,
+                    void* workspace, size_t ws_bytes, void* stream, discord_plan* out);
+
+/* Search stage (Algorithms 3 and 4) and FP64 certification.  Blocks until the
+ * result is on the host.  May be called repeatedly on one plan (each call redoes
+ * the whole search; the prepared structures are reused). */
+int discord_search(discord_plan plan, discord_result* out);
+
+/* Frees the plan and the device memory it owns.  NULL is ignored. */
+void discord_release(discord_plan plan);
+
+/* Static text for a status code. */
+const char* discord_strerror(int status);
+
+/* Detail of the last error on this plan ("" if none).  With plan == NULL: the
+ * detail of the calling thread's last failed discord_prepare. */
+const char* discord_plan_error(discord_plan plan);
+
+/* The inner breakpoints beta_1..beta_{alpha-1} of eq. (4) (N(0,1) quantiles
+ * k/alpha) that the library's SAX step uses; out holds alpha-1 doubles.
+ * alpha in 2..8. */
+int discord_sax_breakpoints(int32_t alpha, double* out);
+
+/* One-shot: prepare + search with default options on a library stream. */
+int discord_search_series(const float* T, int64_t m, int32_t n, int64_t* index,
+                          double* distance);
+
+/* ---- introspection of the prepared and searched state (for verification) -- */
+typedef enum {
+    DISCORD_FIELD_WORDS       = 0,  /* int32[N]    word id of each row, eqs. (3)(4)(9)   */
+    DISCORD_FIELD_HIST        = 1,  /* int32[|A|^w] word frequencies, eq. (8)           */
+    DISCORD_FIELD_CAND        = 2,  /* int32[cand] Cand, ascending, eq. (7)             */
+    DISCORD_FIELD_CSR_OFFSETS = 3,  /* int32[|A|^w + 1] Index_Word offsets, eq. (10)    */
+    DISCORD_FIELD_CSR_MEMBERS = 4,  /* int32[N]    Index_Word members (ascending/word)  */
+    DISCORD_FIELD_NN_APPROX   = 5,  /* float[N]    approximate NN d^2 of the last search
+                                       (full rows) or the abandon distance             */
+    DISCORD_FIELD_NN_WITNESS  = 6,  /* int32[N]    j attaining NN_APPROX (-1: none)     */
+    DISCORD_FIELD_ROW_STATE   = 7,  /* int32[N]    0 not scanned, 1 full scan, 2 abandoned */
+    DISCORD_FIELD_ROW_MEAN    = 8,  /* double[N]   mean of each row (FP64)              */
+    DISCORD_FIELD_ROW_CNORM   = 9   /* double[N]   centred squared norm of each row     */
+} discord_field;
+
+/* Number of elements of a field (Cand length after prepare; N or table sizes
+ * otherwise); negative status on error. */
+int64_t discord_plan_count(discord_plan plan, int32_t field);
+
+/* Copies a field to host memory; `bytes` must be >= count * element size. */
+int discord_plan_copy(discord_plan plan, int32_t field, void* host_dst, size_t bytes);
+
+/* Exact FP64 nearest non-self match of the listed rows (the rescoring kernel of
+ * the certification, exposed for verification): d2_out[r], j_out[r] (-1: none).
+ * rows / outputs are host pointers of `count` elements. */
+int discord_rows_nn_fp64(discord_plan plan, const int64_t* rows, int64_t count,
+                         double* d2_out, int64_t* j_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DISCORD_H */

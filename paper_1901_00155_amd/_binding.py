@@ -1,2 +1,255 @@
-"""ctypes binding placeholder (filled in with the C ABI)."""
-__all__ = []
+"""ctypes binding of libdiscord.so (include/discord.h).
+
+Argument marshalling only: every step of the search runs in the HIP library.
+PyTorch is used for device memory (optional caller workspace, device-resident
+series) and streams.  There is no CPU fallback: if the library is missing the
+first call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+__all__ = [
+    "load", "DiscordError", "Opts", "Result", "Plan", "search", "default_opts",
+    "workspace_bytes", "strerror", "sax_breakpoints", "search_series",
+    "FIELD", "PREC_FP32", "PREC_BF16X3", "LIB_PATH", "EXPORTED",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "libdiscord.so")
+
+PREC_FP32 = 0
+PREC_BF16X3 = 1
+_PREC = {"fp32": PREC_FP32, "bf16x3": PREC_BF16X3, PREC_FP32: PREC_FP32, PREC_BF16X3: PREC_BF16X3}
+
+FIELD = {
+    "words": (0, np.int32), "hist": (1, np.int32), "cand": (2, np.int32),
+    "csr_offsets": (3, np.int32), "csr_members": (4, np.int32),
+    "nn_approx": (5, np.float32), "nn_witness": (6, np.int32), "row_state": (7, np.int32),
+    "row_mean": (8, np.float64), "row_cnorm": (9, np.float64),
+}
+
+# every symbol the public header declares (checked by the CPU tests)
+EXPORTED = [
+    "discord_default_opts", "discord_workspace_bytes", "discord_prepare", "discord_search",
+    "discord_release", "discord_strerror", "discord_plan_error", "discord_sax_breakpoints",
+    "discord_search_series", "discord_plan_count", "discord_plan_copy", "discord_rows_nn_fp64",
+]
+
+
+class DiscordError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("abandon", ctypes.c_int32),
+                ("order", ctypes.c_int32), ("topk", ctypes.c_int32),
+                ("paa_w", ctypes.c_int32), ("alphabet", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("index", ctypes.c_int64), ("nn_index", ctypes.c_int64),
+                ("d2", ctypes.c_double), ("distance_raw", ctypes.c_double),
+                ("distance", ctypes.c_double), ("mu", ctypes.c_double),
+                ("sigma", ctypes.c_double), ("max_rel_err", ctypes.c_double),
+                ("certified", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("pairs_evaluated", ctypes.c_uint64), ("rows_rescored", ctypes.c_uint64),
+                ("rows_abandoned", ctypes.c_uint64), ("cand_rows", ctypes.c_uint64),
+                ("ms_prepare", ctypes.c_double), ("ms_search", ctypes.c_double),
+                ("ms_scan", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def load():
+    """Load libdiscord.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                           "(there is no CPU fallback)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+    lib.discord_default_opts.argtypes = [ctypes.POINTER(Opts)]
+    lib.discord_default_opts.restype = None
+    lib.discord_workspace_bytes.argtypes = [i64, i32, ctypes.POINTER(Opts)]
+    lib.discord_workspace_bytes.restype = ctypes.c_size_t
+    lib.discord_prepare.argtypes = [vp, i64, i32, ctypes.POINTER(Opts), vp, ctypes.c_size_t, vp,
+                                    ctypes.POINTER(vp)]
+    lib.discord_prepare.restype = ctypes.c_int
+    lib.discord_search.argtypes = [vp, ctypes.POINTER(Result)]
+    lib.discord_search.restype = ctypes.c_int
+    lib.discord_release.argtypes = [vp]
+    lib.discord_release.restype = None
+    lib.discord_strerror.argtypes = [ctypes.c_int]
+    lib.discord_strerror.restype = ctypes.c_char_p
+    lib.discord_plan_error.argtypes = [vp]
+    lib.discord_plan_error.restype = ctypes.c_char_p
+    lib.discord_sax_breakpoints.argtypes = [i32, ctypes.POINTER(ctypes.c_double)]
+    lib.discord_sax_breakpoints.restype = ctypes.c_int
+    lib.discord_search_series.argtypes = [vp, i64, i32, ctypes.POINTER(i64),
+                                          ctypes.POINTER(ctypes.c_double)]
+    lib.discord_search_series.restype = ctypes.c_int
+    lib.discord_plan_count.argtypes = [vp, i32]
+    lib.discord_plan_count.restype = i64
+    lib.discord_plan_copy.argtypes = [vp, i32, vp, ctypes.c_size_t]
+    lib.discord_plan_copy.restype = ctypes.c_int
+    lib.discord_rows_nn_fp64.argtypes = [vp, vp, i64, vp, vp]
+    lib.discord_rows_nn_fp64.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def strerror(status: int) -> str:
+    return load().discord_strerror(status).decode()
+
+
+def _check(status: int, plan=None):
+    if status != 0:
+        detail = load().discord_plan_error(plan).decode() if plan is not None else ""
+        raise DiscordError(status, strerror(status) + (f": {detail}" if detail else ""))
+
+
+def default_opts(**kw) -> Opts:
+    o = Opts()
+    load().discord_default_opts(ctypes.byref(o))
+    if "precision" in kw:
+        kw["precision"] = _PREC[kw["precision"]]
+    for k, v in kw.items():
+        if v is not None:
+            setattr(o, k, int(v))
+    return o
+
+
+def workspace_bytes(m: int, n: int, **kw) -> int:
+    o = default_opts(**kw)
+    return int(load().discord_workspace_bytes(m, n, ctypes.byref(o)))
+
+
+def sax_breakpoints(alpha: int) -> np.ndarray:
+    out = (ctypes.c_double * max(alpha - 1, 1))()
+    _check(load().discord_sax_breakpoints(alpha, out))
+    return np.array(out[:alpha - 1], dtype=np.float64)
+
+
+def _series_ptr(T):
+    """(pointer, m, keepalive, stream) for a numpy array or a torch tensor."""
+    try:
+        import torch
+        if isinstance(T, torch.Tensor):
+            if T.dtype != torch.float32 or T.dim() != 1:
+                raise ValueError("series must be a 1-D float32 tensor")
+            t = T.contiguous()
+            stream = torch.cuda.current_stream(t.device).cuda_stream if t.is_cuda else None
+            return t.data_ptr(), t.numel(), t, stream
+    except ImportError:
+        pass
+    a = np.ascontiguousarray(T, dtype=np.float32)
+    if a.ndim != 1:
+        raise ValueError("series must be one-dimensional")
+    return a.ctypes.data, a.size, a, None
+
+
+class Plan:
+    """A prepared series (discord_prepare) that can be searched repeatedly."""
+
+    def __init__(self, T, n: int, precision="fp32", abandon=True, order=True, topk=16,
+                 paa_w=4, alphabet=4, stream=None, torch_workspace=False):
+        lib = load()
+        self.opts = default_opts(precision=precision, abandon=int(bool(abandon)),
+                                 order=int(bool(order)), topk=topk, paa_w=paa_w,
+                                 alphabet=alphabet)
+        ptr, m, self._keep, tstream = _series_ptr(T)
+        self.m, self.n = int(m), int(n)
+        self.N = self.m - self.n + 1
+        if stream is None:
+            stream = tstream
+        elif hasattr(stream, "cuda_stream"):
+            stream = stream.cuda_stream
+        self._ws = None
+        ws_ptr, ws_bytes = None, 0
+        if torch_workspace:
+            import torch
+            ws_bytes = lib.discord_workspace_bytes(self.m, self.n, ctypes.byref(self.opts))
+            if ws_bytes == 0:
+                _check(-1)
+            self._ws = torch.empty(ws_bytes + 256, dtype=torch.uint8, device="cuda")
+            base = self._ws.data_ptr()
+            ws_ptr = (base + 255) // 256 * 256
+        h = ctypes.c_void_p()
+        st = lib.discord_prepare(ctypes.c_void_p(ptr), self.m, self.n, ctypes.byref(self.opts),
+                                 ws_ptr, ws_bytes, stream, ctypes.byref(h))
+        if st != 0:
+            detail = lib.discord_plan_error(None).decode()
+            raise DiscordError(st, strerror(st) + (f": {detail}" if detail else ""))
+        self._h = h
+
+    def search(self) -> Result:
+        r = Result()
+        _check(load().discord_search(self._h, ctypes.byref(r)), self._h)
+        return r
+
+    def count(self, field: str) -> int:
+        c = load().discord_plan_count(self._h, FIELD[field][0])
+        if c < 0:
+            _check(int(c), self._h)
+        return int(c)
+
+    def copy(self, field: str) -> np.ndarray:
+        code, dt = FIELD[field]
+        c = self.count(field)
+        out = np.empty(c, dtype=dt)
+        _check(load().discord_plan_copy(self._h, code, out.ctypes.data, out.nbytes), self._h)
+        return out
+
+    def rows_nn_fp64(self, rows):
+        rows = np.ascontiguousarray(rows, dtype=np.int64)
+        d = np.empty(rows.size, dtype=np.float64)
+        j = np.empty(rows.size, dtype=np.int64)
+        _check(load().discord_rows_nn_fp64(self._h, rows.ctypes.data, rows.size, d.ctypes.data,
+                                           j.ctypes.data), self._h)
+        return d, j
+
+    def release(self):
+        if getattr(self, "_h", None):
+            load().discord_release(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.release()
+
+
+def search(T, n: int, precision="fp32", **kw):
+    """One prepared search: returns (index, distance, result-dict)."""
+    with Plan(T, n, precision=precision, **kw) as p:
+        r = p.search()
+        return int(r.index), float(r.distance), r.as_dict()
+
+
+def search_series(T, n: int):
+    ptr, m, keep, _ = _series_ptr(T)
+    idx = ctypes.c_int64()
+    dist = ctypes.c_double()
+    _check(load().discord_search_series(ctypes.c_void_p(ptr), m, n, ctypes.byref(idx),
+                                        ctypes.byref(dist)))
+    return int(idx.value), float(dist.value)

@@ -1,0 +1,534 @@
+// api.hip -- host runtime of libdiscord: the C ABI of include/discord.h.
+//
+// A plan owns (or borrows) one device arena holding the padded series, the
+// preparation structures of PhiDD (Algorithm 2) and the search/certification
+// buffers.  Every step of the method runs in this library's kernels; the host
+// only orders launches and reads back counts and the final result.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "../../include/discord.h"
+#include "internal.hpp"
+
+namespace dd {
+
+void sax_breakpoints(int alpha, double* out) {
+  // beta_k = Phi^{-1}(k / alpha), k = 1..alpha-1, by Newton's method on
+  // Phi(x) = erfc(-x / sqrt(2)) / 2 from x = 0 (Phi is monotone with a
+  // positive density, and the targets lie in [1/8, 7/8]).
+  const double inv_sqrt2 = 0.70710678118654752440;
+  const double inv_sqrt2pi = 0.39894228040143267794;
+  for (int k = 1; k < alpha; ++k) {
+    const double p = (double)k / (double)alpha;
+    double x = 0.0;
+    for (int it = 0; it < 100; ++it) {
+      const double f = 0.5 * std::erfc(-x * inv_sqrt2) - p;
+      const double dens = inv_sqrt2pi * std::exp(-0.5 * x * x);
+      const double nx = x - f / dens;
+      if (nx == x) break;
+      x = nx;
+    }
+    if (2 * k == alpha) x = 0.0;   // the median is exactly 0
+    out[k - 1] = x;
+  }
+  for (int k = alpha - 1; k < 8; ++k) out[k] = HUGE_VAL;
+}
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+  size_t T, stats, partials, bad, words, hist, minfreq, cand, cand_count, seg, csr_off, csr_mem,
+      best, nn_approx, nn_wit, row_state, row_mean, row_cnorm, seed, rows, part_d, part_j, out_d,
+      out_j, exact, unc, unc_count, relerr, total;
+};
+
+Layout make_layout(int64_t m, int32_t n, int dict) {
+  const int64_t N = m - n + 1;
+  const int64_t nchunks = (N + kFp64Cols - 1) / kFp64Cols;
+  const int64_t seg = std::max<int64_t>(csr_waves(N) * dict, compact_waves(N));
+  Layout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  };
+  L.T = take(sizeof(float) * (size_t)(kFrontPad + m + kBackPad));
+  L.stats = take(sizeof(double) * 8);
+  L.partials = take(sizeof(double) * kStatBlocks);
+  L.bad = take(sizeof(int32_t) * 4);
+  L.words = take(sizeof(int32_t) * N);
+  L.hist = take(sizeof(int32_t) * kMaxWords);
+  L.minfreq = take(sizeof(int32_t) * 4);
+  L.cand = take(sizeof(int32_t) * N);
+  L.cand_count = take(sizeof(int32_t) * 4);
+  L.seg = take(sizeof(int32_t) * seg);
+  L.csr_off = take(sizeof(int32_t) * (kMaxWords + 1));
+  L.csr_mem = take(sizeof(int32_t) * N);
+  L.best = take(sizeof(uint64_t) * N);
+  L.nn_approx = take(sizeof(float) * N);
+  L.nn_wit = take(sizeof(int32_t) * N);
+  L.row_state = take(sizeof(int32_t) * N);
+  L.row_mean = take(sizeof(double) * N);
+  L.row_cnorm = take(sizeof(double) * N);
+  L.seed = take(sizeof(uint64_t) * 4);
+  L.rows = take(sizeof(int64_t) * kFp64BatchRows);
+  L.part_d = take(sizeof(double) * kFp64BatchRows * nchunks);
+  L.part_j = take(sizeof(int64_t) * kFp64BatchRows * nchunks);
+  L.out_d = take(sizeof(double) * kFp64BatchRows);
+  L.out_j = take(sizeof(int64_t) * kFp64BatchRows);
+  L.exact = take(sizeof(Exact));
+  L.unc = take(sizeof(int64_t) * N);
+  L.unc_count = take(sizeof(uint32_t) * 4);
+  L.relerr = take(sizeof(uint32_t) * 4);
+  L.total = off;
+  return L;
+}
+
+bool opts_valid(int32_t n, const discord_opts& o) {
+  if (o.precision != DISCORD_PREC_FP32 && o.precision != DISCORD_PREC_BF16X3) return false;
+  if (o.abandon != 0 && o.abandon != 1) return false;
+  if (o.order != 0 && o.order != 1) return false;
+  if (o.topk < 1 || o.topk > 32) return false;
+  (void)n;
+  if (o.paa_w < 1 || o.paa_w > 8) return false;
+  if (o.alphabet < 2 || o.alphabet > 8) return false;
+  int64_t dict = 1;
+  for (int k = 0; k < o.paa_w; ++k) dict *= o.alphabet;
+  return dict <= kMaxWords;
+}
+
+int dict_size(const discord_opts& o) {
+  int d = 1;
+  for (int k = 0; k < o.paa_w; ++k) d *= o.alphabet;
+  return d;
+}
+
+}  // namespace
+}  // namespace dd
+
+using namespace dd;
+
+struct discord_plan_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  char* arena = nullptr;
+  bool own_arena = false;
+  Layout L{};
+  int64_t m = 0, N = 0;
+  int32_t n = 0;
+  discord_opts opts{};
+  int dict = 256;
+  double mu = 0.0, sigma = 0.0;
+  int64_t cand_count = 0;
+  double ms_prepare = 0.0;
+  bool searched = false;
+  char err[512] = {0};
+
+  template <class P>
+  P* at(size_t off) const {
+    return reinterpret_cast<P*>(arena + off);
+  }
+  float* Tp() const { return at<float>(L.T) + kFrontPad; }
+};
+
+namespace {
+
+int fail(discord_plan p, int code, const char* fmt, ...) {
+  if (p) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(p->err, sizeof(p->err), fmt, ap);
+    va_end(ap);
+  }
+  return code;
+}
+
+#define HIP_TRY(plan, expr)                                                                  \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      return fail(plan, DISCORD_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));     \
+  } while (0)
+
+int check_launch(discord_plan p, const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(p, DISCORD_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+  return DISCORD_OK;
+}
+
+#define LAUNCH_OK(plan, what)                       \
+  do {                                              \
+    int st_ = check_launch(plan, what);             \
+    if (st_ != DISCORD_OK) return st_;              \
+  } while (0)
+
+bool is_device_pointer(const void* p) {
+  hipPointerAttribute_t a;
+  hipError_t e = hipPointerGetAttributes(&a, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+struct EventPair {
+  hipEvent_t a = nullptr, b = nullptr;
+  EventPair() {
+    (void)hipEventCreate(&a);
+    (void)hipEventCreate(&b);
+  }
+  ~EventPair() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+  float ms() {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, a, b) != hipSuccess) {
+      (void)hipGetLastError();
+      return 0.f;
+    }
+    return t;
+  }
+};
+
+int rows_nn_batch(discord_plan p, const int64_t* d_rows, int64_t count) {
+  launch_rows_nn_fp64(p->Tp(), p->n, p->N, d_rows, count, p->at<double>(p->L.part_d),
+                      p->at<int64_t>(p->L.part_j), p->at<double>(p->L.out_d),
+                      p->at<int64_t>(p->L.out_j), p->stream);
+  LAUNCH_OK(p, "rows_nn_fp64");
+  return DISCORD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void discord_default_opts(discord_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->precision = DISCORD_PREC_FP32;
+  o->abandon = 1;
+  o->order = 1;
+  o->topk = 16;
+  o->paa_w = 4;
+  o->alphabet = 4;
+}
+
+const char* discord_strerror(int status) {
+  switch (status) {
+    case DISCORD_OK: return "ok";
+    case DISCORD_EINVAL: return "invalid argument (NULL series, n < 1, m < 2n, non-finite value or bad option)";
+    case DISCORD_ECONST: return "constant series: sigma == 0, z-normalisation undefined";
+    case DISCORD_ENOMEM: return "not enough device memory or workspace too small";
+    case DISCORD_EDEVICE: return "HIP runtime error";
+    case DISCORD_EBUSY: return "busy";
+    case DISCORD_ERANGE: return "size beyond a documented limit";
+    default: return "unknown status";
+  }
+}
+
+static thread_local char g_prepare_err[512];
+
+const char* discord_plan_error(discord_plan p) { return p ? p->err : g_prepare_err; }
+
+size_t discord_workspace_bytes(int64_t m, int32_t n, const discord_opts* opts) {
+  discord_opts o;
+  if (opts) o = *opts; else discord_default_opts(&o);
+  if (n >= 1 && o.paa_w >= 1 && o.paa_w <= 8 && o.paa_w > n) o.paa_w = n;
+  if (n < 1 || m < 2 * (int64_t)n || !opts_valid(n, o)) return 0;
+  if (m > (int64_t)INT32_MAX - kBackPad - kFrontPad) return 0;
+  return make_layout(m, n, dict_size(o)).total;
+}
+
+int discord_prepare(const float* T, int64_t m, int32_t n, const discord_opts* opts, void* workspace,
+                    size_t ws_bytes, void* stream, discord_plan* out) {
+  if (!out) return DISCORD_EINVAL;
+  *out = nullptr;
+  discord_opts o;
+  if (opts) o = *opts; else discord_default_opts(&o);
+  if (o.paa_w >= 1 && o.paa_w <= 8 && o.paa_w > n) o.paa_w = n;   // eq. (3) needs w <= n
+  g_prepare_err[0] = 0;
+  if (!T || n < 1 || m < 2 * (int64_t)n || !opts_valid(n, o)) return DISCORD_EINVAL;
+  if (m > (int64_t)INT32_MAX - kBackPad - kFrontPad) return DISCORD_ERANGE;
+
+  discord_plan p = new (std::nothrow) discord_plan_s();
+  if (!p) return DISCORD_ENOMEM;
+  p->m = m;
+  p->n = n;
+  p->N = m - n + 1;
+  p->opts = o;
+  p->dict = dict_size(o);
+  p->L = make_layout(m, n, p->dict);
+  auto bail = [&](int st) {
+    discord_release(p);
+    return st;
+  };
+  if (hipGetDevice(&p->device) != hipSuccess) return bail(DISCORD_EDEVICE);
+  if (stream) {
+    p->stream = (hipStream_t)stream;
+  } else {
+    if (hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking) != hipSuccess)
+      return bail(DISCORD_EDEVICE);
+    p->own_stream = true;
+  }
+  if (workspace) {
+    if (ws_bytes < p->L.total || ((uintptr_t)workspace % kAlign) != 0) return bail(DISCORD_ENOMEM);
+    p->arena = (char*)workspace;
+  } else {
+    if (hipMalloc(&p->arena, p->L.total) != hipSuccess) {
+      (void)hipGetLastError();
+      p->arena = nullptr;
+      return bail(DISCORD_ENOMEM);
+    }
+    p->own_arena = true;
+  }
+  int st = DISCORD_OK;
+  EventPair ev;
+  hipStream_t s = p->stream;
+  auto run = [&]() -> int {
+    HIP_TRY(p, hipEventRecord(ev.a, s));
+    // padded series: zero pads, then the values
+    float* Tbase = p->at<float>(p->L.T);
+    launch_init_i32(reinterpret_cast<int32_t*>(Tbase), kFrontPad, 0, s);
+    launch_init_i32(reinterpret_cast<int32_t*>(Tbase + kFrontPad + m), kBackPad, 0, s);
+    const hipMemcpyKind kind = is_device_pointer(T) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    HIP_TRY(p, hipMemcpyAsync(p->Tp(), T, sizeof(float) * m, kind, s));
+    // eq. (2)
+    launch_init_i32(p->at<int32_t>(p->L.bad), 4, 0, s);
+    launch_stats(p->Tp(), m, p->at<double>(p->L.partials), p->at<double>(p->L.stats),
+                 p->at<int32_t>(p->L.bad), s);
+    LAUNCH_OK(p, "stats");
+    double hstats[3];
+    int32_t hbad = 0;
+    HIP_TRY(p, hipMemcpyAsync(hstats, p->at<double>(p->L.stats), sizeof(hstats),
+                              hipMemcpyDeviceToHost, s));
+    HIP_TRY(p, hipMemcpyAsync(&hbad, p->at<int32_t>(p->L.bad), sizeof(hbad), hipMemcpyDeviceToHost, s));
+    HIP_TRY(p, hipStreamSynchronize(s));
+    if (hbad) return fail(p, DISCORD_EINVAL, "series holds NaN or Inf");
+    p->mu = hstats[0];
+    p->sigma = hstats[1];
+    if (!(p->sigma > 0.0)) return fail(p, DISCORD_ECONST, "sigma == 0");
+    // row statistics, PAA -> SAX -> word ids, histogram, Cand, Index_Word
+    launch_row_stats(p->Tp(), p->N, n, p->at<double>(p->L.row_mean), p->at<double>(p->L.row_cnorm), s);
+    launch_init_i32(p->at<int32_t>(p->L.hist), kMaxWords, 0, s);
+    launch_sax(p->Tp(), p->N, n, o.paa_w, o.alphabet, p->at<double>(p->L.stats),
+               p->at<int32_t>(p->L.words), p->at<int32_t>(p->L.hist), s);
+    launch_cand(p->at<int32_t>(p->L.words), p->at<int32_t>(p->L.hist), p->N, p->dict,
+                p->at<int32_t>(p->L.minfreq), p->at<int32_t>(p->L.seg), p->at<int32_t>(p->L.cand),
+                p->at<int32_t>(p->L.cand_count), s);
+    launch_csr(p->at<int32_t>(p->L.words), p->at<int32_t>(p->L.hist), p->N, p->dict,
+               p->at<int32_t>(p->L.seg), p->at<int32_t>(p->L.csr_off),
+               p->at<int32_t>(p->L.csr_mem), s);
+    LAUNCH_OK(p, "prepare kernels");
+    int32_t hc = 0;
+    HIP_TRY(p, hipMemcpyAsync(&hc, p->at<int32_t>(p->L.cand_count), sizeof(hc), hipMemcpyDeviceToHost, s));
+    HIP_TRY(p, hipEventRecord(ev.b, s));
+    HIP_TRY(p, hipStreamSynchronize(s));
+    p->cand_count = hc;
+    p->ms_prepare = ev.ms();
+    return DISCORD_OK;
+  };
+  st = run();
+  if (st != DISCORD_OK) {
+    // keep the message for the caller: copy before release
+    std::snprintf(g_prepare_err, sizeof(g_prepare_err), "%s", p->err);
+    return bail(st);
+  }
+  *out = p;
+  return DISCORD_OK;
+}
+
+int discord_search(discord_plan p, discord_result* out) {
+  if (!p || !out) return DISCORD_EINVAL;
+  hipStream_t s = p->stream;
+  const int64_t N = p->N;
+  const int n = p->n;
+  EventPair ev, evs;
+  discord_result r;
+  std::memset(&r, 0, sizeof(r));
+  HIP_TRY(p, hipSetDevice(p->device));
+  HIP_TRY(p, hipEventRecord(ev.a, s));
+
+  uint64_t* best = p->at<uint64_t>(p->L.best);
+  launch_init_u64(best, N, kEmptyMin, s);
+  // ---- approximate scan -------------------------------------------------------
+  HIP_TRY(p, hipEventRecord(evs.a, s));
+  {
+    const int64_t row_groups = (N + kRowGroup - 1) / kRowGroup;
+    // split the columns so that a small problem still fills the GPU
+    int64_t chunks = 1;
+    while (row_groups * chunks < 8192 && chunks * 2048 < N) chunks *= 2;
+    int64_t cols = (N + chunks - 1) / chunks;
+    cols = (cols + 511) / 512 * 512;
+    chunks = (N + cols - 1) / cols;
+    launch_scan_fp32_full(p->Tp(), n, N, row_groups, chunks, cols, best, s);
+    LAUNCH_OK(p, "scan_fp32_full");
+  }
+  HIP_TRY(p, hipEventRecord(evs.b, s));
+  r.pairs_evaluated = (N - n > 0) ? (uint64_t)(N - n) * (uint64_t)(N - n + 1) : 0;
+
+  // ---- certification in FP64 ---------------------------------------------------
+  float* nn_approx = p->at<float>(p->L.nn_approx);
+  int32_t* nn_wit = p->at<int32_t>(p->L.nn_wit);
+  int32_t* row_state = p->at<int32_t>(p->L.row_state);
+  launch_unpack_best(best, N, n, nn_approx, nn_wit, row_state, s);
+  uint64_t* seed = p->at<uint64_t>(p->L.seed);
+  launch_init_u64(seed, 1, 0, s);
+  launch_seed_argmax(best, row_state, N, seed, s);
+  int64_t* rows = p->at<int64_t>(p->L.rows);
+  launch_seed_row(seed, rows, s);
+  int st = rows_nn_batch(p, rows, 1);
+  if (st) return st;
+  Exact* ex = p->at<Exact>(p->L.exact);
+  launch_exact_from_rows(rows, p->at<double>(p->L.out_d), p->at<int64_t>(p->L.out_j), 1, ex, s);
+  uint32_t* unc_count = p->at<uint32_t>(p->L.unc_count);
+  uint32_t* relerr = p->at<uint32_t>(p->L.relerr);
+  launch_init_i32(reinterpret_cast<int32_t*>(unc_count), 1, 0, s);
+  launch_init_i32(reinterpret_cast<int32_t*>(relerr), 1, 0, s);
+  int64_t* unc = p->at<int64_t>(p->L.unc);
+  launch_verify(p->Tp(), n, N, nn_wit, nn_approx, ex, unc, unc_count, relerr, s);
+  LAUNCH_OK(p, "verify");
+  uint32_t hunc = 0, hrel = 0;
+  HIP_TRY(p, hipMemcpyAsync(&hunc, unc_count, sizeof(hunc), hipMemcpyDeviceToHost, s));
+  HIP_TRY(p, hipMemcpyAsync(&hrel, relerr, sizeof(hrel), hipMemcpyDeviceToHost, s));
+  HIP_TRY(p, hipStreamSynchronize(s));
+  for (int64_t b = 0; b < (int64_t)hunc; b += kFp64BatchRows) {
+    const int64_t c = std::min<int64_t>(kFp64BatchRows, (int64_t)hunc - b);
+    st = rows_nn_batch(p, unc + b, c);
+    if (st) return st;
+    launch_merge_exact(unc + b, p->at<double>(p->L.out_d), p->at<int64_t>(p->L.out_j), c, ex,
+                       nn_wit, s);
+    LAUNCH_OK(p, "merge_exact");
+  }
+  Exact hex;
+  HIP_TRY(p, hipMemcpyAsync(&hex, ex, sizeof(hex), hipMemcpyDeviceToHost, s));
+  HIP_TRY(p, hipEventRecord(ev.b, s));
+  HIP_TRY(p, hipStreamSynchronize(s));
+  if (hex.i < 0) return fail(p, DISCORD_EDEVICE, "certification produced no discord");
+
+  r.index = hex.i;
+  r.nn_index = hex.j;
+  r.d2 = hex.d2;
+  r.distance_raw = std::sqrt(hex.d2);
+  r.distance = r.distance_raw / p->sigma;
+  r.mu = p->mu;
+  r.sigma = p->sigma;
+  r.max_rel_err = (double)__builtin_bit_cast(float, hrel);
+  r.certified = 1;
+  r.precision = p->opts.precision;
+  r.rows_rescored = 1 + hunc;
+  r.rows_abandoned = 0;
+  r.cand_rows = (uint64_t)p->cand_count;
+  r.ms_prepare = p->ms_prepare;
+  r.ms_search = ev.ms();
+  r.ms_scan = evs.ms();
+  p->searched = true;
+  *out = r;
+  return DISCORD_OK;
+}
+
+void discord_release(discord_plan p) {
+  if (!p) return;
+  if (p->stream) (void)hipStreamSynchronize(p->stream);
+  if (p->own_arena && p->arena) (void)hipFree(p->arena);
+  if (p->own_stream && p->stream) (void)hipStreamDestroy(p->stream);
+  delete p;
+}
+
+int discord_search_series(const float* T, int64_t m, int32_t n, int64_t* index, double* distance) {
+  if (!index || !distance) return DISCORD_EINVAL;
+  discord_plan p = nullptr;
+  int st = discord_prepare(T, m, n, nullptr, nullptr, 0, nullptr, &p);
+  if (st != DISCORD_OK) return st;
+  discord_result r;
+  st = discord_search(p, &r);
+  discord_release(p);
+  if (st != DISCORD_OK) return st;
+  *index = r.index;
+  *distance = r.distance;
+  return DISCORD_OK;
+}
+
+int64_t discord_plan_count(discord_plan p, int32_t field) {
+  if (!p) return DISCORD_EINVAL;
+  switch (field) {
+    case DISCORD_FIELD_WORDS:
+    case DISCORD_FIELD_CSR_MEMBERS:
+    case DISCORD_FIELD_NN_APPROX:
+    case DISCORD_FIELD_NN_WITNESS:
+    case DISCORD_FIELD_ROW_STATE:
+    case DISCORD_FIELD_ROW_MEAN:
+    case DISCORD_FIELD_ROW_CNORM: return p->N;
+    case DISCORD_FIELD_HIST: return p->dict;
+    case DISCORD_FIELD_CSR_OFFSETS: return p->dict + 1;
+    case DISCORD_FIELD_CAND: return p->cand_count;
+    default: return DISCORD_EINVAL;
+  }
+}
+
+int discord_plan_copy(discord_plan p, int32_t field, void* host_dst, size_t bytes) {
+  if (!p || !host_dst) return DISCORD_EINVAL;
+  const int64_t count = discord_plan_count(p, field);
+  if (count < 0) return DISCORD_EINVAL;
+  size_t elem = 4, off = 0;
+  switch (field) {
+    case DISCORD_FIELD_WORDS: off = p->L.words; break;
+    case DISCORD_FIELD_HIST: off = p->L.hist; break;
+    case DISCORD_FIELD_CAND: off = p->L.cand; break;
+    case DISCORD_FIELD_CSR_OFFSETS: off = p->L.csr_off; break;
+    case DISCORD_FIELD_CSR_MEMBERS: off = p->L.csr_mem; break;
+    case DISCORD_FIELD_NN_APPROX: off = p->L.nn_approx; break;
+    case DISCORD_FIELD_NN_WITNESS: off = p->L.nn_wit; break;
+    case DISCORD_FIELD_ROW_STATE: off = p->L.row_state; break;
+    case DISCORD_FIELD_ROW_MEAN: off = p->L.row_mean; elem = 8; break;
+    case DISCORD_FIELD_ROW_CNORM: off = p->L.row_cnorm; elem = 8; break;
+    default: return DISCORD_EINVAL;
+  }
+  if (bytes < elem * (size_t)count) return DISCORD_EINVAL;
+  if (count == 0) return DISCORD_OK;
+  HIP_TRY(p, hipMemcpyAsync(host_dst, p->arena + off, elem * (size_t)count, hipMemcpyDeviceToHost,
+                            p->stream));
+  HIP_TRY(p, hipStreamSynchronize(p->stream));
+  return DISCORD_OK;
+}
+
+int discord_rows_nn_fp64(discord_plan p, const int64_t* rows, int64_t count, double* d2_out,
+                         int64_t* j_out) {
+  if (!p || count < 0 || (count > 0 && (!rows || !d2_out || !j_out))) return DISCORD_EINVAL;
+  for (int64_t k = 0; k < count; ++k)
+    if (rows[k] < 0 || rows[k] >= p->N) return DISCORD_EINVAL;
+  int64_t* d_rows = p->at<int64_t>(p->L.rows);
+  for (int64_t b = 0; b < count; b += kFp64BatchRows) {
+    const int64_t c = std::min<int64_t>(kFp64BatchRows, count - b);
+    HIP_TRY(p, hipMemcpyAsync(d_rows, rows + b, sizeof(int64_t) * c, hipMemcpyHostToDevice, p->stream));
+    int st = rows_nn_batch(p, d_rows, c);
+    if (st) return st;
+    HIP_TRY(p, hipMemcpyAsync(d2_out + b, p->at<double>(p->L.out_d), sizeof(double) * c,
+                              hipMemcpyDeviceToHost, p->stream));
+    HIP_TRY(p, hipMemcpyAsync(j_out + b, p->at<int64_t>(p->L.out_j), sizeof(int64_t) * c,
+                              hipMemcpyDeviceToHost, p->stream));
+    HIP_TRY(p, hipStreamSynchronize(p->stream));
+  }
+  return DISCORD_OK;
+}
+
+int discord_sax_breakpoints(int32_t alpha, double* out) {
+  if (!out || alpha < 2 || alpha > 8) return DISCORD_EINVAL;
+  double b[8];
+  sax_breakpoints(alpha, b);
+  for (int k = 0; k < alpha - 1; ++k) out[k] = b[k];
+  return DISCORD_OK;
+}
+
+}  // extern "C"

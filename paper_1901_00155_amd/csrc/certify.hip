@@ -1,0 +1,292 @@
+// certify.hip -- FP64 steps of the search: the exact nearest neighbour of chosen
+// rows, the witness verification that proves every other row cannot be the
+// discord, and the device-wide argmax with the lowest-index tie rule.
+//
+// Why this is exact.  Let L be the exact NN (squared) of some row s.  Every row
+// i carries a witness w(i), a non-self column found by the approximate scan
+// (its approximate argmin, or the column that made it leave early).  Its NN is
+// at most e(i) = d^2(i, w(i)) computed exactly here.  If e(i) < L, or e(i) = L
+// and i > s, row i cannot be the discord under the lowest-index rule.  The rows
+// that fail this test get their exact NN by a full FP64 row scan, and the final
+// answer is the argmax over s and those rows.  No step relies on an error bound
+// of the approximate arithmetic.
+//
+// FP64 distances are the sequential sum over k = 0..n-1 of (a_k - b_k)^2 with a
+// separately rounded multiply and add (contraction off), i.e. the sum eq. (1)
+// defines, accumulated in the order it is written.
+#include <algorithm>
+
+#include "internal.hpp"
+
+namespace dd {
+namespace {
+
+#pragma clang fp contract(off)
+
+__device__ inline double d2_fp64(const float* __restrict__ T, int64_t i, int64_t j, int n) {
+  double s = 0.0;
+  for (int k = 0; k < n; ++k) {
+    const double d = (double)T[i + k] - (double)T[j + k];
+    s = s + d * d;
+  }
+  return s;
+}
+
+__device__ inline bool has_non_self(int64_t i, int64_t N, int n) {
+  return (i - n >= 0) || (i + n <= N - 1);
+}
+
+__global__ void k_fill_u64(uint64_t* p, int64_t count, uint64_t v) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < count;
+       k += (int64_t)gridDim.x * blockDim.x)
+    p[k] = v;
+}
+
+__global__ void k_fill_i32(int32_t* p, int64_t count, int32_t v) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < count;
+       k += (int64_t)gridDim.x * blockDim.x)
+    p[k] = v;
+}
+
+__global__ __launch_bounds__(256) void k_unpack_best(const uint64_t* __restrict__ best, int64_t N,
+                                                     float* __restrict__ nn_approx,
+                                                     int32_t* __restrict__ nn_witness,
+                                                     int32_t* __restrict__ row_state) {
+  const int64_t i = blockIdx.x * 256ll + threadIdx.x;
+  if (i >= N) return;
+  const uint64_t k = best[i];
+  if (k == kEmptyMin) {
+    nn_approx[i] = __builtin_inff();
+    nn_witness[i] = -1;
+    row_state[i] = kRowUnscanned;
+  } else {
+    nn_approx[i] = key_dist(k);
+    nn_witness[i] = (int32_t)(k & 0xFFFFFFFFu);
+    row_state[i] = kRowFull;
+  }
+}
+
+__device__ inline uint64_t wave_max_u64(uint64_t v) {
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint64_t o = __shfl_xor(v, off, 64);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+
+// max approximate NN over fully scanned rows, lowest row on ties
+__global__ __launch_bounds__(256) void k_seed_argmax(const uint64_t* __restrict__ best,
+                                                     const int32_t* __restrict__ row_state,
+                                                     int64_t N, uint64_t* __restrict__ seed) {
+  const int64_t i = blockIdx.x * 256ll + threadIdx.x;
+  uint64_t key = 0;
+  if (i < N && row_state[i] == kRowFull) key = pack_max(key_dist(best[i]), (uint32_t)i);
+  key = wave_max_u64(key);
+  if ((threadIdx.x & 63) == 0 && key) atomicMax((unsigned long long*)seed, (unsigned long long)key);
+}
+
+__global__ void k_seed_row(const uint64_t* __restrict__ seed, int64_t* __restrict__ rows) {
+  const uint64_t k = *seed;
+  rows[0] = k ? (int64_t)(0xFFFFFFFFu - (uint32_t)(k & 0xFFFFFFFFu)) : 0;
+}
+
+// Exact NN of rows[y] over the columns of chunk x: block min, lowest j on ties.
+__global__ __launch_bounds__(256) void k_rows_nn_fp64(const float* __restrict__ T, int n, int64_t N,
+                                                      const int64_t* __restrict__ rows,
+                                                      int64_t nchunks,
+                                                      double* __restrict__ part_d,
+                                                      int64_t* __restrict__ part_j) {
+  __shared__ double sd[256];
+  __shared__ int64_t sj[256];
+  const int64_t i = rows[blockIdx.y];
+  const int64_t cb = (int64_t)blockIdx.x * kFp64Cols;
+  const int64_t ce = min<int64_t>(N, cb + kFp64Cols);
+  double bd = __builtin_inf();
+  int64_t bj = -1;
+  for (int64_t j = cb + threadIdx.x; j < ce; j += 256) {
+    const int64_t dij = i > j ? i - j : j - i;
+    if (dij < n) continue;
+    const double d = d2_fp64(T, i, j, n);
+    if (d < bd) {
+      bd = d;
+      bj = j;
+    }
+  }
+  sd[threadIdx.x] = bd;
+  sj[threadIdx.x] = bj;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      const double od = sd[threadIdx.x + h];
+      const int64_t oj = sj[threadIdx.x + h];
+      const double md = sd[threadIdx.x];
+      const int64_t mj = sj[threadIdx.x];
+      if (oj >= 0 && (mj < 0 || od < md || (od == md && oj < mj))) {
+        sd[threadIdx.x] = od;
+        sj[threadIdx.x] = oj;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part_d[blockIdx.y * nchunks + blockIdx.x] = sd[0];
+    part_j[blockIdx.y * nchunks + blockIdx.x] = sj[0];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_rows_nn_reduce(const double* __restrict__ part_d,
+                                                        const int64_t* __restrict__ part_j,
+                                                        int64_t nchunks, double* __restrict__ out_d,
+                                                        int64_t* __restrict__ out_j) {
+  __shared__ double sd[256];
+  __shared__ int64_t sj[256];
+  double bd = __builtin_inf();
+  int64_t bj = -1;
+  const double* pd = part_d + blockIdx.x * nchunks;
+  const int64_t* pj = part_j + blockIdx.x * nchunks;
+  for (int64_t c = threadIdx.x; c < nchunks; c += 256) {
+    const double d = pd[c];
+    const int64_t j = pj[c];
+    if (j >= 0 && (bj < 0 || d < bd || (d == bd && j < bj))) {
+      bd = d;
+      bj = j;
+    }
+  }
+  sd[threadIdx.x] = bd;
+  sj[threadIdx.x] = bj;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      const double od = sd[threadIdx.x + h];
+      const int64_t oj = sj[threadIdx.x + h];
+      const double md = sd[threadIdx.x];
+      const int64_t mj = sj[threadIdx.x];
+      if (oj >= 0 && (mj < 0 || od < md || (od == md && oj < mj))) {
+        sd[threadIdx.x] = od;
+        sj[threadIdx.x] = oj;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out_d[blockIdx.x] = sd[0];
+    out_j[blockIdx.x] = sj[0];
+  }
+}
+
+__global__ void k_exact_from_rows(const int64_t* __restrict__ rows, const double* __restrict__ d,
+                                  const int64_t* __restrict__ j, Exact* __restrict__ ex) {
+  ex->d2 = d[0];
+  ex->i = j[0] >= 0 ? rows[0] : -1;
+  ex->j = j[0];
+}
+
+// Witness verification (see the file comment); appends failing rows.
+__global__ __launch_bounds__(256) void k_verify(const float* __restrict__ T, int n, int64_t N,
+                                                const int32_t* __restrict__ nn_witness,
+                                                const float* __restrict__ nn_approx,
+                                                const Exact* __restrict__ ex,
+                                                int64_t* __restrict__ uncertain,
+                                                uint32_t* __restrict__ count,
+                                                uint32_t* __restrict__ max_rel_err_bits) {
+  const int64_t i = blockIdx.x * 256ll + threadIdx.x;
+  float rel = 0.0f;
+  if (i < N) {
+    const double L = ex->d2;
+    const int64_t s = ex->i;
+    if (i != s && has_non_self(i, N, n)) {
+      const int32_t w = nn_witness[i];
+      bool ok = false;
+      if (w >= 0 && s >= 0) {
+        const double e = d2_fp64(T, i, w, n);
+        ok = (e < L) || (e == L && i > s);
+        if (e > 0.0) rel = (float)(fabs((double)nn_approx[i] - e) / e);
+      }
+      if (!ok) uncertain[atomicAdd(count, 1u)] = i;
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) rel = fmaxf(rel, __shfl_xor(rel, off, 64));
+  if ((threadIdx.x & 63) == 0 && rel > 0.0f)
+    atomicMax(max_rel_err_bits, __builtin_bit_cast(uint32_t, rel));
+}
+
+// argmax of (ex, rows[k] with exact d[k]): larger d wins, lower row on ties.
+// The exact nearest neighbours also replace the rows' witnesses, so the exported
+// witness array is a complete certificate.
+__global__ void k_merge_exact(const int64_t* __restrict__ rows, const double* __restrict__ d,
+                              const int64_t* __restrict__ j, int64_t count, Exact* __restrict__ ex,
+                              int32_t* __restrict__ nn_witness) {
+  for (int64_t k = threadIdx.x; k < count; k += blockDim.x)
+    if (j[k] >= 0) nn_witness[rows[k]] = (int32_t)j[k];
+  if (threadIdx.x != 0) return;
+  Exact b = *ex;
+  for (int64_t k = 0; k < count; ++k) {
+    if (j[k] < 0) continue;
+    if (b.i < 0 || d[k] > b.d2 || (d[k] == b.d2 && rows[k] < b.i)) {
+      b.d2 = d[k];
+      b.i = rows[k];
+      b.j = j[k];
+    }
+  }
+  *ex = b;
+}
+
+}  // namespace
+
+void launch_init_u64(uint64_t* p, int64_t count, uint64_t v, hipStream_t s) {
+  const int64_t blocks = std::min<int64_t>(4096, (count + 255) / 256);
+  if (count > 0) hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)blocks), dim3(256), 0, s, p, count, v);
+}
+
+void launch_init_i32(int32_t* p, int64_t count, int32_t v, hipStream_t s) {
+  const int64_t blocks = std::min<int64_t>(4096, (count + 255) / 256);
+  if (count > 0) hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)blocks), dim3(256), 0, s, p, count, v);
+}
+
+void launch_unpack_best(const uint64_t* best, int64_t N, int n, float* nn_approx,
+                        int32_t* nn_witness, int32_t* row_state, hipStream_t s) {
+  (void)n;
+  hipLaunchKernelGGL(k_unpack_best, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, best, N,
+                     nn_approx, nn_witness, row_state);
+}
+
+void launch_seed_argmax(const uint64_t* best, const int32_t* row_state, int64_t N,
+                        uint64_t* seed_key, hipStream_t s) {
+  hipLaunchKernelGGL(k_seed_argmax, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, best,
+                     row_state, N, seed_key);
+}
+
+void launch_seed_row(const uint64_t* seed_key, int64_t* rows_out, hipStream_t s) {
+  hipLaunchKernelGGL(k_seed_row, dim3(1), dim3(1), 0, s, seed_key, rows_out);
+}
+
+void launch_rows_nn_fp64(const float* Tp, int n, int64_t N, const int64_t* rows, int64_t count,
+                         double* part_d, int64_t* part_j, double* out_d, int64_t* out_j,
+                         hipStream_t s) {
+  if (count <= 0) return;
+  const int64_t nchunks = (N + kFp64Cols - 1) / kFp64Cols;
+  hipLaunchKernelGGL(k_rows_nn_fp64, dim3((unsigned)nchunks, (unsigned)count), dim3(256), 0, s, Tp,
+                     n, N, rows, nchunks, part_d, part_j);
+  hipLaunchKernelGGL(k_rows_nn_reduce, dim3((unsigned)count), dim3(256), 0, s, part_d, part_j,
+                     nchunks, out_d, out_j);
+}
+
+void launch_exact_from_rows(const int64_t* rows, const double* d, const int64_t* j, int64_t count,
+                            Exact* ex, hipStream_t s) {
+  (void)count;
+  hipLaunchKernelGGL(k_exact_from_rows, dim3(1), dim3(1), 0, s, rows, d, j, ex);
+}
+
+void launch_verify(const float* Tp, int n, int64_t N, const int32_t* nn_witness,
+                   const float* nn_approx, const Exact* ex, int64_t* uncertain,
+                   uint32_t* uncertain_count, uint32_t* max_rel_err_bits, hipStream_t s) {
+  hipLaunchKernelGGL(k_verify, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, Tp, n, N,
+                     nn_witness, nn_approx, ex, uncertain, uncertain_count, max_rel_err_bits);
+}
+
+void launch_merge_exact(const int64_t* rows, const double* d, const int64_t* j, int64_t count,
+                        Exact* ex, int32_t* nn_witness, hipStream_t s) {
+  hipLaunchKernelGGL(k_merge_exact, dim3(1), dim3(64), 0, s, rows, d, j, count, ex, nn_witness);
+}
+
+}  // namespace dd

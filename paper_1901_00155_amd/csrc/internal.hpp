@@ -1,0 +1,98 @@
+// internal.hpp -- shared declarations of libdiscord's kernels and host runtime.
+// Not part of the public ABI (include/discord.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace dd {
+
+// The device copy of the series is padded with zeros on both sides so that the
+// scan kernels can read whole aligned vectors past either end without bounds
+// checks; pad values never reach a valid pair (masked by the non-self rule and
+// the row/column limits).
+constexpr int64_t kFrontPad = 64;    // floats before t_0 (keeps t_0 256-byte aligned)
+constexpr int64_t kBackPad = 2048;   // floats after t_{m-1}
+
+constexpr int kRowGroup = 8;         // rows sharing one FP32 scan micro-tile
+constexpr int kColBlock = 8;         // columns per lane in the FP32 scan micro-tile
+constexpr int kWave = 64;
+
+constexpr int kMaxWords = 256;       // |A|^w limit (eq. 9 hash fits a byte)
+constexpr int kStatBlocks = 1024;    // fixed grid of the FP64 reductions (deterministic)
+constexpr int kFp64Cols = 2048;      // columns per block of the FP64 row rescan
+constexpr int kFp64BatchRows = 64;   // rows per launch of the FP64 row rescan
+
+// Packed (distance, index) keys.  Non-negative IEEE floats order like their bit
+// patterns, so one 64-bit integer min/max compares distance first and index
+// second.
+__host__ __device__ inline uint64_t pack_min(float d, uint32_t j) {
+  return (static_cast<uint64_t>(__builtin_bit_cast(uint32_t, d)) << 32) | j;
+}
+// For a max over rows where the lowest row must win ties, store ~i.
+__host__ __device__ inline uint64_t pack_max(float d, uint32_t i) {
+  return (static_cast<uint64_t>(__builtin_bit_cast(uint32_t, d)) << 32) | (0xFFFFFFFFu - i);
+}
+__host__ __device__ inline float key_dist(uint64_t k) {
+  return __builtin_bit_cast(float, static_cast<uint32_t>(k >> 32));
+}
+constexpr uint64_t kEmptyMin = ~0ull;
+
+// Row states written by the scans.
+enum RowState : int32_t { kRowUnscanned = 0, kRowFull = 1, kRowAbandoned = 2 };
+
+// Exact result of the FP64 stage.
+struct Exact {
+  double d2;
+  int64_t i;    // discord row
+  int64_t j;    // its nearest non-self match
+};
+
+// ---- prep.hip -----------------------------------------------------------------
+void launch_stats(const float* Tp, int64_t m, double* partials, double* stats, int* bad,
+                  hipStream_t s);
+void launch_row_stats(const float* Tp, int64_t N, int n, double* row_mean, double* row_cnorm,
+                      hipStream_t s);
+void launch_sax(const float* Tp, int64_t N, int n, int w, int alpha, const double* stats,
+                int32_t* words, int32_t* hist, hipStream_t s);
+void launch_cand(const int32_t* words, const int32_t* hist, int64_t N, int dict,
+                 int32_t* flags_scratch, int32_t* wave_counts, int32_t* cand, int32_t* cand_count,
+                 hipStream_t s);
+void launch_csr(const int32_t* words, const int32_t* hist, int64_t N, int dict,
+                int32_t* wave_counts, int32_t* offsets, int32_t* members, hipStream_t s);
+int64_t csr_waves(int64_t N);
+int64_t compact_waves(int64_t N);
+
+// ---- scan_fp32.hip ------------------------------------------------------------
+struct Fp32ScanItem {   // one wave: a row group against a column range
+  int32_t row_group;
+  int32_t col_begin;    // first column (multiple of kColBlock)
+  int32_t col_end;      // one past the last column
+  int32_t pad;
+};
+void launch_scan_fp32_full(const float* Tp, int n, int64_t N, int64_t row_groups,
+                           int64_t chunks, int64_t cols_per_chunk, uint64_t* best,
+                           hipStream_t s);
+
+// ---- certify.hip --------------------------------------------------------------
+void launch_init_u64(uint64_t* p, int64_t count, uint64_t v, hipStream_t s);
+void launch_init_i32(int32_t* p, int64_t count, int32_t v, hipStream_t s);
+void launch_unpack_best(const uint64_t* best, int64_t N, int n, float* nn_approx,
+                        int32_t* nn_witness, int32_t* row_state, hipStream_t s);
+void launch_seed_argmax(const uint64_t* best, const int32_t* row_state, int64_t N,
+                        uint64_t* seed_key, hipStream_t s);
+void launch_seed_row(const uint64_t* seed_key, int64_t* rows_out, hipStream_t s);
+void launch_rows_nn_fp64(const float* Tp, int n, int64_t N, const int64_t* rows, int64_t count,
+                         double* part_d, int64_t* part_j, double* out_d, int64_t* out_j,
+                         hipStream_t s);
+void launch_exact_from_rows(const int64_t* rows, const double* d, const int64_t* j,
+                            int64_t count, Exact* ex, hipStream_t s);
+void launch_verify(const float* Tp, int n, int64_t N, const int32_t* nn_witness,
+                   const float* nn_approx, const Exact* ex, int64_t* uncertain,
+                   uint32_t* uncertain_count, uint32_t* max_rel_err_bits, hipStream_t s);
+void launch_merge_exact(const int64_t* rows, const double* d, const int64_t* j, int64_t count,
+                        Exact* ex, int32_t* nn_witness, hipStream_t s);
+
+}  // namespace dd

@@ -1,0 +1,334 @@
+// prep.hip -- preparation stage of PhiDD (Algorithm 2, first six steps) for gfx950.
+//
+//   stats     eq. (2): mean and standard deviation of the series, FP64, two-pass,
+//             fixed grid and fixed reduction tree (bit-reproducible run to run).
+//   row stats per-row mean and centred squared norm (FP64), used by the split-BF16
+//             scan and exposed for verification.
+//   sax       eqs. (3), (4), (9): PAA of each row on the z-normalised series, SAX
+//             symbols by the N(0,1) breakpoints, word id = lexicographic rank.
+//             One thread per row; the 256-bin word histogram (eq. 8) is built in
+//             LDS and merged with global atomics.
+//   cand      eq. (7): rows whose word has the minimum frequency, ascending, by a
+//             stable wave-ballot compaction.
+//   csr       eq. (10): Index_Word as CSR (offsets + members), a stable counting
+//             sort: per-segment word counts -> scan over segments -> scatter with
+//             in-wave ranks from ballots.
+#include "internal.hpp"
+
+namespace dd {
+namespace {
+
+constexpr int kSegRows = 4096;   // rows per segment of the stable compaction / counting sort
+
+__device__ inline double block_sum_256(double v, double* sh) {
+  // fixed-shape tree: wave butterfly, then the four wave sums in order
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  if (l == 0) sh[w] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) r = ((sh[0] + sh[1]) + (sh[2] + sh[3]));
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(256) void k_sum(const float* __restrict__ T, int64_t m,
+                                             double* __restrict__ partials, int* __restrict__ bad) {
+  __shared__ double sh[4];
+  double s = 0.0;
+  int nonfinite = 0;
+  for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < m; i += (int64_t)gridDim.x * 256) {
+    const float v = T[i];
+    nonfinite |= !__builtin_isfinite(v);
+    s += (double)v;
+  }
+  if (__any(nonfinite) && (threadIdx.x & 63) == 0) atomicOr(bad, 1);
+  const double r = block_sum_256(s, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = r;
+}
+
+__global__ __launch_bounds__(256) void k_sqdev(const float* __restrict__ T, int64_t m,
+                                               const double* __restrict__ stats,
+                                               double* __restrict__ partials) {
+  __shared__ double sh[4];
+  const double mu = stats[0];
+  double s = 0.0;
+  for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < m; i += (int64_t)gridDim.x * 256) {
+    const double d = (double)T[i] - mu;
+    s += d * d;
+  }
+  const double r = block_sum_256(s, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = r;
+}
+
+// stats[0] = mu, stats[1] = sigma, stats[2] = sum of squared deviations
+__global__ __launch_bounds__(256) void k_finish(const double* __restrict__ partials, int nb,
+                                                int64_t m, double* __restrict__ stats, int which) {
+  __shared__ double sh[4];
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nb; b += 256) s += partials[b];
+  const double r = block_sum_256(s, sh);
+  if (threadIdx.x == 0) {
+    if (which == 0) {
+      stats[0] = r / (double)m;
+    } else {
+      stats[2] = r;
+      stats[1] = sqrt(r / (double)m);
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_row_stats(const float* __restrict__ T, int64_t N, int n,
+                                                   double* __restrict__ mean,
+                                                   double* __restrict__ cnorm) {
+  const int64_t i = blockIdx.x * 256ll + threadIdx.x;
+  if (i >= N) return;
+  const float* x = T + i;
+  double s = 0.0;
+  for (int k = 0; k < n; ++k) s += (double)x[k];
+  const double mu = s / (double)n;
+  double q = 0.0;
+  for (int k = 0; k < n; ++k) {
+    const double d = (double)x[k] - mu;
+    q += d * d;
+  }
+  mean[i] = mu;
+  cnorm[i] = q;
+}
+
+struct Breakpoints {
+  double b[8];
+};
+
+__global__ __launch_bounds__(256) void k_sax(const float* __restrict__ T, int64_t N, int n, int w,
+                                             int alpha, Breakpoints bp,
+                                             const double* __restrict__ stats,
+                                             int32_t* __restrict__ words,
+                                             int32_t* __restrict__ hist) {
+  __shared__ int32_t lh[kMaxWords];
+  for (int b = threadIdx.x; b < kMaxWords; b += 256) lh[b] = 0;
+  __syncthreads();
+  const int64_t i = blockIdx.x * 256ll + threadIdx.x;
+  if (i < N) {
+    const double mu = stats[0], sigma = stats[1];
+    const float* x = T + i;
+    int32_t code = 0;
+    for (int s = 0; s < w; ++s) {
+      const int a = (int)(((int64_t)s * n) / w), e = (int)(((int64_t)(s + 1) * n) / w);
+      double acc = 0.0;
+      for (int k = a; k < e; ++k) acc += (double)x[k];
+      // mean of the segment on the normalised series: (mean(raw) - mu) / sigma
+      const double paa = (acc / (double)(e - a) - mu) / sigma;
+      int sym = 0;
+      while (sym < alpha - 1 && paa >= bp.b[sym]) ++sym;   // beta_{k} <= paa < beta_{k+1}
+      code = code * alpha + sym;
+    }
+    words[i] = code;
+    atomicAdd(&lh[code], 1);
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < kMaxWords; b += 256)
+    if (lh[b]) atomicAdd(&hist[b], lh[b]);
+}
+
+// min over the occurring words of their frequency (eq. 7's min_j Freq(j))
+__global__ __launch_bounds__(256) void k_min_freq(const int32_t* __restrict__ hist, int dict,
+                                                  int32_t* __restrict__ out) {
+  __shared__ int32_t sh[4];
+  int32_t v = 0x7fffffff;
+  for (int b = threadIdx.x; b < dict; b += 256)
+    if (hist[b] > 0) v = min(v, hist[b]);
+  for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) *out = min(min(sh[0], sh[1]), min(sh[2], sh[3]));
+}
+
+__device__ inline uint64_t lanemask_lt() {
+  const int l = threadIdx.x & 63;
+  return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+// Stable compaction of {i : hist[words[i]] == minfreq}: segment counts.
+__global__ __launch_bounds__(64) void k_cand_count(const int32_t* __restrict__ words,
+                                                   const int32_t* __restrict__ hist,
+                                                   const int32_t* __restrict__ minfreq, int64_t N,
+                                                   int32_t* __restrict__ seg_counts) {
+  const int64_t b = (int64_t)blockIdx.x * kSegRows;
+  const int64_t e = min<int64_t>(N, b + kSegRows);
+  const int32_t mf = *minfreq;
+  int32_t c = 0;
+  for (int64_t i = b + threadIdx.x; i < e; i += 64) c += (hist[words[i]] == mf);
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+  if (threadIdx.x == 0) seg_counts[blockIdx.x] = c;
+}
+
+// exclusive scan of segment counts (single block); total to *total
+__global__ __launch_bounds__(256) void k_scan_segments(int32_t* __restrict__ seg, int64_t nseg,
+                                                       int32_t* __restrict__ total) {
+  __shared__ int32_t carry;
+  __shared__ int32_t wsum[4];
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int64_t base = 0; base < nseg; base += 256) {
+    const int64_t k = base + threadIdx.x;
+    const int32_t v = k < nseg ? seg[k] : 0;
+    // inclusive scan within the wave
+    int32_t x = v;
+    for (int off = 1; off < 64; off <<= 1) {
+      const int32_t y = __shfl_up(x, off, 64);
+      if ((threadIdx.x & 63) >= off) x += y;
+    }
+    if ((threadIdx.x & 63) == 63) wsum[threadIdx.x >> 6] = x;
+    __syncthreads();
+    int32_t pre = carry;
+    for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) pre += wsum[w];
+    if (k < nseg) seg[k] = pre + x - v;
+    __syncthreads();
+    if (threadIdx.x == 255) carry = pre + x;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *total = carry;
+}
+
+__global__ __launch_bounds__(64) void k_cand_scatter(const int32_t* __restrict__ words,
+                                                     const int32_t* __restrict__ hist,
+                                                     const int32_t* __restrict__ minfreq, int64_t N,
+                                                     const int32_t* __restrict__ seg_base,
+                                                     int32_t* __restrict__ cand) {
+  const int64_t b = (int64_t)blockIdx.x * kSegRows;
+  const int64_t e = min<int64_t>(N, b + kSegRows);
+  const int32_t mf = *minfreq;
+  int32_t run = seg_base[blockIdx.x];
+  for (int64_t i0 = b; i0 < e; i0 += 64) {
+    const int64_t i = i0 + threadIdx.x;
+    const bool f = i < e && hist[words[i]] == mf;
+    const uint64_t mask = __ballot(f);
+    if (f) cand[run + __popcll(mask & lanemask_lt())] = (int32_t)i;
+    run += __popcll(mask);
+  }
+}
+
+// CSR counting sort: per-segment word counts
+__global__ __launch_bounds__(64) void k_csr_count(const int32_t* __restrict__ words, int64_t N,
+                                                  int dict, int32_t* __restrict__ seg_counts) {
+  __shared__ int32_t lh[kMaxWords];
+  for (int b = threadIdx.x; b < kMaxWords; b += 64) lh[b] = 0;
+  __syncthreads();
+  const int64_t b0 = (int64_t)blockIdx.x * kSegRows;
+  const int64_t e = min<int64_t>(N, b0 + kSegRows);
+  for (int64_t i = b0 + threadIdx.x; i < e; i += 64) atomicAdd(&lh[words[i]], 1);
+  __syncthreads();
+  for (int b = threadIdx.x; b < dict; b += 64) seg_counts[(int64_t)blockIdx.x * dict + b] = lh[b];
+}
+
+// offsets = exclusive scan of hist; seg_counts[s][w] -> base of segment s for word w
+__global__ __launch_bounds__(256) void k_csr_scan(const int32_t* __restrict__ hist, int dict,
+                                                  int64_t nseg, int32_t* __restrict__ seg_counts,
+                                                  int32_t* __restrict__ offsets) {
+  __shared__ int32_t off[kMaxWords + 1];
+  if (threadIdx.x == 0) {
+    int32_t run = 0;
+    for (int w = 0; w < dict; ++w) {
+      off[w] = run;
+      run += hist[w];
+    }
+    off[dict] = run;
+  }
+  __syncthreads();
+  for (int w = threadIdx.x; w <= dict; w += 256) offsets[w] = off[w];
+  for (int w = threadIdx.x; w < dict; w += 256) {
+    int32_t run = off[w];
+    for (int64_t s = 0; s < nseg; ++s) {
+      const int32_t c = seg_counts[s * dict + w];
+      seg_counts[s * dict + w] = run;
+      run += c;
+    }
+  }
+}
+
+__global__ __launch_bounds__(64) void k_csr_scatter(const int32_t* __restrict__ words, int64_t N,
+                                                    int dict, const int32_t* __restrict__ seg_base,
+                                                    int32_t* __restrict__ members) {
+  __shared__ int32_t run[kMaxWords];
+  for (int b = threadIdx.x; b < dict; b += 64) run[b] = seg_base[(int64_t)blockIdx.x * dict + b];
+  __syncthreads();
+  const int64_t b0 = (int64_t)blockIdx.x * kSegRows;
+  const int64_t e = min<int64_t>(N, b0 + kSegRows);
+  const uint64_t lt = lanemask_lt();
+  for (int64_t i0 = b0; i0 < e; i0 += 64) {
+    const int64_t i = i0 + threadIdx.x;
+    const bool valid = i < e;
+    const int32_t wd = valid ? words[i] : -1;
+    uint64_t todo = __ballot(valid);
+    while (todo) {
+      const int leader = __builtin_ctzll(todo);
+      const int32_t w0 = __shfl(wd, leader, 64);
+      const bool mine = valid && wd == w0;
+      const uint64_t same = __ballot(mine);
+      const int32_t base = run[w0];
+      if (mine) members[base + __popcll(same & lt)] = (int32_t)i;
+      __builtin_amdgcn_wave_barrier();
+      if ((int)threadIdx.x == leader) run[w0] = base + __popcll(same);
+      __builtin_amdgcn_wave_barrier();
+      todo &= ~same;
+    }
+  }
+}
+
+}  // namespace
+
+int64_t csr_waves(int64_t N) { return (N + kSegRows - 1) / kSegRows; }
+int64_t compact_waves(int64_t N) { return (N + kSegRows - 1) / kSegRows; }
+
+void launch_stats(const float* Tp, int64_t m, double* partials, double* stats, int* bad,
+                  hipStream_t s) {
+  hipLaunchKernelGGL(k_sum, dim3(kStatBlocks), dim3(256), 0, s, Tp, m, partials, bad);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, partials, kStatBlocks, m, stats, 0);
+  hipLaunchKernelGGL(k_sqdev, dim3(kStatBlocks), dim3(256), 0, s, Tp, m, stats, partials);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, partials, kStatBlocks, m, stats, 1);
+}
+
+void launch_row_stats(const float* Tp, int64_t N, int n, double* row_mean, double* row_cnorm,
+                      hipStream_t s) {
+  const int64_t blocks = (N + 255) / 256;
+  hipLaunchKernelGGL(k_row_stats, dim3((unsigned)blocks), dim3(256), 0, s, Tp, N, n, row_mean,
+                     row_cnorm);
+}
+
+// Breakpoints of eq. (4): beta_k = Phi^{-1}(k / alpha), computed on the host by
+// Newton's method on Phi(x) = erfc(-x / sqrt 2) / 2 from a bracketing start.
+void sax_breakpoints(int alpha, double* out);
+
+void launch_sax(const float* Tp, int64_t N, int n, int w, int alpha, const double* stats,
+                int32_t* words, int32_t* hist, hipStream_t s) {
+  Breakpoints bp{};
+  sax_breakpoints(alpha, bp.b);
+  const int64_t blocks = (N + 255) / 256;
+  hipLaunchKernelGGL(k_sax, dim3((unsigned)blocks), dim3(256), 0, s, Tp, N, n, w, alpha, bp,
+                     stats, words, hist);
+}
+
+void launch_cand(const int32_t* words, const int32_t* hist, int64_t N, int dict,
+                 int32_t* minfreq_scratch, int32_t* seg_counts, int32_t* cand,
+                 int32_t* cand_count, hipStream_t s) {
+  const int64_t nseg = compact_waves(N);
+  hipLaunchKernelGGL(k_min_freq, dim3(1), dim3(256), 0, s, hist, dict, minfreq_scratch);
+  hipLaunchKernelGGL(k_cand_count, dim3((unsigned)nseg), dim3(64), 0, s, words, hist,
+                     minfreq_scratch, N, seg_counts);
+  hipLaunchKernelGGL(k_scan_segments, dim3(1), dim3(256), 0, s, seg_counts, nseg, cand_count);
+  hipLaunchKernelGGL(k_cand_scatter, dim3((unsigned)nseg), dim3(64), 0, s, words, hist,
+                     minfreq_scratch, N, seg_counts, cand);
+}
+
+void launch_csr(const int32_t* words, const int32_t* hist, int64_t N, int dict,
+                int32_t* seg_counts, int32_t* offsets, int32_t* members, hipStream_t s) {
+  const int64_t nseg = csr_waves(N);
+  hipLaunchKernelGGL(k_csr_count, dim3((unsigned)nseg), dim3(64), 0, s, words, N, dict,
+                     seg_counts);
+  hipLaunchKernelGGL(k_csr_scan, dim3(1), dim3(256), 0, s, hist, dict, nseg, seg_counts, offsets);
+  hipLaunchKernelGGL(k_csr_scatter, dim3((unsigned)nseg), dim3(64), 0, s, words, N, dict,
+                     seg_counts, members);
+}
+
+}  // namespace dd

@@ -1,0 +1,167 @@
+// scan_fp32.hip -- FP32 direct-form pair-distance scan for gfx950.
+//
+// Computes ED^2(i, j) = sum_k (t_{i+k} - t_{j+k})^2 (eq. (1) squared, the form the
+// paper's PotentialDiscord/RefineDiscord loops evaluate) for blocks of rows and
+// columns, keeps each row's minimum over non-self columns (|i - j| >= n) and the
+// column attaining it.
+//
+// Layout of the work: one wavefront owns a group of 8 consecutive rows
+// (i0..i0+7); each of its 64 lanes owns 8 consecutive columns (j0..j0+7) per
+// step, so a wave covers 8 x 512 pairs per step.  The subsequences are read
+// straight from the series (Hankel structure: row i is t[i..i+n-1]), so no
+// subsequence matrix is streamed; the row window is wave-uniform.
+//
+// Arithmetic reuse: the difference t_{i+k} - t_{j+k} depends only on the
+// diagonal g = j - i and the position p = i + k, so inside an 8 x 8 block the
+// 64 pairs at position p need only the 15 differences D_g(p), g in [-7, 7].
+// Each pair's sum is still the plain sequential sum over k = 0..n-1 of its own
+// squared differences (one fused multiply-add per term), so the arithmetic per
+// pair is exactly the direct form; only the subtractions are shared.  Cost:
+// 64 FMA + 15 SUB per 64 (pair, k) terms, about 1.23 VALU ops per term.
+#include "internal.hpp"
+
+namespace dd {
+namespace {
+
+constexpr int TM = kRowGroup;   // 8 rows per wave
+constexpr int TN = kColBlock;   // 8 columns per lane
+static_assert(TM == 8 && TN == 8, "the micro-tile below is written for 8 x 8");
+
+// One position p: all 64 pairs of the block that are active at p take
+// acc += D^2 with D = x[p] - y[p + (c - r)].  yw[g + 7] = y[p + g].
+// PRED: apply the activity test 0 <= p - r < n (first and last 7 positions).
+template <bool PRED>
+__device__ __forceinline__ void step(float (&acc)[TM][TN], float xp, const float* yw, int p,
+                                     int n) {
+  float D[TM + TN - 1];
+#pragma unroll
+  for (int g = 0; g < TM + TN - 1; ++g) D[g] = xp - yw[g];
+#pragma unroll
+  for (int r = 0; r < TM; ++r) {
+    bool on = true;
+    if (PRED) {
+      const int k = p - r;
+      on = (k >= 0) && (k < n);
+    }
+#pragma unroll
+    for (int c = 0; c < TN; ++c) {
+      float d = D[c - r + TM - 1];
+      if (PRED) d = on ? d : 0.0f;
+      acc[r][c] = __builtin_fmaf(d, d, acc[r][c]);
+    }
+  }
+}
+
+// y loads for positions [p0, p0+8): y[p0-8 .. p0+15] (24 floats, 16-byte aligned
+// when y and p0 are multiples of 4 floats).
+__device__ __forceinline__ void load_y(const float* __restrict__ y, int p0, float (&yb)[24]) {
+  const float4* v = reinterpret_cast<const float4*>(y + p0 - 8);
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    const float4 f = v[q];
+    yb[4 * q + 0] = f.x;
+    yb[4 * q + 1] = f.y;
+    yb[4 * q + 2] = f.z;
+    yb[4 * q + 3] = f.w;
+  }
+}
+
+__device__ __forceinline__ void load_x(const float* __restrict__ x, int p0, float (&xb)[8]) {
+  const float4* v = reinterpret_cast<const float4*>(x + p0);
+  const float4 a = v[0], b = v[1];
+  xb[0] = a.x; xb[1] = a.y; xb[2] = a.z; xb[3] = a.w;
+  xb[4] = b.x; xb[5] = b.y; xb[6] = b.z; xb[7] = b.w;
+}
+
+template <bool PRED>
+__device__ __forceinline__ void steps8(float (&acc)[TM][TN], const float* __restrict__ x,
+                                       const float* __restrict__ y, int p0, int n) {
+  float xb[8], yb[24];
+  load_x(x, p0, xb);
+  load_y(y, p0, yb);
+#pragma unroll
+  for (int u = 0; u < 8; ++u) step<PRED>(acc, xb[u], &yb[u + 1], p0 + u, n);
+}
+
+// acc[r][c] = sum_{k<n} (x[r+k] - y[c+k])^2 for the 8 x 8 block at x, y.
+__device__ __forceinline__ void block8x8(const float* __restrict__ x, const float* __restrict__ y,
+                                         int n, float (&acc)[TM][TN]) {
+#pragma unroll
+  for (int r = 0; r < TM; ++r)
+#pragma unroll
+    for (int c = 0; c < TN; ++c) acc[r][c] = 0.0f;
+  steps8<true>(acc, x, y, 0, n);            // positions 0..7: rows r > p not started
+  int p0 = 8;
+  for (; p0 + 8 <= n; p0 += 8) steps8<false>(acc, x, y, p0, n);   // every row active
+  for (; p0 < n + TM - 1; p0 += 8) steps8<true>(acc, x, y, p0, n);  // rows finishing
+}
+
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint64_t o = __shfl_xor(v, off, 64);
+    v = o < v ? o : v;
+  }
+  return v;
+}
+
+// Full scan (no abandon): work item w = (row group, column chunk).
+__global__ __launch_bounds__(256) void k_scan_fp32_full(const float* __restrict__ Tp, int n,
+                                                        int64_t N, int64_t row_groups,
+                                                        int64_t chunks, int64_t cols_per_chunk,
+                                                        uint64_t* __restrict__ best) {
+  const int lane = threadIdx.x & 63;
+  const int64_t item = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (item >= row_groups * chunks) return;
+  const int64_t rg = item / chunks;
+  const int64_t ch = item - rg * chunks;
+  const int64_t i0 = __builtin_amdgcn_readfirstlane((int)(rg * TM));
+  const int64_t cb = ch * cols_per_chunk;
+  const int64_t ce = min<int64_t>(N, cb + cols_per_chunk);
+  const float* x = Tp + i0;
+
+  float bd[TM];
+  int32_t bj[TM];
+#pragma unroll
+  for (int r = 0; r < TM; ++r) {
+    bd[r] = __builtin_inff();
+    bj[r] = -1;
+  }
+  for (int64_t jb = cb; jb < ce; jb += 64 * TN) {
+    const int64_t j0 = jb + lane * TN;
+    float acc[TM][TN];
+    block8x8(x, Tp + j0, n, acc);
+#pragma unroll
+    for (int r = 0; r < TM; ++r) {
+      const int64_t i = i0 + r;
+#pragma unroll
+      for (int c = 0; c < TN; ++c) {
+        const int64_t j = j0 + c;
+        const int64_t dij = i > j ? i - j : j - i;
+        const bool ok = (j < ce) && (dij >= n);
+        if (ok && acc[r][c] < bd[r]) {
+          bd[r] = acc[r][c];
+          bj[r] = (int32_t)j;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < TM; ++r) {
+    const uint64_t key = bj[r] < 0 ? kEmptyMin : pack_min(bd[r], (uint32_t)bj[r]);
+    const uint64_t w = wave_min_u64(key);
+    if (lane == 0 && i0 + r < N && w != kEmptyMin) atomicMin((unsigned long long*)&best[i0 + r],
+                                                             (unsigned long long)w);
+  }
+}
+
+}  // namespace
+
+void launch_scan_fp32_full(const float* Tp, int n, int64_t N, int64_t row_groups, int64_t chunks,
+                           int64_t cols_per_chunk, uint64_t* best, hipStream_t s) {
+  const int64_t items = row_groups * chunks;
+  const int64_t blocks = (items + 3) / 4;
+  hipLaunchKernelGGL(k_scan_fp32_full, dim3((unsigned)blocks), dim3(256), 0, s, Tp, n, N,
+                     row_groups, chunks, cols_per_chunk, best);
+}
+
+}  // namespace dd
