@@ -50,7 +50,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("abandon", ctypes.c_int32),
                 ("order", ctypes.c_int32), ("topk", ctypes.c_int32),
                 ("paa_w", ctypes.c_int32), ("alphabet", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("probe_steps", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Result(ctypes.Structure):
@@ -165,11 +165,11 @@ class Plan:
     """A prepared series (discord_prepare) that can be searched repeatedly."""
 
     def __init__(self, T, n: int, precision="fp32", abandon=True, order=True, topk=16,
-                 paa_w=4, alphabet=4, stream=None, torch_workspace=False):
+                 paa_w=4, alphabet=4, probe_steps=0, stream=None, torch_workspace=False):
         lib = load()
         self.opts = default_opts(precision=precision, abandon=int(bool(abandon)),
                                  order=int(bool(order)), topk=topk, paa_w=paa_w,
-                                 alphabet=alphabet)
+                                 alphabet=alphabet, probe_steps=probe_steps)
         ptr, m, self._keep, tstream = _series_ptr(T)
         self.m, self.n = int(m), int(n)
         self.N = self.m - self.n + 1

@@ -47,7 +47,8 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 struct Layout {
   size_t T, stats, partials, bad, words, hist, minfreq, cand, cand_count, seg, csr_off, csr_mem,
       best, nn_approx, nn_wit, row_state, row_mean, row_cnorm, seed, rows, part_d, part_j, out_d,
-      out_j, exact, unc, unc_count, relerr, total;
+      out_j, exact, unc, unc_count, relerr, bsf, pairs, alive, done, survivors, n_surv, gflags,
+      cand_groups, n_cand_groups, n_aband, bgrp_cnt, bgrp_off, bgrp, total;
 };
 
 Layout make_layout(int64_t m, int32_t n, int dict) {
@@ -89,6 +90,20 @@ Layout make_layout(int64_t m, int32_t n, int dict) {
   L.unc = take(sizeof(int64_t) * N);
   L.unc_count = take(sizeof(uint32_t) * 4);
   L.relerr = take(sizeof(uint32_t) * 4);
+  const int64_t G = (N + kRowGroup - 1) / kRowGroup;
+  L.bsf = take(sizeof(uint32_t) * 4);
+  L.pairs = take(sizeof(uint64_t) * 4);
+  L.alive = take(sizeof(uint32_t) * G);
+  L.done = take(sizeof(uint32_t) * G);
+  L.survivors = take(sizeof(int32_t) * G);
+  L.n_surv = take(sizeof(uint32_t) * 4);
+  L.gflags = take(sizeof(int32_t) * G);
+  L.cand_groups = take(sizeof(int32_t) * G);
+  L.n_cand_groups = take(sizeof(int32_t) * 4);
+  L.n_aband = take(sizeof(uint32_t) * 4);
+  L.bgrp_cnt = take(sizeof(int32_t) * kMaxWords);
+  L.bgrp_off = take(sizeof(int32_t) * (kMaxWords + 1));
+  L.bgrp = take(sizeof(int32_t) * N);
   L.total = off;
   return L;
 }
@@ -330,6 +345,10 @@ int discord_prepare(const float* T, int64_t m, int32_t n, const discord_opts* op
     launch_csr(p->at<int32_t>(p->L.words), p->at<int32_t>(p->L.hist), p->N, p->dict,
                p->at<int32_t>(p->L.seg), p->at<int32_t>(p->L.csr_off),
                p->at<int32_t>(p->L.csr_mem), s);
+    // the column groups (of 8) of every word's bucket: the scan's same-word-first order
+    launch_bucket_groups(p->at<int32_t>(p->L.csr_off), p->at<int32_t>(p->L.csr_mem), p->dict, 3,
+                         p->at<int32_t>(p->L.bgrp_cnt), p->at<int32_t>(p->L.bgrp_off),
+                         p->at<int32_t>(p->L.bgrp), s);
     LAUNCH_OK(p, "prepare kernels");
     int32_t hc = 0;
     HIP_TRY(p, hipMemcpyAsync(&hc, p->at<int32_t>(p->L.cand_count), sizeof(hc), hipMemcpyDeviceToHost, s));
@@ -360,29 +379,111 @@ int discord_search(discord_plan p, discord_result* out) {
   HIP_TRY(p, hipSetDevice(p->device));
   HIP_TRY(p, hipEventRecord(ev.a, s));
 
+  const int64_t G = (N + kRowGroup - 1) / kRowGroup;
+  const bool abandon = p->opts.abandon != 0;
+  const bool order = p->opts.order != 0;
   uint64_t* best = p->at<uint64_t>(p->L.best);
+  uint64_t* pairs = p->at<uint64_t>(p->L.pairs);
+  uint32_t* bsf = p->at<uint32_t>(p->L.bsf);
+  uint32_t* alive = p->at<uint32_t>(p->L.alive);
+  uint32_t* n_surv = p->at<uint32_t>(p->L.n_surv);
+  int32_t* gflags = p->at<int32_t>(p->L.gflags);
   launch_init_u64(best, N, kEmptyMin, s);
-  // ---- approximate scan -------------------------------------------------------
+  launch_init_u64(pairs, 1, 0, s);
+  launch_init_i32(reinterpret_cast<int32_t*>(bsf), 1, 0, s);
+  // ---- approximate scan (Algorithms 3 and 4) ----------------------------------
   HIP_TRY(p, hipEventRecord(evs.a, s));
-  {
-    const int64_t row_groups = (N + kRowGroup - 1) / kRowGroup;
-    // split the columns so that a small problem still fills the GPU
-    int64_t chunks = 1;
-    while (row_groups * chunks < 8192 && chunks * 2048 < N) chunks *= 2;
-    int64_t cols = (N + chunks - 1) / chunks;
-    cols = (cols + 511) / 512 * 512;
-    chunks = (N + cols - 1) / cols;
-    launch_scan_fp32_full(p->Tp(), n, N, row_groups, chunks, cols, best, s);
-    LAUNCH_OK(p, "scan_fp32_full");
+  ScanJob J{};
+  J.Tp = p->Tp();
+  J.n = n;
+  J.N = N;
+  J.best = best;
+  J.pairs = pairs;
+  J.bsf = bsf;
+  J.alive = alive;
+  J.done = p->at<uint32_t>(p->L.done);
+  J.survivors = p->at<int32_t>(p->L.survivors);
+  J.n_survivors = n_surv;
+  // A row whose scan completed has exact NN >= (its FP32 minimum) / (1 + gamma),
+  // gamma = (n + 3) 2^-24 bounding the direct-form rounding; raising the
+  // best-so-far by that lower bound keeps it <= the discord's NN.
+  J.raise_scale = (float)(1.0 - ((n + 3) * std::ldexp(1.0, -24) * 1.01 + std::ldexp(1.0, -22)));
+  // split the columns so that the launch holds at least ~4096 wavefronts
+  auto set_chunks = [&](int64_t groups) {
+    const int64_t maxc = std::max<int64_t>(1, (N + 511) / 512);
+    int64_t c = std::min<int64_t>(maxc, std::max<int64_t>(1, (4096 + groups - 1) / std::max<int64_t>(groups, 1)));
+    int64_t cols = ((N + c - 1) / c + 511) / 512 * 512;
+    J.cols_per_chunk = cols;
+    J.chunks = (N + cols - 1) / cols;
+  };
+  if (!abandon) {
+    J.abandon = 0;
+    J.n_groups = G;
+    set_chunks(G);
+    launch_scan_fp32(J, s);
+    LAUNCH_OK(p, "scan (full)");
+  } else {
+    J.abandon = 1;
+    launch_init_alive(alive, G, N, s);
+    launch_init_i32(reinterpret_cast<int32_t*>(J.done), G, 0, s);
+    launch_init_i32(reinterpret_cast<int32_t*>(n_surv), 1, 0, s);
+    launch_init_i32(gflags, G, 0, s);
+    int32_t hcg = 0;
+    if (order && p->cand_count > 0) {
+      // Algorithm 3: the row groups holding Cand rows, each scanned over all
+      // columns (its word's bucket first), split into chunks to fill the GPU
+      int32_t* cgroups = p->at<int32_t>(p->L.cand_groups);
+      int32_t* n_cg = p->at<int32_t>(p->L.n_cand_groups);
+      launch_cand_group_flags(p->at<int32_t>(p->L.cand), p->at<int32_t>(p->L.cand_count),
+                              p->cand_count, 3, gflags, s);
+      launch_compact_flags(gflags, G, p->at<int32_t>(p->L.seg), cgroups, n_cg, s);
+      HIP_TRY(p, hipMemcpyAsync(&hcg, n_cg, sizeof(hcg), hipMemcpyDeviceToHost, s));
+      HIP_TRY(p, hipStreamSynchronize(s));
+      J.groups = cgroups;
+      J.n_groups = hcg;
+      set_chunks(hcg);
+      J.words = p->at<int32_t>(p->L.words);
+      J.bgrp_off = p->at<int32_t>(p->L.bgrp_off);
+      J.bgrp = p->at<int32_t>(p->L.bgrp);
+      J.max_steps = 0;
+      launch_scan_fp32(J, s);
+      LAUNCH_OK(p, "scan (Cand)");
+    }
+    // Algorithm 4, first pass: every other row group walks its word's bucket,
+    // then matrix order, for a bounded number of steps
+    J.groups = nullptr;
+    J.n_groups = G;
+    J.chunks = 1;
+    J.cols_per_chunk = (N + 511) / 512 * 512;
+    J.max_steps = p->opts.probe_steps > 0 ? p->opts.probe_steps : 16;
+    J.words = order ? p->at<int32_t>(p->L.words) : nullptr;
+    J.bgrp_off = p->at<int32_t>(p->L.bgrp_off);
+    J.bgrp = p->at<int32_t>(p->L.bgrp);
+    J.skip = (order && hcg > 0) ? gflags : nullptr;
+    launch_scan_fp32(J, s);
+    LAUNCH_OK(p, "scan (probe)");
+    uint32_t hs = 0;
+    HIP_TRY(p, hipMemcpyAsync(&hs, n_surv, sizeof(hs), hipMemcpyDeviceToHost, s));
+    HIP_TRY(p, hipStreamSynchronize(s));
+    // second pass: the groups with rows still live, all columns, chunked
+    J.groups = J.survivors;
+    J.n_groups = hs;
+    set_chunks(std::max<int64_t>(hs, 1));
+    J.words = nullptr;
+    J.skip = nullptr;
+    J.max_steps = 0;
+    launch_scan_fp32(J, s);
+    LAUNCH_OK(p, "scan (survivors)");
   }
   HIP_TRY(p, hipEventRecord(evs.b, s));
-  r.pairs_evaluated = (N - n > 0) ? (uint64_t)(N - n) * (uint64_t)(N - n + 1) : 0;
 
   // ---- certification in FP64 ---------------------------------------------------
   float* nn_approx = p->at<float>(p->L.nn_approx);
   int32_t* nn_wit = p->at<int32_t>(p->L.nn_wit);
   int32_t* row_state = p->at<int32_t>(p->L.row_state);
-  launch_unpack_best(best, N, n, nn_approx, nn_wit, row_state, s);
+  uint32_t* n_aband = p->at<uint32_t>(p->L.n_aband);
+  launch_init_i32(reinterpret_cast<int32_t*>(n_aband), 1, 0, s);
+  launch_unpack_best(best, N, abandon ? alive : nullptr, nn_approx, nn_wit, row_state, n_aband, s);
   uint64_t* seed = p->at<uint64_t>(p->L.seed);
   launch_init_u64(seed, 1, 0, s);
   launch_seed_argmax(best, row_state, N, seed, s);
@@ -399,9 +500,12 @@ int discord_search(discord_plan p, discord_result* out) {
   int64_t* unc = p->at<int64_t>(p->L.unc);
   launch_verify(p->Tp(), n, N, nn_wit, nn_approx, ex, unc, unc_count, relerr, s);
   LAUNCH_OK(p, "verify");
-  uint32_t hunc = 0, hrel = 0;
+  uint32_t hunc = 0, hrel = 0, hab = 0;
+  uint64_t hpairs = 0;
   HIP_TRY(p, hipMemcpyAsync(&hunc, unc_count, sizeof(hunc), hipMemcpyDeviceToHost, s));
   HIP_TRY(p, hipMemcpyAsync(&hrel, relerr, sizeof(hrel), hipMemcpyDeviceToHost, s));
+  HIP_TRY(p, hipMemcpyAsync(&hab, n_aband, sizeof(hab), hipMemcpyDeviceToHost, s));
+  HIP_TRY(p, hipMemcpyAsync(&hpairs, pairs, sizeof(hpairs), hipMemcpyDeviceToHost, s));
   HIP_TRY(p, hipStreamSynchronize(s));
   for (int64_t b = 0; b < (int64_t)hunc; b += kFp64BatchRows) {
     const int64_t c = std::min<int64_t>(kFp64BatchRows, (int64_t)hunc - b);
@@ -428,7 +532,8 @@ int discord_search(discord_plan p, discord_result* out) {
   r.certified = 1;
   r.precision = p->opts.precision;
   r.rows_rescored = 1 + hunc;
-  r.rows_abandoned = 0;
+  r.rows_abandoned = hab;
+  r.pairs_evaluated = hpairs;
   r.cand_rows = (uint64_t)p->cand_count;
   r.ms_prepare = p->ms_prepare;
   r.ms_search = ev.ms();

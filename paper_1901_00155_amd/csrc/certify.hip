@@ -48,22 +48,39 @@ __global__ void k_fill_i32(int32_t* p, int64_t count, int32_t v) {
     p[k] = v;
 }
 
+// Rows of the scan: minimum (or abandon distance) and its column; a row is
+// abandoned when its bit in the group's alive mask was cleared.
 __global__ __launch_bounds__(256) void k_unpack_best(const uint64_t* __restrict__ best, int64_t N,
+                                                     const uint32_t* __restrict__ alive,
                                                      float* __restrict__ nn_approx,
                                                      int32_t* __restrict__ nn_witness,
-                                                     int32_t* __restrict__ row_state) {
+                                                     int32_t* __restrict__ row_state,
+                                                     uint32_t* __restrict__ n_abandoned) {
   const int64_t i = blockIdx.x * 256ll + threadIdx.x;
-  if (i >= N) return;
-  const uint64_t k = best[i];
-  if (k == kEmptyMin) {
-    nn_approx[i] = __builtin_inff();
-    nn_witness[i] = -1;
-    row_state[i] = kRowUnscanned;
-  } else {
-    nn_approx[i] = key_dist(k);
-    nn_witness[i] = (int32_t)(k & 0xFFFFFFFFu);
-    row_state[i] = kRowFull;
+  bool ab = false;
+  if (i < N) {
+    const uint64_t k = best[i];
+    if (k == kEmptyMin) {
+      nn_approx[i] = __builtin_inff();
+      nn_witness[i] = -1;
+      row_state[i] = kRowUnscanned;
+    } else {
+      ab = alive && !((alive[i / kRowGroup] >> (i % kRowGroup)) & 1u);
+      nn_approx[i] = key_dist(k);
+      nn_witness[i] = (int32_t)(k & 0xFFFFFFFFu);
+      row_state[i] = ab ? kRowAbandoned : kRowFull;
+    }
   }
+  const uint64_t m = __ballot(ab);
+  if ((threadIdx.x & 63) == 0 && m) atomicAdd(n_abandoned, (uint32_t)__popcll(m));
+}
+
+__global__ __launch_bounds__(256) void k_init_alive(uint32_t* __restrict__ alive, int64_t G,
+                                                    int64_t N) {
+  const int64_t g = blockIdx.x * 256ll + threadIdx.x;
+  if (g >= G) return;
+  const int64_t rows = min<int64_t>(kRowGroup, N - g * kRowGroup);
+  alive[g] = rows >= 32 ? 0xFFFFFFFFu : ((1u << rows) - 1u);
 }
 
 __device__ inline uint64_t wave_max_u64(uint64_t v) {
@@ -243,11 +260,16 @@ void launch_init_i32(int32_t* p, int64_t count, int32_t v, hipStream_t s) {
   if (count > 0) hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)blocks), dim3(256), 0, s, p, count, v);
 }
 
-void launch_unpack_best(const uint64_t* best, int64_t N, int n, float* nn_approx,
-                        int32_t* nn_witness, int32_t* row_state, hipStream_t s) {
-  (void)n;
+void launch_unpack_best(const uint64_t* best, int64_t N, const uint32_t* alive, float* nn_approx,
+                        int32_t* nn_witness, int32_t* row_state, uint32_t* n_abandoned,
+                        hipStream_t s) {
   hipLaunchKernelGGL(k_unpack_best, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, best, N,
-                     nn_approx, nn_witness, row_state);
+                     alive, nn_approx, nn_witness, row_state, n_abandoned);
+}
+
+void launch_init_alive(uint32_t* alive, int64_t G, int64_t N, hipStream_t s) {
+  if (G > 0)
+    hipLaunchKernelGGL(k_init_alive, dim3((unsigned)((G + 255) / 256)), dim3(256), 0, s, alive, G, N);
 }
 
 void launch_seed_argmax(const uint64_t* best, const int32_t* row_state, int64_t N,

@@ -64,23 +64,51 @@ void launch_csr(const int32_t* words, const int32_t* hist, int64_t N, int dict,
                 int32_t* wave_counts, int32_t* offsets, int32_t* members, hipStream_t s);
 int64_t csr_waves(int64_t N);
 int64_t compact_waves(int64_t N);
+void launch_compact_flags(const int32_t* flags, int64_t count, int32_t* seg_counts, int32_t* out,
+                          int32_t* out_count, hipStream_t s);
+void launch_cand_group_flags(const int32_t* cand, const int32_t* cand_count, int64_t max_cand,
+                             int shift, int32_t* flags, hipStream_t s);
+void launch_bucket_groups(const int32_t* offsets, const int32_t* members, int dict, int shift,
+                          int32_t* counts, int32_t* goff, int32_t* groups, hipStream_t s);
 
 // ---- scan_fp32.hip ------------------------------------------------------------
-struct Fp32ScanItem {   // one wave: a row group against a column range
-  int32_t row_group;
-  int32_t col_begin;    // first column (multiple of kColBlock)
-  int32_t col_end;      // one past the last column
-  int32_t pad;
+// One launch of the pair scan: n_groups row groups (from `groups`, or 0..n_groups-1)
+// times `chunks` column chunks of cols_per_chunk columns in matrix order; one
+// wavefront per (group, chunk).
+struct ScanJob {
+  const float* Tp;            // padded series (t_0 at Tp[0])
+  int32_t n;
+  int64_t N;
+  const int32_t* groups;      // row-group list or nullptr
+  int64_t n_groups;
+  int64_t chunks;
+  int64_t cols_per_chunk;     // multiple of 512
+  int32_t max_steps;          // step budget per item (<= 0: none)
+  // visiting order: the group's word bucket first (chunk 0 only), then matrix order
+  const int32_t* words;       // word id per row, or nullptr for matrix order only
+  const int32_t* bgrp_off;    // per word: offsets into bgrp
+  const int32_t* bgrp;        // bucket column groups (column / 8), ascending per word
+  const int32_t* skip;        // per row group: 1 = already searched, or nullptr
+  // early abandon against the best-so-far
+  int32_t abandon;
+  uint32_t* bsf;              // float bits of the best-so-far squared distance
+  float raise_scale;          // completed rows raise bsf to (their minimum) * raise_scale
+  uint32_t* alive;            // per row group: bit r set while row r is searched
+  uint32_t* done;             // per row group: chunks finished
+  int32_t* survivors;         // groups left with live rows when the budget ran out
+  uint32_t* n_survivors;
+  uint64_t* best;             // per row: packed (approximate distance, column) minimum
+  uint64_t* pairs;            // pair distances evaluated (non-self, in range)
 };
-void launch_scan_fp32_full(const float* Tp, int n, int64_t N, int64_t row_groups,
-                           int64_t chunks, int64_t cols_per_chunk, uint64_t* best,
-                           hipStream_t s);
+void launch_scan_fp32(const ScanJob& J, hipStream_t s);
 
 // ---- certify.hip --------------------------------------------------------------
 void launch_init_u64(uint64_t* p, int64_t count, uint64_t v, hipStream_t s);
 void launch_init_i32(int32_t* p, int64_t count, int32_t v, hipStream_t s);
-void launch_unpack_best(const uint64_t* best, int64_t N, int n, float* nn_approx,
-                        int32_t* nn_witness, int32_t* row_state, hipStream_t s);
+void launch_unpack_best(const uint64_t* best, int64_t N, const uint32_t* alive, float* nn_approx,
+                        int32_t* nn_witness, int32_t* row_state, uint32_t* n_abandoned,
+                        hipStream_t s);
+void launch_init_alive(uint32_t* alive, int64_t G, int64_t N, hipStream_t s);
 void launch_seed_argmax(const uint64_t* best, const int32_t* row_state, int64_t N,
                         uint64_t* seed_key, hipStream_t s);
 void launch_seed_row(const uint64_t* seed_key, int64_t* rows_out, hipStream_t s);

@@ -209,6 +209,96 @@ __global__ __launch_bounds__(64) void k_cand_scatter(const int32_t* __restrict__
   }
 }
 
+// Generic stable compaction of the indices k with flags[k] != 0 (k < count).
+__global__ __launch_bounds__(64) void k_flag_count(const int32_t* __restrict__ flags, int64_t count,
+                                                   int32_t* __restrict__ seg_counts) {
+  const int64_t b = (int64_t)blockIdx.x * kSegRows;
+  const int64_t e = min<int64_t>(count, b + kSegRows);
+  int32_t c = 0;
+  for (int64_t i = b + threadIdx.x; i < e; i += 64) c += (flags[i] != 0);
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+  if (threadIdx.x == 0) seg_counts[blockIdx.x] = c;
+}
+
+__global__ __launch_bounds__(64) void k_flag_scatter(const int32_t* __restrict__ flags,
+                                                     int64_t count,
+                                                     const int32_t* __restrict__ seg_base,
+                                                     int32_t* __restrict__ out) {
+  const int64_t b = (int64_t)blockIdx.x * kSegRows;
+  const int64_t e = min<int64_t>(count, b + kSegRows);
+  int32_t run = seg_base[blockIdx.x];
+  for (int64_t i0 = b; i0 < e; i0 += 64) {
+    const int64_t i = i0 + threadIdx.x;
+    const bool f = i < e && flags[i] != 0;
+    const uint64_t mask = __ballot(f);
+    if (f) out[run + __popcll(mask & lanemask_lt())] = (int32_t)i;
+    run += __popcll(mask);
+  }
+}
+
+// flags[g] = 1 for every row group g holding a Cand row
+__global__ __launch_bounds__(256) void k_cand_group_flags(const int32_t* __restrict__ cand,
+                                                          const int32_t* __restrict__ cand_count,
+                                                          int shift, int32_t* __restrict__ flags) {
+  const int64_t k = blockIdx.x * 256ll + threadIdx.x;
+  if (k < *cand_count) flags[cand[k] >> shift] = 1;
+}
+
+// Column groups of each word's Index_Word bucket (eq. 10): the distinct values
+// members[k] >> shift over the word's member range, ascending.  One block per word.
+__device__ inline bool bucket_flag(const int32_t* __restrict__ members, int64_t k, int64_t first,
+                                   int shift) {
+  return k == first || (members[k] >> shift) != (members[k - 1] >> shift);
+}
+
+__global__ __launch_bounds__(256) void k_bucket_count(const int32_t* __restrict__ offsets,
+                                                      const int32_t* __restrict__ members, int shift,
+                                                      int32_t* __restrict__ counts) {
+  __shared__ int32_t sh[4];
+  const int w = blockIdx.x;
+  const int64_t b = offsets[w], e = offsets[w + 1];
+  int32_t c = 0;
+  for (int64_t k = b + threadIdx.x; k < e; k += 256) c += bucket_flag(members, k, b, shift);
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) counts[w] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+__global__ void k_bucket_offsets(const int32_t* __restrict__ counts, int dict,
+                                 int32_t* __restrict__ goff) {
+  if (threadIdx.x != 0) return;
+  int32_t run = 0;
+  for (int w = 0; w < dict; ++w) {
+    goff[w] = run;
+    run += counts[w];
+  }
+  goff[dict] = run;
+}
+
+__global__ __launch_bounds__(256) void k_bucket_scatter(const int32_t* __restrict__ offsets,
+                                                        const int32_t* __restrict__ members,
+                                                        int shift, const int32_t* __restrict__ goff,
+                                                        int32_t* __restrict__ groups) {
+  __shared__ int32_t wsum[4];
+  const int w = blockIdx.x;
+  const int64_t b = offsets[w], e = offsets[w + 1];
+  int32_t run = goff[w];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int64_t base = b; base < e; base += 256) {
+    const int64_t k = base + threadIdx.x;
+    const bool f = k < e && bucket_flag(members, k, b, shift);
+    const uint64_t mask = __ballot(f);
+    if (lane == 0) wsum[wv] = __popcll(mask);
+    __syncthreads();
+    int32_t pre = run;
+    for (int q = 0; q < wv; ++q) pre += wsum[q];
+    if (f) groups[pre + __popcll(mask & lanemask_lt())] = members[k] >> shift;
+    run += wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    __syncthreads();
+  }
+}
+
 // CSR counting sort: per-segment word counts
 __global__ __launch_bounds__(64) void k_csr_count(const int32_t* __restrict__ words, int64_t N,
                                                   int dict, int32_t* __restrict__ seg_counts) {
@@ -319,6 +409,31 @@ void launch_cand(const int32_t* words, const int32_t* hist, int64_t N, int dict,
   hipLaunchKernelGGL(k_scan_segments, dim3(1), dim3(256), 0, s, seg_counts, nseg, cand_count);
   hipLaunchKernelGGL(k_cand_scatter, dim3((unsigned)nseg), dim3(64), 0, s, words, hist,
                      minfreq_scratch, N, seg_counts, cand);
+}
+
+void launch_compact_flags(const int32_t* flags, int64_t count, int32_t* seg_counts, int32_t* out,
+                          int32_t* out_count, hipStream_t s) {
+  const int64_t nseg = compact_waves(count);
+  hipLaunchKernelGGL(k_flag_count, dim3((unsigned)nseg), dim3(64), 0, s, flags, count, seg_counts);
+  hipLaunchKernelGGL(k_scan_segments, dim3(1), dim3(256), 0, s, seg_counts, nseg, out_count);
+  hipLaunchKernelGGL(k_flag_scatter, dim3((unsigned)nseg), dim3(64), 0, s, flags, count,
+                     seg_counts, out);
+}
+
+void launch_cand_group_flags(const int32_t* cand, const int32_t* cand_count, int64_t max_cand,
+                             int shift, int32_t* flags, hipStream_t s) {
+  const int64_t blocks = (max_cand + 255) / 256;
+  if (blocks > 0)
+    hipLaunchKernelGGL(k_cand_group_flags, dim3((unsigned)blocks), dim3(256), 0, s, cand,
+                       cand_count, shift, flags);
+}
+
+void launch_bucket_groups(const int32_t* offsets, const int32_t* members, int dict, int shift,
+                          int32_t* counts, int32_t* goff, int32_t* groups, hipStream_t s) {
+  hipLaunchKernelGGL(k_bucket_count, dim3(dict), dim3(256), 0, s, offsets, members, shift, counts);
+  hipLaunchKernelGGL(k_bucket_offsets, dim3(1), dim3(64), 0, s, counts, dict, goff);
+  hipLaunchKernelGGL(k_bucket_scatter, dim3(dict), dim3(256), 0, s, offsets, members, shift, goff,
+                     groups);
 }
 
 void launch_csr(const int32_t* words, const int32_t* hist, int64_t N, int dict,

@@ -104,20 +104,60 @@ __device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
   return v;
 }
 
-// Full scan (no abandon): work item w = (row group, column chunk).
-__global__ __launch_bounds__(256) void k_scan_fp32_full(const float* __restrict__ Tp, int n,
-                                                        int64_t N, int64_t row_groups,
-                                                        int64_t chunks, int64_t cols_per_chunk,
-                                                        uint64_t* __restrict__ best) {
+__device__ __forceinline__ float wave_min_f32(float v) {
+  for (int off = 32; off > 0; off >>= 1) v = fminf(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+__device__ __forceinline__ uint32_t load_relaxed(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint64_t load_relaxed64(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// One wavefront per work item (row group, column chunk).  The item's column
+// sequence is the bucket of the group's word (Index_Word, eq. (10)), when given,
+// followed by the chunk's columns in matrix order; each step covers 64 column
+// groups of 8.  With abandon on, after every step each live row compares its
+// running minimum with the device best-so-far and leaves as soon as it is below
+// (Algorithms 3-4); the leaving row keeps that column as its witness.
+__global__ __launch_bounds__(256) void k_scan_fp32(ScanJob J) {
   const int lane = threadIdx.x & 63;
   const int64_t item = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (item >= row_groups * chunks) return;
-  const int64_t rg = item / chunks;
-  const int64_t ch = item - rg * chunks;
-  const int64_t i0 = __builtin_amdgcn_readfirstlane((int)(rg * TM));
-  const int64_t cb = ch * cols_per_chunk;
-  const int64_t ce = min<int64_t>(N, cb + cols_per_chunk);
-  const float* x = Tp + i0;
+  if (item >= J.n_groups * J.chunks) return;
+  const int64_t li = item / J.chunks;
+  const int64_t ch = item - li * J.chunks;
+  const int64_t g = __builtin_amdgcn_readfirstlane((int)(J.groups ? J.groups[li] : li));
+  if (J.skip && J.skip[g]) return;
+  const int64_t N = J.N;
+  const int n = J.n;
+  const int64_t i0 = g * TM;
+  uint32_t valid = 0;
+#pragma unroll
+  for (int r = 0; r < TM; ++r) valid |= (i0 + r < N ? 1u : 0u) << r;
+  uint32_t live = J.abandon ? (load_relaxed(&J.alive[g]) & valid) : valid;
+
+  // column sequence
+  int64_t nb = 0, b0 = 0;
+  if (J.words && ch == 0) {
+    const int w = J.words[i0];
+    b0 = J.bgrp_off[w];
+    nb = J.bgrp_off[w + 1] - b0;
+  }
+  const int64_t cb = ch * J.cols_per_chunk;
+  const int64_t ce = min<int64_t>(N, cb + J.cols_per_chunk);
+  const int64_t q0 = cb / TN;
+  const int64_t nm = ce > cb ? (ce + TN - 1) / TN - q0 : 0;
+  const int64_t total_q = nb + nm;
+  int64_t steps = (total_q + 63) / 64;
+  bool exhausted = true;
+  if (J.max_steps > 0 && steps > J.max_steps) {
+    steps = J.max_steps;
+    exhausted = false;
+  }
+  const float* x = J.Tp + i0;
 
   float bd[TM];
   int32_t bj[TM];
@@ -126,10 +166,16 @@ __global__ __launch_bounds__(256) void k_scan_fp32_full(const float* __restrict_
     bd[r] = __builtin_inff();
     bj[r] = -1;
   }
-  for (int64_t jb = cb; jb < ce; jb += 64 * TN) {
-    const int64_t j0 = jb + lane * TN;
+  uint32_t cnt = 0;
+  for (int64_t s = 0; s < steps && live; ++s) {
+    const int64_t qi = s * 64 + lane;
+    const bool in_seq = qi < total_q;
+    const bool from_bucket = qi < nb;
+    const int64_t q = in_seq ? (from_bucket ? (int64_t)J.bgrp[b0 + qi] : q0 + (qi - nb)) : 0;
+    const int64_t jlim = from_bucket ? N : ce;
+    const int64_t j0 = q * TN;
     float acc[TM][TN];
-    block8x8(x, Tp + j0, n, acc);
+    block8x8(x, J.Tp + j0, n, acc);
 #pragma unroll
     for (int r = 0; r < TM; ++r) {
       const int64_t i = i0 + r;
@@ -137,31 +183,85 @@ __global__ __launch_bounds__(256) void k_scan_fp32_full(const float* __restrict_
       for (int c = 0; c < TN; ++c) {
         const int64_t j = j0 + c;
         const int64_t dij = i > j ? i - j : j - i;
-        const bool ok = (j < ce) && (dij >= n);
+        const bool ok = in_seq && (j < jlim) && (dij >= n) && ((valid >> r) & 1u);
+        cnt += ok;
         if (ok && acc[r][c] < bd[r]) {
           bd[r] = acc[r][c];
           bj[r] = (int32_t)j;
         }
       }
     }
+    if (J.abandon) {
+      const float b = __builtin_bit_cast(float, load_relaxed(J.bsf));
+      uint32_t dead = 0;
+#pragma unroll
+      for (int r = 0; r < TM; ++r)
+        if ((live >> r) & 1u) dead |= (wave_min_f32(bd[r]) < b ? 1u : 0u) << r;
+      if (dead) {
+#pragma unroll
+        for (int r = 0; r < TM; ++r) {
+          if ((dead >> r) & 1u) {
+            const uint64_t key = wave_min_u64(bj[r] < 0 ? kEmptyMin : pack_min(bd[r], (uint32_t)bj[r]));
+            if (lane == 0) atomicMin((unsigned long long*)&J.best[i0 + r], (unsigned long long)key);
+          }
+        }
+        if (lane == 0) atomicAnd(&J.alive[g], ~dead);
+        live &= ~dead;
+      }
+      if (J.chunks > 1) live &= load_relaxed(&J.alive[g]);
+    }
   }
+  // rows still live: publish their minimum over this item's columns
 #pragma unroll
   for (int r = 0; r < TM; ++r) {
-    const uint64_t key = bj[r] < 0 ? kEmptyMin : pack_min(bd[r], (uint32_t)bj[r]);
-    const uint64_t w = wave_min_u64(key);
-    if (lane == 0 && i0 + r < N && w != kEmptyMin) atomicMin((unsigned long long*)&best[i0 + r],
-                                                             (unsigned long long)w);
+    if ((live >> r) & 1u) {
+      const uint64_t key = wave_min_u64(bj[r] < 0 ? kEmptyMin : pack_min(bd[r], (uint32_t)bj[r]));
+      if (lane == 0 && key != kEmptyMin)
+        atomicMin((unsigned long long*)&J.best[i0 + r], (unsigned long long)key);
+    }
+  }
+  uint64_t c64 = cnt;
+  for (int off = 32; off > 0; off >>= 1) c64 += __shfl_xor(c64, off, 64);
+  if (lane == 0 && c64) atomicAdd((unsigned long long*)J.pairs, (unsigned long long)c64);
+  if (!J.abandon) return;
+
+  if (J.chunks == 1) {
+    if (exhausted) {
+      // every column seen: the live rows' minima are complete
+#pragma unroll
+      for (int r = 0; r < TM; ++r) {
+        if ((live >> r) & 1u) {
+          const float m = wave_min_f32(bd[r]);
+          if (lane == 0 && m < __builtin_inff())
+            atomicMax(J.bsf, __builtin_bit_cast(uint32_t, m * J.raise_scale));
+        }
+      }
+    } else if (live && lane == 0) {
+      J.survivors[atomicAdd(J.n_survivors, 1u)] = (int32_t)g;
+    }
+    return;
+  }
+  // chunked: the last chunk of the group to finish raises the best-so-far
+  __threadfence();
+  uint32_t prev = 0;
+  if (lane == 0) prev = atomicAdd(&J.done[g], 1u);
+  prev = __shfl(prev, 0, 64);
+  if (prev + 1 != (uint32_t)J.chunks) return;
+  __threadfence();
+  const uint32_t fin = load_relaxed(&J.alive[g]) & valid;
+  if (lane < TM && ((fin >> lane) & 1u)) {
+    const uint64_t k = load_relaxed64(&J.best[i0 + lane]);
+    if (k != kEmptyMin) atomicMax(J.bsf, __builtin_bit_cast(uint32_t, key_dist(k) * J.raise_scale));
   }
 }
 
 }  // namespace
 
-void launch_scan_fp32_full(const float* Tp, int n, int64_t N, int64_t row_groups, int64_t chunks,
-                           int64_t cols_per_chunk, uint64_t* best, hipStream_t s) {
-  const int64_t items = row_groups * chunks;
+void launch_scan_fp32(const ScanJob& J, hipStream_t s) {
+  const int64_t items = J.n_groups * J.chunks;
+  if (items <= 0) return;
   const int64_t blocks = (items + 3) / 4;
-  hipLaunchKernelGGL(k_scan_fp32_full, dim3((unsigned)blocks), dim3(256), 0, s, Tp, n, N,
-                     row_groups, chunks, cols_per_chunk, best);
+  hipLaunchKernelGGL(k_scan_fp32, dim3((unsigned)blocks), dim3(256), 0, s, J);
 }
 
 }  // namespace dd

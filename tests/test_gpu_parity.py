@@ -97,6 +97,27 @@ def test_discord_matches_oracle(gpu, m, n, seed, abandon):
     _assert_same(r, ref, (m, n, seed))
 
 
+@pytest.mark.parametrize("probe_steps", [1, 3, 16, 100000])
+@pytest.mark.parametrize("order", [True, False])
+def test_abandon_reaches_same_discord_and_prunes(gpu, probe_steps, order):
+    """Early abandon (Algorithms 3-4) changes the work, never the answer: every
+    probe budget and visiting order gives the oracle's discord, and rows are
+    actually left early."""
+    m, n = 30000, 64
+    T = workloads.random_walk(m, seed=4242, noise=0.01)
+    ref = oracle.discord(T, n)
+    with gpu.Plan(T, n, abandon=True, order=order, probe_steps=probe_steps) as p:
+        r = p.search()
+        state = p.copy("row_state")
+        wit = p.copy("nn_witness")
+    _assert_same(r, ref, (probe_steps, order))
+    P = oracle.pair_count(m - n + 1, n)
+    assert r.rows_abandoned > 0 and r.pairs_evaluated < P
+    assert np.sum(state == 2) == r.rows_abandoned
+    bad, first, _ = oracle.witness_check(T, n, r.index, r.d2, wit)
+    assert bad == 0, first
+
+
 @pytest.mark.parametrize("seed", range(6))
 def test_integer_series_exact_ties(gpu, seed):
     """Integer series: squared distances are exact in FP32 and FP64, so exact ties
