@@ -41,6 +41,7 @@ void sax_breakpoints(int alpha, double* out) {
 namespace {
 
 constexpr size_t kAlign = 256;
+constexpr int64_t kRowPad = 64;   // zero rows after N in the FP32 row-statistics arrays
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -48,7 +49,7 @@ struct Layout {
   size_t T, stats, partials, bad, words, hist, minfreq, cand, cand_count, seg, csr_off, csr_mem,
       best, nn_approx, nn_wit, row_state, row_mean, row_cnorm, seed, rows, part_d, part_j, out_d,
       out_j, exact, unc, unc_count, relerr, bsf, pairs, alive, done, survivors, n_surv, gflags,
-      cand_groups, n_cand_groups, n_aband, bgrp_cnt, bgrp_off, bgrp, total;
+      cand_groups, n_cand_groups, n_aband, bgrp_cnt, bgrp_off, bgrp, mu32, smu32, cn32, total;
 };
 
 Layout make_layout(int64_t m, int32_t n, int dict) {
@@ -104,6 +105,9 @@ Layout make_layout(int64_t m, int32_t n, int dict) {
   L.bgrp_cnt = take(sizeof(int32_t) * kMaxWords);
   L.bgrp_off = take(sizeof(int32_t) * (kMaxWords + 1));
   L.bgrp = take(sizeof(int32_t) * N);
+  L.mu32 = take(sizeof(float) * (N + kRowPad));
+  L.smu32 = take(sizeof(float) * (N + kRowPad));
+  L.cn32 = take(sizeof(float) * (N + kRowPad));
   L.total = off;
   return L;
 }
@@ -276,6 +280,7 @@ int discord_prepare(const float* T, int64_t m, int32_t n, const discord_opts* op
   g_prepare_err[0] = 0;
   if (!T || n < 1 || m < 2 * (int64_t)n || !opts_valid(n, o)) return DISCORD_EINVAL;
   if (m > (int64_t)INT32_MAX - kBackPad - kFrontPad) return DISCORD_ERANGE;
+  if (o.precision == DISCORD_PREC_BF16X3 && n > kMixedMaxN) return DISCORD_ERANGE;
 
   discord_plan p = new (std::nothrow) discord_plan_s();
   if (!p) return DISCORD_ENOMEM;
@@ -346,7 +351,13 @@ int discord_prepare(const float* T, int64_t m, int32_t n, const discord_opts* op
                p->at<int32_t>(p->L.seg), p->at<int32_t>(p->L.csr_off),
                p->at<int32_t>(p->L.csr_mem), s);
     // the column groups (of 8) of every word's bucket: the scan's same-word-first order
-    launch_bucket_groups(p->at<int32_t>(p->L.csr_off), p->at<int32_t>(p->L.csr_mem), p->dict, 3,
+    const bool mixed = o.precision == DISCORD_PREC_BF16X3;
+    if (mixed)
+      launch_row_stats32(p->Tp(), p->N, n, p->N + kRowPad, p->at<double>(p->L.row_mean),
+                         p->at<double>(p->L.stats), p->at<float>(p->L.mu32),
+                         p->at<float>(p->L.smu32), p->at<float>(p->L.cn32), s);
+    launch_bucket_groups(p->at<int32_t>(p->L.csr_off), p->at<int32_t>(p->L.csr_mem), p->dict,
+                         mixed ? 5 : 3,
                          p->at<int32_t>(p->L.bgrp_cnt), p->at<int32_t>(p->L.bgrp_off),
                          p->at<int32_t>(p->L.bgrp), s);
     LAUNCH_OK(p, "prepare kernels");
@@ -379,7 +390,12 @@ int discord_search(discord_plan p, discord_result* out) {
   HIP_TRY(p, hipSetDevice(p->device));
   HIP_TRY(p, hipEventRecord(ev.a, s));
 
-  const int64_t G = (N + kRowGroup - 1) / kRowGroup;
+  const bool mixed = p->opts.precision == DISCORD_PREC_BF16X3;
+  // rows per scan group: 8 (FP32 micro-tile) or 32 (one MFMA tile side)
+  const int gsz = mixed ? kMixedBlock : kRowGroup;
+  const int gshift = mixed ? 5 : 3;
+  const int64_t G = (N + gsz - 1) / gsz;
+  const int rb = mixed ? mfma_row_blocks(n) : 1;   // row groups per wavefront
   const bool abandon = p->opts.abandon != 0;
   const bool order = p->opts.order != 0;
   uint64_t* best = p->at<uint64_t>(p->L.best);
@@ -404,27 +420,46 @@ int discord_search(discord_plan p, discord_result* out) {
   J.done = p->at<uint32_t>(p->L.done);
   J.survivors = p->at<int32_t>(p->L.survivors);
   J.n_survivors = n_surv;
-  // A row whose scan completed has exact NN >= (its FP32 minimum) / (1 + gamma),
-  // gamma = (n + 3) 2^-24 bounding the direct-form rounding; raising the
-  // best-so-far by that lower bound keeps it <= the discord's NN.
-  J.raise_scale = (float)(1.0 - ((n + 3) * std::ldexp(1.0, -24) * 1.01 + std::ldexp(1.0, -22)));
+  const MixedRows R{p->at<float>(p->L.mu32), p->at<float>(p->L.smu32), p->at<float>(p->L.cn32)};
+  if (mixed) {
+    // The split-BF16 minima carry errors of order 2^-16 |a'||b'|, with no
+    // simple relative bound; raising the best-so-far by a 2^-10 margin is a
+    // heuristic only -- the FP64 certification below keeps the result exact
+    // whatever the best-so-far was.
+    J.raise_scale = (float)(1.0 - std::ldexp(1.0, -10));
+  } else {
+    // A row whose scan completed has exact NN >= (its FP32 minimum) / (1 + gamma),
+    // gamma = (n + 3) 2^-24 bounding the direct-form rounding; raising the
+    // best-so-far by that lower bound keeps it <= the discord's NN.
+    J.raise_scale = (float)(1.0 - ((n + 3) * std::ldexp(1.0, -24) * 1.01 + std::ldexp(1.0, -22)));
+  }
+  auto launch = [&](const char* what) -> int {
+    if (mixed) {
+      if (!launch_scan_mfma(J, R, s)) return fail(p, DISCORD_ERANGE, "window too long for bf16x3");
+    } else {
+      launch_scan_fp32(J, s);
+    }
+    LAUNCH_OK(p, what);
+    return DISCORD_OK;
+  };
   // split the columns so that the launch holds at least ~4096 wavefronts
   auto set_chunks = [&](int64_t groups) {
+    const int64_t waves = std::max<int64_t>(1, (groups + rb - 1) / rb);
     const int64_t maxc = std::max<int64_t>(1, (N + 511) / 512);
-    int64_t c = std::min<int64_t>(maxc, std::max<int64_t>(1, (4096 + groups - 1) / std::max<int64_t>(groups, 1)));
+    int64_t c = std::min<int64_t>(maxc, std::max<int64_t>(1, (4096 + waves - 1) / waves));
     int64_t cols = ((N + c - 1) / c + 511) / 512 * 512;
     J.cols_per_chunk = cols;
     J.chunks = (N + cols - 1) / cols;
   };
+  int st = DISCORD_OK;
   if (!abandon) {
     J.abandon = 0;
     J.n_groups = G;
     set_chunks(G);
-    launch_scan_fp32(J, s);
-    LAUNCH_OK(p, "scan (full)");
+    if ((st = launch("scan (full)"))) return st;
   } else {
     J.abandon = 1;
-    launch_init_alive(alive, G, N, s);
+    launch_init_alive(alive, G, N, gsz, s);
     launch_init_i32(reinterpret_cast<int32_t*>(J.done), G, 0, s);
     launch_init_i32(reinterpret_cast<int32_t*>(n_surv), 1, 0, s);
     launch_init_i32(gflags, G, 0, s);
@@ -435,7 +470,7 @@ int discord_search(discord_plan p, discord_result* out) {
       int32_t* cgroups = p->at<int32_t>(p->L.cand_groups);
       int32_t* n_cg = p->at<int32_t>(p->L.n_cand_groups);
       launch_cand_group_flags(p->at<int32_t>(p->L.cand), p->at<int32_t>(p->L.cand_count),
-                              p->cand_count, 3, gflags, s);
+                              p->cand_count, gshift, gflags, s);
       launch_compact_flags(gflags, G, p->at<int32_t>(p->L.seg), cgroups, n_cg, s);
       HIP_TRY(p, hipMemcpyAsync(&hcg, n_cg, sizeof(hcg), hipMemcpyDeviceToHost, s));
       HIP_TRY(p, hipStreamSynchronize(s));
@@ -446,22 +481,21 @@ int discord_search(discord_plan p, discord_result* out) {
       J.bgrp_off = p->at<int32_t>(p->L.bgrp_off);
       J.bgrp = p->at<int32_t>(p->L.bgrp);
       J.max_steps = 0;
-      launch_scan_fp32(J, s);
-      LAUNCH_OK(p, "scan (Cand)");
+      if ((st = launch("scan (Cand)"))) return st;
     }
     // Algorithm 4, first pass: every other row group walks its word's bucket,
-    // then matrix order, for a bounded number of steps
+    // then matrix order, for a bounded number of 512-column steps
     J.groups = nullptr;
     J.n_groups = G;
     J.chunks = 1;
     J.cols_per_chunk = (N + 511) / 512 * 512;
-    J.max_steps = p->opts.probe_steps > 0 ? p->opts.probe_steps : 16;
+    const int probe = p->opts.probe_steps > 0 ? p->opts.probe_steps : 16;
+    J.max_steps = mixed ? probe * (512 / kMixedBlock) : probe;
     J.words = order ? p->at<int32_t>(p->L.words) : nullptr;
     J.bgrp_off = p->at<int32_t>(p->L.bgrp_off);
     J.bgrp = p->at<int32_t>(p->L.bgrp);
     J.skip = (order && hcg > 0) ? gflags : nullptr;
-    launch_scan_fp32(J, s);
-    LAUNCH_OK(p, "scan (probe)");
+    if ((st = launch("scan (probe)"))) return st;
     uint32_t hs = 0;
     HIP_TRY(p, hipMemcpyAsync(&hs, n_surv, sizeof(hs), hipMemcpyDeviceToHost, s));
     HIP_TRY(p, hipStreamSynchronize(s));
@@ -472,8 +506,7 @@ int discord_search(discord_plan p, discord_result* out) {
     J.words = nullptr;
     J.skip = nullptr;
     J.max_steps = 0;
-    launch_scan_fp32(J, s);
-    LAUNCH_OK(p, "scan (survivors)");
+    if ((st = launch("scan (survivors)"))) return st;
   }
   HIP_TRY(p, hipEventRecord(evs.b, s));
 
@@ -483,13 +516,14 @@ int discord_search(discord_plan p, discord_result* out) {
   int32_t* row_state = p->at<int32_t>(p->L.row_state);
   uint32_t* n_aband = p->at<uint32_t>(p->L.n_aband);
   launch_init_i32(reinterpret_cast<int32_t*>(n_aband), 1, 0, s);
-  launch_unpack_best(best, N, abandon ? alive : nullptr, nn_approx, nn_wit, row_state, n_aband, s);
+  launch_unpack_best(best, N, abandon ? alive : nullptr, gsz, nn_approx, nn_wit, row_state, n_aband,
+                     s);
   uint64_t* seed = p->at<uint64_t>(p->L.seed);
   launch_init_u64(seed, 1, 0, s);
   launch_seed_argmax(best, row_state, N, seed, s);
   int64_t* rows = p->at<int64_t>(p->L.rows);
   launch_seed_row(seed, rows, s);
-  int st = rows_nn_batch(p, rows, 1);
+  st = rows_nn_batch(p, rows, 1);
   if (st) return st;
   Exact* ex = p->at<Exact>(p->L.exact);
   launch_exact_from_rows(rows, p->at<double>(p->L.out_d), p->at<int64_t>(p->L.out_j), 1, ex, s);

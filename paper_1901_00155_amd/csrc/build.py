@@ -18,7 +18,7 @@ LIBDIR = os.path.join(PKG, "lib")
 LIB = os.path.join(LIBDIR, "libdiscord.so")
 OBJDIR = os.path.join(ROOT, "_build", "obj")
 
-SOURCES = ["prep.hip", "scan_fp32.hip", "certify.hip", "api.hip"]
+SOURCES = ["scan_mfma.hip", "prep.hip", "scan_fp32.hip", "certify.hip", "api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -51,7 +51,7 @@ __global__ void k_fill_i32(int32_t* p, int64_t count, int32_t v) {
 // Rows of the scan: minimum (or abandon distance) and its column; a row is
 // abandoned when its bit in the group's alive mask was cleared.
 __global__ __launch_bounds__(256) void k_unpack_best(const uint64_t* __restrict__ best, int64_t N,
-                                                     const uint32_t* __restrict__ alive,
+                                                     const uint32_t* __restrict__ alive, int gsz,
                                                      float* __restrict__ nn_approx,
                                                      int32_t* __restrict__ nn_witness,
                                                      int32_t* __restrict__ row_state,
@@ -65,7 +65,7 @@ __global__ __launch_bounds__(256) void k_unpack_best(const uint64_t* __restrict_
       nn_witness[i] = -1;
       row_state[i] = kRowUnscanned;
     } else {
-      ab = alive && !((alive[i / kRowGroup] >> (i % kRowGroup)) & 1u);
+      ab = alive && !((alive[i / gsz] >> (i % gsz)) & 1u);
       nn_approx[i] = key_dist(k);
       nn_witness[i] = (int32_t)(k & 0xFFFFFFFFu);
       row_state[i] = ab ? kRowAbandoned : kRowFull;
@@ -76,10 +76,10 @@ __global__ __launch_bounds__(256) void k_unpack_best(const uint64_t* __restrict_
 }
 
 __global__ __launch_bounds__(256) void k_init_alive(uint32_t* __restrict__ alive, int64_t G,
-                                                    int64_t N) {
+                                                    int64_t N, int gsz) {
   const int64_t g = blockIdx.x * 256ll + threadIdx.x;
   if (g >= G) return;
-  const int64_t rows = min<int64_t>(kRowGroup, N - g * kRowGroup);
+  const int64_t rows = min<int64_t>(gsz, N - g * gsz);
   alive[g] = rows >= 32 ? 0xFFFFFFFFu : ((1u << rows) - 1u);
 }
 
@@ -260,16 +260,17 @@ void launch_init_i32(int32_t* p, int64_t count, int32_t v, hipStream_t s) {
   if (count > 0) hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)blocks), dim3(256), 0, s, p, count, v);
 }
 
-void launch_unpack_best(const uint64_t* best, int64_t N, const uint32_t* alive, float* nn_approx,
-                        int32_t* nn_witness, int32_t* row_state, uint32_t* n_abandoned,
-                        hipStream_t s) {
+void launch_unpack_best(const uint64_t* best, int64_t N, const uint32_t* alive, int gsz,
+                        float* nn_approx, int32_t* nn_witness, int32_t* row_state,
+                        uint32_t* n_abandoned, hipStream_t s) {
   hipLaunchKernelGGL(k_unpack_best, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, best, N,
-                     alive, nn_approx, nn_witness, row_state, n_abandoned);
+                     alive, gsz, nn_approx, nn_witness, row_state, n_abandoned);
 }
 
-void launch_init_alive(uint32_t* alive, int64_t G, int64_t N, hipStream_t s) {
+void launch_init_alive(uint32_t* alive, int64_t G, int64_t N, int gsz, hipStream_t s) {
   if (G > 0)
-    hipLaunchKernelGGL(k_init_alive, dim3((unsigned)((G + 255) / 256)), dim3(256), 0, s, alive, G, N);
+    hipLaunchKernelGGL(k_init_alive, dim3((unsigned)((G + 255) / 256)), dim3(256), 0, s, alive, G, N,
+                       gsz);
 }
 
 void launch_seed_argmax(const uint64_t* best, const int32_t* row_state, int64_t N,

@@ -102,13 +102,30 @@ struct ScanJob {
 };
 void launch_scan_fp32(const ScanJob& J, hipStream_t s);
 
+// ---- scan_mfma.hip ------------------------------------------------------------
+// Row statistics of the split-BF16 scan (FP32, padded with zeros to N + 64):
+// mu = fp32 row mean (the centre), smu = sqrt(n) (mean - series mean),
+// cnorm = squared norm about the centre.
+struct MixedRows {
+  const float* mu;
+  const float* smu;
+  const float* cnorm;
+};
+constexpr int kMixedBlock = 32;      // rows per MFMA row block = columns per column block
+constexpr int kMixedMaxN = 512;      // longest window of the split-BF16 scan (32 K-steps)
+bool launch_scan_mfma(const ScanJob& J, const MixedRows& R, hipStream_t s);
+int mfma_row_blocks(int n);
+void launch_row_stats32(const float* Tp, int64_t N, int n, int64_t padded, const double* row_mean,
+                        const double* stats, float* c32, float* smu32, float* cn32,
+                        hipStream_t s);
+
 // ---- certify.hip --------------------------------------------------------------
 void launch_init_u64(uint64_t* p, int64_t count, uint64_t v, hipStream_t s);
 void launch_init_i32(int32_t* p, int64_t count, int32_t v, hipStream_t s);
-void launch_unpack_best(const uint64_t* best, int64_t N, const uint32_t* alive, float* nn_approx,
-                        int32_t* nn_witness, int32_t* row_state, uint32_t* n_abandoned,
-                        hipStream_t s);
-void launch_init_alive(uint32_t* alive, int64_t G, int64_t N, hipStream_t s);
+void launch_unpack_best(const uint64_t* best, int64_t N, const uint32_t* alive, int gsz,
+                        float* nn_approx, int32_t* nn_witness, int32_t* row_state,
+                        uint32_t* n_abandoned, hipStream_t s);
+void launch_init_alive(uint32_t* alive, int64_t G, int64_t N, int gsz, hipStream_t s);
 void launch_seed_argmax(const uint64_t* best, const int32_t* row_state, int64_t N,
                         uint64_t* seed_key, hipStream_t s);
 void launch_seed_row(const uint64_t* seed_key, int64_t* rows_out, hipStream_t s);

@@ -96,6 +96,41 @@ __global__ __launch_bounds__(256) void k_row_stats(const float* __restrict__ T, 
   cnorm[i] = q;
 }
 
+// FP32 row statistics of the split-BF16 scan.  The centre of row i is
+// c_i = fp32(mean_i); the scan centres with exactly c_i, so the centred norm is
+// taken about c_i (FP64), while the mean term uses the exact mean:
+//   d^2 = |a - c_a|^2 + |b - c_b|^2 - 2 (a - c_a).(b - c_b) + n (mu_a - mu_b)^2
+//         - n ((mu_a - c_a) - (mu_b - c_b))^2,
+// whose last term (below n * ulp(mu)^2) is dropped.  smu = sqrt(n) (mu - mu_T)
+// with mu_T the series mean.  Entries N .. N+pad-1 are zero.
+__global__ __launch_bounds__(256) void k_row_stats32(const float* __restrict__ T, int64_t N, int n,
+                                                     int64_t padded,
+                                                     const double* __restrict__ mean,
+                                                     const double* __restrict__ stats,
+                                                     float* __restrict__ c32,
+                                                     float* __restrict__ smu32,
+                                                     float* __restrict__ cn32) {
+  const int64_t i = blockIdx.x * 256ll + threadIdx.x;
+  if (i >= padded) return;
+  if (i >= N) {
+    c32[i] = 0.0f;
+    smu32[i] = 0.0f;
+    cn32[i] = 0.0f;
+    return;
+  }
+  const double mu = mean[i];
+  const float c = (float)mu;
+  const double cd = (double)c;
+  double q = 0.0;
+  for (int k = 0; k < n; ++k) {
+    const double d = (double)T[i + k] - cd;
+    q += d * d;
+  }
+  c32[i] = c;
+  smu32[i] = (float)(sqrt((double)n) * (mu - stats[0]));
+  cn32[i] = (float)q;
+}
+
 struct Breakpoints {
   double b[8];
 };
@@ -384,6 +419,14 @@ void launch_row_stats(const float* Tp, int64_t N, int n, double* row_mean, doubl
   const int64_t blocks = (N + 255) / 256;
   hipLaunchKernelGGL(k_row_stats, dim3((unsigned)blocks), dim3(256), 0, s, Tp, N, n, row_mean,
                      row_cnorm);
+}
+
+void launch_row_stats32(const float* Tp, int64_t N, int n, int64_t padded, const double* row_mean,
+                        const double* stats, float* c32, float* smu32, float* cn32,
+                        hipStream_t s) {
+  const int64_t blocks = (padded + 255) / 256;
+  hipLaunchKernelGGL(k_row_stats32, dim3((unsigned)blocks), dim3(256), 0, s, Tp, N, n, padded,
+                     row_mean, stats, c32, smu32, cn32);
 }
 
 // Breakpoints of eq. (4): beta_k = Phi^{-1}(k / alpha), computed on the host by

@@ -4,6 +4,8 @@ Bars: discord index and nearest-neighbour index bit-exact; the FP64 squared
 distance within 1e-9 relative (the kernels sum in the oracle's order, so it is
 normally bit-identical); approximate FP32 NN values within the direct-form
 rounding bound (n + 3) * 2^-24 relative; integer/word/index structures exact.
+Both scan precisions (FP32 direct form, split-BF16 MFMA) must reach the same
+exact answer, since every approximate decision is certified in FP64.
 """
 import math
 
@@ -17,6 +19,7 @@ from helpers import periodic_spike as _periodic_spike
 pytestmark = pytest.mark.gpu
 
 REL = 1e-9
+PRECS = ["fp32", "bf16x3"]
 
 
 def _fp32_bound(n):
@@ -79,34 +82,60 @@ def test_fp32_full_scan_profile(gpu, m, n):
     assert bad == 0, first
 
 
+@pytest.mark.parametrize("m,n", [(1000, 8), (1500, 21), (4096, 64), (2500, 100), (3000, 256),
+                                 (2000, 512)])
+def test_bf16x3_full_scan_profile(gpu, m, n):
+    """Split-BF16 MFMA minima: within 2^-14 of the centred norms of the exact NN
+    (the split products carry ~2^-16 |a'||b'|), and every witness is a valid
+    non-self match; the certificate over them holds."""
+    T = workloads.random_walk(m, seed=m + n)
+    ref = oracle.discord(T, n, profile=True)
+    with gpu.Plan(T, n, precision="bf16x3", abandon=False) as p:
+        r = p.search()
+        approx = p.copy("nn_approx").astype(np.float64)
+        wit = p.copy("nn_witness")
+        cn = p.copy("row_cnorm")
+    _assert_same(r, ref, (m, n))
+    prof = ref["profile"]
+    N = m - n + 1
+    scale = cn + np.max(cn)
+    assert np.all(np.abs(approx - prof) <= 2.0 ** -12 * scale + 1e-6)
+    assert np.all(np.abs(np.arange(N) - wit) >= n)
+    bad, first, _ = oracle.witness_check(T, n, ref["index"], ref["d2"], wit)
+    assert bad == 0, first
+
+
 # --------------------------------------------------------------------- discord parity
 SMALL_CASES = [
     (16, 1, 0), (40, 3, 1), (64, 32, 2), (63, 21, 3), (100, 7, 4), (257, 9, 5), (300, 64, 6),
     (513, 100, 7), (1000, 1, 8), (1001, 333, 9), (2049, 17, 10), (3000, 128, 11),
-    (4100, 200, 12), (777, 259, 13), (4096, 64, 14),
+    (4100, 200, 12), (777, 259, 13), (4096, 64, 14), (1500, 512, 15),
 ]
 
 
 @pytest.mark.parametrize("m,n,seed", SMALL_CASES)
 @pytest.mark.parametrize("abandon", [False, True])
-def test_discord_matches_oracle(gpu, m, n, seed, abandon):
+@pytest.mark.parametrize("precision", PRECS)
+def test_discord_matches_oracle(gpu, m, n, seed, abandon, precision):
     T = workloads.random_walk(m, seed=seed)
     ref = oracle.discord(T, n)
-    with gpu.Plan(T, n, abandon=abandon) as p:
+    with gpu.Plan(T, n, abandon=abandon, precision=precision) as p:
         r = p.search()
     _assert_same(r, ref, (m, n, seed))
 
 
 @pytest.mark.parametrize("probe_steps", [1, 3, 16, 100000])
 @pytest.mark.parametrize("order", [True, False])
-def test_abandon_reaches_same_discord_and_prunes(gpu, probe_steps, order):
+@pytest.mark.parametrize("precision", PRECS)
+def test_abandon_reaches_same_discord_and_prunes(gpu, probe_steps, order, precision):
     """Early abandon (Algorithms 3-4) changes the work, never the answer: every
     probe budget and visiting order gives the oracle's discord, and rows are
     actually left early."""
     m, n = 30000, 64
     T = workloads.random_walk(m, seed=4242, noise=0.01)
     ref = oracle.discord(T, n)
-    with gpu.Plan(T, n, abandon=True, order=order, probe_steps=probe_steps) as p:
+    with gpu.Plan(T, n, abandon=True, order=order, probe_steps=probe_steps,
+                  precision=precision) as p:
         r = p.search()
         state = p.copy("row_state")
         wit = p.copy("nn_witness")
@@ -119,7 +148,8 @@ def test_abandon_reaches_same_discord_and_prunes(gpu, probe_steps, order):
 
 
 @pytest.mark.parametrize("seed", range(6))
-def test_integer_series_exact_ties(gpu, seed):
+@pytest.mark.parametrize("precision", PRECS)
+def test_integer_series_exact_ties(gpu, seed, precision):
     """Integer series: squared distances are exact in FP32 and FP64, so exact ties
     are common and the lowest-index rules decide."""
     rng = np.random.default_rng(900 + seed)
@@ -127,36 +157,39 @@ def test_integer_series_exact_ties(gpu, seed):
     n = int(rng.integers(2, 12))
     T = rng.integers(-3, 4, m).astype(np.float32)
     ref = oracle.discord(T, n)
-    with gpu.Plan(T, n) as p:
+    with gpu.Plan(T, n, precision=precision) as p:
         _assert_same(p.search(), ref, (m, n))
 
 
 @pytest.mark.parametrize("seed", range(8))
-def test_periodic_spike_closed_form(gpu, seed):
+@pytest.mark.parametrize("precision", PRECS)
+def test_periodic_spike_closed_form(gpu, seed, precision):
     rng = np.random.default_rng(300 + seed)
     n = int(rng.integers(2, 9))
     T, pos, h = _periodic_spike(rng, n)
-    with gpu.Plan(T, n) as p:
+    with gpu.Plan(T, n, precision=precision) as p:
         r = p.search()
     assert r.index == max(0, pos - n + 1)
     assert r.d2 == float(h * h)
 
 
 @pytest.mark.parametrize("n", [1, 5, 64])
-def test_m_equals_2n(gpu, n):
+@pytest.mark.parametrize("precision", PRECS)
+def test_m_equals_2n(gpu, n, precision):
     rng = np.random.default_rng(n)
     T = rng.standard_normal(2 * n).astype(np.float32)
     ref = oracle.discord(T, n)
-    with gpu.Plan(T, n, paa_w=min(4, n)) as p:
+    with gpu.Plan(T, n, paa_w=min(4, n), precision=precision) as p:
         r = p.search()
     _assert_same(r, ref)
     assert r.index == 0 and r.nn_index == n
 
 
-def test_small_workload(gpu):
+@pytest.mark.parametrize("precision", PRECS)
+def test_small_workload(gpu, precision):
     w = workloads.small()
     ref = oracle.discord(w.series, w.n)
-    with gpu.Plan(w.series, w.n) as p:
+    with gpu.Plan(w.series, w.n, precision=precision) as p:
         r = p.search()
     _assert_same(r, ref)
     assert 2000 - w.n < r.index < 2064
@@ -187,6 +220,9 @@ def test_error_paths(gpu):
     assert e.value.status == -1
     with pytest.raises(gpu.DiscordError):
         gpu.Plan(np.arange(100, dtype=np.float32), 3, paa_w=9)
+    with pytest.raises(gpu.DiscordError) as e:
+        gpu.Plan(workloads.random_walk(3000, seed=1), 600, precision="bf16x3")
+    assert e.value.status == -6
 
 
 def test_device_series_torch_workspace_and_stream(gpu):
@@ -196,7 +232,7 @@ def test_device_series_torch_workspace_and_stream(gpu):
     s = torch.cuda.Stream()
     with torch.cuda.stream(s):
         Td = torch.from_numpy(w.series).cuda()
-        with gpu.Plan(Td, w.n, torch_workspace=True) as p:
+        with gpu.Plan(Td, w.n, torch_workspace=True, precision="bf16x3") as p:
             r = p.search()
     _assert_same(r, ref)
     idx, dist = gpu.search_series(w.series, w.n)
@@ -204,17 +240,36 @@ def test_device_series_torch_workspace_and_stream(gpu):
 
 
 # --------------------------------------------------------------------- full size
-def test_walk1m_certificate(gpu):
-    """m = 2^20, n = 128, four planted anomalies: the oracle cannot brute-force
-    this size, so it checks the GPU's answer with the FP64 witness certificate
-    (exact NN of the claimed row + one witness per other row)."""
-    w = workloads.walk1m()
-    with gpu.Plan(w.series, w.n) as p:
-        r = p.search()
-        wit = p.copy("nn_witness")
+def _certify(w, r, wit):
     bad, first, nn = oracle.witness_check(w.series, w.n, r.index, r.d2, wit)
     assert bad == 0, first
     assert abs(r.d2 - nn) <= REL * nn
-    # Under the global normalisation of eq. (2) the raw-distance discord of a
-    # long random walk lies at a level the walk visits rarely, not necessarily
-    # at a planted anomaly, so no location is asserted here.
+
+
+@pytest.mark.parametrize("precision", PRECS)
+def test_walk1m_certificate(gpu, precision):
+    """m = 2^20, n = 128, four planted anomalies: the oracle cannot brute-force
+    this size, so it checks the GPU's answer with the FP64 witness certificate
+    (exact NN of the claimed row + one witness per other row).  Under the global
+    normalisation of eq. (2) the raw-distance discord of a long random walk lies
+    at a level the walk visits rarely, not necessarily at a planted anomaly, so
+    no location is asserted here."""
+    w = workloads.walk1m()
+    with gpu.Plan(w.series, w.n, precision=precision) as p:
+        r = p.search()
+        wit = p.copy("nn_witness")
+    _certify(w, r, wit)
+
+
+def test_noisy1m_both_precisions_agree(gpu):
+    """m = 2^20 walk + N(0, 0.05), n = 256: the split-BF16 MFMA search and the
+    FP32 search give the same certified discord."""
+    w = workloads.noisy1m()
+    out = {}
+    for precision in PRECS:
+        with gpu.Plan(w.series, w.n, precision=precision) as p:
+            r = p.search()
+            wit = p.copy("nn_witness")
+        _certify(w, r, wit)
+        out[precision] = (r.index, r.nn_index, r.d2)
+    assert out["fp32"] == out["bf16x3"]
