@@ -49,10 +49,10 @@ struct Layout {
   size_t T, stats, partials, bad, words, hist, minfreq, cand, cand_count, seg, csr_off, csr_mem,
       best, nn_approx, nn_wit, row_state, row_mean, row_cnorm, seed, rows, part_d, part_j, out_d,
       out_j, exact, unc, unc_count, relerr, bsf, pairs, alive, done, survivors, n_surv, gflags,
-      cand_groups, n_cand_groups, n_aband, bgrp_cnt, bgrp_off, bgrp, mu32, smu32, cn32, total;
+      cand_groups, n_cand_groups, n_aband, bgrp_cnt, bgrp_off, bgrp, mu32, smu32, cn32, sblk, total;
 };
 
-Layout make_layout(int64_t m, int32_t n, int dict) {
+Layout make_layout(int64_t m, int32_t n, int dict, bool mixed) {
   const int64_t N = m - n + 1;
   const int64_t nchunks = (N + kFp64Cols - 1) / kFp64Cols;
   const int64_t seg = std::max<int64_t>(csr_waves(N) * dict, compact_waves(N));
@@ -108,6 +108,8 @@ Layout make_layout(int64_t m, int32_t n, int dict) {
   L.mu32 = take(sizeof(float) * (N + kRowPad));
   L.smu32 = take(sizeof(float) * (N + kRowPad));
   L.cn32 = take(sizeof(float) * (N + kRowPad));
+  // the split subsequence matrix of the MFMA scan, resident for the plan's life
+  L.sblk = take(mixed ? (size_t)mixed_blocks(N) * mixed_block_bytes(n) : 0);
   L.total = off;
   return L;
 }
@@ -267,7 +269,7 @@ size_t discord_workspace_bytes(int64_t m, int32_t n, const discord_opts* opts) {
   if (n >= 1 && o.paa_w >= 1 && o.paa_w <= 8 && o.paa_w > n) o.paa_w = n;
   if (n < 1 || m < 2 * (int64_t)n || !opts_valid(n, o)) return 0;
   if (m > (int64_t)INT32_MAX - kBackPad - kFrontPad) return 0;
-  return make_layout(m, n, dict_size(o)).total;
+  return make_layout(m, n, dict_size(o), o.precision == DISCORD_PREC_BF16X3).total;
 }
 
 int discord_prepare(const float* T, int64_t m, int32_t n, const discord_opts* opts, void* workspace,
@@ -289,7 +291,7 @@ int discord_prepare(const float* T, int64_t m, int32_t n, const discord_opts* op
   p->N = m - n + 1;
   p->opts = o;
   p->dict = dict_size(o);
-  p->L = make_layout(m, n, p->dict);
+  p->L = make_layout(m, n, p->dict, o.precision == DISCORD_PREC_BF16X3);
   auto bail = [&](int st) {
     discord_release(p);
     return st;
@@ -356,6 +358,9 @@ int discord_prepare(const float* T, int64_t m, int32_t n, const discord_opts* op
       launch_row_stats32(p->Tp(), p->N, n, p->N + kRowPad, p->at<double>(p->L.row_mean),
                          p->at<double>(p->L.stats), p->at<float>(p->L.mu32),
                          p->at<float>(p->L.smu32), p->at<float>(p->L.cn32), s);
+    if (mixed)
+      launch_split_blocks(p->Tp(), p->N, n, p->at<float>(p->L.mu32), p->at<float>(p->L.cn32),
+                          p->at<uint4>(p->L.sblk), s);
     launch_bucket_groups(p->at<int32_t>(p->L.csr_off), p->at<int32_t>(p->L.csr_mem), p->dict,
                          mixed ? 5 : 3,
                          p->at<int32_t>(p->L.bgrp_cnt), p->at<int32_t>(p->L.bgrp_off),
@@ -395,7 +400,9 @@ int discord_search(discord_plan p, discord_result* out) {
   const int gsz = mixed ? kMixedBlock : kRowGroup;
   const int gshift = mixed ? 5 : 3;
   const int64_t G = (N + gsz - 1) / gsz;
-  const int rb = mixed ? mfma_row_blocks(n) : 1;   // row groups per wavefront
+  // row groups per work item: one wavefront (FP32) or one workgroup (MFMA)
+  const int rb = mixed ? mfma_row_blocks(n) : 1;
+  const int64_t target_items = mixed ? 1024 : 4096;   // ~4 wavefronts per SIMD
   const bool abandon = p->opts.abandon != 0;
   const bool order = p->opts.order != 0;
   uint64_t* best = p->at<uint64_t>(p->L.best);
@@ -420,7 +427,8 @@ int discord_search(discord_plan p, discord_result* out) {
   J.done = p->at<uint32_t>(p->L.done);
   J.survivors = p->at<int32_t>(p->L.survivors);
   J.n_survivors = n_surv;
-  const MixedRows R{p->at<float>(p->L.mu32), p->at<float>(p->L.smu32), p->at<float>(p->L.cn32)};
+  const MixedRows R{p->at<float>(p->L.mu32), p->at<float>(p->L.smu32), p->at<float>(p->L.cn32),
+                    p->at<uint4>(p->L.sblk)};
   if (mixed) {
     // The split-BF16 minima carry errors of order 2^-16 |a'||b'|, with no
     // simple relative bound; raising the best-so-far by a 2^-10 margin is a
@@ -442,11 +450,11 @@ int discord_search(discord_plan p, discord_result* out) {
     LAUNCH_OK(p, what);
     return DISCORD_OK;
   };
-  // split the columns so that the launch holds at least ~4096 wavefronts
+  // split the columns so that the launch holds enough work items to fill the GPU
   auto set_chunks = [&](int64_t groups) {
-    const int64_t waves = std::max<int64_t>(1, (groups + rb - 1) / rb);
+    const int64_t items = std::max<int64_t>(1, (groups + rb - 1) / rb);
     const int64_t maxc = std::max<int64_t>(1, (N + 511) / 512);
-    int64_t c = std::min<int64_t>(maxc, std::max<int64_t>(1, (4096 + waves - 1) / waves));
+    int64_t c = std::min<int64_t>(maxc, std::max<int64_t>(1, (target_items + items - 1) / items));
     int64_t cols = ((N + c - 1) / c + 511) / 512 * 512;
     J.cols_per_chunk = cols;
     J.chunks = (N + cols - 1) / cols;

@@ -105,16 +105,26 @@ void launch_scan_fp32(const ScanJob& J, hipStream_t s);
 // ---- scan_mfma.hip ------------------------------------------------------------
 // Row statistics of the split-BF16 scan (FP32, padded with zeros to N + 64):
 // mu = fp32 row mean (the centre), smu = sqrt(n) (mean - series mean),
-// cnorm = squared norm about the centre.
+// cnorm = squared norm about the centre.  sblk is the split subsequence matrix
+// in MFMA operand layout (see mixed_block_bytes).
 struct MixedRows {
   const float* mu;
   const float* smu;
   const float* cnorm;
+  const uint4* sblk;
 };
 constexpr int kMixedBlock = 32;      // rows per MFMA row block = columns per column block
 constexpr int kMixedMaxN = 512;      // longest window of the split-BF16 scan (32 K-steps)
 bool launch_scan_mfma(const ScanJob& J, const MixedRows& R, hipStream_t s);
 int mfma_row_blocks(int n);
+// The split subsequence matrix: for every block of 32 consecutive rows, KS+1
+// K-steps of 16 operand slots per lane (64 lanes): KS steps of the centred
+// window (hi then lo, 1 KB each) and one extra step holding the norm terms as
+// an A operand and as a B operand (1 KB each).  ceil(N/32) + 1 blocks.
+size_t mixed_block_bytes(int n);
+int64_t mixed_blocks(int64_t N);
+void launch_split_blocks(const float* Tp, int64_t N, int n, const float* c32, const float* cn32,
+                         uint4* sblk, hipStream_t s);
 void launch_row_stats32(const float* Tp, int64_t N, int n, int64_t padded, const double* row_mean,
                         const double* stats, float* c32, float* smu32, float* cn32,
                         hipStream_t s);

@@ -1,23 +1,39 @@
 // scan_mfma.hip -- split-BF16 pair-distance scan on the gfx950 matrix cores.
 //
-// For rows a = T_{i,n} and columns b = T_{j,n} with means mu_a, mu_b and centred
-// vectors a' = a - mu_a, b' = b - mu_b, the squared Euclidean distance (eq. (1))
-// is exactly
-//     d^2 = |a'|^2 + |b'|^2 - 2 a'.b' + n (mu_a - mu_b)^2 .
-// The centred norms and means come from the FP64 preparation; the dot products
-// run on v_mfma_f32_32x32x16_bf16 with each centred value split as
-// x = hi + lo (hi = bf16(x), lo = bf16(x - hi)) and a'.b' ~ hi.hi + hi.lo + lo.hi,
-// accumulated in FP32.  Centring first keeps the operands small, so the split
-// products carry ~2^-16 relative error of |a'||b'|; every decision is then
-// certified in FP64 (certify.hip), so these errors never reach the result.
+// For rows a = T_{i,n} and columns b = T_{j,n} with centres c_a, c_b (the FP32
+// rounding of the window means mu_a, mu_b) the squared Euclidean distance of
+// eq. (1) is, up to a term below n ulp(mu)^2,
+//     d^2 = |a - c_a|^2 + |b - c_b|^2 - 2 (a - c_a).(b - c_b) + n (mu_a - mu_b)^2 .
+// The dot products run on v_mfma_f32_32x32x16_bf16 with each centred value
+// split as x = hi + lo (hi = bf16(x), lo = bf16(x - hi)) and
+// a'.b' ~ hi.hi + hi.lo + lo.hi, accumulated in FP32.  Centring first keeps
+// the operands small, so the split products carry ~2^-16 relative error of
+// |a'||b'|; every decision is then certified in FP64 (certify.hip), so these
+// errors never reach the result.
 //
-// Operand roles (lane layout checked on the hardware): the MFMA's B operand is a
-// block of 32 search rows (lane l <-> row l % 32, k-half l / 32) held in
-// registers for the whole sweep; the A operand is a block of 32 candidate
-// columns built per K-step straight from the series (the subsequence matrix is
-// Hankel: column j is t[j .. j+n-1]) and pre-scaled by -2.  The 32x32 result
-// then gives lane l the 16 columns 8(v/4) + 4(l/32) + v%4 of row l % 32, so the
-// row minimum is mostly a per-lane running minimum.
+// The split subsequence matrix (the paper's S of eq. (5), centred and split)
+// is built once by the preparation stage and stays resident in HBM, laid out
+// per block of 32 rows exactly as the MFMA operand registers want it: lane l
+// holds row l % 32, elements k = 16 s + 8 (l / 32) + 0..7 of K-step s.  Since
+// the A and B operands share this lane layout, the same array feeds both.  One
+// extra K-step per block carries the norms: as an A operand
+// (P_hi, P_mid, P_lo, 1, 1, 1) with P = -|b'|^2 / 2 of the column, as a B operand
+// (1, 1, 1, Q_hi, Q_mid, Q_lo) with Q = -|a'|^2 / 2 of the row (three-way bf16
+// splits hold P and Q to 2^-24).  The accumulator then ends at
+// a'.b' - (|a'|^2 + |b'|^2) / 2, so d^2 = -2 acc + (sqrt(n) (mu_a - mu_b))^2:
+// two VALU operations per pair.
+//
+// Operand roles (lane layout checked on the hardware): B = a block of 32 search
+// rows held in registers for the whole sweep; A = a block of 32 candidate
+// columns.  The 32x32 result gives lane l the 16 columns 8(v/4) + 4(l/32) + v%4
+// of row l % 32, so the row minimum is mostly a per-lane running minimum.
+//
+// Work sharing: a workgroup of 8 wavefronts (4 for windows over 256) owns one
+// row block per wavefront and sweeps a
+// column sequence together.  Each column block is copied once per workgroup
+// from HBM into LDS (double-buffered; the copy of block s+1 is issued before
+// block s is multiplied and stored after), and every wavefront reads it with
+// ds_read_b128.
 #include "internal.hpp"
 
 namespace dd {
@@ -26,8 +42,18 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
-constexpr int BM = 32;   // rows per row block (one MFMA tile side)
-constexpr int BN = 32;   // columns per column block
+constexpr int BM = 32;      // rows per row block (one MFMA tile side)
+constexpr int BN = 32;      // columns per column block
+// wavefronts per workgroup: 8 (two per SIMD, one row block each) while a row
+// block's operands fit in half the register file, else 4
+template <int KS>
+constexpr int kWaves = KS <= 16 ? 8 : 4;
+
+template <int KS>
+struct Blk {
+  static constexpr int SLOTS = (KS + 1) * 128;                 // 16-byte slots per block
+  static constexpr int PER_T = (SLOTS + kWaves<KS> * 64 - 1) / (kWaves<KS> * 64);
+};
 
 __device__ __forceinline__ void split8(const float (&x)[8], bf16x8& hi, bf16x8& lo) {
 #pragma unroll
@@ -36,6 +62,13 @@ __device__ __forceinline__ void split8(const float (&x)[8], bf16x8& hi, bf16x8& 
     hi[e] = h;
     lo[e] = (__bf16)(x[e] - (float)h);
   }
+}
+
+__device__ __forceinline__ void split3(float x, __bf16& a, __bf16& b, __bf16& c) {
+  a = (__bf16)x;
+  const float r1 = x - (float)a;
+  b = (__bf16)r1;
+  c = (__bf16)(r1 - (float)b);
 }
 
 // 8 consecutive series values t[p .. p+7] (p only 4-byte aligned)
@@ -47,14 +80,6 @@ __device__ __forceinline__ void load8(const float* __restrict__ p, float (&v)[8]
   v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
 }
 
-__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
-  for (int off = 32; off > 0; off >>= 1) {
-    const uint64_t o = __shfl_xor(v, off, 64);
-    v = o < v ? o : v;
-  }
-  return v;
-}
-
 __device__ __forceinline__ uint32_t load_relaxed(const uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -63,20 +88,71 @@ __device__ __forceinline__ uint64_t load_relaxed64(const uint64_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// One wavefront per work item: RB row blocks of 32 rows (consecutive entries of
-// the group list) against one column chunk; the column sequence is the first
-// block's word bucket (32-column blocks) when given, then the chunk in matrix
+// Preparation: one thread per (block, K-step slot, lane).
+template <int KS>
+__global__ __launch_bounds__(256) void k_split_blocks(const float* __restrict__ Tp, int64_t nblk,
+                                                      int n, const float* __restrict__ c32,
+                                                      const float* __restrict__ cn32,
+                                                      bf16x8* __restrict__ out) {
+  const int64_t t = blockIdx.x * 256ll + threadIdx.x;
+  const int64_t per_blk = (KS + 1) * 64;
+  if (t >= nblk * per_blk) return;
+  const int64_t q = t / per_blk;
+  const int r = (int)(t - q * per_blk);
+  const int s = r >> 6, l = r & 63;
+  const int64_t row = q * BM + (l & 31);
+  const int h = l >> 5;
+  bf16x8* blk = out + q * Blk<KS>::SLOTS;
+  if (s < KS) {
+    const int k0 = 16 * s + 8 * h;
+    const float c = c32[row];
+    float v[8];
+    load8(Tp + row + k0, v);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = (k0 + e < n) ? v[e] - c : 0.0f;
+    bf16x8 hi, lo;
+    split8(v, hi, lo);
+    blk[s * 128 + l] = hi;
+    blk[s * 128 + 64 + l] = lo;
+  } else {
+    const __bf16 one = (__bf16)1.0f, zero = (__bf16)0.0f;
+    bf16x8 xa, xb;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) xa[e] = xb[e] = zero;
+    if (h == 0) {
+      const float P = -0.5f * cn32[row];
+      __bf16 p0, p1, p2;
+      split3(P, p0, p1, p2);
+      xa[0] = p0; xa[1] = p1; xa[2] = p2; xa[3] = one; xa[4] = one; xa[5] = one;
+      xb[0] = one; xb[1] = one; xb[2] = one; xb[3] = p0; xb[4] = p1; xb[5] = p2;
+    }
+    blk[KS * 128 + l] = xa;        // extra step as an A (column) operand
+    blk[KS * 128 + 64 + l] = xb;   // extra step as a B (row) operand
+  }
+}
+
+// One workgroup per work item: kWaves * RB row blocks (consecutive entries of the
+// group list) against one column chunk; the column sequence is the first
+// entry's word bucket (32-column blocks) when given, then the chunk in matrix
 // order, one 32-column block per step.
 template <int KS, int RB>
-__global__ __launch_bounds__(256) void k_scan_mfma(ScanJob J, MixedRows R) {
+__global__ __launch_bounds__(kWaves<KS> * 64) void k_scan_mfma(ScanJob J, MixedRows R) {
+  constexpr int WAVES = kWaves<KS>;
+  extern __shared__ bf16x8 smem[];   // two column-block buffers of Blk<KS>::SLOTS slots
+  __shared__ uint32_t wave_live[WAVES];
+  constexpr int SLOTS = Blk<KS>::SLOTS;
+  constexpr int PER_T = Blk<KS>::PER_T;
+  const bf16x8* __restrict__ S = reinterpret_cast<const bf16x8*>(R.sblk);
+
   const int lane = threadIdx.x & 63;
-  const int h = lane >> 5;        // k-half of the operands
-  const int rl = lane & 31;       // row (B) / column (A) within the block
-  const int64_t item = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int64_t items_per_chunk = (J.n_groups + RB - 1) / RB;
-  if (item >= items_per_chunk * J.chunks) return;
-  const int64_t li = item / J.chunks;
-  const int64_t ch = item - li * J.chunks;
+  const int wv = threadIdx.x >> 6;
+  const int h = lane >> 5;
+  const int rl = lane & 31;
+  const int64_t per_item = WAVES * RB;
+  const int64_t items_per_chunk = (J.n_groups + per_item - 1) / per_item;
+  const int64_t li = blockIdx.x / J.chunks;
+  const int64_t ch = blockIdx.x - li * J.chunks;
+  if (li >= items_per_chunk) return;
   const int64_t N = J.N;
   const int n = J.n;
 
@@ -85,7 +161,7 @@ __global__ __launch_bounds__(256) void k_scan_mfma(ScanJob J, MixedRows R) {
   bool any_live = false;
 #pragma unroll
   for (int b = 0; b < RB; ++b) {
-    const int64_t e = li * RB + b;
+    const int64_t e = li * per_item + wv * RB + b;
     g[b] = -1;
     valid[b] = live[b] = 0;
     if (e < J.n_groups) {
@@ -96,44 +172,33 @@ __global__ __launch_bounds__(256) void k_scan_mfma(ScanJob J, MixedRows R) {
       const int64_t r0 = g[b] * BM;
       const int64_t rows = min<int64_t>(BM, N - r0);
       valid[b] = rows >= 32 ? 0xFFFFFFFFu : ((1u << rows) - 1u);
-      live[b] = J.abandon ? (load_relaxed(&J.alive[g[b]]) & valid[b]) : valid[b];
+      live[b] = J.abandon ? __builtin_amdgcn_readfirstlane(load_relaxed(&J.alive[g[b]]) & valid[b])
+                          : valid[b];
       any_live |= live[b] != 0;
     }
   }
-  if (!any_live) {
-    // nothing to do; still count the finished chunk for completion tracking
-    if (J.abandon && J.chunks > 1) {
-#pragma unroll
-      for (int b = 0; b < RB; ++b)
-        if (g[b] >= 0 && lane == 0) atomicAdd(&J.done[g[b]], 1u);
-    }
-    return;
-  }
 
   // ---- row operands, held for the whole sweep ---------------------------------
-  bf16x8 bh[RB][KS], bl[RB][KS];
-  float nA[RB], smr[RB];
+  bf16x8 bh[RB][KS], bl[RB][KS], bx[RB];
+  float smr[RB];
 #pragma unroll
   for (int b = 0; b < RB; ++b) {
-    const int64_t row = (g[b] >= 0 ? g[b] * BM : 0) + rl;
-    const float mu = R.mu[row];
-    nA[b] = R.cnorm[row];
-    smr[b] = R.smu[row];
+    const int64_t gb = g[b] >= 0 ? g[b] : 0;
+    const bf16x8* blk = S + gb * SLOTS;
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
-      const int k0 = 16 * s + 8 * h;
-      float v[8];
-      load8(J.Tp + row + k0, v);
-#pragma unroll
-      for (int e = 0; e < 8; ++e) v[e] = (k0 + e < n) ? v[e] - mu : 0.0f;
-      split8(v, bh[b][s], bl[b][s]);
+      bh[b][s] = blk[s * 128 + lane];
+      bl[b][s] = blk[s * 128 + 64 + lane];
     }
+    bx[b] = blk[KS * 128 + 64 + lane];
+    smr[b] = R.smu[gb * BM + rl];
   }
 
-  // ---- column sequence ---------------------------------------------------------
+  // ---- column sequence (uniform over the workgroup) ---------------------------
   int64_t nb = 0, b0 = 0;
   if (J.words && ch == 0) {
-    const int64_t gf = g[0] >= 0 ? g[0] : (RB > 1 ? g[RB - 1] : 0);
+    const int64_t e0 = li * per_item;
+    const int64_t gf = J.groups ? J.groups[e0] : e0;
     const int w = J.words[gf * BM];
     b0 = J.bgrp_off[w];
     nb = J.bgrp_off[w + 1] - b0;
@@ -149,6 +214,17 @@ __global__ __launch_bounds__(256) void k_scan_mfma(ScanJob J, MixedRows R) {
     steps = J.max_steps;
     exhausted = false;
   }
+  auto block_of = [&](int64_t s) -> int64_t {
+    return s < nb ? (int64_t)J.bgrp[b0 + s] : q0 + (s - nb);
+  };
+
+  // workgroup-wide: is any row of any wavefront still live?
+  if (lane == 0) wave_live[wv] = any_live ? 1u : 0u;
+  __syncthreads();
+  bool wg_live = false;
+#pragma unroll
+  for (int w = 0; w < WAVES; ++w) wg_live |= wave_live[w] != 0;
+  if (!wg_live) steps = 0;
 
   float rmin[RB];
   int32_t rj[RB];
@@ -158,114 +234,146 @@ __global__ __launch_bounds__(256) void k_scan_mfma(ScanJob J, MixedRows R) {
     rj[b] = -1;
   }
   uint32_t cnt = 0;
-  const float fn = (float)n;
-  (void)fn;
 
+  bf16x8 pre[PER_T];
+  auto fetch = [&](int64_t q) {
+    const bf16x8* src = S + q * SLOTS;
+#pragma unroll
+    for (int i = 0; i < PER_T; ++i) {
+      const int k = i * WAVES * 64 + (int)threadIdx.x;
+      if (k < SLOTS) pre[i] = src[k];
+    }
+  };
+  auto store = [&](bf16x8* dst) {
+#pragma unroll
+    for (int i = 0; i < PER_T; ++i) {
+      const int k = i * WAVES * 64 + (int)threadIdx.x;
+      if (k < SLOTS) dst[k] = pre[i];
+    }
+  };
+  if (steps > 0) {
+    fetch(block_of(0));
+    store(smem);
+  }
+  __syncthreads();
   for (int64_t s = 0; s < steps; ++s) {
+    const int cur = (int)(s & 1);
+    if (s + 1 < steps) fetch(block_of(s + 1));
+    const bool from_bucket = s < nb;
+    const int64_t jlim = from_bucket ? N : ce;
+    const int64_t j0 = block_of(s) * BN;
+    const bf16x8* buf = smem + cur * SLOTS;
+
     bool go = false;
 #pragma unroll
     for (int b = 0; b < RB; ++b) go |= live[b] != 0;
-    if (!go) break;
-    const bool from_bucket = s < nb;
-    const int64_t q = from_bucket ? (int64_t)J.bgrp[b0 + s] : q0 + (s - nb);
-    const int64_t jlim = from_bucket ? N : ce;
-    const int64_t j0 = q * BN;
-    const int64_t col = j0 + rl;
-    const float mu2 = 2.0f * R.mu[col];
-
-    floatx16 acc[RB];
+    if (go) {
+      floatx16 acc[RB];
+      {
+        const bf16x8 ax = buf[KS * 128 + lane];
+        floatx16 z;
 #pragma unroll
-    for (int b = 0; b < RB; ++b)
+        for (int v = 0; v < 16; ++v) z[v] = 0.0f;
 #pragma unroll
-      for (int v = 0; v < 16; ++v) acc[b][v] = 0.0f;
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-      const int k0 = 16 * ks + 8 * h;
-      float v[8];
-      load8(J.Tp + col + k0, v);
-#pragma unroll
-      for (int e = 0; e < 8; ++e) v[e] = (k0 + e < n) ? __builtin_fmaf(v[e], -2.0f, mu2) : 0.0f;
-      bf16x8 ah, al;
-      split8(v, ah, al);
-#pragma unroll
-      for (int b = 0; b < RB; ++b) {
-        acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[b][ks], acc[b], 0, 0, 0);
-        acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl[b][ks], acc[b], 0, 0, 0);
-        acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[b][ks], acc[b], 0, 0, 0);
+        for (int b = 0; b < RB; ++b)
+          acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ax, bx[b], z, 0, 0, 0);
       }
-    }
-    // ---- epilogue: squared distances of this lane's 16 columns ----------------
-    float nB[16], smc[16];
 #pragma unroll
-    for (int qd = 0; qd < 4; ++qd) {
-      const int c0 = 8 * qd + 4 * h;
-      const float4 a = *reinterpret_cast<const float4*>(R.cnorm + j0 + c0);
-      const float4 m = *reinterpret_cast<const float4*>(R.smu + j0 + c0);
-      nB[4 * qd + 0] = a.x; nB[4 * qd + 1] = a.y; nB[4 * qd + 2] = a.z; nB[4 * qd + 3] = a.w;
-      smc[4 * qd + 0] = m.x; smc[4 * qd + 1] = m.y; smc[4 * qd + 2] = m.z; smc[4 * qd + 3] = m.w;
-    }
+      for (int ks = 0; ks < KS; ++ks) {
+        const bf16x8 ah = buf[ks * 128 + lane];
+        const bf16x8 al = buf[ks * 128 + 64 + lane];
 #pragma unroll
-    for (int b = 0; b < RB; ++b) {
-      if (!live[b]) continue;
-      const int64_t r0 = g[b] * BM;
-      const int64_t i = r0 + rl;
-      // tile needs the per-element mask near the exclusion band or the end
-      const bool clean = (j0 + BN <= jlim) && ((j0 >= r0 + BM - 1 + n) || (j0 + BN - 1 + n <= r0));
-      float d[16];
-#pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const float t = smr[b] - smc[v];
-        d[v] = acc[b][v] + __builtin_fmaf(t, t, nA[b] + nB[v]);
-      }
-      if (!clean) {
-#pragma unroll
-        for (int v = 0; v < 16; ++v) {
-          const int64_t j = j0 + 8 * (v >> 2) + 4 * h + (v & 3);
-          const int64_t dij = i > j ? i - j : j - i;
-          if (!(j < jlim && dij >= n)) d[v] = __builtin_inff();
+        for (int b = 0; b < RB; ++b) {
+          acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[b][ks], acc[b], 0, 0, 0);
+          acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl[b][ks], acc[b], 0, 0, 0);
+          acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[b][ks], acc[b], 0, 0, 0);
         }
       }
-      float tmin = d[0];
+      // ---- epilogue: d^2 = -2 acc + (smu_row - smu_col)^2 for the 16 columns --
+      float smc[16];
 #pragma unroll
-      for (int v = 1; v < 16; ++v) tmin = fminf(tmin, d[v]);
-      if (__ballot(tmin < rmin[b])) {
-        if (tmin < rmin[b]) {
-          int32_t jj = -1;
-#pragma unroll
-          for (int v = 15; v >= 0; --v)
-            if (d[v] == tmin) jj = (int32_t)(j0 + 8 * (v >> 2) + 4 * h + (v & 3));
-          rmin[b] = tmin;
-          rj[b] = jj;
-        }
+      for (int qd = 0; qd < 4; ++qd) {
+        const float4 m = *reinterpret_cast<const float4*>(R.smu + j0 + 8 * qd + 4 * h);
+        smc[4 * qd + 0] = m.x; smc[4 * qd + 1] = m.y; smc[4 * qd + 2] = m.z; smc[4 * qd + 3] = m.w;
       }
-      if ((valid[b] >> rl) & 1u) {
-        if (clean) {
-          cnt += 16;
-        } else {
-#pragma unroll
-          for (int v = 0; v < 16; ++v) cnt += d[v] < __builtin_inff();
-        }
-      }
-    }
-    if (J.abandon) {
-      const float bsf = __builtin_bit_cast(float, load_relaxed(J.bsf));
 #pragma unroll
       for (int b = 0; b < RB; ++b) {
         if (!live[b]) continue;
-        const float m = fminf(rmin[b], __shfl_xor(rmin[b], 32, 64));
-        const uint32_t dead = (uint32_t)(__ballot(m < bsf && h == 0) & 0xFFFFFFFFull) & live[b];
-        if (dead) {
-          uint64_t key = rj[b] < 0 ? kEmptyMin : pack_min(rmin[b], (uint32_t)rj[b]);
-          const uint64_t o = __shfl_xor(key, 32, 64);
-          key = o < key ? o : key;
-          if (h == 0 && ((dead >> rl) & 1u))
-            atomicMin((unsigned long long*)&J.best[g[b] * BM + rl], (unsigned long long)key);
-          if (lane == 0) atomicAnd(&J.alive[g[b]], ~dead);
-          live[b] &= ~dead;
+        const int64_t r0 = g[b] * BM;
+        const int64_t i = r0 + rl;
+        // the per-element mask is needed only near the exclusion band or the end
+        const bool clean =
+            (j0 + BN <= jlim) && ((j0 >= r0 + BM - 1 + n) || (j0 + BN - 1 + n <= r0));
+        float d[16];
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const float t = smr[b] - smc[v];
+          d[v] = __builtin_fmaf(-2.0f, acc[b][v], t * t);
         }
-        if (J.chunks > 1) live[b] &= load_relaxed(&J.alive[g[b]]);
+        if (!clean) {
+#pragma unroll
+          for (int v = 0; v < 16; ++v) {
+            const int64_t j = j0 + 8 * (v >> 2) + 4 * h + (v & 3);
+            const int64_t dij = i > j ? i - j : j - i;
+            if (!(j < jlim && dij >= n)) d[v] = __builtin_inff();
+          }
+        }
+        float tmin = d[0];
+#pragma unroll
+        for (int v = 1; v < 16; ++v) tmin = fminf(tmin, d[v]);
+        if (__ballot(tmin < rmin[b])) {
+          if (tmin < rmin[b]) {
+            int32_t jj = -1;
+#pragma unroll
+            for (int v = 15; v >= 0; --v)
+              if (d[v] == tmin) jj = (int32_t)(j0 + 8 * (v >> 2) + 4 * h + (v & 3));
+            rmin[b] = tmin;
+            rj[b] = jj;
+          }
+        }
+        if ((valid[b] >> rl) & 1u) {
+          if (clean) {
+            cnt += 16;
+          } else {
+#pragma unroll
+            for (int v = 0; v < 16; ++v) cnt += d[v] < __builtin_inff();
+          }
+        }
+      }
+      if (J.abandon) {
+        const float bsf = __builtin_bit_cast(float, load_relaxed(J.bsf));
+#pragma unroll
+        for (int b = 0; b < RB; ++b) {
+          if (!live[b]) continue;
+          const float m = fminf(rmin[b], __shfl_xor(rmin[b], 32, 64));
+          const uint32_t dead =
+              (uint32_t)(__ballot(m < bsf && h == 0) & 0xFFFFFFFFull) & live[b];
+          if (dead) {
+            uint64_t key = rj[b] < 0 ? kEmptyMin : pack_min(rmin[b], (uint32_t)rj[b]);
+            const uint64_t o = __shfl_xor(key, 32, 64);
+            key = o < key ? o : key;
+            if (h == 0 && ((dead >> rl) & 1u))
+              atomicMin((unsigned long long*)&J.best[g[b] * BM + rl], (unsigned long long)key);
+            if (lane == 0) atomicAnd(&J.alive[g[b]], ~dead);
+            live[b] &= ~dead;
+          }
+          if (J.chunks > 1)
+            live[b] &= __builtin_amdgcn_readfirstlane(load_relaxed(&J.alive[g[b]]));
+        }
       }
     }
+    if (s + 1 < steps) store(smem + (cur ^ 1) * SLOTS);
+    // all wavefronts agree on leaving once no row of the workgroup is live
+    bool mine = false;
+#pragma unroll
+    for (int b = 0; b < RB; ++b) mine |= live[b] != 0;
+    if (lane == 0) wave_live[wv] = mine ? 1u : 0u;
+    __syncthreads();
+    bool any = false;
+#pragma unroll
+    for (int w = 0; w < WAVES; ++w) any |= wave_live[w] != 0;
+    if (!any) break;
+    __syncthreads();   // wave_live is rewritten next step
   }
 
   // ---- publish ------------------------------------------------------------------
@@ -296,6 +404,7 @@ __global__ __launch_bounds__(256) void k_scan_mfma(ScanJob J, MixedRows R) {
       }
       continue;
     }
+    // chunked: the last chunk of the group to finish raises the best-so-far
     __threadfence();
     uint32_t prev = 0;
     if (lane == 0) prev = atomicAdd(&J.done[g[b]], 1u);
@@ -310,34 +419,65 @@ __global__ __launch_bounds__(256) void k_scan_mfma(ScanJob J, MixedRows R) {
   }
 }
 
+template <int KS, int RB>
+void launch_kr(const ScanJob& J, const MixedRows& R, hipStream_t s) {
+  const int64_t per_item = kWaves<KS> * RB;
+  const int64_t blocks = ((J.n_groups + per_item - 1) / per_item) * J.chunks;
+  if (blocks <= 0) return;
+  const size_t lds = sizeof(bf16x8) * 2 * Blk<KS>::SLOTS;
+  static bool attr_set = false;   // the LDS opt-in is per kernel, set once per process
+  if (!attr_set && lds > 65536) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_scan_mfma<KS, RB>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    attr_set = true;
+  }
+  hipLaunchKernelGGL((k_scan_mfma<KS, RB>), dim3((unsigned)blocks), dim3(kWaves<KS> * 64), lds, s, J, R);
+}
+
 template <int KS>
-void launch_ks(const ScanJob& J, const MixedRows& R, int rb, hipStream_t s) {
-  const int64_t items = ((J.n_groups + rb - 1) / rb) * J.chunks;
-  if (items <= 0) return;
-  const int64_t blocks = (items + 3) / 4;
-  if (rb == 2 && KS <= 16)
-    hipLaunchKernelGGL((k_scan_mfma<KS, (KS <= 16 ? 2 : 1)>), dim3((unsigned)blocks), dim3(256), 0,
-                       s, J, R);
-  else
-    hipLaunchKernelGGL((k_scan_mfma<KS, 1>), dim3((unsigned)blocks), dim3(256), 0, s, J, R);
+void launch_ks(const ScanJob& J, const MixedRows& R, hipStream_t s) {
+  launch_kr<KS, 1>(J, R, s);
+}
+
+template <int KS>
+void launch_split(const float* Tp, int64_t nblk, int n, const float* c32, const float* cn32,
+                  uint4* sblk, hipStream_t s) {
+  const int64_t threads = nblk * (KS + 1) * 64;
+  hipLaunchKernelGGL(k_split_blocks<KS>, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s,
+                     Tp, nblk, n, c32, cn32, reinterpret_cast<bf16x8*>(sblk));
 }
 
 }  // namespace
 
-int mfma_row_blocks(int n) { return ((n + 15) / 16) <= 16 ? 2 : 1; }
+int mfma_row_blocks(int n) { return ((n + 15) / 16) <= 16 ? 8 : 4; }
+
+size_t mixed_block_bytes(int n) { return (size_t)(((n + 15) / 16) + 1) * 128 * 16; }
+
+int64_t mixed_blocks(int64_t N) { return (N + BM - 1) / BM + 1; }
+
+#define DD_KS_CASES(X)                                                                         \
+  X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) X(17) \
+  X(18) X(19) X(20) X(21) X(22) X(23) X(24) X(25) X(26) X(27) X(28) X(29) X(30) X(31) X(32)
 
 bool launch_scan_mfma(const ScanJob& J, const MixedRows& R, hipStream_t s) {
-  const int ks = (J.n + 15) / 16;
-  const int rb = mfma_row_blocks(J.n);
-  switch (ks) {
-#define DD_KS(K) \
-  case K: launch_ks<K>(J, R, rb, s); return true;
-    DD_KS(1) DD_KS(2) DD_KS(3) DD_KS(4) DD_KS(5) DD_KS(6) DD_KS(7) DD_KS(8)
-    DD_KS(9) DD_KS(10) DD_KS(11) DD_KS(12) DD_KS(13) DD_KS(14) DD_KS(15) DD_KS(16)
-    DD_KS(17) DD_KS(18) DD_KS(19) DD_KS(20) DD_KS(21) DD_KS(22) DD_KS(23) DD_KS(24)
-    DD_KS(25) DD_KS(26) DD_KS(27) DD_KS(28) DD_KS(29) DD_KS(30) DD_KS(31) DD_KS(32)
-#undef DD_KS
+  switch ((J.n + 15) / 16) {
+#define DD_CASE(K) \
+  case K: launch_ks<K>(J, R, s); return true;
+    DD_KS_CASES(DD_CASE)
+#undef DD_CASE
     default: return false;
+  }
+}
+
+void launch_split_blocks(const float* Tp, int64_t N, int n, const float* c32, const float* cn32,
+                         uint4* sblk, hipStream_t s) {
+  const int64_t nblk = mixed_blocks(N);
+  switch ((n + 15) / 16) {
+#define DD_CASE(K) \
+  case K: launch_split<K>(Tp, nblk, n, c32, cn32, sblk, s); return;
+    DD_KS_CASES(DD_CASE)
+#undef DD_CASE
+    default: return;
   }
 }
 
