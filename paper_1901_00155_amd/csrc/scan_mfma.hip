@@ -19,18 +19,19 @@
 // extra K-step per block carries the norms: as an A operand
 // (P_hi, P_mid, P_lo, 1, 1, 1) with P = -|b'|^2 / 2 of the column, as a B operand
 // (1, 1, 1, Q_hi, Q_mid, Q_lo) with Q = -|a'|^2 / 2 of the row (three-way bf16
-// splits hold P and Q to 2^-24).  The accumulator then ends at
-// a'.b' - (|a'|^2 + |b'|^2) / 2, so d^2 = -2 acc + (sqrt(n) (mu_a - mu_b))^2:
-// two VALU operations per pair.
+// splits hold P and Q to 2^-24).  The row operands are scaled by -2 once when
+// they are loaded (exact in bf16), so the accumulator ends at
+// |a'|^2 + |b'|^2 - 2 a'.b' and d^2 = acc + (sqrt(n) (mu_a - mu_b))^2: two
+// VALU operations per pair.
 //
 // Operand roles (lane layout checked on the hardware): B = a block of 32 search
 // rows held in registers for the whole sweep; A = a block of 32 candidate
 // columns.  The 32x32 result gives lane l the 16 columns 8(v/4) + 4(l/32) + v%4
 // of row l % 32, so the row minimum is mostly a per-lane running minimum.
 //
-// Work sharing: a workgroup of 8 wavefronts (4 for windows over 256) owns one
-// row block per wavefront and sweeps a
-// column sequence together.  Each column block is copied once per workgroup
+// Work sharing: a workgroup of 8 wavefronts (two per SIMD; 4 for windows over
+// 256) owns one row block per wavefront (two for windows up to 128) and sweeps
+// a column sequence together.  Each column block is copied once per workgroup
 // from HBM into LDS (double-buffered; the copy of block s+1 is issued before
 // block s is multiplied and stored after), and every wavefront reads it with
 // ds_read_b128.
@@ -48,6 +49,10 @@ constexpr int BN = 32;      // columns per column block
 // block's operands fit in half the register file, else 4
 template <int KS>
 constexpr int kWaves = KS <= 16 ? 8 : 4;
+// row blocks per wavefront: two while both fit in the registers of a
+// two-waves-per-SIMD kernel (windows up to 128), else one
+template <int KS>
+constexpr int kRowBlocks = KS <= 8 ? 2 : 1;
 
 template <int KS>
 struct Blk {
@@ -136,10 +141,11 @@ __global__ __launch_bounds__(256) void k_split_blocks(const float* __restrict__ 
 // entry's word bucket (32-column blocks) when given, then the chunk in matrix
 // order, one 32-column block per step.
 template <int KS, int RB>
-__global__ __launch_bounds__(kWaves<KS> * 64) void k_scan_mfma(ScanJob J, MixedRows R) {
+__global__ __launch_bounds__(kWaves<KS> * 64, (KS <= 16 ? 2 : 1)) void k_scan_mfma(ScanJob J,
+                                                                                  MixedRows R) {
   constexpr int WAVES = kWaves<KS>;
   extern __shared__ bf16x8 smem[];   // two column-block buffers of Blk<KS>::SLOTS slots
-  __shared__ uint32_t wave_live[WAVES];
+  __shared__ uint32_t wave_live[2 * WAVES];
   constexpr int SLOTS = Blk<KS>::SLOTS;
   constexpr int PER_T = Blk<KS>::PER_T;
   const bf16x8* __restrict__ S = reinterpret_cast<const bf16x8*>(R.sblk);
@@ -179,18 +185,21 @@ __global__ __launch_bounds__(kWaves<KS> * 64) void k_scan_mfma(ScanJob J, MixedR
   }
 
   // ---- row operands, held for the whole sweep ---------------------------------
+  // Scaled by -2 (exact in bf16), so the accumulator ends at
+  // -2 a'.b' + |a'|^2 + |b'|^2 = d^2 - n (mu_a - mu_b)^2.
   bf16x8 bh[RB][KS], bl[RB][KS], bx[RB];
   float smr[RB];
+  const __bf16 m2 = (__bf16)(-2.0f);
 #pragma unroll
   for (int b = 0; b < RB; ++b) {
     const int64_t gb = g[b] >= 0 ? g[b] : 0;
     const bf16x8* blk = S + gb * SLOTS;
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
-      bh[b][s] = blk[s * 128 + lane];
-      bl[b][s] = blk[s * 128 + 64 + lane];
+      bh[b][s] = blk[s * 128 + lane] * m2;
+      bl[b][s] = blk[s * 128 + 64 + lane] * m2;
     }
-    bx[b] = blk[KS * 128 + 64 + lane];
+    bx[b] = blk[KS * 128 + 64 + lane] * m2;
     smr[b] = R.smu[gb * BM + rl];
   }
 
@@ -215,7 +224,7 @@ __global__ __launch_bounds__(kWaves<KS> * 64) void k_scan_mfma(ScanJob J, MixedR
     exhausted = false;
   }
   auto block_of = [&](int64_t s) -> int64_t {
-    return s < nb ? (int64_t)J.bgrp[b0 + s] : q0 + (s - nb);
+    return s < nb ? (int64_t)__builtin_amdgcn_readfirstlane(J.bgrp[b0 + s]) : q0 + (s - nb);
   };
 
   // workgroup-wide: is any row of any wavefront still live?
@@ -268,6 +277,8 @@ __global__ __launch_bounds__(kWaves<KS> * 64) void k_scan_mfma(ScanJob J, MixedR
 #pragma unroll
     for (int b = 0; b < RB; ++b) go |= live[b] != 0;
     if (go) {
+      // one accumulation chain per row block (a second, interleaved chain
+      // measured no faster: dependent MFMAs issue back to back)
       floatx16 acc[RB];
       {
         const bf16x8 ax = buf[KS * 128 + lane];
@@ -289,7 +300,7 @@ __global__ __launch_bounds__(kWaves<KS> * 64) void k_scan_mfma(ScanJob J, MixedR
           acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[b][ks], acc[b], 0, 0, 0);
         }
       }
-      // ---- epilogue: d^2 = -2 acc + (smu_row - smu_col)^2 for the 16 columns --
+      // ---- epilogue: d^2 = acc + (smu_row - smu_col)^2 for the 16 columns -----
       float smc[16];
 #pragma unroll
       for (int qd = 0; qd < 4; ++qd) {
@@ -308,7 +319,7 @@ __global__ __launch_bounds__(kWaves<KS> * 64) void k_scan_mfma(ScanJob J, MixedR
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
           const float t = smr[b] - smc[v];
-          d[v] = __builtin_fmaf(-2.0f, acc[b][v], t * t);
+          d[v] = __builtin_fmaf(t, t, acc[b][v]);
         }
         if (!clean) {
 #pragma unroll
@@ -367,13 +378,15 @@ __global__ __launch_bounds__(kWaves<KS> * 64) void k_scan_mfma(ScanJob J, MixedR
     bool mine = false;
 #pragma unroll
     for (int b = 0; b < RB; ++b) mine |= live[b] != 0;
-    if (lane == 0) wave_live[wv] = mine ? 1u : 0u;
+    // (flags alternate between two rows, so one barrier per step suffices: a
+    // wavefront rewrites a row only after every wavefront has read it)
+    uint32_t* flags = wave_live + ((s + 1) & 1) * WAVES;
+    if (lane == 0) flags[wv] = mine ? 1u : 0u;
     __syncthreads();
     bool any = false;
 #pragma unroll
-    for (int w = 0; w < WAVES; ++w) any |= wave_live[w] != 0;
+    for (int w = 0; w < WAVES; ++w) any |= flags[w] != 0;
     if (!any) break;
-    __syncthreads();   // wave_live is rewritten next step
   }
 
   // ---- publish ------------------------------------------------------------------
@@ -431,12 +444,13 @@ void launch_kr(const ScanJob& J, const MixedRows& R, hipStream_t s) {
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     attr_set = true;
   }
-  hipLaunchKernelGGL((k_scan_mfma<KS, RB>), dim3((unsigned)blocks), dim3(kWaves<KS> * 64), lds, s, J, R);
+  hipLaunchKernelGGL((k_scan_mfma<KS, RB>), dim3((unsigned)blocks), dim3(kWaves<KS> * 64), lds, s,
+                     J, R);
 }
 
 template <int KS>
 void launch_ks(const ScanJob& J, const MixedRows& R, hipStream_t s) {
-  launch_kr<KS, 1>(J, R, s);
+  launch_kr<KS, kRowBlocks<KS>>(J, R, s);
 }
 
 template <int KS>
@@ -449,7 +463,10 @@ void launch_split(const float* Tp, int64_t nblk, int n, const float* c32, const 
 
 }  // namespace
 
-int mfma_row_blocks(int n) { return ((n + 15) / 16) <= 16 ? 8 : 4; }
+int mfma_row_blocks(int n) {
+  const int ks = (n + 15) / 16;
+  return (ks <= 16 ? 8 : 4) * (ks <= 8 ? 2 : 1);
+}
 
 size_t mixed_block_bytes(int n) { return (size_t)(((n + 15) / 16) + 1) * 128 * 16; }
 
