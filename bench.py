@@ -3,20 +3,23 @@
 
 One step = one complete exact discord search through the C ABI on a series
 already resident in HBM: discord_prepare (eq. (2) statistics, PAA/SAX words,
-Cand, Index_Word) + discord_search (the two-phase pair-distance scan with early
-abandon, row minima, device argmax, FP64 certification).  The workload is the
-m = 2^20 random walk with four planted anomalies and window n = 128.
+Cand, Index_Word, row statistics) + discord_search (the two-phase pair-distance
+scan with early abandon, row minima, device argmax, FP64 certification).  The
+workload is the m = 2^20 random walk with four planted anomalies and window
+n = 128, searched with the plain FP32 scan and exact early abandon.
 
 Printed: one JSON line.  `value` is pair distances computed per second of step
-time (the scan's own count of evaluated non-self pairs).  Extra fields give the
-time to discord, the brute-force-equivalent rate P(N, n) / time, full-scan
-rates of each precision, the roofline of the dominant kernel (the pair scan;
-kernel time from HIP events on the plan's stream) and the FP64 CPU oracle timed
-on a bounded sample of the same workload on the host cores.
+time (the scan's own count of evaluated non-self pairs).  Beside it: the time
+to discord, the brute-force-equivalent rate P(N, n) / time, the split-BF16
+MFMA search of the same input (`mixed`), full-scan rates of both precisions,
+the roofline of each scan kernel (kernel time from HIP events on the plan's
+stream) and the FP64 CPU oracle timed on a bounded sample of the same workload
+on the host cores.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -30,7 +33,17 @@ sys.path.insert(0, ROOT)
 # MI355X published peaks
 PEAK_FP32_VECTOR_TFLOPS = 157.3
 PEAK_BF16_MFMA_TFLOPS = 2500.0
-PEAK_HBM_GBS = 8000.0
+
+# The paper's own numbers (Xeon Phi 7290 KNL, 288 threads, real SCD series):
+# context only, another machine and another dataset.
+PAPER_CONTEXT = {
+    "phidd_knl7290_288thr_scd1m_n128_s": 10.4,
+    "phidd_knl7290_288thr_scd10m_n128_s": 81.9,
+    "phidd_knl7290_10thr_scd1m_n128_s": 109.2,
+    "hotsax_corei5_scd1m_n128_s": 147600.0,
+}
+
+SCAN_SOURCES = {"fp32": "scan_fp32.hip", "bf16x3": "scan_mfma.hip"}
 
 
 def pair_count(N: int, n: int) -> int:
@@ -38,14 +51,30 @@ def pair_count(N: int, n: int) -> int:
 
 
 def scan_flops_per_pair(n: int, precision: str) -> float:
-    # direct form: per term one subtract, one multiply, one add
-    if precision == "fp32":
-        return 3.0 * n
-    # split-BF16: three n-long dot products of 2 flops per term
-    return 6.0 * n
+    # FP32 direct form: per term one subtract, one multiply, one add.
+    # split-BF16: three n-long bf16 dot products, 2 flop per term each.
+    return 3.0 * n if precision == "fp32" else 6.0 * n
 
 
-def time_steps(dd, Td, n, precision, abandon, steps, warmup, ws_holder):
+def source_sha(precision: str) -> str:
+    p = os.path.join(ROOT, "paper_1901_00155_amd", "csrc", SCAN_SOURCES[precision])
+    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+
+
+def traffic_for(precision: str, workload: str, mode: str):
+    """HBM bytes per scan launch from the committed rocprofv3 PMC summary, if it
+    was taken on the current kernel source; else None."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        rec = json.load(open(p))[f"{precision}/{workload}/{mode}"]
+    except (OSError, KeyError, ValueError):
+        return None
+    if rec.get("source_sha") != source_sha(precision):
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def time_steps(dd, Td, n, precision, abandon, steps, warmup):
     import torch
     results = []
     stream = torch.cuda.current_stream()
@@ -61,6 +90,16 @@ def time_steps(dd, Td, n, precision, abandon, steps, warmup, ws_holder):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     return (t1 - t0) / max(steps, 1), results
+
+
+def roofline(n, precision, pairs, scan_ms, traffic):
+    flops = scan_flops_per_pair(n, precision) * pairs
+    achieved = flops / (scan_ms * 1e-3) / 1e12
+    peak = PEAK_FP32_VECTOR_TFLOPS if precision == "fp32" else PEAK_BF16_MFMA_TFLOPS
+    return {"bound": "alu" if precision == "fp32" else "mfma", "achieved": achieved,
+            "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
+            "kernel": "k_scan_fp32" if precision == "fp32" else "k_scan_mfma",
+            "flops_per_pair": scan_flops_per_pair(n, precision), "scan_ms": scan_ms}
 
 
 def cpu_baseline(series, n, budget_s=15.0):
@@ -117,20 +156,17 @@ def main():
     P = pair_count(N, n)
     Td = torch.from_numpy(w.series).cuda()
     abandon = not args.no_abandon
+    mode = "abandon" if abandon else "full"
 
     print(f"# workload {w.name}: m={m} n={n} N={N} P={P:.4e}", file=sys.stderr, flush=True)
-    sec, res = time_steps(dd, Td, n, args.precision, abandon, args.steps, args.warmup, None)
+    sec, res = time_steps(dd, Td, n, args.precision, abandon, args.steps, args.warmup)
     r = res[-1]
-    idx = {int(x.index) for x in res}
-    assert len(idx) == 1, "steps disagree"
+    assert len({int(x.index) for x in res}) == 1, "steps disagree"
     pairs = float(np.mean([x.pairs_evaluated for x in res]))
     scan_ms = float(np.mean([x.ms_scan for x in res]))
-    print(f"# step {sec * 1e3:.2f} ms, scan {scan_ms:.2f} ms, index {r.index} "
+    print(f"# {args.precision} step {sec * 1e3:.2f} ms, scan {scan_ms:.2f} ms, index {r.index} "
           f"d={r.distance:.6f}", file=sys.stderr, flush=True)
 
-    flops = scan_flops_per_pair(n, args.precision) * pairs
-    achieved_tflops = flops / (scan_ms * 1e-3) / 1e12
-    peak = PEAK_FP32_VECTOR_TFLOPS if args.precision == "fp32" else PEAK_BF16_MFMA_TFLOPS
     out = {
         "metric": "subseq-pair distances/s",
         "value": pairs / sec,
@@ -151,24 +187,39 @@ def main():
         "brute_force_equiv_pairs_per_s": P / sec,
         "pairs_evaluated": pairs,
         "discord": {"index": int(r.index), "nn_index": int(r.nn_index),
-                    "distance": float(r.distance), "certified": int(r.certified),
-                    "rows_rescored": int(r.rows_rescored), "max_rel_err": float(r.max_rel_err)},
-        "roofline": {"bound": "alu" if args.precision == "fp32" else "mfma",
-                     "achieved": achieved_tflops, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved_tflops / peak, "traffic": None,
-                     "kernel": "scan (pair-distance tiles)",
-                     "flops_per_pair": scan_flops_per_pair(n, args.precision),
-                     "scan_ms_per_launch": scan_ms},
+                    "distance": float(r.distance), "d2": float(r.d2),
+                    "certified": int(r.certified), "rows_rescored": int(r.rows_rescored),
+                    "rows_abandoned": int(r.rows_abandoned),
+                    "max_rel_err_of_approx_nn": float(r.max_rel_err)},
+        "roofline": roofline(n, args.precision, pairs, scan_ms,
+                             traffic_for(args.precision, w.name, mode)),
+        "paper_context": PAPER_CONTEXT,
     }
     if not args.no_extras:
-        extras = {}
-        for prec in ("fp32",):
-            s2, rr = time_steps(dd, Td, n, prec, False, 1, 0, None)
-            x = rr[-1]
-            extras[prec] = {"full_scan_pairs_per_s": P / (x.ms_scan * 1e-3),
-                            "step_ms": s2 * 1e3, "scan_ms": x.ms_scan, "index": int(x.index)}
-            print(f"# full scan {prec}: {x.ms_scan:.1f} ms", file=sys.stderr, flush=True)
-        out["full_scan"] = extras
+        other = "bf16x3" if args.precision == "fp32" else "fp32"
+        s2, rr = time_steps(dd, Td, n, other, abandon, args.steps, args.warmup)
+        x = rr[-1]
+        assert int(x.index) == int(r.index) and x.d2 == r.d2, "precisions disagree"
+        p2 = float(np.mean([y.pairs_evaluated for y in rr]))
+        sm2 = float(np.mean([y.ms_scan for y in rr]))
+        out["mixed" if other == "bf16x3" else "plain_fp32"] = {
+            "precision": other, "time_to_discord_ms": s2 * 1e3, "pairs_per_s": p2 / s2,
+            "brute_force_equiv_pairs_per_s": P / s2, "speedup_vs_step": sec / s2,
+            "max_rel_err_of_approx_nn": float(x.max_rel_err),
+            "roofline": roofline(n, other, p2, sm2, traffic_for(other, w.name, mode))}
+        print(f"# {other} step {s2 * 1e3:.2f} ms", file=sys.stderr, flush=True)
+        full = {}
+        for prec in ("fp32", "bf16x3"):
+            _, rf = time_steps(dd, Td, n, prec, False, 1, 0)
+            y = rf[-1]
+            assert int(y.index) == int(r.index)
+            full[prec] = {"pairs_per_s": y.pairs_evaluated / (y.ms_scan * 1e-3),
+                          "scan_ms": y.ms_scan,
+                          "roofline_frac": roofline(n, prec, y.pairs_evaluated, y.ms_scan,
+                                                    None)["frac"]}
+            print(f"# full scan {prec}: {y.ms_scan:.1f} ms", file=sys.stderr, flush=True)
+        full["bf16x3_speedup_vs_fp32"] = full["fp32"]["scan_ms"] / full["bf16x3"]["scan_ms"]
+        out["full_scan"] = full
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w.series, n, args.cpu_budget)
     print(json.dumps(out), flush=True)
