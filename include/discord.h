@@ -52,6 +52,9 @@ typedef enum {
     DISCORD_PREC_BF16X3 = 1   /* centred split-BF16 hi/lo products on MFMA, FP32 accumulate */
 } discord_precision;
 
+/* Largest window the split-BF16 MFMA scan takes (ERANGE beyond it). */
+#define DISCORD_MIXED_MAX_N 512
+
 typedef struct {
     int32_t precision;  /* discord_precision                                         */
     int32_t abandon;    /* 1: leave a row once a distance below the best-so-far appears
@@ -163,6 +166,113 @@ int discord_plan_copy(discord_plan plan, int32_t field, void* host_dst, size_t b
  * rows / outputs are host pointers of `count` elements. */
 int discord_rows_nn_fp64(discord_plan plan, const int64_t* rows, int64_t count,
                          double* d2_out, int64_t* j_out);
+
+/* ---- serving ---------------------------------------------------------------
+ * The paper has no serving layer; this is a request loop around the same
+ * prepare + search path.  Requests (T, m, n) of uneven size are queued in
+ * arrival order and admitted, strictly first-in first-out, as soon as a slot is
+ * free and their device footprint (discord_workspace_bytes, rounded up to 256 B)
+ * fits in the free part of one device arena of `hbm_budget_bytes` allocated at
+ * creation.  Each slot is a host worker thread with its own HIP stream (default
+ * priority), so the kernels of all admitted requests run concurrently on the
+ * device; a request's prepared structures stay resident in its arena block from
+ * prepare to the end of its search, and the block returns to the arena when the
+ * request completes.  A request's result depends only on its own series: the
+ * requests share no device state besides the arena, whose blocks are disjoint.
+ * A failing request completes with its status and never disturbs the others.
+ * All server functions are thread-safe. */
+typedef struct discord_server_s* discord_server;
+
+typedef struct {
+    size_t       hbm_budget_bytes; /* size of the device arena                         */
+    int32_t      slots;            /* requests in flight at once, 1..64                */
+    int32_t      max_queued;       /* waiting requests beyond which submit returns
+                                      EBUSY (0: 65536)                                */
+    discord_opts opts;             /* options of every request                         */
+} discord_server_config;
+
+/* One request as an executor sees it. */
+typedef struct {
+    uint64_t     tag;        /* caller's tag from discord_server_submit               */
+    const float* T;          /* host copy of the series (m values), valid for the call */
+    int64_t      m;
+    int32_t      n;
+    int32_t      slot;       /* worker slot running the request, 0..slots-1           */
+    void*        workspace;  /* device block of ws_bytes inside the arena (NULL when the
+                                server was created with an executor: virtual arena) */
+    size_t       ws_offset;  /* offset of the block in the arena                       */
+    size_t       ws_bytes;   /* the request's footprint                                */
+} discord_request;
+
+/* An executor runs one admitted request on the calling worker thread and fills
+ * `out`; it returns a status and may write a message of at most `detail_len`
+ * bytes (NUL-terminated) to `detail`. */
+typedef int (*discord_executor_fn)(void* ctx, const discord_request* req,
+                                   const discord_opts* opts, discord_result* out,
+                                   char* detail, size_t detail_len);
+
+typedef struct {
+    uint64_t tag;
+    int32_t  status;        /* DISCORD_OK or the request's error                      */
+    int32_t  slot;
+    size_t   ws_offset;     /* arena block the request held                           */
+    size_t   ws_bytes;
+    double   t_submit_ms;   /* server clock (steady, ms since creation)               */
+    double   t_admit_ms;    /* slot and arena block granted                            */
+    double   t_done_ms;     /* result on the host                                      */
+    discord_result result;  /* valid when status == DISCORD_OK                         */
+    char     detail[96];    /* error text ("" on success)                              */
+} discord_completion;
+
+typedef struct {
+    uint64_t submitted;     /* accepted by submit                                      */
+    uint64_t rejected;      /* refused by submit (EINVAL, ENOMEM, EBUSY)               */
+    uint64_t completed;     /* completions produced, successful or not                 */
+    uint64_t failed;        /* completions with a negative status                      */
+    int32_t  queued;        /* waiting for admission now                               */
+    int32_t  running;       /* admitted and not yet complete now                       */
+    int32_t  peak_running;
+    int32_t  slots;
+    size_t   budget_bytes;
+    size_t   bytes_in_use;
+    size_t   peak_bytes_in_use;
+    double   busy_ms;       /* sum over completed requests of (done - admit): divided
+                               by elapsed_ms it is the mean admitted concurrency      */
+    double   elapsed_ms;    /* server clock now                                        */
+} discord_server_stats;
+
+/* Server on the current device: allocates the arena (ENOMEM if it cannot) and
+ * starts cfg->slots workers, each running prepare + search of its requests on
+ * its own stream with a pinned host staging buffer. */
+int discord_server_create(const discord_server_config* cfg, discord_server* out);
+
+/* The same scheduler with a caller-supplied executor instead of the GPU path
+ * (for cost models and host tests): no device memory is allocated and blocks
+ * are offsets in a virtual arena of hbm_budget_bytes. */
+int discord_server_create_with_executor(const discord_server_config* cfg,
+                                        discord_executor_fn exec, void* ctx,
+                                        discord_server* out);
+
+/* Queues a request; T is a host pointer of m float32 values, copied before the
+ * call returns.  Returns DISCORD_OK, EINVAL (NULL T, n < 1, m < 2n, m beyond
+ * the length limit), ERANGE (split-BF16 with n > DISCORD_MIXED_MAX_N), ENOMEM
+ * (footprint larger than the whole arena: it could never run, or no host memory
+ * for the copy) or EBUSY (queue full).  Errors found later (NaN/Inf in T, a
+ * constant series, a device error) arrive as the request's completion status. */
+int discord_server_submit(discord_server s, const float* T, int64_t m, int32_t n,
+                          uint64_t tag);
+
+/* Moves up to `max` completions, oldest first, into `out`; waits up to
+ * timeout_ms (0: no wait, at most 60000) for the first one.  *count receives the
+ * number written. */
+int discord_server_poll(discord_server s, discord_completion* out, int32_t max,
+                        int32_t timeout_ms, int32_t* count);
+
+int discord_server_get_stats(discord_server s, discord_server_stats* out);
+
+/* Stops admitting, waits for the running requests, drops the queued ones and
+ * frees everything.  NULL is ignored. */
+void discord_server_destroy(discord_server s);
 
 #ifdef __cplusplus
 }

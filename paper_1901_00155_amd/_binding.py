@@ -15,7 +15,8 @@ import numpy as np
 __all__ = [
     "load", "DiscordError", "Opts", "Result", "Plan", "search", "default_opts",
     "workspace_bytes", "strerror", "sax_breakpoints", "search_series",
-    "FIELD", "PREC_FP32", "PREC_BF16X3", "LIB_PATH", "EXPORTED",
+    "FIELD", "PREC_FP32", "PREC_BF16X3", "LIB_PATH", "EXPORTED", "Server", "ServerConfig",
+    "Request", "Completion", "ServerStats", "EXECUTOR_FN",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -37,6 +38,8 @@ EXPORTED = [
     "discord_default_opts", "discord_workspace_bytes", "discord_prepare", "discord_search",
     "discord_release", "discord_strerror", "discord_plan_error", "discord_sax_breakpoints",
     "discord_search_series", "discord_plan_count", "discord_plan_copy", "discord_rows_nn_fp64",
+    "discord_server_create", "discord_server_create_with_executor", "discord_server_submit",
+    "discord_server_poll", "discord_server_get_stats", "discord_server_destroy",
 ]
 
 
@@ -67,6 +70,50 @@ class Result(ctypes.Structure):
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
 
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("slots", ctypes.c_int32),
+                ("max_queued", ctypes.c_int32), ("opts", Opts)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_uint64), ("T", ctypes.POINTER(ctypes.c_float)),
+                ("m", ctypes.c_int64), ("n", ctypes.c_int32), ("slot", ctypes.c_int32),
+                ("workspace", ctypes.c_void_p), ("ws_offset", ctypes.c_size_t),
+                ("ws_bytes", ctypes.c_size_t)]
+
+
+class Completion(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_uint64), ("status", ctypes.c_int32), ("slot", ctypes.c_int32),
+                ("ws_offset", ctypes.c_size_t), ("ws_bytes", ctypes.c_size_t),
+                ("t_submit_ms", ctypes.c_double), ("t_admit_ms", ctypes.c_double),
+                ("t_done_ms", ctypes.c_double), ("result", Result),
+                ("detail", ctypes.c_char * 96)]
+
+    def as_dict(self) -> dict:
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("result", "detail")}
+        d["detail"] = self.detail.decode(errors="replace")
+        d["result"] = self.result.as_dict()
+        return d
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("rejected", ctypes.c_uint64),
+                ("completed", ctypes.c_uint64), ("failed", ctypes.c_uint64),
+                ("queued", ctypes.c_int32), ("running", ctypes.c_int32),
+                ("peak_running", ctypes.c_int32), ("slots", ctypes.c_int32),
+                ("budget_bytes", ctypes.c_size_t), ("bytes_in_use", ctypes.c_size_t),
+                ("peak_bytes_in_use", ctypes.c_size_t), ("busy_ms", ctypes.c_double),
+                ("elapsed_ms", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+# int (*)(void* ctx, const discord_request*, const discord_opts*, discord_result*, char*, size_t)
+EXECUTOR_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(Request),
+                               ctypes.POINTER(Opts), ctypes.POINTER(Result), ctypes.c_void_p,
+                               ctypes.c_size_t)
 
 _lib = None
 
@@ -107,6 +154,20 @@ def load():
     lib.discord_plan_copy.restype = ctypes.c_int
     lib.discord_rows_nn_fp64.argtypes = [vp, vp, i64, vp, vp]
     lib.discord_rows_nn_fp64.restype = ctypes.c_int
+    lib.discord_server_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]
+    lib.discord_server_create.restype = ctypes.c_int
+    lib.discord_server_create_with_executor.argtypes = [ctypes.POINTER(ServerConfig), EXECUTOR_FN,
+                                                        vp, ctypes.POINTER(vp)]
+    lib.discord_server_create_with_executor.restype = ctypes.c_int
+    lib.discord_server_submit.argtypes = [vp, vp, i64, i32, ctypes.c_uint64]
+    lib.discord_server_submit.restype = ctypes.c_int
+    lib.discord_server_poll.argtypes = [vp, ctypes.POINTER(Completion), i32, i32,
+                                        ctypes.POINTER(i32)]
+    lib.discord_server_poll.restype = ctypes.c_int
+    lib.discord_server_get_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
+    lib.discord_server_get_stats.restype = ctypes.c_int
+    lib.discord_server_destroy.argtypes = [vp]
+    lib.discord_server_destroy.restype = None
     _lib = lib
     return lib
 
@@ -253,3 +314,73 @@ def search_series(T, n: int):
     _check(load().discord_search_series(ctypes.c_void_p(ptr), m, n, ctypes.byref(idx),
                                         ctypes.byref(dist)))
     return int(idx.value), float(dist.value)
+
+
+class Server:
+    """The serving loop (discord_server_*): FIFO admission by slot and HBM
+    footprint, one worker stream per slot, completions polled by the caller.
+
+    `executor`: None for the GPU path; else a Python callable
+    ``executor(request: Request, opts: Opts, result: Result) -> int`` run on a
+    worker thread with a virtual arena (for cost models and host tests)."""
+
+    def __init__(self, budget_bytes: int, slots: int = 4, max_queued: int = 0,
+                 executor=None, **opts):
+        lib = load()
+        self.cfg = ServerConfig(int(budget_bytes), int(slots), int(max_queued),
+                                default_opts(**opts))
+        h = ctypes.c_void_p()
+        if executor is None:
+            self._fn = None
+            st = lib.discord_server_create(ctypes.byref(self.cfg), ctypes.byref(h))
+        else:
+            def trampoline(ctx, req, o, res, detail, detail_len):
+                try:
+                    return int(executor(req.contents, o.contents, res.contents))
+                except Exception as e:  # an executor error becomes the request's status
+                    msg = f"{type(e).__name__}: {e}".encode()[:max(int(detail_len) - 1, 0)]
+                    if detail and detail_len:
+                        ctypes.memmove(detail, msg + b"\0", len(msg) + 1)
+                    return -4
+            self._fn = EXECUTOR_FN(trampoline)
+            st = lib.discord_server_create_with_executor(ctypes.byref(self.cfg), self._fn, None,
+                                                         ctypes.byref(h))
+        _check(st)
+        self._h = h
+
+    def submit(self, T, n: int, tag: int) -> int:
+        """Queue a request (host float32 series); returns the status (0 = queued)."""
+        a = np.ascontiguousarray(T, dtype=np.float32)
+        if a.ndim != 1:
+            raise ValueError("series must be one-dimensional")
+        return int(load().discord_server_submit(self._h, ctypes.c_void_p(a.ctypes.data), a.size,
+                                                int(n), int(tag)))
+
+    def poll(self, max_count: int = 64, timeout_ms: int = 0) -> list:
+        buf = (Completion * max_count)()
+        cnt = ctypes.c_int32()
+        _check(load().discord_server_poll(self._h, buf, max_count, int(timeout_ms),
+                                          ctypes.byref(cnt)))
+        return [buf[i].as_dict() for i in range(cnt.value)]
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        _check(load().discord_server_get_stats(self._h, ctypes.byref(s)))
+        return s.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().discord_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include "../../include/discord.h"
 
 #include <cstddef>
 #include <cstdint>
@@ -114,7 +115,7 @@ struct MixedRows {
   const uint4* sblk;
 };
 constexpr int kMixedBlock = 32;      // rows per MFMA row block = columns per column block
-constexpr int kMixedMaxN = 512;      // longest window of the split-BF16 scan (32 K-steps)
+constexpr int kMixedMaxN = DISCORD_MIXED_MAX_N;  // longest window of the split-BF16 scan (32 K-steps)
 bool launch_scan_mfma(const ScanJob& J, const MixedRows& R, hipStream_t s);
 int mfma_row_blocks(int n);
 // The split subsequence matrix: for every block of 32 consecutive rows, KS+1

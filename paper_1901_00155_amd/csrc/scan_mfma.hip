@@ -438,12 +438,16 @@ void launch_kr(const ScanJob& J, const MixedRows& R, hipStream_t s) {
   const int64_t blocks = ((J.n_groups + per_item - 1) / per_item) * J.chunks;
   if (blocks <= 0) return;
   const size_t lds = sizeof(bf16x8) * 2 * Blk<KS>::SLOTS;
-  static bool attr_set = false;   // the LDS opt-in is per kernel, set once per process
-  if (!attr_set && lds > 65536) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_scan_mfma<KS, RB>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    attr_set = true;
-  }
+  // the LDS opt-in is per kernel and set once per process; the initialisation of a
+  // function-local static is thread-safe, so concurrent first launches from several
+  // host threads (one per serving slot) do not race
+  static const bool attr_set = [lds] {
+    if (lds > 65536)
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_scan_mfma<KS, RB>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    return true;
+  }();
+  (void)attr_set;
   hipLaunchKernelGGL((k_scan_mfma<KS, RB>), dim3((unsigned)blocks), dim3(kWaves<KS> * 64), lds, s,
                      J, R);
 }

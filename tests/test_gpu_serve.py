@@ -1,0 +1,107 @@
+"""GPU tests of the serving loop: every request's result is the same when it runs
+alone (one plan, one stream) and when it runs in the mix with others overlapping
+on the device, and equals the FP64 oracle where the oracle is quick; failing
+requests complete with their status without disturbing the rest; an open-loop
+replay completes every request with a certified result."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1901_00155_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+PRECS = ["fp32", "bf16x3"]
+
+
+def _requests(count=24, seed=4, log2_max=16):
+    return workloads.serve_requests(seed=seed, count=count, rate_hz=200.0, log2_min=12,
+                                    log2_max=log2_max)
+
+
+def _drain(s, count, timeout_ms=120000):
+    import time
+    out = []
+    t0 = time.time()
+    while len(out) < count:
+        out += s.poll(64, 100)
+        assert (time.time() - t0) * 1e3 < timeout_ms, f"{len(out)} of {count} completed"
+    return {c["tag"]: c for c in out}
+
+
+@pytest.mark.parametrize("precision", PRECS)
+def test_same_result_alone_and_in_the_mix(gpu, precision):
+    dd = gpu
+    reqs = _requests()
+    alone = {}
+    for r in reqs:
+        with dd.Plan(r.series, r.n, precision=precision) as p:
+            alone[r.tag] = p.search().as_dict()
+    with dd.Server(4 << 30, slots=4, precision=precision) as s:
+        for r in reqs:
+            assert s.submit(r.series, r.n, r.tag) == 0
+        mix = _drain(s, len(reqs))
+        st = s.stats()
+    assert st["peak_running"] >= 2, "requests did not overlap"
+    assert st["failed"] == 0 and st["bytes_in_use"] == 0
+    for r in reqs:
+        c = mix[r.tag]
+        assert c["status"] == 0, c["detail"]
+        a, b = alone[r.tag], c["result"]
+        assert b["certified"] == 1
+        assert (b["index"], b["nn_index"]) == (a["index"], a["nn_index"]), r.tag
+        assert b["d2"] == a["d2"] and b["distance"] == a["distance"], r.tag
+
+
+@pytest.mark.parametrize("precision", PRECS)
+def test_mix_matches_oracle_on_short_series(gpu, precision):
+    dd = gpu
+    reqs = [r for r in _requests(count=40, seed=7, log2_max=13)][:16]
+    with dd.Server(2 << 30, slots=4, precision=precision) as s:
+        for r in reqs:
+            assert s.submit(r.series, r.n, r.tag) == 0
+        mix = _drain(s, len(reqs))
+    for r in reqs:
+        ref = oracle.discord(r.series, r.n)
+        got = mix[r.tag]["result"]
+        assert mix[r.tag]["status"] == 0
+        assert got["index"] == ref["index"], (r.tag, r.series.size, r.n)
+        assert got["d2"] == pytest.approx(ref["d2"], rel=1e-9, abs=0)
+        assert got["distance"] == pytest.approx(ref["distance"], rel=1e-9, abs=0)
+
+
+def test_failing_requests_do_not_disturb_the_mix(gpu):
+    dd = gpu
+    reqs = _requests(count=8, seed=11, log2_max=14)
+    bad_const = np.full(8192, 3.0, dtype=np.float32)
+    bad_nan = reqs[0].series.copy()
+    bad_nan[100] = np.nan
+    with dd.Server(2 << 30, slots=3, precision="bf16x3") as s:
+        for r in reqs[:4]:
+            assert s.submit(r.series, r.n, r.tag) == 0
+        assert s.submit(bad_const, 64, 1000) == 0
+        assert s.submit(bad_nan, reqs[0].n, 1001) == 0
+        for r in reqs[4:]:
+            assert s.submit(r.series, r.n, r.tag) == 0
+        mix = _drain(s, len(reqs) + 2)
+        st = s.stats()
+    assert mix[1000]["status"] == -2 and mix[1001]["status"] == -1
+    assert st["failed"] == 2 and st["bytes_in_use"] == 0
+    for r in reqs:
+        with dd.Plan(r.series, r.n, precision="bf16x3") as p:
+            a = p.search()
+        c = mix[r.tag]
+        assert c["status"] == 0 and c["result"]["index"] == a.index and c["result"]["d2"] == a.d2
+
+
+def test_open_loop_replay_completes(gpu):
+    dd = gpu
+    from paper_1901_00155_amd import serve
+    reqs = workloads.serve_requests(seed=4, count=200, rate_hz=200.0)
+    with dd.Server(8 << 30, slots=4, precision="bf16x3") as s:
+        out = serve.replay(s, reqs, timeout_s=100)
+    sm = out["summary"]
+    assert sm["completed_ok"] == 200 and sm["failed"] == 0 and sm["rejected"] == 0
+    assert all(c["result"]["certified"] == 1 for c in out["records"].values())
+    assert sm["p50_ms"] <= sm["p99_ms"]
+    print(sm)
