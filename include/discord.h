@@ -59,8 +59,12 @@ typedef struct {
     int32_t precision;  /* discord_precision                                         */
     int32_t abandon;    /* 1: leave a row once a distance below the best-so-far appears
                            (Algorithms 1, 3, 4); 0: scan every pair (full scan)      */
-    int32_t order;      /* 1: PhiDD visiting order (Cand rows first, same-word rows
-                           first, Algorithms 3-4); 0: matrix order only              */
+    int32_t order;      /* visiting order; the result never depends on it:
+                           1: PhiDD (Cand rows first, Algorithm 3; then each row's
+                              same-word columns first, then matrix order, Alg. 4)
+                           2: Cand rows first, then each row's columns nearest in
+                              time first, alternating forward and backward
+                           0: matrix order only                                    */
     int32_t topk;       /* approximate candidates per finalist row rescored in FP64
                            (mixed precision; 1..32)                                  */
     int32_t paa_w;      /* PAA segments w of eq. (3) (1..8; min(w, n) is used)       */

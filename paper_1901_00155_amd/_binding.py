@@ -229,7 +229,7 @@ class Plan:
                  paa_w=4, alphabet=4, probe_steps=0, stream=None, torch_workspace=False):
         lib = load()
         self.opts = default_opts(precision=precision, abandon=int(bool(abandon)),
-                                 order=int(bool(order)), topk=topk, paa_w=paa_w,
+                                 order=int(order), topk=topk, paa_w=paa_w,
                                  alphabet=alphabet, probe_steps=probe_steps)
         ptr, m, self._keep, tstream = _series_ptr(T)
         self.m, self.n = int(m), int(n)

@@ -117,7 +117,7 @@ Layout make_layout(int64_t m, int32_t n, int dict, bool mixed) {
 bool opts_valid(int32_t n, const discord_opts& o) {
   if (o.precision != DISCORD_PREC_FP32 && o.precision != DISCORD_PREC_BF16X3) return false;
   if (o.abandon != 0 && o.abandon != 1) return false;
-  if (o.order != 0 && o.order != 1) return false;
+  if (o.order < 0 || o.order > 2) return false;
   if (o.topk < 1 || o.topk > 32) return false;
   (void)n;
   if (o.paa_w < 1 || o.paa_w > 8) return false;
@@ -404,7 +404,9 @@ int discord_search(discord_plan p, discord_result* out) {
   const int rb = mixed ? mfma_row_blocks(n) : 1;
   const int64_t target_items = mixed ? 1024 : 4096;   // ~4 wavefronts per SIMD
   const bool abandon = p->opts.abandon != 0;
-  const bool order = p->opts.order != 0;
+  const bool order = p->opts.order != 0;          // Cand first (Algorithm 3)
+  const bool buckets = p->opts.order == 1;        // same-word columns first
+  const bool near_first = p->opts.order == 2;     // columns nearest the row first
   uint64_t* best = p->at<uint64_t>(p->L.best);
   uint64_t* pairs = p->at<uint64_t>(p->L.pairs);
   uint32_t* bsf = p->at<uint32_t>(p->L.bsf);
@@ -485,21 +487,24 @@ int discord_search(discord_plan p, discord_result* out) {
       J.groups = cgroups;
       J.n_groups = hcg;
       set_chunks(hcg);
-      J.words = p->at<int32_t>(p->L.words);
+      J.words = buckets ? p->at<int32_t>(p->L.words) : nullptr;
       J.bgrp_off = p->at<int32_t>(p->L.bgrp_off);
       J.bgrp = p->at<int32_t>(p->L.bgrp);
+      J.near_first = near_first;
       J.max_steps = 0;
       if ((st = launch("scan (Cand)"))) return st;
     }
-    // Algorithm 4, first pass: every other row group walks its word's bucket,
-    // then matrix order, for a bounded number of 512-column steps
+    // Algorithm 4, first pass: every other row group walks its column sequence
+    // (its word's bucket, then matrix order; or near-first) for a bounded
+    // number of 512-column steps
     J.groups = nullptr;
     J.n_groups = G;
     J.chunks = 1;
     J.cols_per_chunk = (N + 511) / 512 * 512;
     const int probe = p->opts.probe_steps > 0 ? p->opts.probe_steps : 16;
     J.max_steps = mixed ? probe * (512 / kMixedBlock) : probe;
-    J.words = order ? p->at<int32_t>(p->L.words) : nullptr;
+    J.words = buckets ? p->at<int32_t>(p->L.words) : nullptr;
+    J.near_first = near_first;
     J.bgrp_off = p->at<int32_t>(p->L.bgrp_off);
     J.bgrp = p->at<int32_t>(p->L.bgrp);
     J.skip = (order && hcg > 0) ? gflags : nullptr;

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 #include "../../include/discord.h"
+#include "spiral.hpp"
 
 #include <cstddef>
 #include <cstdint>
@@ -74,8 +75,9 @@ void launch_bucket_groups(const int32_t* offsets, const int32_t* members, int di
 
 // ---- scan_fp32.hip ------------------------------------------------------------
 // One launch of the pair scan: n_groups row groups (from `groups`, or 0..n_groups-1)
-// times `chunks` column chunks of cols_per_chunk columns in matrix order; one
-// wavefront per (group, chunk).
+// times `chunks` column chunks of cols_per_chunk columns each (consecutive in the
+// matrix order or in the near-first order of spiral.hpp); one wavefront (FP32)
+// or one workgroup (MFMA) per (item, chunk).
 struct ScanJob {
   const float* Tp;            // padded series (t_0 at Tp[0])
   int32_t n;
@@ -90,6 +92,7 @@ struct ScanJob {
   const int32_t* bgrp_off;    // per word: offsets into bgrp
   const int32_t* bgrp;        // bucket column groups (column / 8), ascending per word
   const int32_t* skip;        // per row group: 1 = already searched, or nullptr
+  int32_t near_first;         // 1: the chunks split the near-first order instead of matrix order
   // early abandon against the best-so-far
   int32_t abandon;
   uint32_t* bsf;              // float bits of the best-so-far squared distance

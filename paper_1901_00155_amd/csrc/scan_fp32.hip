@@ -119,8 +119,8 @@ __device__ __forceinline__ uint64_t load_relaxed64(const uint64_t* p) {
 
 // One wavefront per work item (row group, column chunk).  The item's column
 // sequence is the bucket of the group's word (Index_Word, eq. (10)), when given,
-// followed by the chunk's columns in matrix order; each step covers 64 column
-// groups of 8.  With abandon on, after every step each live row compares its
+// followed by the chunk's share of the column groups, in matrix order or
+// near-first (spiral.hpp); each step covers 64 column groups of 8.  With abandon on, after every step each live row compares its
 // running minimum with the device best-so-far and leaves as soon as it is below
 // (Algorithms 3-4); the leaving row keeps that column as its witness.
 __global__ __launch_bounds__(256) void k_scan_fp32(ScanJob J) {
@@ -139,17 +139,19 @@ __global__ __launch_bounds__(256) void k_scan_fp32(ScanJob J) {
   for (int r = 0; r < TM; ++r) valid |= (i0 + r < N ? 1u : 0u) << r;
   uint32_t live = J.abandon ? (load_relaxed(&J.alive[g]) & valid) : valid;
 
-  // column sequence
+  // column sequence: the word's bucket (chunk 0 only), then this chunk's share
+  // of the column groups, in matrix order or near-first
   int64_t nb = 0, b0 = 0;
   if (J.words && ch == 0) {
     const int w = J.words[i0];
     b0 = J.bgrp_off[w];
     nb = J.bgrp_off[w + 1] - b0;
   }
-  const int64_t cb = ch * J.cols_per_chunk;
-  const int64_t ce = min<int64_t>(N, cb + J.cols_per_chunk);
-  const int64_t q0 = cb / TN;
-  const int64_t nm = ce > cb ? (ce + TN - 1) / TN - q0 : 0;
+  const int64_t NQ = (N + TN - 1) / TN;
+  const Spiral sp = make_spiral(i0, i0 + TM, n, NQ, TN);
+  const int64_t npos = J.near_first ? spiral_count(sp) : NQ;
+  const int64_t p0 = ch * (J.cols_per_chunk / TN);
+  const int64_t nm = npos > p0 ? min<int64_t>(npos - p0, J.cols_per_chunk / TN) : 0;
   const int64_t total_q = nb + nm;
   int64_t steps = (total_q + 63) / 64;
   bool exhausted = true;
@@ -171,8 +173,11 @@ __global__ __launch_bounds__(256) void k_scan_fp32(ScanJob J) {
     const int64_t qi = s * 64 + lane;
     const bool in_seq = qi < total_q;
     const bool from_bucket = qi < nb;
-    const int64_t q = in_seq ? (from_bucket ? (int64_t)J.bgrp[b0 + qi] : q0 + (qi - nb)) : 0;
-    const int64_t jlim = from_bucket ? N : ce;
+    const int64_t pos = p0 + (qi - nb);
+    const int64_t q = !in_seq ? 0
+                      : from_bucket ? (int64_t)J.bgrp[b0 + qi]
+                      : J.near_first ? spiral_block(sp, pos) : pos;
+    const int64_t jlim = N;
     const int64_t j0 = q * TN;
     float acc[TM][TN];
     block8x8(x, J.Tp + j0, n, acc);

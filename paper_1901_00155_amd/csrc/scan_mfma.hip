@@ -138,8 +138,9 @@ __global__ __launch_bounds__(256) void k_split_blocks(const float* __restrict__ 
 
 // One workgroup per work item: kWaves * RB row blocks (consecutive entries of the
 // group list) against one column chunk; the column sequence is the first
-// entry's word bucket (32-column blocks) when given, then the chunk in matrix
-// order, one 32-column block per step.
+// entry's word bucket (32-column blocks) when given, then the chunk's share of
+// the column blocks in matrix order or near-first (spiral.hpp), one 32-column
+// block per step.
 template <int KS, int RB>
 __global__ __launch_bounds__(kWaves<KS> * 64, (KS <= 16 ? 2 : 1)) void k_scan_mfma(ScanJob J,
                                                                                   MixedRows R) {
@@ -212,10 +213,22 @@ __global__ __launch_bounds__(kWaves<KS> * 64, (KS <= 16 ? 2 : 1)) void k_scan_mf
     b0 = J.bgrp_off[w];
     nb = J.bgrp_off[w + 1] - b0;
   }
-  const int64_t cb = ch * J.cols_per_chunk;
-  const int64_t ce = min<int64_t>(N, cb + J.cols_per_chunk);
-  const int64_t q0 = cb / BN;
-  const int64_t nm = ce > cb ? (ce + BN - 1) / BN - q0 : 0;
+  const int64_t NQ = (N + BN - 1) / BN;
+  Spiral sp{0, -1, NQ, 0};
+  if (J.near_first) {
+    // outward from the span of all the item's row blocks (its list entries may
+    // be scattered: the span keeps every needed block in the order)
+    int64_t r0 = N, r1 = 0;
+    for (int64_t e = li * per_item; e < min<int64_t>(J.n_groups, (li + 1) * per_item); ++e) {
+      const int64_t ge = J.groups ? J.groups[e] : e;
+      r0 = min<int64_t>(r0, ge * BM);
+      r1 = max<int64_t>(r1, ge * BM + BM);
+    }
+    sp = make_spiral(r0, r1, n, NQ, BN);
+  }
+  const int64_t npos = spiral_count(sp);   // NQ in matrix order
+  const int64_t p0 = ch * (J.cols_per_chunk / BN);
+  const int64_t nm = npos > p0 ? min<int64_t>(npos - p0, J.cols_per_chunk / BN) : 0;
   const int64_t total_q = nb + nm;
   int64_t steps = total_q;
   bool exhausted = true;
@@ -224,7 +237,8 @@ __global__ __launch_bounds__(kWaves<KS> * 64, (KS <= 16 ? 2 : 1)) void k_scan_mf
     exhausted = false;
   }
   auto block_of = [&](int64_t s) -> int64_t {
-    return s < nb ? (int64_t)__builtin_amdgcn_readfirstlane(J.bgrp[b0 + s]) : q0 + (s - nb);
+    return s < nb ? (int64_t)__builtin_amdgcn_readfirstlane(J.bgrp[b0 + s])
+                  : spiral_block(sp, p0 + (s - nb));
   };
 
   // workgroup-wide: is any row of any wavefront still live?
@@ -268,8 +282,7 @@ __global__ __launch_bounds__(kWaves<KS> * 64, (KS <= 16 ? 2 : 1)) void k_scan_mf
   for (int64_t s = 0; s < steps; ++s) {
     const int cur = (int)(s & 1);
     if (s + 1 < steps) fetch(block_of(s + 1));
-    const bool from_bucket = s < nb;
-    const int64_t jlim = from_bucket ? N : ce;
+    const int64_t jlim = N;
     const int64_t j0 = block_of(s) * BN;
     const bf16x8* buf = smem + cur * SLOTS;
 

@@ -56,3 +56,23 @@ def test_sax_breakpoints_match_oracle(dd):
 def test_strerror(dd):
     for code in (0, -1, -2, -3, -4, -5, -6):
         assert dd.strerror(code)
+
+
+def test_visiting_order_option(dd):
+    assert dd.workspace_bytes(4096, 64, order=2) > 0
+    assert dd.workspace_bytes(4096, 64, order=3) == 0
+
+
+def test_near_first_order_covers_every_needed_block(tmp_path):
+    """tests/native/spiral_check.cpp: exhaustive check of the near-first column
+    order of the scan kernels (csrc/spiral.hpp) on small sizes."""
+    import shutil
+    import subprocess
+    cxx = shutil.which("g++") or shutil.which("c++")
+    if not cxx:
+        pytest.skip("no host C++ compiler")
+    exe = str(tmp_path / "spiral_check")
+    subprocess.run([cxx, "-std=c++17", "-O2", os.path.join(ROOT, "tests", "native", "spiral_check.cpp"),
+                    "-o", exe], check=True, timeout=120)
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0 and "OK" in r.stdout, r.stdout + r.stderr

@@ -114,18 +114,19 @@ SMALL_CASES = [
 
 
 @pytest.mark.parametrize("m,n,seed", SMALL_CASES)
-@pytest.mark.parametrize("abandon", [False, True])
+@pytest.mark.parametrize("mode", ["full", "abandon-matrix", "abandon-phidd", "abandon-near"])
 @pytest.mark.parametrize("precision", PRECS)
-def test_discord_matches_oracle(gpu, m, n, seed, abandon, precision):
+def test_discord_matches_oracle(gpu, m, n, seed, mode, precision):
     T = workloads.random_walk(m, seed=seed)
     ref = oracle.discord(T, n)
-    with gpu.Plan(T, n, abandon=abandon, precision=precision) as p:
+    order = {"full": 1, "abandon-matrix": 0, "abandon-phidd": 1, "abandon-near": 2}[mode]
+    with gpu.Plan(T, n, abandon=mode != "full", order=order, precision=precision) as p:
         r = p.search()
-    _assert_same(r, ref, (m, n, seed))
+    _assert_same(r, ref, (m, n, seed, mode))
 
 
 @pytest.mark.parametrize("probe_steps", [1, 3, 16, 100000])
-@pytest.mark.parametrize("order", [True, False])
+@pytest.mark.parametrize("order", [1, 0, 2])
 @pytest.mark.parametrize("precision", PRECS)
 def test_abandon_reaches_same_discord_and_prunes(gpu, probe_steps, order, precision):
     """Early abandon (Algorithms 3-4) changes the work, never the answer: every
@@ -246,8 +247,9 @@ def _certify(w, r, wit):
     assert abs(r.d2 - nn) <= REL * nn
 
 
+@pytest.mark.parametrize("order", [1, 2])
 @pytest.mark.parametrize("precision", PRECS)
-def test_walk1m_certificate(gpu, precision):
+def test_walk1m_certificate(gpu, precision, order):
     """m = 2^20, n = 128, four planted anomalies: the oracle cannot brute-force
     this size, so it checks the GPU's answer with the FP64 witness certificate
     (exact NN of the claimed row + one witness per other row).  Under the global
@@ -255,10 +257,11 @@ def test_walk1m_certificate(gpu, precision):
     at a level the walk visits rarely, not necessarily at a planted anomaly, so
     no location is asserted here."""
     w = workloads.walk1m()
-    with gpu.Plan(w.series, w.n, precision=precision) as p:
+    with gpu.Plan(w.series, w.n, precision=precision, order=order) as p:
         r = p.search()
         wit = p.copy("nn_witness")
     _certify(w, r, wit)
+    print(precision, order, r.index, r.pairs_evaluated, r.ms_search, r.rows_rescored)
 
 
 def test_noisy1m_both_precisions_agree(gpu):
@@ -267,9 +270,10 @@ def test_noisy1m_both_precisions_agree(gpu):
     w = workloads.noisy1m()
     out = {}
     for precision in PRECS:
-        with gpu.Plan(w.series, w.n, precision=precision) as p:
-            r = p.search()
-            wit = p.copy("nn_witness")
-        _certify(w, r, wit)
-        out[precision] = (r.index, r.nn_index, r.d2)
-    assert out["fp32"] == out["bf16x3"]
+        for order in (1, 2):
+            with gpu.Plan(w.series, w.n, precision=precision, order=order) as p:
+                r = p.search()
+                wit = p.copy("nn_witness")
+            _certify(w, r, wit)
+            out[precision, order] = (r.index, r.nn_index, r.d2)
+    assert len(set(out.values())) == 1, out
