@@ -3,18 +3,19 @@
 
 One step = one complete exact discord search through the C ABI on a series
 already resident in HBM: discord_prepare (eq. (2) statistics, PAA/SAX words,
-Cand, Index_Word, row statistics) + discord_search (the two-phase pair-distance
-scan with early abandon, row minima, device argmax, FP64 certification).  The
-workload is the m = 2^20 random walk with four planted anomalies and window
-n = 128, searched with the plain FP32 scan and exact early abandon.
+Cand, Index_Word, row statistics) + discord_search (the pair-distance scan with
+early abandon, row minima, device argmax, FP64 certification).  The workload is
+the m = 2^20 random walk with four planted anomalies and window n = 128,
+searched with the plain FP32 scan and exact early abandon.
 
 Printed: one JSON line.  `value` is pair distances computed per second of step
 time (the scan's own count of evaluated non-self pairs).  Beside it: the time
 to discord, the brute-force-equivalent rate P(N, n) / time, the split-BF16
-MFMA search of the same input (`mixed`), full-scan rates of both precisions,
-the roofline of each scan kernel (kernel time from HIP events on the plan's
-stream) and the FP64 CPU oracle timed on a bounded sample of the same workload
-on the host cores.
+MFMA search of the same input (`mixed`), the time to discord under each
+visiting order, full-scan rates of both precisions, the roofline of each scan
+kernel (kernel time from HIP events on the plan's stream), the serving stream
+(p50/p99 latency and throughput) and the FP64 CPU oracle timed on a bounded
+sample of the same workload on the host cores.
 """
 from __future__ import annotations
 
@@ -74,7 +75,7 @@ def traffic_for(precision: str, workload: str, mode: str):
     return rec.get("bytes_per_launch")
 
 
-def time_steps(dd, Td, n, precision, abandon, steps, warmup):
+def time_steps(dd, Td, n, precision, abandon, steps, warmup, order=2):
     import torch
     results = []
     stream = torch.cuda.current_stream()
@@ -82,7 +83,7 @@ def time_steps(dd, Td, n, precision, abandon, steps, warmup):
         if it == warmup:
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-        with dd.Plan(Td, n, precision=precision, abandon=abandon, stream=stream,
+        with dd.Plan(Td, n, precision=precision, abandon=abandon, order=order, stream=stream,
                      torch_workspace=True) as p:
             r = p.search()
         if it >= warmup:
@@ -126,6 +127,41 @@ def cpu_baseline(series, n, budget_s=15.0):
                       f"({pairs:.3e} pairs, {dt:.1f} s)"}
 
 
+def serving(dd, workloads, precision="bf16x3", slots=4, budget=8 << 30, count=4096):
+    """The request stream of the serving configuration (Poisson arrivals at
+    200 req/s, m log-uniform in [2^12, 2^18], n in {64, 128, 256}, one planted
+    anomaly each), replayed open-loop through the serving loop."""
+    from paper_1901_00155_amd import serve
+    t = time.perf_counter()
+    reqs = workloads.serve_requests(count=count)
+    gen_s = time.perf_counter() - t
+    with dd.Server(budget, slots=slots, precision=precision) as s:
+        for r in reqs[:8]:                     # warm the slots' streams and staging
+            s.submit(r.series, r.n, 10 ** 9 + r.tag)
+        got = 0
+        while got < 8:
+            got += len(s.poll(64, 100))
+        out = serve.replay(s, reqs, timeout_s=600)
+    sm = out["summary"]
+    recs = list(out["records"].values())
+    ok = [c for c in recs if c["status"] == 0]
+    assert sm["failed"] == 0 and all(c["result"]["certified"] == 1 for c in ok)
+    return {
+        "workload": f"{count} requests, Poisson 200 req/s, m log-uniform [2^12, 2^18], "
+                    "n in {64,128,256}, random walk + 1 planted anomaly each (seed 4)",
+        "precision": precision, "slots": slots, "hbm_budget_bytes": budget,
+        "p50_ms": sm["p50_ms"], "p99_ms": sm["p99_ms"], "mean_ms": sm["mean_ms"],
+        "max_ms": sm["max_ms"], "throughput_rps": sm["throughput_rps"],
+        "offered_rps": sm["offered_rps"], "completed": sm["completed_ok"],
+        "failed": sm["failed"], "rejected": sm["rejected"],
+        "queue_p99_ms": sm["queue_p99_ms"], "service_p50_ms": sm["service_p50_ms"],
+        "service_p99_ms": sm["service_p99_ms"], "mean_concurrency": sm["mean_concurrency"],
+        "peak_running": sm["peak_running"], "peak_bytes_in_use": sm["peak_bytes_in_use"],
+        "pairs_evaluated_total": float(sum(c["result"]["pairs_evaluated"] for c in ok)),
+        "span_s": sm["span_s"], "generate_s": gen_s,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -136,6 +172,8 @@ def main():
     ap.add_argument("--no-abandon", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--order", type=int, default=2, choices=[0, 1, 2])
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     args = ap.parse_args()
 
@@ -159,7 +197,7 @@ def main():
     mode = "abandon" if abandon else "full"
 
     print(f"# workload {w.name}: m={m} n={n} N={N} P={P:.4e}", file=sys.stderr, flush=True)
-    sec, res = time_steps(dd, Td, n, args.precision, abandon, args.steps, args.warmup)
+    sec, res = time_steps(dd, Td, n, args.precision, abandon, args.steps, args.warmup, args.order)
     r = res[-1]
     assert len({int(x.index) for x in res}) == 1, "steps disagree"
     pairs = float(np.mean([x.pairs_evaluated for x in res]))
@@ -168,7 +206,7 @@ def main():
           f"d={r.distance:.6f}", file=sys.stderr, flush=True)
 
     out = {
-        "metric": "subseq-pair distances/s",
+        "metric": "subseq-pair distances/s & time-to-discord vs plain FP32; serve p50/p99 ms",
         "value": pairs / sec,
         "unit": "pairs/s",
         "n_gpus": 1,
@@ -182,7 +220,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{w.name}: m={m} seeded series, {len(w.anomalies)} planted "
                                f"anomalies, window n={n}", "m": m, "n": n,
-                   "precision": args.precision, "abandon": abandon, "order": "phidd"},
+                   "precision": args.precision, "abandon": abandon,
+                   "order": {0: "matrix", 1: "phidd", 2: "cand+near-first"}[args.order]},
         "time_to_discord_ms": sec * 1e3,
         "brute_force_equiv_pairs_per_s": P / sec,
         "pairs_evaluated": pairs,
@@ -197,7 +236,7 @@ def main():
     }
     if not args.no_extras:
         other = "bf16x3" if args.precision == "fp32" else "fp32"
-        s2, rr = time_steps(dd, Td, n, other, abandon, args.steps, args.warmup)
+        s2, rr = time_steps(dd, Td, n, other, abandon, args.steps, args.warmup, args.order)
         x = rr[-1]
         assert int(x.index) == int(r.index) and x.d2 == r.d2, "precisions disagree"
         p2 = float(np.mean([y.pairs_evaluated for y in rr]))
@@ -208,6 +247,21 @@ def main():
             "max_rel_err_of_approx_nn": float(x.max_rel_err),
             "roofline": roofline(n, other, p2, sm2, traffic_for(other, w.name, mode))}
         print(f"# {other} step {s2 * 1e3:.2f} ms", file=sys.stderr, flush=True)
+        if abandon:
+            # the paper's visiting order (PhiDD: Cand first, same-word columns first)
+            # and plain matrix order, both precisions, for comparison
+            orders = {}
+            for oname, oval in (("phidd", 1), ("matrix", 0), ("cand+near-first", 2)):
+                orders[oname] = {}
+                for prec in ("fp32", "bf16x3"):
+                    so, ro = time_steps(dd, Td, n, prec, True, 2, 1, oval)
+                    assert int(ro[-1].index) == int(r.index) and ro[-1].d2 == r.d2
+                    orders[oname][prec] = {
+                        "time_to_discord_ms": so * 1e3,
+                        "pairs_evaluated": float(np.mean([y.pairs_evaluated for y in ro]))}
+                    print(f"# order {oname} {prec}: {so * 1e3:.1f} ms", file=sys.stderr,
+                          flush=True)
+            out["time_to_discord_by_order"] = orders
         full = {}
         for prec in ("fp32", "bf16x3"):
             _, rf = time_steps(dd, Td, n, prec, False, 1, 0)
@@ -220,6 +274,11 @@ def main():
             print(f"# full scan {prec}: {y.ms_scan:.1f} ms", file=sys.stderr, flush=True)
         full["bf16x3_speedup_vs_fp32"] = full["fp32"]["scan_ms"] / full["bf16x3"]["scan_ms"]
         out["full_scan"] = full
+    if not args.no_serve:
+        out["serving"] = serving(dd, workloads)
+        sv = out["serving"]
+        print(f"# serving: p50 {sv['p50_ms']:.2f} ms p99 {sv['p99_ms']:.2f} ms "
+              f"{sv['throughput_rps']:.1f} req/s", file=sys.stderr, flush=True)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w.series, n, args.cpu_budget)
     print(json.dumps(out), flush=True)

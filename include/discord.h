@@ -75,7 +75,8 @@ typedef struct {
     int32_t reserved;
 } discord_opts;
 
-/* Defaults: FP32, abandon on, PhiDD order, topk 16, w = |A| = 4 (section 3.1). */
+/* Defaults: FP32, abandon on, order 2 (Cand first, then near-first columns),
+ * topk 16, w = |A| = 4 (section 3.1). */
 void discord_default_opts(discord_opts* opts);
 
 /* ---- result -------------------------------------------------------------- */

@@ -225,7 +225,7 @@ def _series_ptr(T):
 class Plan:
     """A prepared series (discord_prepare) that can be searched repeatedly."""
 
-    def __init__(self, T, n: int, precision="fp32", abandon=True, order=True, topk=16,
+    def __init__(self, T, n: int, precision="fp32", abandon=True, order=2, topk=16,
                  paa_w=4, alphabet=4, probe_steps=0, stream=None, torch_workspace=False):
         lib = load()
         self.opts = default_opts(precision=precision, abandon=int(bool(abandon)),

@@ -240,7 +240,7 @@ void discord_default_opts(discord_opts* o) {
   std::memset(o, 0, sizeof(*o));
   o->precision = DISCORD_PREC_FP32;
   o->abandon = 1;
-  o->order = 1;
+  o->order = 2;
   o->topk = 16;
   o->paa_w = 4;
   o->alphabet = 4;
