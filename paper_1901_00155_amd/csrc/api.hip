@@ -48,8 +48,9 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 struct Layout {
   size_t T, stats, partials, bad, words, hist, minfreq, cand, cand_count, seg, csr_off, csr_mem,
       best, nn_approx, nn_wit, row_state, row_mean, row_cnorm, seed, rows, part_d, part_j, out_d,
-      out_j, exact, unc, unc_count, relerr, bsf, pairs, alive, done, survivors, n_surv, gflags,
-      cand_groups, n_cand_groups, n_aband, bgrp_cnt, bgrp_off, bgrp, mu32, smu32, cn32, sblk, total;
+      out_j, exact, unc, unc_count, relerr, bsf, pairs, alive, done, survivors, survivors2, n_surv,
+      score, rank_hist, gflags, cand_groups, n_cand_groups, n_aband, bgrp_cnt, bgrp_off, bgrp,
+      max_bucket, mu32, smu32, cn32, sblk, total;
 };
 
 Layout make_layout(int64_t m, int32_t n, int dict, bool mixed) {
@@ -97,7 +98,10 @@ Layout make_layout(int64_t m, int32_t n, int dict, bool mixed) {
   L.alive = take(sizeof(uint32_t) * G);
   L.done = take(sizeof(uint32_t) * G);
   L.survivors = take(sizeof(int32_t) * G);
+  L.survivors2 = take(sizeof(int32_t) * G);
   L.n_surv = take(sizeof(uint32_t) * 4);
+  L.score = take(sizeof(uint32_t) * G);
+  L.rank_hist = take(sizeof(uint32_t) * rank_hist_bins());
   L.gflags = take(sizeof(int32_t) * G);
   L.cand_groups = take(sizeof(int32_t) * G);
   L.n_cand_groups = take(sizeof(int32_t) * 4);
@@ -105,6 +109,7 @@ Layout make_layout(int64_t m, int32_t n, int dict, bool mixed) {
   L.bgrp_cnt = take(sizeof(int32_t) * kMaxWords);
   L.bgrp_off = take(sizeof(int32_t) * (kMaxWords + 1));
   L.bgrp = take(sizeof(int32_t) * N);
+  L.max_bucket = take(sizeof(int32_t) * 4);
   L.mu32 = take(sizeof(float) * (N + kRowPad));
   L.smu32 = take(sizeof(float) * (N + kRowPad));
   L.cn32 = take(sizeof(float) * (N + kRowPad));
@@ -151,6 +156,7 @@ struct discord_plan_s {
   int dict = 256;
   double mu = 0.0, sigma = 0.0;
   int64_t cand_count = 0;
+  int64_t max_bucket = 0;     // longest word bucket, in scan column blocks
   double ms_prepare = 0.0;
   bool searched = false;
   char err[512] = {0};
@@ -365,12 +371,16 @@ int discord_prepare(const float* T, int64_t m, int32_t n, const discord_opts* op
                          mixed ? 5 : 3,
                          p->at<int32_t>(p->L.bgrp_cnt), p->at<int32_t>(p->L.bgrp_off),
                          p->at<int32_t>(p->L.bgrp), s);
+    launch_max_bucket(p->at<int32_t>(p->L.bgrp_off), p->dict, p->at<int32_t>(p->L.max_bucket), s);
     LAUNCH_OK(p, "prepare kernels");
-    int32_t hc = 0;
+    int32_t hc = 0, hmb = 0;
     HIP_TRY(p, hipMemcpyAsync(&hc, p->at<int32_t>(p->L.cand_count), sizeof(hc), hipMemcpyDeviceToHost, s));
+    HIP_TRY(p, hipMemcpyAsync(&hmb, p->at<int32_t>(p->L.max_bucket), sizeof(hmb),
+                              hipMemcpyDeviceToHost, s));
     HIP_TRY(p, hipEventRecord(ev.b, s));
     HIP_TRY(p, hipStreamSynchronize(s));
     p->cand_count = hc;
+    p->max_bucket = hmb;
     p->ms_prepare = ev.ms();
     return DISCORD_OK;
   };
@@ -398,10 +408,15 @@ int discord_search(discord_plan p, discord_result* out) {
   const bool mixed = p->opts.precision == DISCORD_PREC_BF16X3;
   // rows per scan group: 8 (FP32 micro-tile) or 32 (one MFMA tile side)
   const int gsz = mixed ? kMixedBlock : kRowGroup;
-  const int gshift = mixed ? 5 : 3;
   const int64_t G = (N + gsz - 1) / gsz;
   // row groups per work item: one wavefront (FP32) or one workgroup (MFMA)
   const int rb = mixed ? mfma_row_blocks(n) : 1;
+  // the unit of the scan's lists: one row group (FP32) or one workgroup's fixed
+  // set of rb row blocks (MFMA)
+  const int64_t item_rows = (int64_t)gsz * rb;
+  int item_shift = 0;
+  while ((int64_t{1} << item_shift) < item_rows) ++item_shift;
+  const int64_t n_items = (N + item_rows - 1) / item_rows;
   const int64_t target_items = mixed ? 1024 : 4096;   // ~4 wavefronts per SIMD
   const bool abandon = p->opts.abandon != 0;
   const bool order = p->opts.order != 0;          // Cand first (Algorithm 3)
@@ -452,74 +467,111 @@ int discord_search(discord_plan p, discord_result* out) {
     LAUNCH_OK(p, what);
     return DISCORD_OK;
   };
-  // split the columns so that the launch holds enough work items to fill the GPU
-  auto set_chunks = [&](int64_t groups) {
-    const int64_t items = std::max<int64_t>(1, (groups + rb - 1) / rb);
-    const int64_t maxc = std::max<int64_t>(1, (N + 511) / 512);
-    int64_t c = std::min<int64_t>(maxc, std::max<int64_t>(1, (target_items + items - 1) / items));
-    int64_t cols = ((N + c - 1) / c + 511) / 512 * 512;
-    J.cols_per_chunk = cols;
-    J.chunks = (N + cols - 1) / cols;
+  // Sequence entries are column groups of 8 (FP32) or blocks of 32 (MFMA); a
+  // sequence is at most the word bucket plus every column block.
+  const int64_t nq = (N + (mixed ? kMixedBlock : kColBlock) - 1) / (mixed ? kMixedBlock : kColBlock);
+  const int64_t seq_max = nq + (buckets ? p->max_bucket : 0);
+  const int64_t gran = mixed ? 16 : 64;   // entries per 512 columns
+  // entries [begin, end) of every listed item, split into chunks so that the
+  // launch holds enough work items to fill the GPU
+  auto set_window = [&](int64_t groups, int64_t begin, int64_t end) {
+    const int64_t items = std::max<int64_t>(1, groups);
+    const int64_t width = std::max<int64_t>(end - begin, 1);
+    const int64_t maxc = (width + gran - 1) / gran;
+    const int64_t c = std::min<int64_t>(maxc, std::max<int64_t>(1, (target_items + items - 1) / items));
+    J.seq_begin = begin;
+    J.seq_chunk = ((width + c - 1) / c + gran - 1) / gran * gran;
+    J.chunks = (width + J.seq_chunk - 1) / J.seq_chunk;
   };
   int st = DISCORD_OK;
   if (!abandon) {
     J.abandon = 0;
-    J.n_groups = G;
-    set_chunks(G);
+    J.n_groups = n_items;
+    set_window(n_items, 0, nq);
     if ((st = launch("scan (full)"))) return st;
   } else {
     J.abandon = 1;
     launch_init_alive(alive, G, N, gsz, s);
     launch_init_i32(reinterpret_cast<int32_t*>(J.done), G, 0, s);
-    launch_init_i32(reinterpret_cast<int32_t*>(n_surv), 1, 0, s);
     launch_init_i32(gflags, G, 0, s);
+    J.words = buckets ? p->at<int32_t>(p->L.words) : nullptr;
+    J.bgrp_off = p->at<int32_t>(p->L.bgrp_off);
+    J.bgrp = p->at<int32_t>(p->L.bgrp);
+    J.near_first = near_first;
     int32_t hcg = 0;
     if (order && p->cand_count > 0) {
-      // Algorithm 3: the row groups holding Cand rows, each scanned over all
-      // columns (its word's bucket first), split into chunks to fill the GPU
+      // Algorithm 3: the row groups holding Cand rows, each scanned over its
+      // whole sequence, split into chunks to fill the GPU
       int32_t* cgroups = p->at<int32_t>(p->L.cand_groups);
       int32_t* n_cg = p->at<int32_t>(p->L.n_cand_groups);
       launch_cand_group_flags(p->at<int32_t>(p->L.cand), p->at<int32_t>(p->L.cand_count),
-                              p->cand_count, gshift, gflags, s);
-      launch_compact_flags(gflags, G, p->at<int32_t>(p->L.seg), cgroups, n_cg, s);
+                              p->cand_count, item_shift, gflags, s);
+      launch_compact_flags(gflags, n_items, p->at<int32_t>(p->L.seg), cgroups, n_cg, s);
       HIP_TRY(p, hipMemcpyAsync(&hcg, n_cg, sizeof(hcg), hipMemcpyDeviceToHost, s));
       HIP_TRY(p, hipStreamSynchronize(s));
       J.groups = cgroups;
       J.n_groups = hcg;
-      set_chunks(hcg);
-      J.words = buckets ? p->at<int32_t>(p->L.words) : nullptr;
-      J.bgrp_off = p->at<int32_t>(p->L.bgrp_off);
-      J.bgrp = p->at<int32_t>(p->L.bgrp);
-      J.near_first = near_first;
-      J.max_steps = 0;
+      set_window(hcg, 0, seq_max);
       if ((st = launch("scan (Cand)"))) return st;
     }
-    // Algorithm 4, first pass: every other row group walks its column sequence
-    // (its word's bucket, then matrix order; or near-first) for a bounded
-    // number of 512-column steps
-    J.groups = nullptr;
-    J.n_groups = G;
-    J.chunks = 1;
-    J.cols_per_chunk = (N + 511) / 512 * 512;
+    // Algorithm 4 over the other groups, in windows of their sequences: a first
+    // window of probe_steps x 512 columns for every group; then the groups with
+    // rows still live continue.  PhiDD and matrix order: one more launch over
+    // the rest of the sequence.  Near-first order: the survivors are ranked by
+    // their rows' published minima, the best-ranked are completed at once (to
+    // raise the best-so-far), and the rest continue in windows 4x longer each
+    // time.  Every launch resumes an item where its previous window ended, and
+    // rows already below the best-so-far leave before any work.
+    const bool resume = true;
     const int probe = p->opts.probe_steps > 0 ? p->opts.probe_steps : 16;
-    J.max_steps = mixed ? probe * (512 / kMixedBlock) : probe;
-    J.words = buckets ? p->at<int32_t>(p->L.words) : nullptr;
-    J.near_first = near_first;
-    J.bgrp_off = p->at<int32_t>(p->L.bgrp_off);
-    J.bgrp = p->at<int32_t>(p->L.bgrp);
-    J.skip = (order && hcg > 0) ? gflags : nullptr;
-    if ((st = launch("scan (probe)"))) return st;
-    uint32_t hs = 0;
-    HIP_TRY(p, hipMemcpyAsync(&hs, n_surv, sizeof(hs), hipMemcpyDeviceToHost, s));
-    HIP_TRY(p, hipStreamSynchronize(s));
-    // second pass: the groups with rows still live, all columns, chunked
-    J.groups = J.survivors;
-    J.n_groups = hs;
-    set_chunks(std::max<int64_t>(hs, 1));
-    J.words = nullptr;
-    J.skip = nullptr;
-    J.max_steps = 0;
-    if ((st = launch("scan (survivors)"))) return st;
+    const int64_t seeds = mixed ? 2 : 32;       // items completed first after each ranking
+    int32_t* in = nullptr;                        // nullptr: all groups
+    int32_t* out_buf = J.survivors;
+    int32_t* spare = p->at<int32_t>(p->L.survivors2);
+    int64_t count = n_items;
+    int64_t covered = 0;                          // entries already seen by every listed item
+    int64_t width = (int64_t)probe * gran;
+    for (int round = 0;; ++round) {
+      const int64_t end = std::min<int64_t>(seq_max, covered + width);
+      J.groups = in;
+      J.n_groups = count;
+      J.skip = (round == 0 && order && hcg > 0) ? gflags : nullptr;
+      J.precheck = round > 0;
+      J.survivors = out_buf;
+      launch_init_i32(reinterpret_cast<int32_t*>(n_surv), 1, 0, s);
+      set_window(count, resume ? covered : 0, end);
+      if ((st = launch("scan (window)"))) return st;
+      if (end >= seq_max) break;                  // final for every item
+      uint32_t hs = 0;
+      HIP_TRY(p, hipMemcpyAsync(&hs, n_surv, sizeof(hs), hipMemcpyDeviceToHost, s));
+      HIP_TRY(p, hipStreamSynchronize(s));
+      if (hs == 0) break;
+      covered = end;
+      count = hs;
+      if (near_first) {
+        // rank the survivors into `spare`, complete the best-ranked
+        launch_rank_groups(out_buf, count, item_rows, gsz, alive, best, N, p->at<uint32_t>(p->L.score),
+                           p->at<uint32_t>(p->L.rank_hist), spare, s);
+        LAUNCH_OK(p, "rank");
+        const int64_t k = std::min<int64_t>(count, seeds);
+        J.groups = spare;
+        J.n_groups = k;
+        J.skip = nullptr;
+        J.precheck = 1;
+        set_window(k, resume ? covered : 0, seq_max);
+        if ((st = launch("scan (seeds)"))) return st;
+        if (k == count) break;
+        // the rest continue from the ranked list; their survivors go to out_buf
+        // again (its previous contents were consumed by the ranking)
+        in = spare + k;
+        count -= k;
+        width *= 4;
+      } else {
+        in = out_buf;
+        std::swap(out_buf, spare);
+        width = seq_max;
+      }
+    }
   }
   HIP_TRY(p, hipEventRecord(evs.b, s));
 

@@ -72,34 +72,44 @@ void launch_cand_group_flags(const int32_t* cand, const int32_t* cand_count, int
                              int shift, int32_t* flags, hipStream_t s);
 void launch_bucket_groups(const int32_t* offsets, const int32_t* members, int dict, int shift,
                           int32_t* counts, int32_t* goff, int32_t* groups, hipStream_t s);
+// largest bucket (entries of bgrp per word) into *out
+void launch_max_bucket(const int32_t* goff, int dict, int32_t* out, hipStream_t s);
 
 // ---- scan_fp32.hip ------------------------------------------------------------
-// One launch of the pair scan: n_groups row groups (from `groups`, or 0..n_groups-1)
-// times `chunks` column chunks of cols_per_chunk columns each (consecutive in the
-// matrix order or in the near-first order of spiral.hpp); one wavefront (FP32)
-// or one workgroup (MFMA) per (item, chunk).
+// One launch of the pair scan.  Every row group (an item of 8 rows for the FP32
+// scan, of kWaves * RB blocks of 32 rows for the MFMA scan) has a column
+// sequence: its word's bucket (when `words` is given; Index_Word, eq. (10)),
+// then all column blocks in matrix order or in the near-first order of
+// spiral.hpp.  A launch covers entries [seq_begin, seq_begin + chunks *
+// seq_chunk) of every listed item's sequence, split into `chunks` consecutive
+// chunks that run in parallel; when that reaches the end of an item's sequence
+// the launch is final for it and its rows still live are complete, else they
+// are appended to `survivors` for a later launch that resumes at the next entry.
 struct ScanJob {
   const float* Tp;            // padded series (t_0 at Tp[0])
   int32_t n;
   int64_t N;
-  const int32_t* groups;      // row-group list or nullptr
-  int64_t n_groups;
+  const int32_t* groups;      // item list (FP32: row groups; MFMA: sets of row blocks) or
+                              // nullptr: items 0 .. n_groups - 1
+  int64_t n_groups;           // items in the launch
   int64_t chunks;
-  int64_t cols_per_chunk;     // multiple of 512
-  int32_t max_steps;          // step budget per item (<= 0: none)
-  // visiting order: the group's word bucket first (chunk 0 only), then matrix order
-  const int32_t* words;       // word id per row, or nullptr for matrix order only
+  int64_t seq_begin;          // first sequence entry of this launch
+  int64_t seq_chunk;          // entries per chunk
+  // visiting order
+  const int32_t* words;       // word id per row, or nullptr: no bucket in the sequence
   const int32_t* bgrp_off;    // per word: offsets into bgrp
-  const int32_t* bgrp;        // bucket column groups (column / 8), ascending per word
-  const int32_t* skip;        // per row group: 1 = already searched, or nullptr
-  int32_t near_first;         // 1: the chunks split the near-first order instead of matrix order
+  const int32_t* bgrp;        // bucket column blocks, ascending per word
+  const int32_t* skip;        // per item: 1 = already searched, or nullptr
+  int32_t near_first;         // 1: near-first order after the bucket, 0: matrix order
+  int32_t precheck;           // 1: rows whose published minimum is below the best-so-far
+                              //    leave before any work (later launches of a search)
   // early abandon against the best-so-far
   int32_t abandon;
   uint32_t* bsf;              // float bits of the best-so-far squared distance
   float raise_scale;          // completed rows raise bsf to (their minimum) * raise_scale
   uint32_t* alive;            // per row group: bit r set while row r is searched
-  uint32_t* done;             // per row group: chunks finished
-  int32_t* survivors;         // groups left with live rows when the budget ran out
+  uint32_t* done;             // per item: chunks finished (reset by the last one)
+  int32_t* survivors;         // items left with live rows by a non-final launch
   uint32_t* n_survivors;
   uint64_t* best;             // per row: packed (approximate distance, column) minimum
   uint64_t* pairs;            // pair distances evaluated (non-self, in range)
@@ -132,6 +142,16 @@ void launch_split_blocks(const float* Tp, int64_t N, int n, const float* c32, co
 void launch_row_stats32(const float* Tp, int64_t N, int n, int64_t padded, const double* row_mean,
                         const double* stats, float* c32, float* smu32, float* cn32,
                         hipStream_t s);
+
+// ---- rank.hip -----------------------------------------------------------------
+// Items (item_rows consecutive rows each; alive masks per gsz rows) of `list`,
+// in descending order of the largest published minimum of a live row (score
+// and hist are scratch: count and rank_hist_bins() entries).
+size_t rank_hist_bins();
+void launch_rank_groups(const int32_t* list, int64_t count, int64_t item_rows, int gsz,
+                        const uint32_t* alive,
+                        const uint64_t* best, int64_t N, uint32_t* score, uint32_t* hist,
+                        int32_t* out, hipStream_t s);
 
 // ---- certify.hip --------------------------------------------------------------
 void launch_init_u64(uint64_t* p, int64_t count, uint64_t v, hipStream_t s);

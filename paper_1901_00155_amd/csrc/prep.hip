@@ -311,6 +311,13 @@ __global__ void k_bucket_offsets(const int32_t* __restrict__ counts, int dict,
   goff[dict] = run;
 }
 
+__global__ void k_max_bucket(const int32_t* __restrict__ goff, int dict, int32_t* __restrict__ out) {
+  if (threadIdx.x != 0) return;
+  int32_t m = 0;
+  for (int w = 0; w < dict; ++w) m = max(m, goff[w + 1] - goff[w]);
+  *out = m;
+}
+
 __global__ __launch_bounds__(256) void k_bucket_scatter(const int32_t* __restrict__ offsets,
                                                         const int32_t* __restrict__ members,
                                                         int shift, const int32_t* __restrict__ goff,
@@ -477,6 +484,10 @@ void launch_bucket_groups(const int32_t* offsets, const int32_t* members, int di
   hipLaunchKernelGGL(k_bucket_offsets, dim3(1), dim3(64), 0, s, counts, dict, goff);
   hipLaunchKernelGGL(k_bucket_scatter, dim3(dict), dim3(256), 0, s, offsets, members, shift, goff,
                      groups);
+}
+
+void launch_max_bucket(const int32_t* goff, int dict, int32_t* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_max_bucket, dim3(1), dim3(64), 0, s, goff, dict, out);
 }
 
 void launch_csr(const int32_t* words, const int32_t* hist, int64_t N, int dict,

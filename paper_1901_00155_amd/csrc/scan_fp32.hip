@@ -117,12 +117,13 @@ __device__ __forceinline__ uint64_t load_relaxed64(const uint64_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// One wavefront per work item (row group, column chunk).  The item's column
+// One wavefront per work item (row group, chunk of its column sequence).  The
 // sequence is the bucket of the group's word (Index_Word, eq. (10)), when given,
-// followed by the chunk's share of the column groups, in matrix order or
-// near-first (spiral.hpp); each step covers 64 column groups of 8.  With abandon on, after every step each live row compares its
-// running minimum with the device best-so-far and leaves as soon as it is below
-// (Algorithms 3-4); the leaving row keeps that column as its witness.
+// followed by all column groups in matrix order or near-first (spiral.hpp);
+// each step covers 64 column groups of 8.  With abandon on, after every step
+// each live row compares its running minimum with the device best-so-far and
+// leaves as soon as it is below (Algorithms 3-4); the leaving row keeps that
+// column as its witness.
 __global__ __launch_bounds__(256) void k_scan_fp32(ScanJob J) {
   const int lane = threadIdx.x & 63;
   const int64_t item = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -138,27 +139,37 @@ __global__ __launch_bounds__(256) void k_scan_fp32(ScanJob J) {
 #pragma unroll
   for (int r = 0; r < TM; ++r) valid |= (i0 + r < N ? 1u : 0u) << r;
   uint32_t live = J.abandon ? (load_relaxed(&J.alive[g]) & valid) : valid;
+  if (J.abandon && J.precheck && live) {
+    // a row whose minimum over the columns of earlier launches is already below
+    // the best-so-far cannot be the discord: it leaves with that witness
+    const float b = __builtin_bit_cast(float, load_relaxed(J.bsf));
+    bool below = false;
+    if (lane < TM && ((live >> lane) & 1u)) {
+      const uint64_t k = load_relaxed64(&J.best[i0 + lane]);
+      below = k != kEmptyMin && key_dist(k) < b;
+    }
+    const uint32_t dead = (uint32_t)(__ballot(below) & 0xFFull);
+    if (dead) {
+      if (lane == 0) atomicAnd(&J.alive[g], ~dead);
+      live &= ~dead;
+    }
+  }
 
-  // column sequence: the word's bucket (chunk 0 only), then this chunk's share
-  // of the column groups, in matrix order or near-first
+  // column sequence: this chunk's entries of bucket ++ order
   int64_t nb = 0, b0 = 0;
-  if (J.words && ch == 0) {
+  if (J.words) {
     const int w = J.words[i0];
     b0 = J.bgrp_off[w];
     nb = J.bgrp_off[w + 1] - b0;
   }
   const int64_t NQ = (N + TN - 1) / TN;
   const Spiral sp = make_spiral(i0, i0 + TM, n, NQ, TN);
-  const int64_t npos = J.near_first ? spiral_count(sp) : NQ;
-  const int64_t p0 = ch * (J.cols_per_chunk / TN);
-  const int64_t nm = npos > p0 ? min<int64_t>(npos - p0, J.cols_per_chunk / TN) : 0;
-  const int64_t total_q = nb + nm;
-  int64_t steps = (total_q + 63) / 64;
-  bool exhausted = true;
-  if (J.max_steps > 0 && steps > J.max_steps) {
-    steps = J.max_steps;
-    exhausted = false;
-  }
+  const int64_t len = nb + (J.near_first ? spiral_count(sp) : NQ);
+  const int64_t e0 = J.seq_begin + ch * J.seq_chunk;
+  const int64_t e1 = min<int64_t>(len, e0 + J.seq_chunk);
+  const int64_t total = e1 > e0 ? e1 - e0 : 0;
+  const bool final = J.seq_begin + J.chunks * J.seq_chunk >= len;
+  const int64_t steps = live ? (total + 63) / 64 : 0;
   const float* x = J.Tp + i0;
 
   float bd[TM];
@@ -170,14 +181,11 @@ __global__ __launch_bounds__(256) void k_scan_fp32(ScanJob J) {
   }
   uint32_t cnt = 0;
   for (int64_t s = 0; s < steps && live; ++s) {
-    const int64_t qi = s * 64 + lane;
-    const bool in_seq = qi < total_q;
-    const bool from_bucket = qi < nb;
-    const int64_t pos = p0 + (qi - nb);
+    const int64_t e = e0 + s * 64 + lane;
+    const bool in_seq = e < e1;
     const int64_t q = !in_seq ? 0
-                      : from_bucket ? (int64_t)J.bgrp[b0 + qi]
-                      : J.near_first ? spiral_block(sp, pos) : pos;
-    const int64_t jlim = N;
+                      : e < nb ? (int64_t)J.bgrp[b0 + e]
+                      : J.near_first ? spiral_block(sp, e - nb) : e - nb;
     const int64_t j0 = q * TN;
     float acc[TM][TN];
     block8x8(x, J.Tp + j0, n, acc);
@@ -188,7 +196,7 @@ __global__ __launch_bounds__(256) void k_scan_fp32(ScanJob J) {
       for (int c = 0; c < TN; ++c) {
         const int64_t j = j0 + c;
         const int64_t dij = i > j ? i - j : j - i;
-        const bool ok = in_seq && (j < jlim) && (dij >= n) && ((valid >> r) & 1u);
+        const bool ok = in_seq && (j < N) && (dij >= n) && ((valid >> r) & 1u);
         cnt += ok;
         if (ok && acc[r][c] < bd[r]) {
           bd[r] = acc[r][c];
@@ -230,33 +238,28 @@ __global__ __launch_bounds__(256) void k_scan_fp32(ScanJob J) {
   if (lane == 0 && c64) atomicAdd((unsigned long long*)J.pairs, (unsigned long long)c64);
   if (!J.abandon) return;
 
-  if (J.chunks == 1) {
-    if (exhausted) {
-      // every column seen: the live rows' minima are complete
-#pragma unroll
-      for (int r = 0; r < TM; ++r) {
-        if ((live >> r) & 1u) {
-          const float m = wave_min_f32(bd[r]);
-          if (lane == 0 && m < __builtin_inff())
-            atomicMax(J.bsf, __builtin_bit_cast(uint32_t, m * J.raise_scale));
-        }
-      }
-    } else if (live && lane == 0) {
-      J.survivors[atomicAdd(J.n_survivors, 1u)] = (int32_t)g;
-    }
-    return;
+  // the item's last chunk to finish decides: complete rows raise the best-so-far
+  // with their minimum over the whole sequence (all launches), rows still live
+  // after a non-final launch make the group a survivor
+  uint32_t fin = live;
+  if (J.chunks > 1) {
+    __threadfence();
+    uint32_t prev = 0;
+    if (lane == 0) prev = atomicAdd(&J.done[g], 1u);
+    prev = __shfl(prev, 0, 64);
+    if (prev + 1 != (uint32_t)J.chunks) return;
+    if (lane == 0) atomicExch(&J.done[g], 0u);   // ready for the next launch
+    __threadfence();
+    fin = load_relaxed(&J.alive[g]) & valid;
   }
-  // chunked: the last chunk of the group to finish raises the best-so-far
-  __threadfence();
-  uint32_t prev = 0;
-  if (lane == 0) prev = atomicAdd(&J.done[g], 1u);
-  prev = __shfl(prev, 0, 64);
-  if (prev + 1 != (uint32_t)J.chunks) return;
-  __threadfence();
-  const uint32_t fin = load_relaxed(&J.alive[g]) & valid;
-  if (lane < TM && ((fin >> lane) & 1u)) {
-    const uint64_t k = load_relaxed64(&J.best[i0 + lane]);
-    if (k != kEmptyMin) atomicMax(J.bsf, __builtin_bit_cast(uint32_t, key_dist(k) * J.raise_scale));
+  if (!fin) return;
+  if (final) {
+    if (lane < TM && ((fin >> lane) & 1u)) {
+      const uint64_t k = load_relaxed64(&J.best[i0 + lane]);
+      if (k != kEmptyMin) atomicMax(J.bsf, __builtin_bit_cast(uint32_t, key_dist(k) * J.raise_scale));
+    }
+  } else if (lane == 0) {
+    J.survivors[atomicAdd(J.n_survivors, 1u)] = (int32_t)g;
   }
 }
 

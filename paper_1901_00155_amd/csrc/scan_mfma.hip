@@ -136,11 +136,12 @@ __global__ __launch_bounds__(256) void k_split_blocks(const float* __restrict__ 
   }
 }
 
-// One workgroup per work item: kWaves * RB row blocks (consecutive entries of the
-// group list) against one column chunk; the column sequence is the first
-// entry's word bucket (32-column blocks) when given, then the chunk's share of
-// the column blocks in matrix order or near-first (spiral.hpp), one 32-column
-// block per step.
+// One workgroup per (item, chunk of its column sequence).  An item is a fixed
+// set of kWaves * RB consecutive row blocks (the list holds item numbers), so
+// its sequence is the same in every launch and a search can resume it: the
+// word bucket (32-column blocks) of its first row, when given, then the column
+// blocks in matrix order or near-first (spiral.hpp) around the item's rows,
+// one 32-column block per step.
 template <int KS, int RB>
 __global__ __launch_bounds__(kWaves<KS> * 64, (KS <= 16 ? 2 : 1)) void k_scan_mfma(ScanJob J,
                                                                                   MixedRows R) {
@@ -156,31 +157,44 @@ __global__ __launch_bounds__(kWaves<KS> * 64, (KS <= 16 ? 2 : 1)) void k_scan_mf
   const int h = lane >> 5;
   const int rl = lane & 31;
   const int64_t per_item = WAVES * RB;
-  const int64_t items_per_chunk = (J.n_groups + per_item - 1) / per_item;
   const int64_t li = blockIdx.x / J.chunks;
   const int64_t ch = blockIdx.x - li * J.chunks;
-  if (li >= items_per_chunk) return;
+  if (li >= J.n_groups) return;
   const int64_t N = J.N;
   const int n = J.n;
+  // the item: row blocks item * per_item .. + per_item - 1, always the same set
+  const int64_t item = __builtin_amdgcn_readfirstlane((int)(J.groups ? J.groups[li] : li));
+  if (J.skip && J.skip[item]) return;
 
   int64_t g[RB];
   uint32_t valid[RB], live[RB];
   bool any_live = false;
 #pragma unroll
   for (int b = 0; b < RB; ++b) {
-    const int64_t e = li * per_item + wv * RB + b;
-    g[b] = -1;
+    g[b] = item * per_item + wv * RB + b;
     valid[b] = live[b] = 0;
-    if (e < J.n_groups) {
-      g[b] = __builtin_amdgcn_readfirstlane((int)(J.groups ? J.groups[e] : e));
-      if (J.skip && J.skip[g[b]]) g[b] = -1;
-    }
+    if (g[b] * BM >= N) g[b] = -1;
     if (g[b] >= 0) {
       const int64_t r0 = g[b] * BM;
       const int64_t rows = min<int64_t>(BM, N - r0);
       valid[b] = rows >= 32 ? 0xFFFFFFFFu : ((1u << rows) - 1u);
       live[b] = J.abandon ? __builtin_amdgcn_readfirstlane(load_relaxed(&J.alive[g[b]]) & valid[b])
                           : valid[b];
+      if (J.abandon && J.precheck && live[b]) {
+        // rows whose minimum over the columns of earlier launches is already
+        // below the best-so-far cannot be the discord: they leave with that witness
+        const float bs = __builtin_bit_cast(float, load_relaxed(J.bsf));
+        bool below = false;
+        if (h == 0 && ((live[b] >> rl) & 1u)) {
+          const uint64_t k = load_relaxed64(&J.best[g[b] * BM + rl]);
+          below = k != kEmptyMin && key_dist(k) < bs;
+        }
+        const uint32_t dead = (uint32_t)(__ballot(below) & 0xFFFFFFFFull);
+        if (dead) {
+          if (lane == 0) atomicAnd(&J.alive[g[b]], ~dead);
+          live[b] &= ~dead;
+        }
+      }
       any_live |= live[b] != 0;
     }
   }
@@ -206,39 +220,24 @@ __global__ __launch_bounds__(kWaves<KS> * 64, (KS <= 16 ? 2 : 1)) void k_scan_mf
 
   // ---- column sequence (uniform over the workgroup) ---------------------------
   int64_t nb = 0, b0 = 0;
-  if (J.words && ch == 0) {
-    const int64_t e0 = li * per_item;
-    const int64_t gf = J.groups ? J.groups[e0] : e0;
-    const int w = J.words[gf * BM];
+  const int64_t r_first = item * per_item * BM;
+  if (J.words) {
+    const int w = J.words[r_first];
     b0 = J.bgrp_off[w];
     nb = J.bgrp_off[w + 1] - b0;
   }
   const int64_t NQ = (N + BN - 1) / BN;
   Spiral sp{0, -1, NQ, 0};
-  if (J.near_first) {
-    // outward from the span of all the item's row blocks (its list entries may
-    // be scattered: the span keeps every needed block in the order)
-    int64_t r0 = N, r1 = 0;
-    for (int64_t e = li * per_item; e < min<int64_t>(J.n_groups, (li + 1) * per_item); ++e) {
-      const int64_t ge = J.groups ? J.groups[e] : e;
-      r0 = min<int64_t>(r0, ge * BM);
-      r1 = max<int64_t>(r1, ge * BM + BM);
-    }
-    sp = make_spiral(r0, r1, n, NQ, BN);
-  }
-  const int64_t npos = spiral_count(sp);   // NQ in matrix order
-  const int64_t p0 = ch * (J.cols_per_chunk / BN);
-  const int64_t nm = npos > p0 ? min<int64_t>(npos - p0, J.cols_per_chunk / BN) : 0;
-  const int64_t total_q = nb + nm;
-  int64_t steps = total_q;
-  bool exhausted = true;
-  if (J.max_steps > 0 && steps > J.max_steps) {
-    steps = J.max_steps;
-    exhausted = false;
-  }
+  if (J.near_first) sp = make_spiral(r_first, r_first + per_item * BM, n, NQ, BN);
+  const int64_t len = nb + spiral_count(sp);   // spiral_count = NQ in matrix order
+  const int64_t e0 = J.seq_begin + ch * J.seq_chunk;
+  const int64_t e1 = min<int64_t>(len, e0 + J.seq_chunk);
+  int64_t steps = e1 > e0 ? e1 - e0 : 0;
+  const bool final = J.seq_begin + J.chunks * J.seq_chunk >= len;
   auto block_of = [&](int64_t s) -> int64_t {
-    return s < nb ? (int64_t)__builtin_amdgcn_readfirstlane(J.bgrp[b0 + s])
-                  : spiral_block(sp, p0 + (s - nb));
+    const int64_t e = e0 + s;
+    return e < nb ? (int64_t)__builtin_amdgcn_readfirstlane(J.bgrp[b0 + e])
+                  : spiral_block(sp, e - nb);
   };
 
   // workgroup-wide: is any row of any wavefront still live?
@@ -373,7 +372,7 @@ __global__ __launch_bounds__(kWaves<KS> * 64, (KS <= 16 ? 2 : 1)) void k_scan_mf
           const uint32_t dead =
               (uint32_t)(__ballot(m < bsf && h == 0) & 0xFFFFFFFFull) & live[b];
           if (dead) {
-            uint64_t key = rj[b] < 0 ? kEmptyMin : pack_min(rmin[b], (uint32_t)rj[b]);
+            uint64_t key = rj[b] < 0 ? kEmptyMin : pack_min(fmaxf(rmin[b], 0.0f), (uint32_t)rj[b]);
             const uint64_t o = __shfl_xor(key, 32, 64);
             key = o < key ? o : key;
             if (h == 0 && ((dead >> rl) & 1u))
@@ -406,7 +405,9 @@ __global__ __launch_bounds__(kWaves<KS> * 64, (KS <= 16 ? 2 : 1)) void k_scan_mf
 #pragma unroll
   for (int b = 0; b < RB; ++b) {
     if (g[b] < 0) continue;
-    uint64_t key = rj[b] < 0 ? kEmptyMin : pack_min(rmin[b], (uint32_t)rj[b]);
+    // (the split products can round a near-zero distance below zero; keys hold
+    // non-negative distances so that they order like the values)
+    uint64_t key = rj[b] < 0 ? kEmptyMin : pack_min(fmaxf(rmin[b], 0.0f), (uint32_t)rj[b]);
     const uint64_t o = __shfl_xor(key, 32, 64);
     key = o < key ? o : key;
     if (h == 0 && ((live[b] >> rl) & 1u) && key != kEmptyMin)
@@ -417,38 +418,51 @@ __global__ __launch_bounds__(kWaves<KS> * 64, (KS <= 16 ? 2 : 1)) void k_scan_mf
   if (lane == 0 && c64) atomicAdd((unsigned long long*)J.pairs, (unsigned long long)c64);
   if (!J.abandon) return;
 
+  // the item's last chunk to finish decides: complete rows raise the
+  // best-so-far with their minimum over all launches; rows still live after a
+  // non-final launch make the item a survivor
+  __shared__ uint32_t tail[WAVES + 1];
+  if (J.chunks > 1) {
+    __threadfence();
+    __syncthreads();                              // every wavefront has published
+    if (threadIdx.x == 0) {
+      const uint32_t prev = atomicAdd(&J.done[item], 1u);
+      const bool last = prev + 1 == (uint32_t)J.chunks;
+      if (last) atomicExch(&J.done[item], 0u);   // ready for the next launch
+      tail[WAVES] = last ? 1u : 0u;
+    }
+    __syncthreads();
+    if (!tail[WAVES]) return;
+    __threadfence();
+  }
+  bool wave_fin = false;
 #pragma unroll
   for (int b = 0; b < RB; ++b) {
     if (g[b] < 0) continue;
-    if (J.chunks == 1) {
-      if (exhausted) {
-        const float m = fminf(rmin[b], __shfl_xor(rmin[b], 32, 64));
-        if (h == 0 && ((live[b] >> rl) & 1u) && m < __builtin_inff())
-          atomicMax(J.bsf, __builtin_bit_cast(uint32_t, m * J.raise_scale));
-      } else if (live[b] && lane == 0) {
-        J.survivors[atomicAdd(J.n_survivors, 1u)] = (int32_t)g[b];
-      }
-      continue;
-    }
-    // chunked: the last chunk of the group to finish raises the best-so-far
-    __threadfence();
-    uint32_t prev = 0;
-    if (lane == 0) prev = atomicAdd(&J.done[g[b]], 1u);
-    prev = __shfl(prev, 0, 64);
-    if (prev + 1 != (uint32_t)J.chunks) continue;
-    __threadfence();
-    const uint32_t fin = load_relaxed(&J.alive[g[b]]) & valid[b];
-    if (h == 0 && ((fin >> rl) & 1u)) {
+    const uint32_t fin =
+        J.chunks > 1 ? __builtin_amdgcn_readfirstlane(load_relaxed(&J.alive[g[b]])) & valid[b]
+                     : live[b];
+    if (!fin) continue;
+    wave_fin = true;
+    if (final && h == 0 && ((fin >> rl) & 1u)) {
       const uint64_t k = load_relaxed64(&J.best[g[b] * BM + rl]);
-      if (k != kEmptyMin) atomicMax(J.bsf, __builtin_bit_cast(uint32_t, key_dist(k) * J.raise_scale));
+      if (k != kEmptyMin)
+        atomicMax(J.bsf, __builtin_bit_cast(uint32_t, key_dist(k) * J.raise_scale));
     }
+  }
+  if (final) return;
+  if (lane == 0) tail[wv] = wave_fin ? 1u : 0u;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    bool any = false;
+    for (int w = 0; w < WAVES; ++w) any |= tail[w] != 0;
+    if (any) J.survivors[atomicAdd(J.n_survivors, 1u)] = (int32_t)item;
   }
 }
 
 template <int KS, int RB>
 void launch_kr(const ScanJob& J, const MixedRows& R, hipStream_t s) {
-  const int64_t per_item = kWaves<KS> * RB;
-  const int64_t blocks = ((J.n_groups + per_item - 1) / per_item) * J.chunks;
+  const int64_t blocks = J.n_groups * J.chunks;
   if (blocks <= 0) return;
   const size_t lds = sizeof(bf16x8) * 2 * Blk<KS>::SLOTS;
   // the LDS opt-in is per kernel and set once per process; the initialisation of a

@@ -76,3 +76,15 @@ def test_near_first_order_covers_every_needed_block(tmp_path):
                     "-o", exe], check=True, timeout=120)
     r = subprocess.run([exe], capture_output=True, text=True, timeout=120)
     assert r.returncode == 0 and "OK" in r.stdout, r.stdout + r.stderr
+
+
+def test_library_has_no_unresolved_internal_symbols(dd):
+    """Every internal function the library calls is linked in (a source file
+    missing from the build would leave an undefined dd:: symbol)."""
+    import shutil
+    import subprocess
+    nm = shutil.which("nm")
+    if not nm:
+        pytest.skip("nm not available")
+    out = subprocess.run([nm, "-uC", dd.LIB_PATH], capture_output=True, text=True, check=True).stdout
+    assert "dd::" not in out, [ln for ln in out.splitlines() if "dd::" in ln]
