@@ -69,9 +69,10 @@ typedef struct {
                            (mixed precision; 1..32)                                  */
     int32_t paa_w;      /* PAA segments w of eq. (3) (1..8; min(w, n) is used)       */
     int32_t alphabet;   /* SAX alphabet size |A| of eq. (4) (2..8, |A|^w <= 256)      */
-    int32_t probe_steps;/* abandon mode: steps of 512 columns each row group walks
-                           before the rows still live are rescanned in parallel
-                           column chunks (0: library default)                     */
+    int32_t probe_steps;/* abandon mode: the first window of every row's column
+                           sequence, in steps of 512 columns; rows still live
+                           then continue in later windows (0: library default,
+                           2 (FP32) or 4 (split-BF16) for order 2, else 16)      */
     int32_t reserved;
 } discord_opts;
 

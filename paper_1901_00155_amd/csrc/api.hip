@@ -519,12 +519,12 @@ int discord_search(discord_plan p, discord_result* out) {
     // rows still live continue.  PhiDD and matrix order: one more launch over
     // the rest of the sequence.  Near-first order: the survivors are ranked by
     // their rows' published minima, the best-ranked are completed at once (to
-    // raise the best-so-far), and the rest continue in windows 4x longer each
+    // raise the best-so-far), and the rest continue in windows twice as long each
     // time.  Every launch resumes an item where its previous window ended, and
     // rows already below the best-so-far leave before any work.
     const bool resume = true;
-    const int probe = p->opts.probe_steps > 0 ? p->opts.probe_steps : 16;
-    const int64_t seeds = mixed ? 2 : 32;       // items completed first after each ranking
+    const int probe = p->opts.probe_steps > 0 ? p->opts.probe_steps : (near_first ? (mixed ? 4 : 2) : 16);
+    const int64_t seeds = mixed ? 8 : 128;      // items completed first after each ranking
     int32_t* in = nullptr;                        // nullptr: all groups
     int32_t* out_buf = J.survivors;
     int32_t* spare = p->at<int32_t>(p->L.survivors2);
@@ -565,7 +565,7 @@ int discord_search(discord_plan p, discord_result* out) {
         // again (its previous contents were consumed by the ranking)
         in = spare + k;
         count -= k;
-        width *= 4;
+        width *= 2;
       } else {
         in = out_buf;
         std::swap(out_buf, spare);
