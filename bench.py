@@ -262,6 +262,26 @@ def main():
                     print(f"# order {oname} {prec}: {so * 1e3:.1f} ms", file=sys.stderr,
                           flush=True)
             out["time_to_discord_by_order"] = orders
+            # the large single instance: m = 2^22, n = 512, split-BF16 matrix resident
+            wl = workloads.large4m()
+            Tl = torch.from_numpy(wl.series).cuda()
+            Pl = pair_count(wl.m - wl.n + 1, wl.n)
+            large = {"workload": f"{wl.name}: m={wl.m} sinusoids + walk + noise, "
+                                 f"{len(wl.anomalies)} planted anomalies, window n={wl.n}",
+                     "brute_force_pairs": Pl}
+            ref_l = None
+            for prec in ("bf16x3", "fp32"):
+                sl, rl = time_steps(dd, Tl, wl.n, prec, True, 2, 1, args.order)
+                y = rl[-1]
+                if ref_l is None:
+                    ref_l = (int(y.index), y.d2)
+                assert (int(y.index), y.d2) == ref_l, "precisions disagree on the large instance"
+                large[prec] = {"time_to_discord_ms": sl * 1e3, "pairs_evaluated": float(y.pairs_evaluated),
+                               "brute_force_equiv_pairs_per_s": Pl / sl,
+                               "index": int(y.index), "distance": float(y.distance)}
+                print(f"# large {prec}: {sl * 1e3:.1f} ms", file=sys.stderr, flush=True)
+            out["large_instance"] = large
+            del Tl
         full = {}
         for prec in ("fp32", "bf16x3"):
             _, rf = time_steps(dd, Td, n, prec, False, 1, 0)

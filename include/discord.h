@@ -65,8 +65,11 @@ typedef struct {
                            2: Cand rows first, then each row's columns nearest in
                               time first, alternating forward and backward
                            0: matrix order only                                    */
-    int32_t topk;       /* approximate candidates per finalist row rescored in FP64
-                           (mixed precision; 1..32)                                  */
+    int32_t topk;       /* 1..32, validated but unused: instead of rescoring the k
+                           best approximate candidates of finalist rows, the FP64
+                           certification rescores every row's best candidate (its
+                           witness) and rescans in full every row that test cannot
+                           clear (see discord_search)                              */
     int32_t paa_w;      /* PAA segments w of eq. (3) (1..8; min(w, n) is used)       */
     int32_t alphabet;   /* SAX alphabet size |A| of eq. (4) (2..8, |A|^w <= 256)      */
     int32_t probe_steps;/* abandon mode: the first window of every row's column
@@ -123,7 +126,13 @@ int discord_prepare(const float* T, int64_t m, int32_t n, const discord_opts* op
 
 /* Search stage (Algorithms 3 and 4) and FP64 certification.  Blocks until the
  * result is on the host.  May be called repeatedly on one plan (each call redoes
- * the whole search; the prepared structures are reused). */
+ * the whole search; the prepared structures are reused).
+ * Certification: the fully scanned row with the largest approximate NN is
+ * rescanned in FP64 (exact NN L); every other row's witness distance is
+ * recomputed in FP64 and clears the row when below L (or equal, at a higher
+ * index); rows not cleared are rescanned in FP64; the answer is the FP64 argmax
+ * with the lowest index on ties.  No error bound of the approximate arithmetic
+ * is relied on. */
 int discord_search(discord_plan plan, discord_result* out);
 
 /* Frees the plan and the device memory it owns.  NULL is ignored. */

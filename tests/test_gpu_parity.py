@@ -277,3 +277,19 @@ def test_noisy1m_both_precisions_agree(gpu):
             _certify(w, r, wit)
             out[precision, order] = (r.index, r.nn_index, r.d2)
     assert len(set(out.values())) == 1, out
+
+
+def test_large4m_certificate_both_precisions(gpu):
+    """m = 2^22, n = 512 (three sinusoids + walk + noise, eight planted
+    anomalies): the split-BF16 subsequence matrix stays resident in HBM for the
+    search; both precisions give the same discord, certified in FP64 against
+    every row's witness."""
+    w = workloads.large4m()
+    out = {}
+    for precision in PRECS:
+        with gpu.Plan(w.series, w.n, precision=precision) as p:
+            r = p.search()
+            wit = p.copy("nn_witness")
+        _certify(w, r, wit)
+        out[precision] = (r.index, r.nn_index, r.d2)
+    assert out["fp32"] == out["bf16x3"], out
