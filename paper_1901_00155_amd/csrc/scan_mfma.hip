@@ -146,10 +146,13 @@ template <int KS, int RB>
 __global__ __launch_bounds__(kWaves<KS> * 64, (KS <= 16 ? 2 : 1)) void k_scan_mfma(ScanJob J,
                                                                                   MixedRows R) {
   constexpr int WAVES = kWaves<KS>;
-  extern __shared__ bf16x8 smem[];   // two column-block buffers of Blk<KS>::SLOTS slots
+  // two stages, each a column block (Blk<KS>::SLOTS slots) followed by the
+  // block's 32 column values sqrt(n) (mean - mu) (8 slots)
+  extern __shared__ bf16x8 smem[];
   __shared__ uint32_t wave_live[2 * WAVES];
   constexpr int SLOTS = Blk<KS>::SLOTS;
   constexpr int PER_T = Blk<KS>::PER_T;
+  constexpr int STAGE = SLOTS + 8;
   const bf16x8* __restrict__ S = reinterpret_cast<const bf16x8*>(R.sblk);
 
   const int lane = threadIdx.x & 63;
@@ -257,7 +260,7 @@ __global__ __launch_bounds__(kWaves<KS> * 64, (KS <= 16 ? 2 : 1)) void k_scan_mf
   }
   uint32_t cnt = 0;
 
-  bf16x8 pre[PER_T];
+  bf16x8 pre[PER_T], pre_m;
   auto fetch = [&](int64_t q) {
     const bf16x8* src = S + q * SLOTS;
 #pragma unroll
@@ -265,6 +268,7 @@ __global__ __launch_bounds__(kWaves<KS> * 64, (KS <= 16 ? 2 : 1)) void k_scan_mf
       const int k = i * WAVES * 64 + (int)threadIdx.x;
       if (k < SLOTS) pre[i] = src[k];
     }
+    if (threadIdx.x < 8) pre_m = reinterpret_cast<const bf16x8*>(R.smu + q * BN)[threadIdx.x];
   };
   auto store = [&](bf16x8* dst) {
 #pragma unroll
@@ -272,6 +276,7 @@ __global__ __launch_bounds__(kWaves<KS> * 64, (KS <= 16 ? 2 : 1)) void k_scan_mf
       const int k = i * WAVES * 64 + (int)threadIdx.x;
       if (k < SLOTS) dst[k] = pre[i];
     }
+    if (threadIdx.x < 8) dst[SLOTS + threadIdx.x] = pre_m;
   };
   if (steps > 0) {
     fetch(block_of(0));
@@ -283,7 +288,7 @@ __global__ __launch_bounds__(kWaves<KS> * 64, (KS <= 16 ? 2 : 1)) void k_scan_mf
     if (s + 1 < steps) fetch(block_of(s + 1));
     const int64_t jlim = N;
     const int64_t j0 = block_of(s) * BN;
-    const bf16x8* buf = smem + cur * SLOTS;
+    const bf16x8* buf = smem + cur * STAGE;
 
     bool go = false;
 #pragma unroll
@@ -316,7 +321,7 @@ __global__ __launch_bounds__(kWaves<KS> * 64, (KS <= 16 ? 2 : 1)) void k_scan_mf
       float smc[16];
 #pragma unroll
       for (int qd = 0; qd < 4; ++qd) {
-        const float4 m = *reinterpret_cast<const float4*>(R.smu + j0 + 8 * qd + 4 * h);
+        const float4 m = reinterpret_cast<const float4*>(buf + SLOTS)[2 * qd + h];
         smc[4 * qd + 0] = m.x; smc[4 * qd + 1] = m.y; smc[4 * qd + 2] = m.z; smc[4 * qd + 3] = m.w;
       }
 #pragma unroll
@@ -385,7 +390,7 @@ __global__ __launch_bounds__(kWaves<KS> * 64, (KS <= 16 ? 2 : 1)) void k_scan_mf
         }
       }
     }
-    if (s + 1 < steps) store(smem + (cur ^ 1) * SLOTS);
+    if (s + 1 < steps) store(smem + (cur ^ 1) * STAGE);
     // all wavefronts agree on leaving once no row of the workgroup is live
     bool mine = false;
 #pragma unroll
@@ -464,7 +469,7 @@ template <int KS, int RB>
 void launch_kr(const ScanJob& J, const MixedRows& R, hipStream_t s) {
   const int64_t blocks = J.n_groups * J.chunks;
   if (blocks <= 0) return;
-  const size_t lds = sizeof(bf16x8) * 2 * Blk<KS>::SLOTS;
+  const size_t lds = sizeof(bf16x8) * 2 * (Blk<KS>::SLOTS + 8);
   // the LDS opt-in is per kernel and set once per process; the initialisation of a
   // function-local static is thread-safe, so concurrent first launches from several
   // host threads (one per serving slot) do not race
