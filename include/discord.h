@@ -101,7 +101,7 @@ typedef struct {
     uint64_t cand_rows;       /* |Cand| (eq. 7)                                       */
     double   ms_prepare;      /* device time of discord_prepare (HIP events)         */
     double   ms_search;       /* device time of discord_search (HIP events)          */
-    double   ms_scan;         /* of which: approximate scan kernels                  */
+    double   ms_scan;         /* of which: the approximate scan launches, summed     */
 } discord_result;
 
 typedef struct discord_plan_s* discord_plan;

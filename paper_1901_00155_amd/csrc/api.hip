@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "../../include/discord.h"
 #include "internal.hpp"
@@ -209,24 +210,47 @@ bool is_device_pointer(const void* p) {
   return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
 }
 
+// HIP events, reused: each host thread keeps a pool that grows as needed and
+// lives until the process ends (a serving worker times every request with the
+// same events instead of creating and destroying them per call).  A search or
+// preparation synchronises its stream before it returns, so the events are idle
+// whenever the next call on the thread takes them.
+struct EventPool {
+  int device = -1;
+  std::vector<hipEvent_t> ev;
+  hipEvent_t get(size_t k) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    if (dev != device) {   // another device: start a new pool (the old events stay valid)
+      ev.clear();
+      device = dev;
+    }
+    while (ev.size() <= k) {
+      hipEvent_t e = nullptr;
+      if (hipEventCreate(&e) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+      }
+      ev.push_back(e);
+    }
+    return ev[k];
+  }
+};
+thread_local EventPool g_events;
+
+float elapsed_ms(hipEvent_t a, hipEvent_t b) {
+  float t = 0.f;
+  if (!a || !b || hipEventElapsedTime(&t, a, b) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0.f;
+  }
+  return t;
+}
+
 struct EventPair {
   hipEvent_t a = nullptr, b = nullptr;
-  EventPair() {
-    (void)hipEventCreate(&a);
-    (void)hipEventCreate(&b);
-  }
-  ~EventPair() {
-    if (a) (void)hipEventDestroy(a);
-    if (b) (void)hipEventDestroy(b);
-  }
-  float ms() {
-    float t = 0.f;
-    if (hipEventElapsedTime(&t, a, b) != hipSuccess) {
-      (void)hipGetLastError();
-      return 0.f;
-    }
-    return t;
-  }
+  explicit EventPair(size_t slot) : a(g_events.get(2 * slot)), b(g_events.get(2 * slot + 1)) {}
+  float ms() const { return elapsed_ms(a, b); }
 };
 
 int rows_nn_batch(discord_plan p, const int64_t* d_rows, int64_t count) {
@@ -322,9 +346,10 @@ int discord_prepare(const float* T, int64_t m, int32_t n, const discord_opts* op
     p->own_arena = true;
   }
   int st = DISCORD_OK;
-  EventPair ev;
+  EventPair ev(0);
   hipStream_t s = p->stream;
   auto run = [&]() -> int {
+    if (!ev.a || !ev.b) return fail(p, DISCORD_EDEVICE, "hipEventCreate failed");
     HIP_TRY(p, hipEventRecord(ev.a, s));
     // padded series: zero pads, then the values
     float* Tbase = p->at<float>(p->L.T);
@@ -399,7 +424,11 @@ int discord_search(discord_plan p, discord_result* out) {
   hipStream_t s = p->stream;
   const int64_t N = p->N;
   const int n = p->n;
-  EventPair ev, evs;
+  EventPair ev(0);
+  if (!ev.a || !ev.b) return fail(p, DISCORD_EDEVICE, "hipEventCreate failed");
+  // scan launches are timed one by one (pairs 1, 2, ...): their sum is ms_scan
+  int timed = 0;
+  constexpr int kMaxTimed = 256;
   discord_result r;
   std::memset(&r, 0, sizeof(r));
   HIP_TRY(p, hipSetDevice(p->device));
@@ -432,7 +461,6 @@ int discord_search(discord_plan p, discord_result* out) {
   launch_init_u64(pairs, 1, 0, s);
   launch_init_i32(reinterpret_cast<int32_t*>(bsf), 1, 0, s);
   // ---- approximate scan (Algorithms 3 and 4) ----------------------------------
-  HIP_TRY(p, hipEventRecord(evs.a, s));
   ScanJob J{};
   J.Tp = p->Tp();
   J.n = n;
@@ -459,12 +487,19 @@ int discord_search(discord_plan p, discord_result* out) {
     J.raise_scale = (float)(1.0 - ((n + 3) * std::ldexp(1.0, -24) * 1.01 + std::ldexp(1.0, -22)));
   }
   auto launch = [&](const char* what) -> int {
+    EventPair t(1 + timed);
+    const bool timing = timed < kMaxTimed && t.a && t.b;
+    if (timing) HIP_TRY(p, hipEventRecord(t.a, s));
     if (mixed) {
       if (!launch_scan_mfma(J, R, s)) return fail(p, DISCORD_ERANGE, "window too long for bf16x3");
     } else {
       launch_scan_fp32(J, s);
     }
     LAUNCH_OK(p, what);
+    if (timing) {
+      HIP_TRY(p, hipEventRecord(t.b, s));
+      ++timed;
+    }
     return DISCORD_OK;
   };
   // Sequence entries are column groups of 8 (FP32) or blocks of 32 (MFMA); a
@@ -573,7 +608,6 @@ int discord_search(discord_plan p, discord_result* out) {
       }
     }
   }
-  HIP_TRY(p, hipEventRecord(evs.b, s));
 
   // ---- certification in FP64 ---------------------------------------------------
   float* nn_approx = p->at<float>(p->L.nn_approx);
@@ -636,7 +670,7 @@ int discord_search(discord_plan p, discord_result* out) {
   r.cand_rows = (uint64_t)p->cand_count;
   r.ms_prepare = p->ms_prepare;
   r.ms_search = ev.ms();
-  r.ms_scan = evs.ms();
+  for (int k = 0; k < timed; ++k) r.ms_scan += EventPair(1 + k).ms();
   p->searched = true;
   *out = r;
   return DISCORD_OK;
