@@ -186,21 +186,43 @@ __global__ __launch_bounds__(256) void k_scan_fp32(ScanJob J) {
     const int64_t q = !in_seq ? 0
                       : e < nb ? (int64_t)J.bgrp[b0 + e]
                       : J.near_first ? spiral_block(sp, e - nb) : e - nb;
-    const int64_t j0 = q * TN;
+    const int32_t j0 = (int32_t)(q * TN);   // N < 2^31 (checked at prepare)
     float acc[TM][TN];
     block8x8(x, J.Tp + j0, n, acc);
+    // blocks inside the matrix and clear of the exclusion band need no mask:
+    // each row's minimum over the 8 columns first, its column only on improvement
+    const bool clean = in_seq && valid == 0xFFu && j0 + TN <= N &&
+                       (j0 >= (int32_t)i0 + TM - 1 + n || j0 + TN - 1 + n <= (int32_t)i0);
+    if (clean) {
+      cnt += TM * TN;
 #pragma unroll
-    for (int r = 0; r < TM; ++r) {
-      const int64_t i = i0 + r;
+      for (int r = 0; r < TM; ++r) {
+        float m = acc[r][0];
 #pragma unroll
-      for (int c = 0; c < TN; ++c) {
-        const int64_t j = j0 + c;
-        const int64_t dij = i > j ? i - j : j - i;
-        const bool ok = in_seq && (j < N) && (dij >= n) && ((valid >> r) & 1u);
-        cnt += ok;
-        if (ok && acc[r][c] < bd[r]) {
-          bd[r] = acc[r][c];
-          bj[r] = (int32_t)j;
+        for (int c = 1; c < TN; ++c) m = fminf(m, acc[r][c]);
+        if (m < bd[r]) {
+          int32_t jj = j0;
+#pragma unroll
+          for (int c = TN - 1; c >= 0; --c)
+            if (acc[r][c] == m) jj = j0 + c;
+          bd[r] = m;
+          bj[r] = jj;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < TM; ++r) {
+        const int32_t i = (int32_t)i0 + r;
+#pragma unroll
+        for (int c = 0; c < TN; ++c) {
+          const int32_t j = j0 + c;
+          const int32_t dij = i > j ? i - j : j - i;
+          const bool ok = in_seq && (j < N) && (dij >= n) && ((valid >> r) & 1u);
+          cnt += ok;
+          if (ok && acc[r][c] < bd[r]) {
+            bd[r] = acc[r][c];
+            bj[r] = j;
+          }
         }
       }
     }
