@@ -105,3 +105,37 @@ def test_open_loop_replay_completes(gpu):
     assert all(c["result"]["certified"] == 1 for c in out["records"].values())
     assert sm["p50_ms"] <= sm["p99_ms"]
     print(sm)
+
+
+def test_concurrent_submitters_many_slots(gpu):
+    """Two host threads submit at once into a server with 8 slots (more streams
+    than hardware queues); every result equals the request run alone."""
+    import threading
+    dd = gpu
+    reqs = _requests(count=48, seed=21, log2_max=15)
+    alone = {}
+    for r in reqs:
+        with dd.Plan(r.series, r.n, precision="bf16x3") as p:
+            a = p.search()
+            alone[r.tag] = (a.index, a.nn_index, a.d2)
+    with dd.Server(4 << 30, slots=8, precision="bf16x3") as s:
+        status = []
+
+        def submit(part):
+            for r in part:
+                status.append(s.submit(r.series, r.n, r.tag))
+
+        threads = [threading.Thread(target=submit, args=(reqs[k::2],)) for k in range(2)]
+        for t in threads:
+            t.start()
+        for t in threads:
+            t.join()
+        assert status.count(0) == len(reqs)
+        mix = _drain(s, len(reqs))
+        st = s.stats()
+    assert st["peak_running"] >= 2 and st["failed"] == 0 and st["bytes_in_use"] == 0
+    for r in reqs:
+        c = mix[r.tag]
+        assert c["status"] == 0, c["detail"]
+        got = (c["result"]["index"], c["result"]["nn_index"], c["result"]["d2"])
+        assert got == alone[r.tag], (r.tag, got, alone[r.tag])

@@ -253,3 +253,24 @@ def test_scheduler_under_sanitizers(san, tmp_path):
     r = subprocess.run([exe], capture_output=True, text=True, timeout=120, env=env)
     assert r.returncode == 0, r.stdout + r.stderr[-4000:]
     assert "OK" in r.stdout and "WARNING" not in r.stderr
+
+
+def test_replay_counts_failures_and_refusals(dd):
+    """The replay summary separates refused submissions, failed completions and
+    successful ones; latencies come only from successful requests."""
+    from paper_1901_00155_amd import serve, workloads
+    reqs = workloads.serve_requests(seed=9, count=30, rate_hz=500.0, log2_min=12, log2_max=13)
+    reqs[4].n = 0                         # refused at submit (n < 1)
+
+    def ex(req, opts, res):
+        time.sleep(0.001)
+        return -2 if req.tag % 7 == 3 else 0
+
+    with dd.Server(1 << 30, slots=2, executor=ex) as s:
+        out = serve.replay(s, reqs, timeout_s=60)
+    sm = out["summary"]
+    failing = sum(1 for r in reqs if r.tag % 7 == 3 and r.tag != 4)
+    assert sm["rejected"] == 1 and out["submit_status"][4] == -1
+    assert sm["failed"] == failing
+    assert sm["completed_ok"] == len(reqs) - 1 - failing
+    assert sm["p50_ms"] is not None and sm["p50_ms"] > 0
