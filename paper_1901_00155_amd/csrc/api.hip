@@ -383,7 +383,6 @@ int discord_prepare(const float* T, int64_t m, int32_t n, const discord_opts* op
     launch_csr(p->at<int32_t>(p->L.words), p->at<int32_t>(p->L.hist), p->N, p->dict,
                p->at<int32_t>(p->L.seg), p->at<int32_t>(p->L.csr_off),
                p->at<int32_t>(p->L.csr_mem), s);
-    // the column groups (of 8) of every word's bucket: the scan's same-word-first order
     const bool mixed = o.precision == DISCORD_PREC_BF16X3;
     if (mixed)
       launch_row_stats32(p->Tp(), p->N, n, p->N + kRowPad, p->at<double>(p->L.row_mean),
@@ -392,16 +391,21 @@ int discord_prepare(const float* T, int64_t m, int32_t n, const discord_opts* op
     if (mixed)
       launch_split_blocks(p->Tp(), p->N, n, p->at<float>(p->L.mu32), p->at<float>(p->L.cn32),
                           p->at<uint4>(p->L.sblk), s);
-    launch_bucket_groups(p->at<int32_t>(p->L.csr_off), p->at<int32_t>(p->L.csr_mem), p->dict,
-                         mixed ? 5 : 3,
-                         p->at<int32_t>(p->L.bgrp_cnt), p->at<int32_t>(p->L.bgrp_off),
-                         p->at<int32_t>(p->L.bgrp), s);
-    launch_max_bucket(p->at<int32_t>(p->L.bgrp_off), p->dict, p->at<int32_t>(p->L.max_bucket), s);
+    // the bucket column blocks serve only the PhiDD order (same-word columns first)
+    const bool buckets = o.order == 1;
+    if (buckets) {
+      launch_bucket_groups(p->at<int32_t>(p->L.csr_off), p->at<int32_t>(p->L.csr_mem), p->dict,
+                           mixed ? 5 : 3,
+                           p->at<int32_t>(p->L.bgrp_cnt), p->at<int32_t>(p->L.bgrp_off),
+                           p->at<int32_t>(p->L.bgrp), s);
+      launch_max_bucket(p->at<int32_t>(p->L.bgrp_off), p->dict, p->at<int32_t>(p->L.max_bucket), s);
+    }
     LAUNCH_OK(p, "prepare kernels");
     int32_t hc = 0, hmb = 0;
     HIP_TRY(p, hipMemcpyAsync(&hc, p->at<int32_t>(p->L.cand_count), sizeof(hc), hipMemcpyDeviceToHost, s));
-    HIP_TRY(p, hipMemcpyAsync(&hmb, p->at<int32_t>(p->L.max_bucket), sizeof(hmb),
-                              hipMemcpyDeviceToHost, s));
+    if (buckets)
+      HIP_TRY(p, hipMemcpyAsync(&hmb, p->at<int32_t>(p->L.max_bucket), sizeof(hmb),
+                                hipMemcpyDeviceToHost, s));
     HIP_TRY(p, hipEventRecord(ev.b, s));
     HIP_TRY(p, hipStreamSynchronize(s));
     p->cand_count = hc;
