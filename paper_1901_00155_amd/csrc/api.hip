@@ -443,7 +443,7 @@ int discord_search(discord_plan p, discord_result* out) {
   const int gsz = mixed ? kMixedBlock : kRowGroup;
   const int64_t G = (N + gsz - 1) / gsz;
   // row groups per work item: one wavefront (FP32) or one workgroup (MFMA)
-  const int rb = mixed ? mfma_row_blocks(n) : 1;
+  const int rb = mixed ? mfma_row_blocks(n, p->opts.abandon != 0) : 1;
   // the unit of the scan's lists: one row group (FP32) or one workgroup's fixed
   // set of rb row blocks (MFMA)
   const int64_t item_rows = (int64_t)gsz * rb;

@@ -130,7 +130,7 @@ struct MixedRows {
 constexpr int kMixedBlock = 32;      // rows per MFMA row block = columns per column block
 constexpr int kMixedMaxN = DISCORD_MIXED_MAX_N;  // longest window of the split-BF16 scan (32 K-steps)
 bool launch_scan_mfma(const ScanJob& J, const MixedRows& R, hipStream_t s);
-int mfma_row_blocks(int n);
+int mfma_row_blocks(int n, bool abandon);   // row blocks per MFMA work item
 // The split subsequence matrix: for every block of 32 consecutive rows, KS+1
 // K-steps of 16 operand slots per lane (64 lanes): KS steps of the centred
 // window (hi then lo, 1 KB each) and one extra step holding the norm terms as

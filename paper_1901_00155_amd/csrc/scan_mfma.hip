@@ -29,12 +29,12 @@
 // columns.  The 32x32 result gives lane l the 16 columns 8(v/4) + 4(l/32) + v%4
 // of row l % 32, so the row minimum is mostly a per-lane running minimum.
 //
-// Work sharing: a workgroup of 8 wavefronts (two per SIMD; 4 for windows over
-// 256) owns one row block per wavefront (two for windows up to 128) and sweeps
-// a column sequence together.  Each column block is copied once per workgroup
-// from HBM into LDS (double-buffered; the copy of block s+1 is issued before
-// block s is multiplied and stored after), and every wavefront reads it with
-// ds_read_b128.
+// Work sharing: a workgroup of 4 wavefronts (8 for full scans with windows of
+// 129..256; see waves_for) owns two row blocks per wavefront for windows up to
+// 128, else one, and sweeps a column sequence together.  Each column block is
+// copied once per workgroup from HBM straight into LDS (double-buffered: the
+// copy of block s+1 is issued before block s is multiplied), and every
+// wavefront reads it with ds_read_b128.
 #include "internal.hpp"
 
 namespace dd {
@@ -45,19 +45,23 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 constexpr int BM = 32;      // rows per row block (one MFMA tile side)
 constexpr int BN = 32;      // columns per column block
-// wavefronts per workgroup: 8 (two per SIMD, one row block each) while a row
-// block's operands fit in half the register file, else 4
-template <int KS>
-constexpr int kWaves = KS <= 16 ? 8 : 4;
-// row blocks per wavefront: two while both fit in the registers of a
-// two-waves-per-SIMD kernel (windows up to 128), else one
+// Work-group shapes (measured on full scans and searches).  Row blocks per
+// wavefront: two while both fit in the registers of a two-waves-per-SIMD kernel
+// (windows up to 128), else one.  Wavefronts per workgroup: 4, and two
+// workgroups share a CU while a wavefront fits in half the register file, so
+// their steps drift apart and one's epilogue overlaps the other's MFMAs; one
+// wavefront per SIMD beyond that.  The exception is a full scan with windows of
+// 129..256 (one row block per wavefront): there 8 wavefronts sharing each column
+// block in LDS do better (0.50 vs 0.46 of peak), while an early-abandon search
+// prefers the finer 4-wavefront items (they leave sooner).
 template <int KS>
 constexpr int kRowBlocks = KS <= 8 ? 2 : 1;
+template <int KS>
+constexpr int waves_for(bool abandon) { return (KS > 8 && KS <= 16 && !abandon) ? 8 : 4; }
 
 template <int KS>
 struct Blk {
   static constexpr int SLOTS = (KS + 1) * 128;                 // 16-byte slots per block
-  static constexpr int PER_T = (SLOTS + kWaves<KS> * 64 - 1) / (kWaves<KS> * 64);
 };
 
 __device__ __forceinline__ void split8(const float (&x)[8], bf16x8& hi, bf16x8& lo) {
@@ -137,21 +141,20 @@ __global__ __launch_bounds__(256) void k_split_blocks(const float* __restrict__ 
 }
 
 // One workgroup per (item, chunk of its column sequence).  An item is a fixed
-// set of kWaves * RB consecutive row blocks (the list holds item numbers), so
+// set of WAVES * RB consecutive row blocks (the list holds item numbers), so
 // its sequence is the same in every launch and a search can resume it: the
 // word bucket (32-column blocks) of its first row, when given, then the column
 // blocks in matrix order or near-first (spiral.hpp) around the item's rows,
 // one 32-column block per step.
-template <int KS, int RB>
-__global__ __launch_bounds__(kWaves<KS> * 64, (KS <= 16 ? 2 : 1)) void k_scan_mfma(ScanJob J,
-                                                                                  MixedRows R) {
-  constexpr int WAVES = kWaves<KS>;
+template <int KS, int RB, int WAVES>
+__global__ __launch_bounds__(WAVES * 64, (KS <= 16 ? 2 : 1)) void k_scan_mfma(ScanJob J,
+                                                                             MixedRows R) {
   // two stages, each a column block (Blk<KS>::SLOTS slots) followed by the
   // block's 32 column values sqrt(n) (mean - mu) (8 slots)
   extern __shared__ bf16x8 smem[];
   __shared__ uint32_t wave_live[2 * WAVES];
   constexpr int SLOTS = Blk<KS>::SLOTS;
-  constexpr int PER_T = Blk<KS>::PER_T;
+  constexpr int PER_T = (SLOTS + WAVES * 64 - 1) / (WAVES * 64);
   constexpr int STAGE = SLOTS + 8;
   const bf16x8* __restrict__ S = reinterpret_cast<const bf16x8*>(R.sblk);
 
@@ -260,32 +263,27 @@ __global__ __launch_bounds__(kWaves<KS> * 64, (KS <= 16 ? 2 : 1)) void k_scan_mf
   }
   uint32_t cnt = 0;
 
-  bf16x8 pre[PER_T], pre_m;
-  auto fetch = [&](int64_t q) {
+  // column blocks go from HBM straight into LDS (global_load_lds_dwordx4: each
+  // lane's 16 bytes land at its wavefront's LDS base + 16 * lane), with no
+  // register staging; the barrier that closes a step waits for them
+  typedef __attribute__((address_space(3))) void lds_void;
+  auto fetch = [&](int64_t q, bf16x8* dst) {
     const bf16x8* src = S + q * SLOTS;
 #pragma unroll
     for (int i = 0; i < PER_T; ++i) {
-      const int k = i * WAVES * 64 + (int)threadIdx.x;
-      if (k < SLOTS) pre[i] = src[k];
+      const int w0 = i * WAVES * 64 + wv * 64;   // this wavefront's first slot
+      if (w0 < SLOTS)                             // SLOTS is a multiple of 64
+        __builtin_amdgcn_global_load_lds(src + w0 + lane, (lds_void*)(dst + w0), 16, 0, 0);
     }
-    if (threadIdx.x < 8) pre_m = reinterpret_cast<const bf16x8*>(R.smu + q * BN)[threadIdx.x];
+    if (wv == 0 && lane < 8)
+      __builtin_amdgcn_global_load_lds(R.smu + q * BN + 4 * lane, (lds_void*)(dst + SLOTS), 16, 0,
+                                       0);
   };
-  auto store = [&](bf16x8* dst) {
-#pragma unroll
-    for (int i = 0; i < PER_T; ++i) {
-      const int k = i * WAVES * 64 + (int)threadIdx.x;
-      if (k < SLOTS) dst[k] = pre[i];
-    }
-    if (threadIdx.x < 8) dst[SLOTS + threadIdx.x] = pre_m;
-  };
-  if (steps > 0) {
-    fetch(block_of(0));
-    store(smem);
-  }
+  if (steps > 0) fetch(block_of(0), smem);
   __syncthreads();
   for (int64_t s = 0; s < steps; ++s) {
     const int cur = (int)(s & 1);
-    if (s + 1 < steps) fetch(block_of(s + 1));
+    if (s + 1 < steps) fetch(block_of(s + 1), smem + (cur ^ 1) * STAGE);
     const int64_t jlim = N;
     const int64_t j0 = block_of(s) * BN;
     const bf16x8* buf = smem + cur * STAGE;
@@ -309,7 +307,7 @@ __global__ __launch_bounds__(kWaves<KS> * 64, (KS <= 16 ? 2 : 1)) void k_scan_mf
       // two wavefronts share each SIMD: the one issuing its MFMA chain goes first
       // (measured: +5% at n = 256, neutral at n = 128, a loss with one
       // wavefront per SIMD)
-      if constexpr (WAVES == 8) __builtin_amdgcn_s_setprio(1);
+      if constexpr (KS <= 16) __builtin_amdgcn_s_setprio(1);
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) {
         const bf16x8 ah = buf[ks * 128 + lane];
@@ -321,7 +319,7 @@ __global__ __launch_bounds__(kWaves<KS> * 64, (KS <= 16 ? 2 : 1)) void k_scan_mf
           acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[b][ks], acc[b], 0, 0, 0);
         }
       }
-      if constexpr (WAVES == 8) __builtin_amdgcn_s_setprio(0);
+      if constexpr (KS <= 16) __builtin_amdgcn_s_setprio(0);
       // ---- epilogue: d^2 = acc + (smu_row - smu_col)^2 for the 16 columns -----
       float smc[16];
 #pragma unroll
@@ -395,7 +393,6 @@ __global__ __launch_bounds__(kWaves<KS> * 64, (KS <= 16 ? 2 : 1)) void k_scan_mf
         }
       }
     }
-    if (s + 1 < steps) store(smem + (cur ^ 1) * STAGE);
     // all wavefronts agree on leaving once no row of the workgroup is live
     bool mine = false;
 #pragma unroll
@@ -470,7 +467,7 @@ __global__ __launch_bounds__(kWaves<KS> * 64, (KS <= 16 ? 2 : 1)) void k_scan_mf
   }
 }
 
-template <int KS, int RB>
+template <int KS, int RB, int WAVES>
 void launch_kr(const ScanJob& J, const MixedRows& R, hipStream_t s) {
   const int64_t blocks = J.n_groups * J.chunks;
   if (blocks <= 0) return;
@@ -480,18 +477,24 @@ void launch_kr(const ScanJob& J, const MixedRows& R, hipStream_t s) {
   // host threads (one per serving slot) do not race
   static const bool attr_set = [lds] {
     if (lds > 65536)
-      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_scan_mfma<KS, RB>),
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_scan_mfma<KS, RB, WAVES>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     return true;
   }();
   (void)attr_set;
-  hipLaunchKernelGGL((k_scan_mfma<KS, RB>), dim3((unsigned)blocks), dim3(kWaves<KS> * 64), lds, s,
-                     J, R);
+  hipLaunchKernelGGL((k_scan_mfma<KS, RB, WAVES>), dim3((unsigned)blocks), dim3(WAVES * 64), lds,
+                     s, J, R);
 }
 
 template <int KS>
 void launch_ks(const ScanJob& J, const MixedRows& R, hipStream_t s) {
-  launch_kr<KS, kRowBlocks<KS>>(J, R, s);
+  if constexpr (KS > 8 && KS <= 16) {
+    if (waves_for<KS>(J.abandon != 0) == 8) {
+      launch_kr<KS, kRowBlocks<KS>, 8>(J, R, s);
+      return;
+    }
+  }
+  launch_kr<KS, kRowBlocks<KS>, 4>(J, R, s);
 }
 
 template <int KS>
@@ -504,9 +507,10 @@ void launch_split(const float* Tp, int64_t nblk, int n, const float* c32, const 
 
 }  // namespace
 
-int mfma_row_blocks(int n) {
+int mfma_row_blocks(int n, bool abandon) {
   const int ks = (n + 15) / 16;
-  return (ks <= 16 ? 8 : 4) * (ks <= 8 ? 2 : 1);
+  const int waves = (ks > 8 && ks <= 16 && !abandon) ? 8 : 4;
+  return waves * (ks <= 8 ? 2 : 1);
 }
 
 size_t mixed_block_bytes(int n) { return (size_t)(((n + 15) / 16) + 1) * 128 * 16; }
