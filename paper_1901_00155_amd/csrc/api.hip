@@ -46,12 +46,29 @@ constexpr int64_t kRowPad = 64;   // zero rows after N in the FP32 row-statistic
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
+// The small per-search counters, in one block so that one fill clears them and
+// one copy reads them back.
+struct SearchScalars {
+  uint64_t pairs;          // pair distances evaluated
+  uint64_t seed;           // packed (distance, ~row) of the certification seed
+  uint32_t bsf;            // best-so-far (float bits)
+  uint32_t n_surv;         // survivors of the last window launch
+  uint32_t n_aband;        // rows left early
+  uint32_t unc_count;      // rows the witnesses could not clear
+  uint32_t relerr;         // largest relative error checked (float bits)
+  int32_t n_cand_groups;   // items holding Cand rows
+  uint32_t pad[2];
+};
+static_assert(sizeof(SearchScalars) % 4 == 0, "filled as 32-bit words");
+
 struct Layout {
+  // stats: 8 doubles (eq. (2)) followed by the NaN/Inf flag (`bad`); cand_count:
+  // |Cand| followed by the longest bucket (`max_bucket`): each pair is read back
+  // with one copy
   size_t T, stats, partials, bad, words, hist, minfreq, cand, cand_count, seg, csr_off, csr_mem,
-      best, nn_approx, nn_wit, row_state, row_mean, row_cnorm, seed, rows, part_d, part_j, out_d,
-      out_j, exact, unc, unc_count, relerr, bsf, pairs, alive, done, survivors, survivors2, n_surv,
-      score, rank_hist, gflags, cand_groups, n_cand_groups, n_aband, bgrp_cnt, bgrp_off, bgrp,
-      max_bucket, mu32, smu32, cn32, sblk, total;
+      best, nn_approx, nn_wit, row_state, row_mean, row_cnorm, rows, part_d, part_j, out_d,
+      out_j, exact, unc, srch, alive, done, survivors, survivors2, score, rank_hist, gflags,
+      cand_groups, bgrp_cnt, bgrp_off, bgrp, max_bucket, mu32, smu32, cn32, sblk, total;
 };
 
 Layout make_layout(int64_t m, int32_t n, int dict, bool mixed) {
@@ -66,14 +83,15 @@ Layout make_layout(int64_t m, int32_t n, int dict, bool mixed) {
     return o;
   };
   L.T = take(sizeof(float) * (size_t)(kFrontPad + m + kBackPad));
-  L.stats = take(sizeof(double) * 8);
+  L.stats = take(sizeof(double) * 8 + sizeof(int32_t) * 4);
+  L.bad = L.stats + sizeof(double) * 8;
   L.partials = take(sizeof(double) * kStatBlocks);
-  L.bad = take(sizeof(int32_t) * 4);
   L.words = take(sizeof(int32_t) * N);
   L.hist = take(sizeof(int32_t) * kMaxWords);
   L.minfreq = take(sizeof(int32_t) * 4);
   L.cand = take(sizeof(int32_t) * N);
-  L.cand_count = take(sizeof(int32_t) * 4);
+  L.cand_count = take(sizeof(int32_t) * 8);
+  L.max_bucket = L.cand_count + sizeof(int32_t) * 4;
   L.seg = take(sizeof(int32_t) * seg);
   L.csr_off = take(sizeof(int32_t) * (kMaxWords + 1));
   L.csr_mem = take(sizeof(int32_t) * N);
@@ -83,7 +101,6 @@ Layout make_layout(int64_t m, int32_t n, int dict, bool mixed) {
   L.row_state = take(sizeof(int32_t) * N);
   L.row_mean = take(sizeof(double) * N);
   L.row_cnorm = take(sizeof(double) * N);
-  L.seed = take(sizeof(uint64_t) * 4);
   L.rows = take(sizeof(int64_t) * kFp64BatchRows);
   L.part_d = take(sizeof(double) * kFp64BatchRows * nchunks);
   L.part_j = take(sizeof(int64_t) * kFp64BatchRows * nchunks);
@@ -91,26 +108,19 @@ Layout make_layout(int64_t m, int32_t n, int dict, bool mixed) {
   L.out_j = take(sizeof(int64_t) * kFp64BatchRows);
   L.exact = take(sizeof(Exact));
   L.unc = take(sizeof(int64_t) * N);
-  L.unc_count = take(sizeof(uint32_t) * 4);
-  L.relerr = take(sizeof(uint32_t) * 4);
   const int64_t G = (N + kRowGroup - 1) / kRowGroup;
-  L.bsf = take(sizeof(uint32_t) * 4);
-  L.pairs = take(sizeof(uint64_t) * 4);
+  L.srch = take(sizeof(SearchScalars));
   L.alive = take(sizeof(uint32_t) * G);
   L.done = take(sizeof(uint32_t) * G);
   L.survivors = take(sizeof(int32_t) * G);
   L.survivors2 = take(sizeof(int32_t) * G);
-  L.n_surv = take(sizeof(uint32_t) * 4);
   L.score = take(sizeof(uint32_t) * G);
   L.rank_hist = take(sizeof(uint32_t) * rank_hist_bins());
   L.gflags = take(sizeof(int32_t) * G);
   L.cand_groups = take(sizeof(int32_t) * G);
-  L.n_cand_groups = take(sizeof(int32_t) * 4);
-  L.n_aband = take(sizeof(uint32_t) * 4);
   L.bgrp_cnt = take(sizeof(int32_t) * kMaxWords);
   L.bgrp_off = take(sizeof(int32_t) * (kMaxWords + 1));
   L.bgrp = take(sizeof(int32_t) * N);
-  L.max_bucket = take(sizeof(int32_t) * 4);
   L.mu32 = take(sizeof(float) * (N + kRowPad));
   L.smu32 = take(sizeof(float) * (N + kRowPad));
   L.cn32 = take(sizeof(float) * (N + kRowPad));
@@ -353,28 +363,36 @@ int discord_prepare(const float* T, int64_t m, int32_t n, const discord_opts* op
     HIP_TRY(p, hipEventRecord(ev.a, s));
     // padded series: zero pads, then the values
     float* Tbase = p->at<float>(p->L.T);
-    launch_init_i32(reinterpret_cast<int32_t*>(Tbase), kFrontPad, 0, s);
-    launch_init_i32(reinterpret_cast<int32_t*>(Tbase + kFrontPad + m), kBackPad, 0, s);
+    {
+      const FillOp fills[] = {
+          {Tbase, kFrontPad, 0, 0},
+          {Tbase + kFrontPad + m, kBackPad, 0, 0},
+          {p->at<int32_t>(p->L.bad), 4, 0, 0},
+          {p->at<int32_t>(p->L.hist), kMaxWords, 0, 0},
+      };
+      launch_fill_many(fills, 4, s);
+    }
     const hipMemcpyKind kind = is_device_pointer(T) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     HIP_TRY(p, hipMemcpyAsync(p->Tp(), T, sizeof(float) * m, kind, s));
     // eq. (2)
-    launch_init_i32(p->at<int32_t>(p->L.bad), 4, 0, s);
     launch_stats(p->Tp(), m, p->at<double>(p->L.partials), p->at<double>(p->L.stats),
                  p->at<int32_t>(p->L.bad), s);
     LAUNCH_OK(p, "stats");
-    double hstats[3];
-    int32_t hbad = 0;
-    HIP_TRY(p, hipMemcpyAsync(hstats, p->at<double>(p->L.stats), sizeof(hstats),
-                              hipMemcpyDeviceToHost, s));
-    HIP_TRY(p, hipMemcpyAsync(&hbad, p->at<int32_t>(p->L.bad), sizeof(hbad), hipMemcpyDeviceToHost, s));
+    struct {
+      double stats[8];
+      int32_t bad[4];
+    } hs;   // the statistics block followed by the flag, as laid out on the device
+    static_assert(sizeof(hs) == sizeof(double) * 8 + sizeof(int32_t) * 4, "layout");
+    HIP_TRY(p, hipMemcpyAsync(&hs, p->at<double>(p->L.stats), sizeof(hs), hipMemcpyDeviceToHost, s));
     HIP_TRY(p, hipStreamSynchronize(s));
+    const double* hstats = hs.stats;
+    const int32_t hbad = hs.bad[0];
     if (hbad) return fail(p, DISCORD_EINVAL, "series holds NaN or Inf");
     p->mu = hstats[0];
     p->sigma = hstats[1];
     if (!(p->sigma > 0.0)) return fail(p, DISCORD_ECONST, "sigma == 0");
     // row statistics, PAA -> SAX -> word ids, histogram, Cand, Index_Word
     launch_row_stats(p->Tp(), p->N, n, p->at<double>(p->L.row_mean), p->at<double>(p->L.row_cnorm), s);
-    launch_init_i32(p->at<int32_t>(p->L.hist), kMaxWords, 0, s);
     launch_sax(p->Tp(), p->N, n, o.paa_w, o.alphabet, p->at<double>(p->L.stats),
                p->at<int32_t>(p->L.words), p->at<int32_t>(p->L.hist), s);
     launch_cand(p->at<int32_t>(p->L.words), p->at<int32_t>(p->L.hist), p->N, p->dict,
@@ -401,15 +419,13 @@ int discord_prepare(const float* T, int64_t m, int32_t n, const discord_opts* op
       launch_max_bucket(p->at<int32_t>(p->L.bgrp_off), p->dict, p->at<int32_t>(p->L.max_bucket), s);
     }
     LAUNCH_OK(p, "prepare kernels");
-    int32_t hc = 0, hmb = 0;
-    HIP_TRY(p, hipMemcpyAsync(&hc, p->at<int32_t>(p->L.cand_count), sizeof(hc), hipMemcpyDeviceToHost, s));
-    if (buckets)
-      HIP_TRY(p, hipMemcpyAsync(&hmb, p->at<int32_t>(p->L.max_bucket), sizeof(hmb),
-                                hipMemcpyDeviceToHost, s));
+    int32_t hcm[8] = {0};   // |Cand| at [0], the longest bucket at [4]
+    HIP_TRY(p, hipMemcpyAsync(hcm, p->at<int32_t>(p->L.cand_count), sizeof(hcm),
+                              hipMemcpyDeviceToHost, s));
     HIP_TRY(p, hipEventRecord(ev.b, s));
     HIP_TRY(p, hipStreamSynchronize(s));
-    p->cand_count = hc;
-    p->max_bucket = hmb;
+    p->cand_count = hcm[0];
+    p->max_bucket = buckets ? hcm[4] : 0;
     p->ms_prepare = ev.ms();
     return DISCORD_OK;
   };
@@ -456,14 +472,22 @@ int discord_search(discord_plan p, discord_result* out) {
   const bool buckets = p->opts.order == 1;        // same-word columns first
   const bool near_first = p->opts.order == 2;     // columns nearest the row first
   uint64_t* best = p->at<uint64_t>(p->L.best);
-  uint64_t* pairs = p->at<uint64_t>(p->L.pairs);
-  uint32_t* bsf = p->at<uint32_t>(p->L.bsf);
+  SearchScalars* sc = p->at<SearchScalars>(p->L.srch);
+  uint64_t* pairs = &sc->pairs;
+  uint32_t* bsf = &sc->bsf;
   uint32_t* alive = p->at<uint32_t>(p->L.alive);
-  uint32_t* n_surv = p->at<uint32_t>(p->L.n_surv);
+  uint32_t* n_surv = &sc->n_surv;
   int32_t* gflags = p->at<int32_t>(p->L.gflags);
-  launch_init_u64(best, N, kEmptyMin, s);
-  launch_init_u64(pairs, 1, 0, s);
-  launch_init_i32(reinterpret_cast<int32_t*>(bsf), 1, 0, s);
+  {
+    // one launch clears the search state (the alive masks follow below)
+    const FillOp fills[] = {
+        {best, N, kEmptyMin, 1},
+        {sc, (int64_t)(sizeof(SearchScalars) / 4), 0, 0},
+        {p->at<uint32_t>(p->L.done), G, 0, 0},
+        {gflags, G, 0, 0},
+    };
+    launch_fill_many(fills, abandon ? 4 : 2, s);
+  }
   // ---- approximate scan (Algorithms 3 and 4) ----------------------------------
   ScanJob J{};
   J.Tp = p->Tp();
@@ -531,8 +555,6 @@ int discord_search(discord_plan p, discord_result* out) {
   } else {
     J.abandon = 1;
     launch_init_alive(alive, G, N, gsz, s);
-    launch_init_i32(reinterpret_cast<int32_t*>(J.done), G, 0, s);
-    launch_init_i32(gflags, G, 0, s);
     J.words = buckets ? p->at<int32_t>(p->L.words) : nullptr;
     J.bgrp_off = p->at<int32_t>(p->L.bgrp_off);
     J.bgrp = p->at<int32_t>(p->L.bgrp);
@@ -542,7 +564,7 @@ int discord_search(discord_plan p, discord_result* out) {
       // Algorithm 3: the row groups holding Cand rows, each scanned over its
       // whole sequence, split into chunks to fill the GPU
       int32_t* cgroups = p->at<int32_t>(p->L.cand_groups);
-      int32_t* n_cg = p->at<int32_t>(p->L.n_cand_groups);
+      int32_t* n_cg = &sc->n_cand_groups;
       launch_cand_group_flags(p->at<int32_t>(p->L.cand), p->at<int32_t>(p->L.cand_count),
                               p->cand_count, item_shift, gflags, s);
       launch_compact_flags(gflags, n_items, p->at<int32_t>(p->L.seg), cgroups, n_cg, s);
@@ -617,12 +639,10 @@ int discord_search(discord_plan p, discord_result* out) {
   float* nn_approx = p->at<float>(p->L.nn_approx);
   int32_t* nn_wit = p->at<int32_t>(p->L.nn_wit);
   int32_t* row_state = p->at<int32_t>(p->L.row_state);
-  uint32_t* n_aband = p->at<uint32_t>(p->L.n_aband);
-  launch_init_i32(reinterpret_cast<int32_t*>(n_aband), 1, 0, s);
+  uint32_t* n_aband = &sc->n_aband;
   launch_unpack_best(best, N, abandon ? alive : nullptr, gsz, nn_approx, nn_wit, row_state, n_aband,
                      s);
-  uint64_t* seed = p->at<uint64_t>(p->L.seed);
-  launch_init_u64(seed, 1, 0, s);
+  uint64_t* seed = &sc->seed;
   launch_seed_argmax(best, row_state, N, seed, s);
   int64_t* rows = p->at<int64_t>(p->L.rows);
   launch_seed_row(seed, rows, s);
@@ -630,20 +650,16 @@ int discord_search(discord_plan p, discord_result* out) {
   if (st) return st;
   Exact* ex = p->at<Exact>(p->L.exact);
   launch_exact_from_rows(rows, p->at<double>(p->L.out_d), p->at<int64_t>(p->L.out_j), 1, ex, s);
-  uint32_t* unc_count = p->at<uint32_t>(p->L.unc_count);
-  uint32_t* relerr = p->at<uint32_t>(p->L.relerr);
-  launch_init_i32(reinterpret_cast<int32_t*>(unc_count), 1, 0, s);
-  launch_init_i32(reinterpret_cast<int32_t*>(relerr), 1, 0, s);
+  uint32_t* unc_count = &sc->unc_count;
+  uint32_t* relerr = &sc->relerr;
   int64_t* unc = p->at<int64_t>(p->L.unc);
   launch_verify(p->Tp(), n, N, nn_wit, nn_approx, ex, unc, unc_count, relerr, s);
   LAUNCH_OK(p, "verify");
-  uint32_t hunc = 0, hrel = 0, hab = 0;
-  uint64_t hpairs = 0;
-  HIP_TRY(p, hipMemcpyAsync(&hunc, unc_count, sizeof(hunc), hipMemcpyDeviceToHost, s));
-  HIP_TRY(p, hipMemcpyAsync(&hrel, relerr, sizeof(hrel), hipMemcpyDeviceToHost, s));
-  HIP_TRY(p, hipMemcpyAsync(&hab, n_aband, sizeof(hab), hipMemcpyDeviceToHost, s));
-  HIP_TRY(p, hipMemcpyAsync(&hpairs, pairs, sizeof(hpairs), hipMemcpyDeviceToHost, s));
+  SearchScalars hsc;
+  HIP_TRY(p, hipMemcpyAsync(&hsc, sc, sizeof(hsc), hipMemcpyDeviceToHost, s));
   HIP_TRY(p, hipStreamSynchronize(s));
+  const uint32_t hunc = hsc.unc_count, hrel = hsc.relerr, hab = hsc.n_aband;
+  const uint64_t hpairs = hsc.pairs;
   for (int64_t b = 0; b < (int64_t)hunc; b += kFp64BatchRows) {
     const int64_t c = std::min<int64_t>(kFp64BatchRows, (int64_t)hunc - b);
     st = rows_nn_batch(p, unc + b, c);

@@ -48,6 +48,18 @@ __global__ void k_fill_i32(int32_t* p, int64_t count, int32_t v) {
     p[k] = v;
 }
 
+// Several fills in one launch: blockIdx.y selects the buffer.
+__global__ void k_fill_many(FillList L) {
+  const FillOp& op = L.op[blockIdx.y];
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < op.count;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    if (op.wide)
+      static_cast<uint64_t*>(op.p)[k] = op.value;
+    else
+      static_cast<uint32_t*>(op.p)[k] = (uint32_t)op.value;
+  }
+}
+
 // Rows of the scan: minimum (or abandon distance) and its column; a row is
 // abandoned when its bit in the group's alive mask was cleared.
 __global__ __launch_bounds__(256) void k_unpack_best(const uint64_t* __restrict__ best, int64_t N,
@@ -249,6 +261,18 @@ __global__ void k_merge_exact(const int64_t* __restrict__ rows, const double* __
 }
 
 }  // namespace
+
+void launch_fill_many(const FillOp* ops, int count, hipStream_t s) {
+  FillList L{};
+  int64_t most = 0;
+  for (int k = 0; k < count && k < kMaxFills; ++k) {
+    L.op[L.n++] = ops[k];
+    most = std::max(most, ops[k].count);
+  }
+  if (L.n == 0 || most <= 0) return;
+  const int64_t blocks = std::min<int64_t>(4096, (most + 255) / 256);
+  hipLaunchKernelGGL(k_fill_many, dim3((unsigned)blocks, (unsigned)L.n), dim3(256), 0, s, L);
+}
 
 void launch_init_u64(uint64_t* p, int64_t count, uint64_t v, hipStream_t s) {
   const int64_t blocks = std::min<int64_t>(4096, (count + 255) / 256);

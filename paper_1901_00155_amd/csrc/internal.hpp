@@ -154,6 +154,19 @@ void launch_rank_groups(const int32_t* list, int64_t count, int64_t item_rows, i
                         int32_t* out, hipStream_t s);
 
 // ---- certify.hip --------------------------------------------------------------
+// Fills of several buffers (32- or 64-bit elements) in one launch.
+struct FillOp {
+  void* p;
+  int64_t count;
+  uint64_t value;
+  int32_t wide;   // 1: 64-bit elements, 0: 32-bit
+};
+constexpr int kMaxFills = 8;
+struct FillList {
+  int32_t n;
+  FillOp op[kMaxFills];
+};
+void launch_fill_many(const FillOp* ops, int count, hipStream_t s);
 void launch_init_u64(uint64_t* p, int64_t count, uint64_t v, hipStream_t s);
 void launch_init_i32(int32_t* p, int64_t count, int32_t v, hipStream_t s);
 void launch_unpack_best(const uint64_t* best, int64_t N, const uint32_t* alive, int gsz,
