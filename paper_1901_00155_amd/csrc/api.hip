@@ -580,8 +580,8 @@ int discord_search(discord_plan p, discord_result* out) {
     // rows still live continue.  PhiDD and matrix order: one more launch over
     // the rest of the sequence.  Near-first order: the survivors are ranked by
     // their rows' published minima, the best-ranked are completed at once (to
-    // raise the best-so-far), and the rest continue in windows twice as long each
-    // time.  Every launch resumes an item where its previous window ended, and
+    // raise the best-so-far), and the rest continue in windows twice (four times,
+    // on short sequences) as long each time.  Every launch resumes an item where its previous window ended, and
     // rows already below the best-so-far leave before any work.
     const bool resume = true;
     const int probe = p->opts.probe_steps > 0 ? p->opts.probe_steps : (near_first ? (mixed ? 4 : 2) : 16);
@@ -626,7 +626,9 @@ int discord_search(discord_plan p, discord_result* out) {
         // again (its previous contents were consumed by the ranking)
         in = spare + k;
         count -= k;
-        width *= 2;
+        // windows double on long sequences and grow 4x on short ones (fewer
+        // rounds, each a host round trip, where a round costs little work)
+        width *= seq_max >= (int64_t{1} << 15) ? 2 : 4;
       } else {
         in = out_buf;
         std::swap(out_buf, spare);
