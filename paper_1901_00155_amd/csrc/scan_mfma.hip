@@ -478,6 +478,185 @@ __global__ __launch_bounds__(WAVES * 64, (KS <= 16 ? 2 : 1)) void k_scan_mfma(Sc
   }
 }
 
+// Full scans (no early abandon, matrix order) with windows of 129..256: one row
+// block per wavefront, 8 wavefronts per workgroup, software-pipelined so that the
+// FP32 epilogue of column block s-1 runs while the MFMAs of block s are in
+// flight.  Two accumulator sets; three LDS stages (block s+1 is loading while
+// block s feeds the MFMAs and block s-1's column values feed the epilogue), one
+// barrier per step.
+template <int KS>
+__global__ __launch_bounds__(8 * 64, 2) void k_scan_mfma_full(ScanJob J, MixedRows R) {
+  constexpr int WAVES = 8;
+  extern __shared__ bf16x8 smem[];
+  constexpr int SLOTS = Blk<KS>::SLOTS;
+  constexpr int PER_T = (SLOTS + WAVES * 64 - 1) / (WAVES * 64);
+  constexpr int STAGE = SLOTS + 8;
+  const bf16x8* __restrict__ S = reinterpret_cast<const bf16x8*>(R.sblk);
+
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int h = lane >> 5;
+  const int rl = lane & 31;
+  const int64_t item = blockIdx.x / J.chunks;
+  const int64_t ch = blockIdx.x - item * J.chunks;
+  if (item >= J.n_groups) return;
+  const int64_t N = J.N;
+  const int n = J.n;
+  const int64_t g = item * WAVES + wv;            // this wavefront's row block
+  const bool has = g * BM < N;
+  const int64_t gb = has ? g : 0;
+  const int64_t rows = has ? min<int64_t>(BM, N - g * BM) : 0;
+  const uint32_t valid = rows >= 32 ? 0xFFFFFFFFu : ((1u << rows) - 1u);
+
+  bf16x8 bh[KS], bl[KS], bx;
+  const __bf16 m2 = (__bf16)(-2.0f);
+  {
+    const bf16x8* blk = S + gb * SLOTS;
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+      bh[k] = blk[k * 128 + lane] * m2;
+      bl[k] = blk[k * 128 + 64 + lane] * m2;
+    }
+    bx = blk[KS * 128 + 64 + lane] * m2;
+  }
+  const float smr = R.smu[gb * BM + rl];
+
+  const int64_t NQ = (N + BN - 1) / BN;
+  const int64_t e0 = J.seq_begin + ch * J.seq_chunk;
+  const int64_t e1 = min<int64_t>(NQ, e0 + J.seq_chunk);
+  const int64_t steps = e1 > e0 ? e1 - e0 : 0;
+
+  typedef __attribute__((address_space(3))) void lds_void;
+  auto fetch = [&](int64_t q, bf16x8* dst) {
+    const bf16x8* src = S + q * SLOTS;
+#pragma unroll
+    for (int i = 0; i < PER_T; ++i) {
+      const int w0 = i * WAVES * 64 + wv * 64;
+      if (w0 < SLOTS)
+        __builtin_amdgcn_global_load_lds(src + w0 + lane, (lds_void*)(dst + w0), 16, 0, 0);
+    }
+    if (wv == 0 && lane < 8)
+      __builtin_amdgcn_global_load_lds(R.smu + q * BN + 4 * lane, (lds_void*)(dst + SLOTS), 16, 0,
+                                       0);
+  };
+  auto stage = [&](int64_t t) { return smem + (t % 3) * STAGE; };
+
+  float rmin = __builtin_inff();
+  int32_t rj = -1;
+  uint32_t cnt = 0;
+  auto mma = [&](floatx16& a, const bf16x8* buf) {
+    const bf16x8 ax = buf[KS * 128 + lane];
+    floatx16 z;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) z[v] = 0.0f;
+    a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ax, bx, z, 0, 0, 0);
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+      const bf16x8 ah = buf[k * 128 + lane];
+      const bf16x8 al = buf[k * 128 + 64 + lane];
+      a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[k], a, 0, 0, 0);
+      a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl[k], a, 0, 0, 0);
+      a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[k], a, 0, 0, 0);
+    }
+  };
+  auto epilogue = [&](const floatx16& a, int64_t q, const bf16x8* buf) {
+    const int32_t j0 = (int32_t)(q * BN);
+    const int32_t r0 = (int32_t)(gb * BM);
+    const int32_t i = r0 + rl;
+    float smc[16];
+#pragma unroll
+    for (int qd = 0; qd < 4; ++qd) {
+      const float4 m = reinterpret_cast<const float4*>(buf + SLOTS)[2 * qd + h];
+      smc[4 * qd + 0] = m.x; smc[4 * qd + 1] = m.y; smc[4 * qd + 2] = m.z; smc[4 * qd + 3] = m.w;
+    }
+    const bool clean =
+        (j0 + BN <= (int32_t)N) && ((j0 >= r0 + BM - 1 + n) || (j0 + BN - 1 + n <= r0));
+    float d[16];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const float t = smr - smc[v];
+      d[v] = __builtin_fmaf(t, t, a[v]);
+    }
+    if (!clean) {
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int32_t j = j0 + 8 * (v >> 2) + 4 * h + (v & 3);
+        const int32_t dij = i > j ? i - j : j - i;
+        if (!(j < (int32_t)N && dij >= n)) d[v] = __builtin_inff();
+      }
+    }
+    float tmin = d[0];
+#pragma unroll
+    for (int v = 1; v < 16; ++v) tmin = fminf(tmin, d[v]);
+    if (__ballot(tmin < rmin)) {
+      if (tmin < rmin) {
+        int32_t jj = -1;
+#pragma unroll
+        for (int v = 15; v >= 0; --v)
+          if (d[v] == tmin) jj = j0 + 8 * (v >> 2) + 4 * h + (v & 3);
+        rmin = tmin;
+        rj = jj;
+      }
+    }
+    if ((valid >> rl) & 1u) {
+      if (clean) {
+        cnt += 16;
+      } else {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) cnt += d[v] < __builtin_inff();
+      }
+    }
+  };
+  // step t: load block t+1, multiply block t into `cur`, finish block t-1 from `prev`
+  auto step = [&](int64_t t, floatx16& cur, const floatx16& prev) {
+    if (t + 1 < steps) fetch(e0 + t + 1, stage(t + 1));
+    __builtin_amdgcn_s_setprio(1);
+    mma(cur, stage(t));
+    __builtin_amdgcn_s_setprio(0);
+    if (t > 0) epilogue(prev, e0 + t - 1, stage(t - 1));
+    __syncthreads();
+  };
+
+  if (steps > 0) fetch(e0, stage(0));
+  __syncthreads();
+  floatx16 acc0, acc1;
+  int64_t t = 0;
+  for (; t + 1 < steps; t += 2) {
+    step(t, acc0, acc1);
+    step(t + 1, acc1, acc0);
+  }
+  if (t < steps) {
+    step(t, acc0, acc1);
+    epilogue(acc0, e0 + t, stage(t));
+  } else if (steps > 0) {
+    epilogue(acc1, e0 + steps - 1, stage(steps - 1));
+  }
+
+  uint64_t key = rj < 0 ? kEmptyMin : pack_min(fmaxf(rmin, 0.0f), (uint32_t)rj);
+  const uint64_t o = __shfl_xor(key, 32, 64);
+  key = o < key ? o : key;
+  if (h == 0 && ((valid >> rl) & 1u) && key != kEmptyMin)
+    atomicMin((unsigned long long*)&J.best[g * BM + rl], (unsigned long long)key);
+  uint64_t c64 = cnt;
+  for (int off = 32; off > 0; off >>= 1) c64 += __shfl_xor(c64, off, 64);
+  if (lane == 0 && c64) atomicAdd((unsigned long long*)J.pairs, (unsigned long long)c64);
+}
+
+template <int KS>
+void launch_full_pipelined(const ScanJob& J, const MixedRows& R, hipStream_t s) {
+  const int64_t blocks = J.n_groups * J.chunks;
+  if (blocks <= 0) return;
+  const size_t lds = sizeof(bf16x8) * 3 * (Blk<KS>::SLOTS + 8);
+  static const bool attr_set = [lds] {
+    if (lds > 65536)
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_scan_mfma_full<KS>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    return true;
+  }();
+  (void)attr_set;
+  hipLaunchKernelGGL((k_scan_mfma_full<KS>), dim3((unsigned)blocks), dim3(8 * 64), lds, s, J, R);
+}
+
 template <int KS, int RB, int WAVES>
 void launch_kr(const ScanJob& J, const MixedRows& R, hipStream_t s) {
   const int64_t blocks = J.n_groups * J.chunks;
@@ -501,7 +680,8 @@ template <int KS>
 void launch_ks(const ScanJob& J, const MixedRows& R, hipStream_t s) {
   if constexpr (KS > 8 && KS <= 16) {
     if (waves_for<KS>(J.abandon != 0) == 8) {
-      launch_kr<KS, kRowBlocks<KS>, 8>(J, R, s);
+      // full scans only: no abandon, matrix order, every item listed
+      launch_full_pipelined<KS>(J, R, s);
       return;
     }
   }
