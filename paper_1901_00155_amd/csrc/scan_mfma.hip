@@ -559,24 +559,28 @@ __global__ __launch_bounds__(8 * 64, 2) void k_scan_mfma_full(ScanJob J, MixedRo
       a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[k], a, 0, 0, 0);
     }
   };
-  auto epilogue = [&](const floatx16& a, int64_t q, const bf16x8* buf) {
-    const int32_t j0 = (int32_t)(q * BN);
-    const int32_t r0 = (int32_t)(gb * BM);
-    const int32_t i = r0 + rl;
+  // epilogue, first part (straight-line, so that it can be interleaved with the
+  // MFMA chain of the next block): the 16 distances of this lane
+  auto distances = [&](const floatx16& a, const bf16x8* buf, float (&d)[16]) {
     float smc[16];
 #pragma unroll
     for (int qd = 0; qd < 4; ++qd) {
       const float4 m = reinterpret_cast<const float4*>(buf + SLOTS)[2 * qd + h];
       smc[4 * qd + 0] = m.x; smc[4 * qd + 1] = m.y; smc[4 * qd + 2] = m.z; smc[4 * qd + 3] = m.w;
     }
-    const bool clean =
-        (j0 + BN <= (int32_t)N) && ((j0 >= r0 + BM - 1 + n) || (j0 + BN - 1 + n <= r0));
-    float d[16];
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       const float t = smr - smc[v];
       d[v] = __builtin_fmaf(t, t, a[v]);
     }
+  };
+  // second part: exclusion mask, row minimum and witness, pair count
+  auto finish = [&](float (&d)[16], int64_t q) {
+    const int32_t j0 = (int32_t)(q * BN);
+    const int32_t r0 = (int32_t)(gb * BM);
+    const int32_t i = r0 + rl;
+    const bool clean =
+        (j0 + BN <= (int32_t)N) && ((j0 >= r0 + BM - 1 + n) || (j0 + BN - 1 + n <= r0));
     if (!clean) {
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
@@ -607,29 +611,48 @@ __global__ __launch_bounds__(8 * 64, 2) void k_scan_mfma_full(ScanJob J, MixedRo
       }
     }
   };
-  // step t: load block t+1, multiply block t into `cur`, finish block t-1 from `prev`
+  auto epilogue = [&](const floatx16& a, int64_t q, const bf16x8* buf) {
+    float d[16];
+    distances(a, buf, d);
+    finish(d, q);
+  };
+  // step t >= 1: load block t+1, multiply block t into `cur` and compute block
+  // t-1's distances from `prev` in one straight-line region (the scheduler is
+  // asked to interleave the two), then finish block t-1
   auto step = [&](int64_t t, floatx16& cur, const floatx16& prev) {
     if (t + 1 < steps) fetch(e0 + t + 1, stage(t + 1));
+    float d[16];
     __builtin_amdgcn_s_setprio(1);
     mma(cur, stage(t));
+    distances(prev, stage(t - 1), d);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 3, 0);   // 3 MFMA
+      __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);   // 2 VALU
+    }
     __builtin_amdgcn_s_setprio(0);
-    if (t > 0) epilogue(prev, e0 + t - 1, stage(t - 1));
+    finish(d, e0 + t - 1);
     __syncthreads();
   };
 
-  if (steps > 0) fetch(e0, stage(0));
-  __syncthreads();
   floatx16 acc0, acc1;
-  int64_t t = 0;
+  if (steps > 0) {
+    fetch(e0, stage(0));
+    __syncthreads();
+    if (steps > 1) fetch(e0 + 1, stage(1));
+    mma(acc0, stage(0));
+    __syncthreads();
+  }
+  int64_t t = 1;
   for (; t + 1 < steps; t += 2) {
-    step(t, acc0, acc1);
-    step(t + 1, acc1, acc0);
+    step(t, acc1, acc0);
+    step(t + 1, acc0, acc1);
   }
   if (t < steps) {
-    step(t, acc0, acc1);
-    epilogue(acc0, e0 + t, stage(t));
+    step(t, acc1, acc0);
+    epilogue(acc1, e0 + t, stage(t));
   } else if (steps > 0) {
-    epilogue(acc1, e0 + steps - 1, stage(steps - 1));
+    epilogue(acc0, e0 + steps - 1, stage(steps - 1));
   }
 
   uint64_t key = rj < 0 ? kEmptyMin : pack_min(fmaxf(rmin, 0.0f), (uint32_t)rj);
