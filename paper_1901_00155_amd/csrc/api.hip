@@ -47,17 +47,20 @@ constexpr int64_t kRowPad = 64;   // zero rows after N in the FP32 row-statistic
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 // The small per-search counters, in one block so that one fill clears them and
-// one copy reads them back.
+// one copy reads them back.  The best-so-far, which every scanning wavefront
+// polls after each step, and the pair counter, which every wavefront adds to,
+// sit on cache lines of their own (sharing one with the other counters made the
+// polls wait behind the atomics: the first window of a walk1m search took 2x
+// as long).
 struct SearchScalars {
-  uint64_t pairs;          // pair distances evaluated
-  uint64_t seed;           // packed (distance, ~row) of the certification seed
-  uint32_t bsf;            // best-so-far (float bits)
-  uint32_t n_surv;         // survivors of the last window launch
-  uint32_t n_aband;        // rows left early
-  uint32_t unc_count;      // rows the witnesses could not clear
-  uint32_t relerr;         // largest relative error checked (float bits)
-  int32_t n_cand_groups;   // items holding Cand rows
-  uint32_t pad[2];
+  alignas(128) uint64_t pairs;   // pair distances evaluated
+  alignas(128) uint32_t bsf;     // best-so-far (float bits)
+  alignas(128) uint64_t seed;    // packed (distance, ~row) of the certification seed
+  uint32_t n_surv;               // survivors of the last window launch
+  uint32_t n_aband;              // rows left early
+  uint32_t unc_count;            // rows the witnesses could not clear
+  uint32_t relerr;               // largest relative error checked (float bits)
+  int32_t n_cand_groups;         // items holding Cand rows
 };
 static_assert(sizeof(SearchScalars) % 4 == 0, "filled as 32-bit words");
 

@@ -478,15 +478,14 @@ __global__ __launch_bounds__(WAVES * 64, (KS <= 16 ? 2 : 1)) void k_scan_mfma(Sc
   }
 }
 
-// Full scans (no early abandon, matrix order) with windows of 129..256: one row
-// block per wavefront, 8 wavefronts per workgroup, software-pipelined so that the
-// FP32 epilogue of column block s-1 runs while the MFMAs of block s are in
-// flight.  Two accumulator sets; three LDS stages (block s+1 is loading while
-// block s feeds the MFMAs and block s-1's column values feed the epilogue), one
-// barrier per step.
-template <int KS>
-__global__ __launch_bounds__(8 * 64, 2) void k_scan_mfma_full(ScanJob J, MixedRows R) {
-  constexpr int WAVES = 8;
+// Full scans (no early abandon, matrix order, every item listed), software-
+// pipelined: the FP32 epilogue of column block s-1 runs while the MFMAs of
+// block s are in flight.  Two accumulator sets; three LDS stages (block s+1 is
+// loading while block s feeds the MFMAs and block s-1's column values feed the
+// epilogue), one barrier per step.  RB row blocks per wavefront, WAVES
+// wavefronts, MINW wavefronts per SIMD (launch bound).
+template <int KS, int RB, int WAVES, int MINW>
+__global__ __launch_bounds__(WAVES * 64, MINW) void k_scan_mfma_full(ScanJob J, MixedRows R) {
   extern __shared__ bf16x8 smem[];
   constexpr int SLOTS = Blk<KS>::SLOTS;
   constexpr int PER_T = (SLOTS + WAVES * 64 - 1) / (WAVES * 64);
@@ -502,24 +501,28 @@ __global__ __launch_bounds__(8 * 64, 2) void k_scan_mfma_full(ScanJob J, MixedRo
   if (item >= J.n_groups) return;
   const int64_t N = J.N;
   const int n = J.n;
-  const int64_t g = item * WAVES + wv;            // this wavefront's row block
-  const bool has = g * BM < N;
-  const int64_t gb = has ? g : 0;
-  const int64_t rows = has ? min<int64_t>(BM, N - g * BM) : 0;
-  const uint32_t valid = rows >= 32 ? 0xFFFFFFFFu : ((1u << rows) - 1u);
 
-  bf16x8 bh[KS], bl[KS], bx;
+  int64_t gb[RB];          // this wavefront's row blocks (0 for a block past the end)
+  uint32_t valid[RB];
+  bf16x8 bh[RB][KS], bl[RB][KS], bx[RB];
+  float smr[RB];
   const __bf16 m2 = (__bf16)(-2.0f);
-  {
-    const bf16x8* blk = S + gb * SLOTS;
+#pragma unroll
+  for (int b = 0; b < RB; ++b) {
+    const int64_t g = (item * WAVES + wv) * RB + b;
+    const bool has = g * BM < N;
+    gb[b] = has ? g : 0;
+    const int64_t rows = has ? min<int64_t>(BM, N - g * BM) : 0;
+    valid[b] = rows >= 32 ? 0xFFFFFFFFu : ((1u << rows) - 1u);
+    const bf16x8* blk = S + gb[b] * SLOTS;
 #pragma unroll
     for (int k = 0; k < KS; ++k) {
-      bh[k] = blk[k * 128 + lane] * m2;
-      bl[k] = blk[k * 128 + 64 + lane] * m2;
+      bh[b][k] = blk[k * 128 + lane] * m2;
+      bl[b][k] = blk[k * 128 + 64 + lane] * m2;
     }
-    bx = blk[KS * 128 + 64 + lane] * m2;
+    bx[b] = blk[KS * 128 + 64 + lane] * m2;
+    smr[b] = R.smu[gb[b] * BM + rl];
   }
-  const float smr = R.smu[gb * BM + rl];
 
   const int64_t NQ = (N + BN - 1) / BN;
   const int64_t e0 = J.seq_begin + ch * J.seq_chunk;
@@ -541,27 +544,36 @@ __global__ __launch_bounds__(8 * 64, 2) void k_scan_mfma_full(ScanJob J, MixedRo
   };
   auto stage = [&](int64_t t) { return smem + (t % 3) * STAGE; };
 
-  float rmin = __builtin_inff();
-  int32_t rj = -1;
+  float rmin[RB];
+  int32_t rj[RB];
+#pragma unroll
+  for (int b = 0; b < RB; ++b) {
+    rmin[b] = __builtin_inff();
+    rj[b] = -1;
+  }
   uint32_t cnt = 0;
-  auto mma = [&](floatx16& a, const bf16x8* buf) {
+  auto mma = [&](floatx16 (&a)[RB], const bf16x8* buf) {
     const bf16x8 ax = buf[KS * 128 + lane];
     floatx16 z;
 #pragma unroll
     for (int v = 0; v < 16; ++v) z[v] = 0.0f;
-    a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ax, bx, z, 0, 0, 0);
+#pragma unroll
+    for (int b = 0; b < RB; ++b) a[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ax, bx[b], z, 0, 0, 0);
 #pragma unroll
     for (int k = 0; k < KS; ++k) {
       const bf16x8 ah = buf[k * 128 + lane];
       const bf16x8 al = buf[k * 128 + 64 + lane];
-      a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[k], a, 0, 0, 0);
-      a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl[k], a, 0, 0, 0);
-      a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[k], a, 0, 0, 0);
+#pragma unroll
+      for (int b = 0; b < RB; ++b) {
+        a[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[b][k], a[b], 0, 0, 0);
+        a[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl[b][k], a[b], 0, 0, 0);
+        a[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[b][k], a[b], 0, 0, 0);
+      }
     }
   };
   // epilogue, first part (straight-line, so that it can be interleaved with the
-  // MFMA chain of the next block): the 16 distances of this lane
-  auto distances = [&](const floatx16& a, const bf16x8* buf, float (&d)[16]) {
+  // MFMA chain of the next block): the 16 distances of this lane per row block
+  auto distances = [&](const floatx16 (&a)[RB], const bf16x8* buf, float (&d)[RB][16]) {
     float smc[16];
 #pragma unroll
     for (int qd = 0; qd < 4; ++qd) {
@@ -569,64 +581,69 @@ __global__ __launch_bounds__(8 * 64, 2) void k_scan_mfma_full(ScanJob J, MixedRo
       smc[4 * qd + 0] = m.x; smc[4 * qd + 1] = m.y; smc[4 * qd + 2] = m.z; smc[4 * qd + 3] = m.w;
     }
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const float t = smr - smc[v];
-      d[v] = __builtin_fmaf(t, t, a[v]);
-    }
-  };
-  // second part: exclusion mask, row minimum and witness, pair count
-  auto finish = [&](float (&d)[16], int64_t q) {
-    const int32_t j0 = (int32_t)(q * BN);
-    const int32_t r0 = (int32_t)(gb * BM);
-    const int32_t i = r0 + rl;
-    const bool clean =
-        (j0 + BN <= (int32_t)N) && ((j0 >= r0 + BM - 1 + n) || (j0 + BN - 1 + n <= r0));
-    if (!clean) {
+    for (int b = 0; b < RB; ++b)
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
-        const int32_t j = j0 + 8 * (v >> 2) + 4 * h + (v & 3);
-        const int32_t dij = i > j ? i - j : j - i;
-        if (!(j < (int32_t)N && dij >= n)) d[v] = __builtin_inff();
+        const float t = smr[b] - smc[v];
+        d[b][v] = __builtin_fmaf(t, t, a[b][v]);
       }
-    }
-    float tmin = d[0];
+  };
+  // second part: exclusion mask, row minimum and witness, pair count
+  auto finish = [&](float (&d)[RB][16], int64_t q) {
+    const int32_t j0 = (int32_t)(q * BN);
 #pragma unroll
-    for (int v = 1; v < 16; ++v) tmin = fminf(tmin, d[v]);
-    if (__ballot(tmin < rmin)) {
-      if (tmin < rmin) {
-        int32_t jj = -1;
+    for (int b = 0; b < RB; ++b) {
+      const int32_t r0 = (int32_t)(gb[b] * BM);
+      const int32_t i = r0 + rl;
+      const bool clean =
+          (j0 + BN <= (int32_t)N) && ((j0 >= r0 + BM - 1 + n) || (j0 + BN - 1 + n <= r0));
+      if (!clean) {
 #pragma unroll
-        for (int v = 15; v >= 0; --v)
-          if (d[v] == tmin) jj = j0 + 8 * (v >> 2) + 4 * h + (v & 3);
-        rmin = tmin;
-        rj = jj;
+        for (int v = 0; v < 16; ++v) {
+          const int32_t j = j0 + 8 * (v >> 2) + 4 * h + (v & 3);
+          const int32_t dij = i > j ? i - j : j - i;
+          if (!(j < (int32_t)N && dij >= n)) d[b][v] = __builtin_inff();
+        }
       }
-    }
-    if ((valid >> rl) & 1u) {
-      if (clean) {
-        cnt += 16;
-      } else {
+      float tmin = d[b][0];
 #pragma unroll
-        for (int v = 0; v < 16; ++v) cnt += d[v] < __builtin_inff();
+      for (int v = 1; v < 16; ++v) tmin = fminf(tmin, d[b][v]);
+      if (__ballot(tmin < rmin[b])) {
+        if (tmin < rmin[b]) {
+          int32_t jj = -1;
+#pragma unroll
+          for (int v = 15; v >= 0; --v)
+            if (d[b][v] == tmin) jj = j0 + 8 * (v >> 2) + 4 * h + (v & 3);
+          rmin[b] = tmin;
+          rj[b] = jj;
+        }
+      }
+      if ((valid[b] >> rl) & 1u) {
+        if (clean) {
+          cnt += 16;
+        } else {
+#pragma unroll
+          for (int v = 0; v < 16; ++v) cnt += d[b][v] < __builtin_inff();
+        }
       }
     }
   };
-  auto epilogue = [&](const floatx16& a, int64_t q, const bf16x8* buf) {
-    float d[16];
+  auto epilogue = [&](const floatx16 (&a)[RB], int64_t q, const bf16x8* buf) {
+    float d[RB][16];
     distances(a, buf, d);
     finish(d, q);
   };
   // step t >= 1: load block t+1, multiply block t into `cur` and compute block
   // t-1's distances from `prev` in one straight-line region (the scheduler is
   // asked to interleave the two), then finish block t-1
-  auto step = [&](int64_t t, floatx16& cur, const floatx16& prev) {
+  auto step = [&](int64_t t, floatx16 (&cur)[RB], const floatx16 (&prev)[RB]) {
     if (t + 1 < steps) fetch(e0 + t + 1, stage(t + 1));
-    float d[16];
+    float d[RB][16];
     __builtin_amdgcn_s_setprio(1);
     mma(cur, stage(t));
     distances(prev, stage(t - 1), d);
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
+    for (int k = 0; k < 16 * RB; ++k) {
       __builtin_amdgcn_sched_group_barrier(0x008, 3, 0);   // 3 MFMA
       __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);   // 2 VALU
     }
@@ -635,7 +652,7 @@ __global__ __launch_bounds__(8 * 64, 2) void k_scan_mfma_full(ScanJob J, MixedRo
     __syncthreads();
   };
 
-  floatx16 acc0, acc1;
+  floatx16 acc0[RB], acc1[RB];
   if (steps > 0) {
     fetch(e0, stage(0));
     __syncthreads();
@@ -655,29 +672,33 @@ __global__ __launch_bounds__(8 * 64, 2) void k_scan_mfma_full(ScanJob J, MixedRo
     epilogue(acc0, e0 + steps - 1, stage(steps - 1));
   }
 
-  uint64_t key = rj < 0 ? kEmptyMin : pack_min(fmaxf(rmin, 0.0f), (uint32_t)rj);
-  const uint64_t o = __shfl_xor(key, 32, 64);
-  key = o < key ? o : key;
-  if (h == 0 && ((valid >> rl) & 1u) && key != kEmptyMin)
-    atomicMin((unsigned long long*)&J.best[g * BM + rl], (unsigned long long)key);
+#pragma unroll
+  for (int b = 0; b < RB; ++b) {
+    uint64_t key = rj[b] < 0 ? kEmptyMin : pack_min(fmaxf(rmin[b], 0.0f), (uint32_t)rj[b]);
+    const uint64_t o = __shfl_xor(key, 32, 64);
+    key = o < key ? o : key;
+    if (h == 0 && ((valid[b] >> rl) & 1u) && key != kEmptyMin)
+      atomicMin((unsigned long long*)&J.best[gb[b] * BM + rl], (unsigned long long)key);
+  }
   uint64_t c64 = cnt;
   for (int off = 32; off > 0; off >>= 1) c64 += __shfl_xor(c64, off, 64);
   if (lane == 0 && c64) atomicAdd((unsigned long long*)J.pairs, (unsigned long long)c64);
 }
 
-template <int KS>
+template <int KS, int RB, int WAVES, int MINW>
 void launch_full_pipelined(const ScanJob& J, const MixedRows& R, hipStream_t s) {
   const int64_t blocks = J.n_groups * J.chunks;
   if (blocks <= 0) return;
   const size_t lds = sizeof(bf16x8) * 3 * (Blk<KS>::SLOTS + 8);
   static const bool attr_set = [lds] {
     if (lds > 65536)
-      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_scan_mfma_full<KS>),
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_scan_mfma_full<KS, RB, WAVES, MINW>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     return true;
   }();
   (void)attr_set;
-  hipLaunchKernelGGL((k_scan_mfma_full<KS>), dim3((unsigned)blocks), dim3(8 * 64), lds, s, J, R);
+  hipLaunchKernelGGL((k_scan_mfma_full<KS, RB, WAVES, MINW>), dim3((unsigned)blocks),
+                     dim3(WAVES * 64), lds, s, J, R);
 }
 
 template <int KS, int RB, int WAVES>
@@ -704,7 +725,7 @@ void launch_ks(const ScanJob& J, const MixedRows& R, hipStream_t s) {
   if constexpr (KS > 8 && KS <= 16) {
     if (waves_for<KS>(J.abandon != 0) == 8) {
       // full scans only: no abandon, matrix order, every item listed
-      launch_full_pipelined<KS>(J, R, s);
+      launch_full_pipelined<KS, 1, 8, 2>(J, R, s);
       return;
     }
   }
