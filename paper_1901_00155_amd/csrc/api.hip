@@ -53,7 +53,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 // polls wait behind the atomics: the first window of a walk1m search took 2x
 // as long).
 struct SearchScalars {
-  alignas(128) uint64_t pairs;   // pair distances evaluated
+  alignas(128) uint64_t pairs;   // pair distances evaluated (the sum of the pair slots)
   alignas(128) uint32_t bsf;     // best-so-far (float bits)
   alignas(128) uint64_t seed;    // packed (distance, ~row) of the certification seed
   uint32_t n_surv;               // survivors of the last window launch
@@ -70,7 +70,7 @@ struct Layout {
   // with one copy
   size_t T, stats, partials, bad, words, hist, minfreq, cand, cand_count, seg, csr_off, csr_mem,
       best, nn_approx, nn_wit, row_state, row_mean, row_cnorm, rows, part_d, part_j, out_d,
-      out_j, exact, unc, srch, alive, done, survivors, survivors2, score, rank_hist, gflags,
+      out_j, exact, unc, srch, pair_slots, alive, done, survivors, survivors2, score, rank_hist, gflags,
       cand_groups, bgrp_cnt, bgrp_off, bgrp, max_bucket, mu32, smu32, cn32, sblk, total;
 };
 
@@ -113,6 +113,7 @@ Layout make_layout(int64_t m, int32_t n, int dict, bool mixed) {
   L.unc = take(sizeof(int64_t) * N);
   const int64_t G = (N + kRowGroup - 1) / kRowGroup;
   L.srch = take(sizeof(SearchScalars));
+  L.pair_slots = take(sizeof(uint64_t) * kPairSlots * kPairStride);
   L.alive = take(sizeof(uint32_t) * G);
   L.done = take(sizeof(uint32_t) * G);
   L.survivors = take(sizeof(int32_t) * G);
@@ -476,7 +477,7 @@ int discord_search(discord_plan p, discord_result* out) {
   const bool near_first = p->opts.order == 2;     // columns nearest the row first
   uint64_t* best = p->at<uint64_t>(p->L.best);
   SearchScalars* sc = p->at<SearchScalars>(p->L.srch);
-  uint64_t* pairs = &sc->pairs;
+  uint64_t* pairs = p->at<uint64_t>(p->L.pair_slots);
   uint32_t* bsf = &sc->bsf;
   uint32_t* alive = p->at<uint32_t>(p->L.alive);
   uint32_t* n_surv = &sc->n_surv;
@@ -486,10 +487,11 @@ int discord_search(discord_plan p, discord_result* out) {
     const FillOp fills[] = {
         {best, N, kEmptyMin, 1},
         {sc, (int64_t)(sizeof(SearchScalars) / 4), 0, 0},
+        {pairs, (int64_t)kPairSlots * kPairStride, 0, 1},
         {p->at<uint32_t>(p->L.done), G, 0, 0},
         {gflags, G, 0, 0},
     };
-    launch_fill_many(fills, abandon ? 4 : 2, s);
+    launch_fill_many(fills, abandon ? 5 : 3, s);
   }
   // ---- approximate scan (Algorithms 3 and 4) ----------------------------------
   ScanJob J{};
@@ -641,6 +643,7 @@ int discord_search(discord_plan p, discord_result* out) {
   }
 
   // ---- certification in FP64 ---------------------------------------------------
+  launch_sum_pairs(pairs, &sc->pairs, s);
   float* nn_approx = p->at<float>(p->L.nn_approx);
   int32_t* nn_wit = p->at<int32_t>(p->L.nn_wit);
   int32_t* row_state = p->at<int32_t>(p->L.row_state);

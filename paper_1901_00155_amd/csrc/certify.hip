@@ -60,39 +60,16 @@ __global__ void k_fill_many(FillList L) {
   }
 }
 
-// Rows of the scan: minimum (or abandon distance) and its column; a row is
-// abandoned when its bit in the group's alive mask was cleared.
-__global__ __launch_bounds__(256) void k_unpack_best(const uint64_t* __restrict__ best, int64_t N,
-                                                     const uint32_t* __restrict__ alive, int gsz,
-                                                     float* __restrict__ nn_approx,
-                                                     int32_t* __restrict__ nn_witness,
-                                                     int32_t* __restrict__ row_state,
-                                                     uint32_t* __restrict__ n_abandoned) {
-  const int64_t i = blockIdx.x * 256ll + threadIdx.x;
-  bool ab = false;
-  if (i < N) {
-    const uint64_t k = best[i];
-    if (k == kEmptyMin) {
-      nn_approx[i] = __builtin_inff();
-      nn_witness[i] = -1;
-      row_state[i] = kRowUnscanned;
-    } else {
-      ab = alive && !((alive[i / gsz] >> (i % gsz)) & 1u);
-      nn_approx[i] = key_dist(k);
-      nn_witness[i] = (int32_t)(k & 0xFFFFFFFFu);
-      row_state[i] = ab ? kRowAbandoned : kRowFull;
-    }
-  }
-  const uint64_t m = __ballot(ab);
-  if ((threadIdx.x & 63) == 0 && m) atomicAdd(n_abandoned, (uint32_t)__popcll(m));
-}
-
-__global__ __launch_bounds__(256) void k_init_alive(uint32_t* __restrict__ alive, int64_t G,
-                                                    int64_t N, int gsz) {
-  const int64_t g = blockIdx.x * 256ll + threadIdx.x;
-  if (g >= G) return;
-  const int64_t rows = min<int64_t>(gsz, N - g * gsz);
-  alive[g] = rows >= 32 ? 0xFFFFFFFFu : ((1u << rows) - 1u);
+// Block-wide reductions that end in one atomic per block.  Device-scope
+// atomics on one address are serialised in the memory system (about 10 ns
+// each), so a grid that issued one per wavefront spent most of its time there.
+__device__ inline uint32_t block_sum_u32(uint32_t v, uint32_t* red) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  uint32_t t = 0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+  return t;
 }
 
 __device__ inline uint64_t wave_max_u64(uint64_t v) {
@@ -103,15 +80,72 @@ __device__ inline uint64_t wave_max_u64(uint64_t v) {
   return v;
 }
 
+__device__ inline uint64_t block_max_u64(uint64_t v, uint64_t* red) {
+  v = wave_max_u64(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  uint64_t t = 0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t = red[w] > t ? red[w] : t;
+  return t;
+}
+
+// grid of the row-wise passes below: at most kRowPassBlocks blocks of 256,
+// each thread striding over rows
+constexpr int64_t kRowPassBlocks = 1024;
+
+unsigned row_pass_blocks(int64_t N) {
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(kRowPassBlocks, (N + 255) / 256));
+}
+
+// Rows of the scan: minimum (or abandon distance) and its column; a row is
+// abandoned when its bit in the group's alive mask was cleared.
+__global__ __launch_bounds__(256) void k_unpack_best(const uint64_t* __restrict__ best, int64_t N,
+                                                     const uint32_t* __restrict__ alive, int gsz,
+                                                     float* __restrict__ nn_approx,
+                                                     int32_t* __restrict__ nn_witness,
+                                                     int32_t* __restrict__ row_state,
+                                                     uint32_t* __restrict__ n_abandoned) {
+  __shared__ uint32_t red[4];
+  uint32_t ab_count = 0;
+  for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < N; i += (int64_t)gridDim.x * 256) {
+    const uint64_t k = best[i];
+    if (k == kEmptyMin) {
+      nn_approx[i] = __builtin_inff();
+      nn_witness[i] = -1;
+      row_state[i] = kRowUnscanned;
+    } else {
+      const bool ab = alive && !((alive[i / gsz] >> (i % gsz)) & 1u);
+      nn_approx[i] = key_dist(k);
+      nn_witness[i] = (int32_t)(k & 0xFFFFFFFFu);
+      row_state[i] = ab ? kRowAbandoned : kRowFull;
+      ab_count += ab ? 1u : 0u;
+    }
+  }
+  const uint32_t t = block_sum_u32(ab_count, red);
+  if (threadIdx.x == 0 && t) atomicAdd(n_abandoned, t);
+}
+
+__global__ __launch_bounds__(256) void k_init_alive(uint32_t* __restrict__ alive, int64_t G,
+                                                    int64_t N, int gsz) {
+  const int64_t g = blockIdx.x * 256ll + threadIdx.x;
+  if (g >= G) return;
+  const int64_t rows = min<int64_t>(gsz, N - g * gsz);
+  alive[g] = rows >= 32 ? 0xFFFFFFFFu : ((1u << rows) - 1u);
+}
+
 // max approximate NN over fully scanned rows, lowest row on ties
 __global__ __launch_bounds__(256) void k_seed_argmax(const uint64_t* __restrict__ best,
                                                      const int32_t* __restrict__ row_state,
                                                      int64_t N, uint64_t* __restrict__ seed) {
-  const int64_t i = blockIdx.x * 256ll + threadIdx.x;
+  __shared__ uint64_t red[4];
   uint64_t key = 0;
-  if (i < N && row_state[i] == kRowFull) key = pack_max(key_dist(best[i]), (uint32_t)i);
-  key = wave_max_u64(key);
-  if ((threadIdx.x & 63) == 0 && key) atomicMax((unsigned long long*)seed, (unsigned long long)key);
+  for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < N; i += (int64_t)gridDim.x * 256)
+    if (row_state[i] == kRowFull) {
+      const uint64_t k = pack_max(key_dist(best[i]), (uint32_t)i);
+      key = k > key ? k : key;
+    }
+  key = block_max_u64(key, red);
+  if (threadIdx.x == 0 && key) atomicMax((unsigned long long*)seed, (unsigned long long)key);
 }
 
 __global__ void k_seed_row(const uint64_t* __restrict__ seed, int64_t* __restrict__ rows) {
@@ -218,25 +252,24 @@ __global__ __launch_bounds__(256) void k_verify(const float* __restrict__ T, int
                                                 int64_t* __restrict__ uncertain,
                                                 uint32_t* __restrict__ count,
                                                 uint32_t* __restrict__ max_rel_err_bits) {
-  const int64_t i = blockIdx.x * 256ll + threadIdx.x;
+  __shared__ uint64_t red[4];
+  const double L = ex->d2;
+  const int64_t s = ex->i;
   float rel = 0.0f;
-  if (i < N) {
-    const double L = ex->d2;
-    const int64_t s = ex->i;
-    if (i != s && has_non_self(i, N, n)) {
-      const int32_t w = nn_witness[i];
-      bool ok = false;
-      if (w >= 0 && s >= 0) {
-        const double e = d2_fp64(T, i, w, n);
-        ok = (e < L) || (e == L && i > s);
-        if (e > 0.0) rel = (float)(fabs((double)nn_approx[i] - e) / e);
-      }
-      if (!ok) uncertain[atomicAdd(count, 1u)] = i;
+  for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < N; i += (int64_t)gridDim.x * 256) {
+    if (i == s || !has_non_self(i, N, n)) continue;
+    const int32_t w = nn_witness[i];
+    bool ok = false;
+    if (w >= 0 && s >= 0) {
+      const double e = d2_fp64(T, i, w, n);
+      ok = (e < L) || (e == L && i > s);
+      if (e > 0.0) rel = fmaxf(rel, (float)(fabs((double)nn_approx[i] - e) / e));
     }
+    if (!ok) uncertain[atomicAdd(count, 1u)] = i;
   }
-  for (int off = 32; off > 0; off >>= 1) rel = fmaxf(rel, __shfl_xor(rel, off, 64));
-  if ((threadIdx.x & 63) == 0 && rel > 0.0f)
-    atomicMax(max_rel_err_bits, __builtin_bit_cast(uint32_t, rel));
+  // non-negative floats order like their bit patterns
+  const uint64_t m = block_max_u64(__builtin_bit_cast(uint32_t, rel), red);
+  if (threadIdx.x == 0 && m) atomicMax(max_rel_err_bits, (uint32_t)m);
 }
 
 // argmax of (ex, rows[k] with exact d[k]): larger d wins, lower row on ties.
@@ -260,7 +293,19 @@ __global__ void k_merge_exact(const int64_t* __restrict__ rows, const double* __
   *ex = b;
 }
 
+__global__ __launch_bounds__(64) void k_sum_pairs(const uint64_t* __restrict__ slots,
+                                                  uint64_t* __restrict__ total) {
+  static_assert(kPairSlots <= 64, "one wavefront sums the slots");
+  uint64_t v = threadIdx.x < kPairSlots ? slots[threadIdx.x * kPairStride] : 0;
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if (threadIdx.x == 0) *total = v;
+}
+
 }  // namespace
+
+void launch_sum_pairs(const uint64_t* slots, uint64_t* total, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_pairs, dim3(1), dim3(64), 0, s, slots, total);
+}
 
 void launch_fill_many(const FillOp* ops, int count, hipStream_t s) {
   FillList L{};
@@ -287,7 +332,7 @@ void launch_init_i32(int32_t* p, int64_t count, int32_t v, hipStream_t s) {
 void launch_unpack_best(const uint64_t* best, int64_t N, const uint32_t* alive, int gsz,
                         float* nn_approx, int32_t* nn_witness, int32_t* row_state,
                         uint32_t* n_abandoned, hipStream_t s) {
-  hipLaunchKernelGGL(k_unpack_best, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, best, N,
+  hipLaunchKernelGGL(k_unpack_best, dim3(row_pass_blocks(N)), dim3(256), 0, s, best, N,
                      alive, gsz, nn_approx, nn_witness, row_state, n_abandoned);
 }
 
@@ -299,7 +344,7 @@ void launch_init_alive(uint32_t* alive, int64_t G, int64_t N, int gsz, hipStream
 
 void launch_seed_argmax(const uint64_t* best, const int32_t* row_state, int64_t N,
                         uint64_t* seed_key, hipStream_t s) {
-  hipLaunchKernelGGL(k_seed_argmax, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, best,
+  hipLaunchKernelGGL(k_seed_argmax, dim3(row_pass_blocks(N)), dim3(256), 0, s, best,
                      row_state, N, seed_key);
 }
 
@@ -327,7 +372,7 @@ void launch_exact_from_rows(const int64_t* rows, const double* d, const int64_t*
 void launch_verify(const float* Tp, int n, int64_t N, const int32_t* nn_witness,
                    const float* nn_approx, const Exact* ex, int64_t* uncertain,
                    uint32_t* uncertain_count, uint32_t* max_rel_err_bits, hipStream_t s) {
-  hipLaunchKernelGGL(k_verify, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, Tp, n, N,
+  hipLaunchKernelGGL(k_verify, dim3(row_pass_blocks(N)), dim3(256), 0, s, Tp, n, N,
                      nn_witness, nn_approx, ex, uncertain, uncertain_count, max_rel_err_bits);
 }
 

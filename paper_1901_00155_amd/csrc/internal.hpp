@@ -112,9 +112,21 @@ struct ScanJob {
   int32_t* survivors;         // items left with live rows by a non-final launch
   uint32_t* n_survivors;
   uint64_t* best;             // per row: packed (approximate distance, column) minimum
-  uint64_t* pairs;            // pair distances evaluated (non-self, in range)
+  uint64_t* pairs;            // pair distances evaluated (non-self, in range), counted in
+                              // kPairSlots slots kPairStride words apart (see pair_slot)
 };
 void launch_scan_fp32(const ScanJob& J, hipStream_t s);
+
+// The pair counter is spread over slots on cache lines of their own, chosen by
+// workgroup number: device-scope atomics on one address are serialised in the
+// memory system, and one counter added to by every wavefront of a launch cost
+// a few per cent of the scan.  launch_sum_pairs folds the slots into one total.
+constexpr int kPairSlots = 64;
+constexpr int kPairStride = 16;   // 128 bytes
+__device__ __forceinline__ unsigned long long* pair_slot(uint64_t* pairs) {
+  return reinterpret_cast<unsigned long long*>(pairs + (blockIdx.x % kPairSlots) * kPairStride);
+}
+void launch_sum_pairs(const uint64_t* slots, uint64_t* total, hipStream_t s);
 
 // ---- scan_mfma.hip ------------------------------------------------------------
 // Row statistics of the split-BF16 scan (FP32, padded with zeros to N + 64):

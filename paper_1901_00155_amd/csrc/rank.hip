@@ -23,6 +23,16 @@ __device__ __forceinline__ uint32_t load_relaxed(const uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+__device__ __forceinline__ uint32_t row_score(const uint32_t* __restrict__ alive,
+                                              const uint64_t* __restrict__ best, int64_t i,
+                                              int gsz) {
+  if (!((load_relaxed(&alive[i / gsz]) >> (i % gsz)) & 1u)) return 0;
+  const uint64_t key = best[i];
+  const uint32_t bits = key == kEmptyMin ? 0x7F800000u : (uint32_t)(key >> 32);
+  return bits > 0x7F800000u ? 0 : bits;   // not a non-negative number: rank last
+}
+
+// Small items (up to 64 rows): one thread per item.
 __global__ __launch_bounds__(256) void k_group_score(const int32_t* __restrict__ list,
                                                      int64_t count, int64_t item_rows, int gsz,
                                                      const uint32_t* __restrict__ alive,
@@ -31,17 +41,35 @@ __global__ __launch_bounds__(256) void k_group_score(const int32_t* __restrict__
   const int64_t k = blockIdx.x * 256ll + threadIdx.x;
   if (k >= count) return;
   const int64_t r0 = (int64_t)list[k] * item_rows;
-  uint32_t s = 0, live = 0;
+  uint32_t s = 0;
   for (int64_t i = r0; i < r0 + item_rows && i < N; ++i) {
-    const int r = (int)((i - r0) % gsz);
-    if (r == 0) live = load_relaxed(&alive[i / gsz]);
-    if (!((live >> r) & 1u)) continue;
-    const uint64_t key = best[i];
-    uint32_t bits = key == kEmptyMin ? 0x7F800000u : (uint32_t)(key >> 32);
-    if (bits > 0x7F800000u) bits = 0;   // not a non-negative number: rank last
-    s = bits > s ? bits : s;
+    const uint32_t b = row_score(alive, best, i, gsz);
+    s = b > s ? b : s;
   }
   score[k] = s;
+}
+
+// Large items: one wavefront per item, its lanes striding over the rows.
+__global__ __launch_bounds__(256) void k_group_score_wave(const int32_t* __restrict__ list,
+                                                          int64_t count, int64_t item_rows, int gsz,
+                                                          const uint32_t* __restrict__ alive,
+                                                          const uint64_t* __restrict__ best,
+                                                          int64_t N, uint32_t* __restrict__ score) {
+  const int64_t k = blockIdx.x * 4ll + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (k >= count) return;
+  const int64_t r0 = (int64_t)list[k] * item_rows;
+  const int64_t r1 = min<int64_t>(N, r0 + item_rows);
+  uint32_t s = 0;
+  for (int64_t i = r0 + lane; i < r1; i += 64) {
+    const uint32_t b = row_score(alive, best, i, gsz);
+    s = b > s ? b : s;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint32_t o = __shfl_xor(s, off, 64);
+    s = o > s ? o : s;
+  }
+  if (lane == 0) score[k] = s;
 }
 
 __global__ __launch_bounds__(256) void k_rank_hist(const uint32_t* __restrict__ score,
@@ -83,14 +111,28 @@ __global__ __launch_bounds__(1024) void k_rank_offsets(uint32_t* __restrict__ hi
   }
 }
 
+// Each block ranks its items in LDS first and reserves its slots with one
+// atomic per occupied bin, so a bin's global cursor sees one atomic per block
+// rather than one per item.
 __global__ __launch_bounds__(256) void k_rank_scatter(const int32_t* __restrict__ list,
                                                       const uint32_t* __restrict__ score,
                                                       int64_t count, uint32_t* __restrict__ cursor,
                                                       int32_t* __restrict__ out) {
+  __shared__ uint32_t local[kBins];
+  __shared__ uint32_t base[kBins];
+  for (int b = threadIdx.x; b < kBins; b += 256) local[b] = 0;
+  __syncthreads();
   const int64_t k = blockIdx.x * 256ll + threadIdx.x;
-  if (k >= count) return;
-  const uint32_t slot = atomicAdd(&cursor[min(score[k] >> kBinShift, (uint32_t)(kBins - 1))], 1u);
-  out[slot] = list[k];
+  uint32_t bin = 0, pos = 0;
+  if (k < count) {
+    bin = min(score[k] >> kBinShift, (uint32_t)(kBins - 1));
+    pos = atomicAdd(&local[bin], 1u);
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < kBins; b += 256)
+    if (local[b]) base[b] = atomicAdd(&cursor[b], local[b]);
+  __syncthreads();
+  if (k < count) out[base[bin] + pos] = list[k];
 }
 
 }  // namespace
@@ -104,8 +146,12 @@ void launch_rank_groups(const int32_t* list, int64_t count, int64_t item_rows, i
   if (count <= 0) return;
   const unsigned blocks = (unsigned)((count + 255) / 256);
   launch_init_i32(reinterpret_cast<int32_t*>(hist), kBins, 0, s);
-  hipLaunchKernelGGL(k_group_score, dim3(blocks), dim3(256), 0, s, list, count, item_rows, gsz, alive,
-                     best, N, score);
+  if (item_rows > 64)
+    hipLaunchKernelGGL(k_group_score_wave, dim3((unsigned)((count + 3) / 4)), dim3(256), 0, s, list,
+                       count, item_rows, gsz, alive, best, N, score);
+  else
+    hipLaunchKernelGGL(k_group_score, dim3(blocks), dim3(256), 0, s, list, count, item_rows, gsz,
+                       alive, best, N, score);
   hipLaunchKernelGGL(k_rank_hist, dim3(std::min(blocks, 1024u)), dim3(256), 0, s, score, count,
                      hist);
   hipLaunchKernelGGL(k_rank_offsets, dim3(1), dim3(1024), 0, s, hist);

@@ -257,7 +257,7 @@ __global__ __launch_bounds__(256) void k_scan_fp32(ScanJob J) {
   }
   uint64_t c64 = cnt;
   for (int off = 32; off > 0; off >>= 1) c64 += __shfl_xor(c64, off, 64);
-  if (lane == 0 && c64) atomicAdd((unsigned long long*)J.pairs, (unsigned long long)c64);
+  if (lane == 0 && c64) atomicAdd(pair_slot(J.pairs), (unsigned long long)c64);
   if (!J.abandon) return;
 
   // the item's last chunk to finish decides: complete rows raise the best-so-far

@@ -433,7 +433,7 @@ __global__ __launch_bounds__(WAVES * 64, (KS <= 16 ? 2 : 1)) void k_scan_mfma(Sc
   }
   uint64_t c64 = cnt;
   for (int off = 32; off > 0; off >>= 1) c64 += __shfl_xor(c64, off, 64);
-  if (lane == 0 && c64) atomicAdd((unsigned long long*)J.pairs, (unsigned long long)c64);
+  if (lane == 0 && c64) atomicAdd(pair_slot(J.pairs), (unsigned long long)c64);
   if (!J.abandon) return;
 
   // the item's last chunk to finish decides: complete rows raise the
@@ -682,7 +682,7 @@ __global__ __launch_bounds__(WAVES * 64, MINW) void k_scan_mfma_full(ScanJob J, 
   }
   uint64_t c64 = cnt;
   for (int off = 32; off > 0; off >>= 1) c64 += __shfl_xor(c64, off, 64);
-  if (lane == 0 && c64) atomicAdd((unsigned long long*)J.pairs, (unsigned long long)c64);
+  if (lane == 0 && c64) atomicAdd(pair_slot(J.pairs), (unsigned long long)c64);
 }
 
 template <int KS, int RB, int WAVES, int MINW>
