@@ -17,6 +17,12 @@ Readings of the paper that this oracle takes (the paper is silent or garbled):
   * eq. (3) segments are [floor(s n / w), floor((s+1) n / w)); eq. (4) symbols are
     left-closed quantile intervals of N(0,1); eq. (9) is the lexicographic rank
     sum_s sym_s * |A|^(w-1-s) of the 0-based symbols.
+
+A second reading is available everywhere as ``znorm=True``: Algorithm 2's
+Znormalize(S) taken row by row, i.e. every window normalised by its own mean
+and standard deviation (eq. (2) over the window), a flat window becoming the
+zero vector.  Distances are then between normalised windows and are reported
+as they are (no division by the series' sigma).
 """
 from __future__ import annotations
 
@@ -30,7 +36,8 @@ import numpy as np
 __all__ = [
     "load", "stats", "pair_d2", "rows_nn", "discord", "witness_check", "sax_words",
     "np_sax_words", "breakpoints", "freq_cand", "index_word", "np_discord",
-    "int_discord", "alg1", "phidd", "pair_count", "OracleError",
+    "int_discord", "alg1", "phidd", "pair_count", "OracleError", "row_zstats",
+    "np_discord_z", "exact_z_profile",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -72,6 +79,20 @@ def load():
     lib.orc_sax_words.argtypes = [f32p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
                                   ctypes.c_int32, f64p, ctypes.c_double, ctypes.c_double,
                                   i32p, ctypes.c_int]
+    lib.orc_row_zstats.restype = ctypes.c_int
+    lib.orc_row_zstats.argtypes = [f32p, ctypes.c_int64, ctypes.c_int32, f64p, f64p]
+    lib.orc_pair_d2_z.restype = ctypes.c_double
+    lib.orc_pair_d2_z.argtypes = [f32p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64,
+                                  ctypes.c_int64, f64p, f64p]
+    lib.orc_rows_nn_z.restype = ctypes.c_int
+    lib.orc_rows_nn_z.argtypes = lib.orc_rows_nn.argtypes
+    lib.orc_discord_z.restype = ctypes.c_int
+    lib.orc_discord_z.argtypes = lib.orc_discord.argtypes
+    lib.orc_witness_check_z.restype = ctypes.c_int64
+    lib.orc_witness_check_z.argtypes = lib.orc_witness_check.argtypes
+    lib.orc_sax_words_z.restype = ctypes.c_int
+    lib.orc_sax_words_z.argtypes = [f32p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                    ctypes.c_int32, f64p, f64p, f64p, i32p, ctypes.c_int]
     _lib = lib
     return lib
 
@@ -110,16 +131,35 @@ def stats(T):
     return mu.value, sd.value
 
 
-def pair_d2(T, n: int, i: int, j: int) -> float:
-    """Squared Euclidean distance of eq. (1) between T_{i,n} and T_{j,n}."""
+def row_zstats(T, n: int):
+    """Mean and standard deviation of every window T_{i,n} (eq. (2) over the
+    window alone; two-pass, sequential sums in C).  Returns (mu[N], sigma[N])."""
+    T = _f32(T)
+    if n < 1 or T.size < n:
+        raise OracleError("need 1 <= n <= m")
+    N = T.size - n + 1
+    mu = np.empty(N, dtype=np.float64)
+    sg = np.empty(N, dtype=np.float64)
+    load().orc_row_zstats(_ptr(T, ctypes.c_float), T.size, n, _ptr(mu, ctypes.c_double),
+                          _ptr(sg, ctypes.c_double))
+    return mu, sg
+
+
+def pair_d2(T, n: int, i: int, j: int, znorm: bool = False) -> float:
+    """Squared Euclidean distance of eq. (1) between T_{i,n} and T_{j,n} (with
+    ``znorm``, between the two windows each normalised on its own)."""
     T = _f32(T)
     N = T.size - n + 1
     if not (0 <= i < N and 0 <= j < N):
         raise OracleError("row out of range")
+    if znorm:
+        mu, sg = row_zstats(T, n)
+        return load().orc_pair_d2_z(_ptr(T, ctypes.c_float), T.size, n, i, j,
+                                    _ptr(mu, ctypes.c_double), _ptr(sg, ctypes.c_double))
     return load().orc_pair_d2(_ptr(T, ctypes.c_float), T.size, n, i, j)
 
 
-def rows_nn(T, n: int, rows, threads=None):
+def rows_nn(T, n: int, rows, threads=None, znorm: bool = False):
     """Exact nearest non-self match (d^2, j) of each listed row; j = -1 if none."""
     T = _f32(T)
     rows = np.ascontiguousarray(rows, dtype=np.int64)
@@ -128,7 +168,8 @@ def rows_nn(T, n: int, rows, threads=None):
         raise OracleError("row out of range")
     d = np.empty(rows.size, dtype=np.float64)
     j = np.empty(rows.size, dtype=np.int64)
-    st = load().orc_rows_nn(_ptr(T, ctypes.c_float), T.size, n, _ptr(rows, ctypes.c_int64),
+    fn = load().orc_rows_nn_z if znorm else load().orc_rows_nn
+    st = fn(_ptr(T, ctypes.c_float), T.size, n, _ptr(rows, ctypes.c_int64),
                             rows.size, _ptr(d, ctypes.c_double), _ptr(j, ctypes.c_int64),
                             _threads(threads))
     if st != 0:
@@ -136,10 +177,12 @@ def rows_nn(T, n: int, rows, threads=None):
     return d, j
 
 
-def discord(T, n: int, threads=None, profile: bool = False) -> dict:
+def discord(T, n: int, threads=None, profile: bool = False, znorm: bool = False) -> dict:
     """Brute-force discord of section 2.1 in FP64 (C).  Returns index, nn_index,
     d2 (raw squared NN distance), distance_raw, distance (z-normalised units,
-    eq. (2)), mu, sigma and, if asked, the NN profile and its argmins."""
+    eq. (2)), mu, sigma and, if asked, the NN profile and its argmins.  With
+    ``znorm`` every window is normalised on its own; d2 is then the squared
+    distance between normalised windows and distance = distance_raw = sqrt(d2)."""
     T = _f32(T)
     m = T.size
     if n < 1 or m < 2 * n:
@@ -149,7 +192,8 @@ def discord(T, n: int, threads=None, profile: bool = False) -> dict:
     d2, mu, sd = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
     prof = np.empty(N, dtype=np.float64) if profile else None
     pj = np.empty(N, dtype=np.int64) if profile else None
-    st = load().orc_discord(_ptr(T, ctypes.c_float), m, n, _threads(threads),
+    fn = load().orc_discord_z if znorm else load().orc_discord
+    st = fn(_ptr(T, ctypes.c_float), m, n, _threads(threads),
                             ctypes.byref(idx), ctypes.byref(nnj), ctypes.byref(d2),
                             ctypes.byref(mu), ctypes.byref(sd),
                             _ptr(prof, ctypes.c_double) if profile else None,
@@ -158,16 +202,16 @@ def discord(T, n: int, threads=None, profile: bool = False) -> dict:
         raise OracleError("sigma == 0: eq. (2) is undefined for a constant series")
     if st != 0:
         raise OracleError("invalid series")
+    dist = math.sqrt(d2.value) if znorm else math.sqrt(d2.value) / sd.value
     out = dict(index=idx.value, nn_index=nnj.value, d2=d2.value,
-               distance_raw=math.sqrt(d2.value), distance=math.sqrt(d2.value) / sd.value,
-               mu=mu.value, sigma=sd.value)
+               distance_raw=math.sqrt(d2.value), distance=dist, mu=mu.value, sigma=sd.value)
     if profile:
         out["profile"] = prof
         out["profile_j"] = pj
     return out
 
 
-def witness_check(T, n: int, idx: int, d2: float, wit, threads=None):
+def witness_check(T, n: int, idx: int, d2: float, wit, threads=None, znorm: bool = False):
     """FP64 certificate (see discord_ref.c).  Returns (bad_rows, first_bad,
     exact NN d^2 of idx)."""
     T = _f32(T)
@@ -176,9 +220,9 @@ def witness_check(T, n: int, idx: int, d2: float, wit, threads=None):
     if wit.size != N:
         raise OracleError("one witness per row expected")
     fb, nn = ctypes.c_int64(), ctypes.c_double()
-    bad = load().orc_witness_check(_ptr(T, ctypes.c_float), T.size, n, int(idx), float(d2),
-                                   _ptr(wit, ctypes.c_int64), _threads(threads),
-                                   ctypes.byref(fb), ctypes.byref(nn))
+    fn = load().orc_witness_check_z if znorm else load().orc_witness_check
+    bad = fn(_ptr(T, ctypes.c_float), T.size, n, int(idx), float(d2),
+             _ptr(wit, ctypes.c_int64), _threads(threads), ctypes.byref(fb), ctypes.byref(nn))
     if bad < 0:
         raise OracleError("invalid arguments")
     return int(bad), int(fb.value), nn.value
@@ -195,17 +239,26 @@ def breakpoints(alpha: int = 4) -> np.ndarray:
     return np.array([nd.inv_cdf(k / alpha) for k in range(1, alpha)], dtype=np.float64)
 
 
-def sax_words(T, n: int, w: int = 4, alpha: int = 4, threads=None) -> np.ndarray:
+def sax_words(T, n: int, w: int = 4, alpha: int = 4, threads=None,
+              znorm: bool = False) -> np.ndarray:
     """Word id of every row: PAA (eq. 3) -> SAX (eq. 4) -> hash (eq. 9), on the
-    z-normalised series of eq. (2).  C, sequential sums."""
+    z-normalised series of eq. (2) (with ``znorm``, on every window normalised
+    on its own).  C, sequential sums."""
     T = _f32(T)
     mu, sd = stats(T)
     N = T.size - n + 1
     bp = breakpoints(alpha)
     words = np.empty(N, dtype=np.int32)
-    st = load().orc_sax_words(_ptr(T, ctypes.c_float), T.size, n, w, alpha,
-                              _ptr(bp, ctypes.c_double), mu, sd,
-                              _ptr(words, ctypes.c_int32), _threads(threads))
+    if znorm:
+        zmu, zsg = row_zstats(T, n)
+        st = load().orc_sax_words_z(_ptr(T, ctypes.c_float), T.size, n, w, alpha,
+                                    _ptr(bp, ctypes.c_double), _ptr(zmu, ctypes.c_double),
+                                    _ptr(zsg, ctypes.c_double), _ptr(words, ctypes.c_int32),
+                                    _threads(threads))
+    else:
+        st = load().orc_sax_words(_ptr(T, ctypes.c_float), T.size, n, w, alpha,
+                                  _ptr(bp, ctypes.c_double), mu, sd,
+                                  _ptr(words, ctypes.c_int32), _threads(threads))
     if st != 0:
         raise OracleError("invalid SAX arguments")
     return words
@@ -278,6 +331,81 @@ def np_discord(T, n: int, block: int = 64) -> dict:
     sd = math.sqrt(((t - t.mean()) ** 2).mean())
     return dict(index=idx, nn_index=int(pj[idx]), d2=float(best), profile=prof,
                 profile_j=pj, distance=math.sqrt(best) / sd)
+
+
+def np_discord_z(T, n: int, block: int = 64) -> dict:
+    """NumPy all-pairs brute force under per-window normalisation (independent
+    of the C code): the normalised window matrix X is built with NumPy's mean
+    and std, a flat window becoming zeros, then direct-form distances."""
+    t = np.asarray(T, dtype=np.float32).astype(np.float64)
+    m = t.size
+    if n < 1 or m < 2 * n:
+        raise OracleError("need n >= 1 and m >= 2n")
+    W = np.lib.stride_tricks.sliding_window_view(t, n)
+    mu = W.mean(axis=1, keepdims=True)
+    sd = W.std(axis=1, keepdims=True)
+    X = np.where(sd > 0, (W - mu) / np.where(sd > 0, sd, 1.0), 0.0)
+    N = X.shape[0]
+    prof = np.full(N, np.inf)
+    pj = np.full(N, -1, dtype=np.int64)
+    cols = np.arange(N)
+    for r0 in range(0, N, block):
+        R = X[r0:r0 + block]
+        D = ((R[:, None, :] - X[None, :, :]) ** 2).sum(axis=2)
+        rows = np.arange(r0, r0 + R.shape[0])
+        D[np.abs(rows[:, None] - cols[None, :]) < n] = np.inf
+        pj[r0:r0 + R.shape[0]] = np.argmin(D, axis=1)
+        prof[r0:r0 + R.shape[0]] = D[np.arange(R.shape[0]), pj[r0:r0 + R.shape[0]]]
+    has = np.isfinite(prof)
+    pj[~has] = -1
+    best = np.max(prof[has])
+    idx = int(np.flatnonzero(has & (prof == best))[0])
+    return dict(index=idx, nn_index=int(pj[idx]), d2=float(best), profile=prof,
+                profile_j=pj, distance=math.sqrt(best))
+
+
+def exact_z_profile(values, n: int, digits: int = 60):
+    """Per-window normalised NN profile from exact rational arithmetic: with
+    integer (or rational) values, C_ij = sum (a - mean a)(b - mean b) and
+    V_i = sum (a - mean a)^2 are exact Fractions and
+        d^2(i, j) = V_i/s_i^2 + V_j/s_j^2 - 2 C_ij/(s_i s_j),  s_i = sqrt(V_i / n),
+    i.e. 2n - 2 C_ij sqrt(n^2 / (V_i V_j)) for non-flat windows (n for one flat
+    window, 0 for two).  The one square root is taken in ``digits``-digit decimal
+    arithmetic.  Returns (profile, profile_j) as lists of Decimal and int."""
+    import decimal
+    from fractions import Fraction
+    vals = [Fraction(v) for v in values]
+    m = len(vals)
+    N = m - n + 1
+    ctx = decimal.Context(prec=digits)
+    wins = []
+    for i in range(N):
+        w = vals[i:i + n]
+        mean = sum(w) / n
+        c = [x - mean for x in w]
+        wins.append((c, sum(x * x for x in c)))
+
+    def dec(fr):
+        return ctx.divide(decimal.Decimal(fr.numerator), decimal.Decimal(fr.denominator))
+
+    prof, pj = [None] * N, [-1] * N
+    for i in range(N):
+        ci, vi = wins[i]
+        for j in range(N):
+            if abs(i - j) < n:
+                continue
+            cj, vj = wins[j]
+            if vi == 0 and vj == 0:
+                d = decimal.Decimal(0)
+            elif vi == 0 or vj == 0:
+                d = decimal.Decimal(n)
+            else:
+                cij = sum(a * b for a, b in zip(ci, cj))
+                r = ctx.sqrt(dec(Fraction(n * n) / (vi * vj)))
+                d = ctx.subtract(decimal.Decimal(2 * n), ctx.multiply(2 * dec(cij), r))
+            if prof[i] is None or d < prof[i]:
+                prof[i], pj[i] = d, j
+    return prof, pj
 
 
 def int_discord(values, n: int):

@@ -1,0 +1,229 @@
+"""Pins for the oracle's per-window normalisation mode (CPU only).
+
+Reading: Algorithm 2 applies Znormalize to the subsequence matrix S; taken row
+by row, every window T_{i,n} is normalised by its own mean and standard
+deviation (eq. (2) over the window), a flat window becoming the zero vector,
+and eq. (1) is taken between the normalised windows.  Nothing here reuses the
+C code's arithmetic: the pins are exact rational arithmetic, an independent
+NumPy brute force, the Pearson-correlation identity d^2 = 2n(1 - rho) against
+numpy.corrcoef, exact scale invariance of one window, the flat-window and n = 1
+special cases, and the Cauchy-Schwarz range 0 <= d^2 <= 4n.
+"""
+import decimal
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1901_00155_amd import workloads
+
+
+def _int_series(rng, m):
+    T = rng.integers(-5, 6, size=m).astype(np.float32)
+    if np.all(T == T[0]):
+        T[0] += 1
+    return T
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_z_exact_rational_arithmetic(seed):
+    """Every NN value equals the exact one (rational sums, one 60-digit square
+    root) within 1e-12 of the window length; the argmax and the NN index agree
+    wherever the exact maximum (minimum) is unique by more than 1e-9."""
+    rng = np.random.default_rng(700 + seed)
+    m = int(rng.integers(8, 22))
+    T = _int_series(rng, m)
+    for n in range(2, m // 2 + 1):
+        prof, pj = oracle.exact_z_profile(T.astype(int).tolist(), n)
+        c = oracle.discord(T, n, threads=2, profile=True, znorm=True)
+        N = m - n + 1
+        for i in range(N):
+            if prof[i] is None:
+                assert c["profile_j"][i] == -1
+                continue
+            assert abs(c["profile"][i] - float(prof[i])) <= 1e-12 * n, (m, n, i)
+        vals = [(float(p), i) for i, p in enumerate(prof) if p is not None]
+        top = max(v for v, _ in vals)
+        near = [i for v, i in vals if v >= top - 1e-9 * n]
+        if len(near) == 1:
+            assert c["index"] == near[0], (m, n)
+        else:
+            assert c["index"] in near
+        # the NN index of the discord: unique exact minimiser, if it is unique
+        i = c["index"]
+        ds = []
+        for j in range(N):
+            if abs(i - j) >= n:
+                ds.append((float(oracle.pair_d2(T, n, i, j, znorm=True)), j))
+        lo = min(d for d, _ in ds)
+        cands = [j for d, j in ds if d <= lo + 1e-9 * n]
+        assert c["nn_index"] in cands
+
+
+@pytest.mark.parametrize("m,n,seed", [(300, 8, 1), (500, 25, 2), (640, 64, 3), (257, 1, 4),
+                                      (400, 100, 5)])
+def test_z_c_equals_numpy(m, n, seed):
+    """The C brute force equals an independent NumPy brute force (window matrix
+    from numpy mean/std) to 1e-12 relative, same argmax."""
+    T = workloads.random_walk(m, seed=seed)
+    c = oracle.discord(T, n, profile=True, znorm=True)
+    p = oracle.np_discord_z(T, n)
+    assert c["index"] == p["index"]
+    np.testing.assert_allclose(c["profile"], p["profile"], rtol=1e-12, atol=1e-12)
+
+
+def test_z_pearson_identity():
+    """d^2 = 2n (1 - rho_ij) with rho the Pearson correlation of the two raw
+    windows, computed by numpy.corrcoef."""
+    rng = np.random.default_rng(5)
+    T = workloads.random_walk(2000, seed=6)
+    for n in (4, 32, 200):
+        N = T.size - n + 1
+        for _ in range(40):
+            i, j = (int(v) for v in rng.integers(0, N, 2))
+            d2 = oracle.pair_d2(T, n, i, j, znorm=True)
+            a = T[i:i + n].astype(np.float64)
+            b = T[j:j + n].astype(np.float64)
+            rho = np.corrcoef(a, b)[0, 1]
+            assert abs(d2 - 2 * n * (1 - rho)) <= 1e-10 * n, (n, i, j)
+
+
+def test_z_range_symmetry_identity():
+    """0 <= d^2 <= 4n (Cauchy-Schwarz on vectors of norm sqrt(n)); d(i,j) =
+    d(j,i) bit for bit; d(i,i) = 0."""
+    T = workloads.random_walk(800, seed=8)
+    n = 16
+    rng = np.random.default_rng(9)
+    N = T.size - n + 1
+    for _ in range(60):
+        i, j = (int(v) for v in rng.integers(0, N, 2))
+        d = oracle.pair_d2(T, n, i, j, znorm=True)
+        assert 0.0 <= d <= 4 * n * (1 + 1e-12)
+        assert d == oracle.pair_d2(T, n, j, i, znorm=True)
+        assert oracle.pair_d2(T, n, i, i, znorm=True) == 0.0
+
+
+def test_z_doubled_copy_is_an_exact_match():
+    """A copy of the discord window scaled by 2 (exact in float32) normalises to
+    the same vector bit for bit, so the discord's NN becomes exactly 0 and the
+    discord moves.  Under the global reading the scaled copy is no match: the
+    pin tells the two readings apart."""
+    T = workloads.random_walk(1200, seed=10)
+    n = 32
+    a = oracle.discord(T, n, znorm=True)
+    i = a["index"]
+    U = T.copy()
+    dst = 100 if i > 600 else 1000
+    U[dst:dst + n] = 2.0 * T[i:i + n]
+    b = oracle.discord(U, n, profile=True, znorm=True)
+    assert b["profile"][i] == 0.0
+    assert b["index"] != i
+    g = oracle.discord(U, n, profile=True)
+    assert g["profile"][i] > 0.0
+    # an affine copy with a shift is a match up to float32 rounding of the copy
+    V = T.copy()
+    V[dst:dst + n] = 0.5 * T[i:i + n] + 37.0
+    c = oracle.discord(V, n, profile=True, znorm=True)
+    assert c["profile"][i] < 1e-8
+
+
+def test_z_flat_windows():
+    """A flat window normalises to zeros: two flat windows are at distance 0, a
+    flat and a non-flat one at n (the normalised window's squared norm)."""
+    rng = np.random.default_rng(12)
+    n = 10
+    T = np.cumsum(rng.standard_normal(200)).astype(np.float32)
+    T[60:60 + 3 * n] = np.float32(1.25)          # rows 60 .. 60+2n are flat
+    mu, sg = oracle.row_zstats(T, n)
+    assert np.all(sg[60:60 + 2 * n + 1] == 0.0) and sg[59] > 0.0
+    assert oracle.pair_d2(T, n, 60, 60 + 2 * n, znorm=True) == 0.0
+    d = oracle.pair_d2(T, n, 60, 150, znorm=True)
+    assert abs(d - n) <= 1e-12 * n
+    c = oracle.discord(T, n, profile=True, znorm=True)
+    assert c["profile"][60] == 0.0                # row 60+2n is a flat non-self match
+
+
+@pytest.mark.parametrize("m", [6, 17, 40])
+def test_z_window_one(m):
+    """n = 1: every window is flat, every distance 0; the lowest index wins the
+    argmax and its nearest non-self match is the lowest j with |i - j| >= 1."""
+    T = workloads.random_walk(m, seed=m)
+    c = oracle.discord(T, 1, profile=True, znorm=True)
+    assert c["index"] == 0 and c["nn_index"] == 1 and c["d2"] == 0.0
+    assert np.all(c["profile"] == 0.0)
+
+
+def test_z_global_affine_invariance():
+    """a T + b (a = 4, b = -3, exact in float32 for small integers): same index,
+    the same NN values."""
+    rng = np.random.default_rng(13)
+    T = rng.integers(-50, 51, 400).astype(np.float32)
+    n = 12
+    a = oracle.discord(T, n, profile=True, znorm=True)
+    b = oracle.discord(4.0 * T - 3.0, n, profile=True, znorm=True)
+    assert a["index"] == b["index"]
+    np.testing.assert_allclose(a["profile"], b["profile"], rtol=1e-12, atol=1e-12)
+
+
+def test_z_witness_certificate():
+    """The certificate accepts the brute-force argmax with its NN witnesses and
+    rejects a broken witness."""
+    T = workloads.random_walk(700, seed=11)
+    n = 20
+    c = oracle.discord(T, n, profile=True, znorm=True)
+    wit = c["profile_j"].copy()
+    bad, first, nn = oracle.witness_check(T, n, c["index"], c["d2"], wit, znorm=True)
+    assert bad == 0 and first == -1 and nn == c["d2"]
+    r = (c["index"] + 300) % (T.size - n + 1)
+    wit2 = wit.copy()
+    wit2[r] = r
+    bad, first, _ = oracle.witness_check(T, n, c["index"], c["d2"], wit2, znorm=True)
+    assert bad >= 1 and first == r
+    # rows_nn agrees with the profile
+    rows = np.arange(0, T.size - n + 1, 37)
+    d, j = oracle.rows_nn(T, n, rows, znorm=True)
+    assert np.array_equal(d, c["profile"][rows]) and np.array_equal(j, c["profile_j"][rows])
+
+
+def test_z_small_workload_recovers_injected_anomaly():
+    """m = 4096 walk with a sine planted over t[2000:2064], n = 64: under
+    per-window normalisation too the discord overlaps the planted window."""
+    w = workloads.small()
+    c = oracle.discord(w.series, w.n, znorm=True)
+    assert 2000 - w.n < c["index"] < 2064
+    assert c["distance"] == c["distance_raw"]
+
+
+@pytest.mark.parametrize("n,w,alpha", [(16, 4, 4), (37, 4, 4), (30, 3, 5)])
+def test_z_sax_words(n, w, alpha):
+    """Words of the normalised windows: C equals a NumPy rewrite (PAA of the
+    normalised window matrix, left-closed breakpoint search); a flat window
+    maps to the word of all middle symbols."""
+    T = workloads.random_walk(900, seed=n)
+    T[400:400 + 2 * n] = np.float32(3.0)
+    words = oracle.sax_words(T, n, w, alpha, znorm=True)
+    t = T.astype(np.float64)
+    W = np.lib.stride_tricks.sliding_window_view(t, n)
+    mu = W.mean(axis=1, keepdims=True)
+    sd = W.std(axis=1, keepdims=True)
+    X = np.where(sd > 0, (W - mu) / np.where(sd > 0, sd, 1.0), 0.0)
+    bp = oracle.breakpoints(alpha)
+    code = np.zeros(X.shape[0], dtype=np.int64)
+    for s in range(w):
+        a, b = (s * n) // w, ((s + 1) * n) // w
+        paa = X[:, a:b].sum(axis=1) / (b - a)
+        code = code * alpha + np.searchsorted(bp, paa, side="right")
+    # rounding can move a PAA value across a breakpoint only within ~1e-15
+    diff = np.flatnonzero(words != code)
+    assert diff.size <= 2, diff
+    mid = sum((alpha // 2) * alpha ** (w - 1 - s) for s in range(w))
+    assert words[400] == mid
+
+
+def test_z_decimal_sqrt_sanity():
+    """The exact profile's one library call, Decimal.sqrt, is correctly rounded
+    at 60 digits on a perfect square and on 2."""
+    ctx = decimal.Context(prec=60)
+    assert ctx.sqrt(decimal.Decimal(144)) == 12
+    r = ctx.sqrt(decimal.Decimal(2))
+    assert abs(r * r - 2) < decimal.Decimal(10) ** -58
