@@ -17,8 +17,10 @@
  *   - Ties: the lowest index wins among maximal nearest-neighbour distances, and
  *     the lowest j among nearest neighbours.  Rows with no non-self match at all
  *     (possible only when 2n <= m <= 3n-2) take no part in the argmax.
- *   - z-normalisation is global (eq. (2)); it is affine, so the argmax is taken on
- *     raw squared distances and `distance` = sqrt(d2) / sigma.
+ *   - z-normalisation is global (eq. (2)) by default; it is affine, so the argmax
+ *     is taken on raw squared distances and `distance` = sqrt(d2) / sigma.  With
+ *     opts.znorm = 1 every window is normalised on its own instead (see
+ *     discord_opts), and `distance` = `distance_raw` = sqrt(d2).
  *   - The result is exact: every approximate (FP32 or split-BF16) decision is
  *     certified or redone in FP64 on the GPU before it is returned.
  *   - A negative status means no output was written.  No C++ exception crosses
@@ -76,7 +78,17 @@ typedef struct {
                            sequence, in steps of 512 columns; rows still live
                            then continue in later windows (0: library default,
                            2 (FP32) or 4 (split-BF16) for order 2, else 16)      */
-    int32_t reserved;
+    int32_t znorm;      /* which z-normalisation the distance uses:
+                           0: the whole series once (eq. (2)); affine, so the
+                              argmax is taken on raw squared distances
+                           1: every window on its own (Algorithm 2's
+                              Znormalize(S) read row by row): window i becomes
+                              x_{i,k} = (t_{i+k} - mu_i) / sigma_i with mu_i,
+                              sigma_i the eq. (2) statistics of that window
+                              (two-pass, FP64); a flat window (sigma_i = 0)
+                              becomes the zero vector.  Distances are between
+                              normalised windows; d2 and distance are in those
+                              units.  SAX words come from the same windows. */
 } discord_opts;
 
 /* Defaults: FP32, abandon on, order 2 (Cand first, then near-first columns),
@@ -87,9 +99,11 @@ void discord_default_opts(discord_opts* opts);
 typedef struct {
     int64_t  index;           /* discord row i (0-based)                            */
     int64_t  nn_index;        /* its nearest non-self match j (lowest j on ties)     */
-    double   d2;              /* squared raw distance to it, FP64 (sequential sum)   */
+    double   d2;              /* squared distance to it, FP64 (sequential sum): raw
+                                 values, or normalised windows when opts.znorm = 1  */
     double   distance_raw;    /* sqrt(d2)                                           */
-    double   distance;        /* sqrt(d2) / sigma: distance on the series of eq. (2) */
+    double   distance;        /* sqrt(d2) / sigma: distance on the series of eq. (2);
+                                 sqrt(d2) when opts.znorm = 1                       */
     double   mu, sigma;       /* eq. (2) statistics (FP64, two-pass)                 */
     double   max_rel_err;     /* largest relative error of an approximate NN value
                                  that was checked in FP64 during certification       */
@@ -166,7 +180,10 @@ typedef enum {
     DISCORD_FIELD_NN_WITNESS  = 6,  /* int32[N]    j attaining NN_APPROX (-1: none)     */
     DISCORD_FIELD_ROW_STATE   = 7,  /* int32[N]    0 not scanned, 1 full scan, 2 abandoned */
     DISCORD_FIELD_ROW_MEAN    = 8,  /* double[N]   mean of each row (FP64)              */
-    DISCORD_FIELD_ROW_CNORM   = 9   /* double[N]   centred squared norm of each row     */
+    DISCORD_FIELD_ROW_CNORM   = 9,  /* double[N]   centred squared norm of each row     */
+    DISCORD_FIELD_ROW_SIGMA   = 10  /* double[N]   standard deviation of each row, FP64,
+                                       sqrt(ROW_CNORM / n) (opts.znorm = 1 plans only;
+                                       EINVAL otherwise)                                */
 } discord_field;
 
 /* Number of elements of a field (Cand length after prepare; N or table sizes

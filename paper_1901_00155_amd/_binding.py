@@ -30,7 +30,7 @@ FIELD = {
     "words": (0, np.int32), "hist": (1, np.int32), "cand": (2, np.int32),
     "csr_offsets": (3, np.int32), "csr_members": (4, np.int32),
     "nn_approx": (5, np.float32), "nn_witness": (6, np.int32), "row_state": (7, np.int32),
-    "row_mean": (8, np.float64), "row_cnorm": (9, np.float64),
+    "row_mean": (8, np.float64), "row_cnorm": (9, np.float64), "row_sigma": (10, np.float64),
 }
 
 # every symbol the public header declares (checked by the CPU tests)
@@ -53,7 +53,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("abandon", ctypes.c_int32),
                 ("order", ctypes.c_int32), ("topk", ctypes.c_int32),
                 ("paa_w", ctypes.c_int32), ("alphabet", ctypes.c_int32),
-                ("probe_steps", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("probe_steps", ctypes.c_int32), ("znorm", ctypes.c_int32)]
 
 
 class Result(ctypes.Structure):
@@ -226,11 +226,13 @@ class Plan:
     """A prepared series (discord_prepare) that can be searched repeatedly."""
 
     def __init__(self, T, n: int, precision="fp32", abandon=True, order=2, topk=16,
-                 paa_w=4, alphabet=4, probe_steps=0, stream=None, torch_workspace=False):
+                 paa_w=4, alphabet=4, probe_steps=0, znorm=False, stream=None,
+                 torch_workspace=False):
         lib = load()
         self.opts = default_opts(precision=precision, abandon=int(bool(abandon)),
                                  order=int(order), topk=topk, paa_w=paa_w,
-                                 alphabet=alphabet, probe_steps=probe_steps)
+                                 alphabet=alphabet, probe_steps=probe_steps,
+                                 znorm=int(bool(znorm)))
         ptr, m, self._keep, tstream = _series_ptr(T)
         self.m, self.n = int(m), int(n)
         self.N = self.m - self.n + 1

@@ -71,10 +71,11 @@ struct Layout {
   size_t T, stats, partials, bad, words, hist, minfreq, cand, cand_count, seg, csr_off, csr_mem,
       best, nn_approx, nn_wit, row_state, row_mean, row_cnorm, rows, part_d, part_j, out_d,
       out_j, exact, unc, srch, pair_slots, alive, done, survivors, survivors2, score, rank_hist, gflags,
-      cand_groups, bgrp_cnt, bgrp_off, bgrp, max_bucket, mu32, smu32, cn32, sblk, total;
+      cand_groups, bgrp_cnt, bgrp_off, bgrp, max_bucket, mu32, smu32, cn32, r32, row_sigma, sblk,
+      total;
 };
 
-Layout make_layout(int64_t m, int32_t n, int dict, bool mixed) {
+Layout make_layout(int64_t m, int32_t n, int dict, bool mixed, bool znorm) {
   const int64_t N = m - n + 1;
   const int64_t nchunks = (N + kFp64Cols - 1) / kFp64Cols;
   const int64_t seg = std::max<int64_t>(csr_waves(N) * dict, compact_waves(N));
@@ -128,6 +129,9 @@ Layout make_layout(int64_t m, int32_t n, int dict, bool mixed) {
   L.mu32 = take(sizeof(float) * (N + kRowPad));
   L.smu32 = take(sizeof(float) * (N + kRowPad));
   L.cn32 = take(sizeof(float) * (N + kRowPad));
+  // per-window normalisation: FP64 row standard deviations, FP32 row scales
+  L.r32 = take(znorm ? sizeof(float) * (N + kRowPad) : 0);
+  L.row_sigma = take(znorm ? sizeof(double) * N : 0);
   // the split subsequence matrix of the MFMA scan, resident for the plan's life
   L.sblk = take(mixed ? (size_t)mixed_blocks(N) * mixed_block_bytes(n) : 0);
   L.total = off;
@@ -138,6 +142,7 @@ bool opts_valid(int32_t n, const discord_opts& o) {
   if (o.precision != DISCORD_PREC_FP32 && o.precision != DISCORD_PREC_BF16X3) return false;
   if (o.abandon != 0 && o.abandon != 1) return false;
   if (o.order < 0 || o.order > 2) return false;
+  if (o.znorm != 0 && o.znorm != 1) return false;
   if (o.topk < 1 || o.topk > 32) return false;
   (void)n;
   if (o.paa_w < 1 || o.paa_w > 8) return false;
@@ -267,8 +272,13 @@ struct EventPair {
   float ms() const { return elapsed_ms(a, b); }
 };
 
+ZStats zstats(discord_plan p) {
+  if (!p->opts.znorm) return ZStats{nullptr, nullptr};
+  return ZStats{p->at<double>(p->L.row_mean), p->at<double>(p->L.row_sigma)};
+}
+
 int rows_nn_batch(discord_plan p, const int64_t* d_rows, int64_t count) {
-  launch_rows_nn_fp64(p->Tp(), p->n, p->N, d_rows, count, p->at<double>(p->L.part_d),
+  launch_rows_nn_fp64(p->Tp(), p->n, p->N, d_rows, count, zstats(p), p->at<double>(p->L.part_d),
                       p->at<int64_t>(p->L.part_j), p->at<double>(p->L.out_d),
                       p->at<int64_t>(p->L.out_j), p->stream);
   LAUNCH_OK(p, "rows_nn_fp64");
@@ -313,7 +323,7 @@ size_t discord_workspace_bytes(int64_t m, int32_t n, const discord_opts* opts) {
   if (n >= 1 && o.paa_w >= 1 && o.paa_w <= 8 && o.paa_w > n) o.paa_w = n;
   if (n < 1 || m < 2 * (int64_t)n || !opts_valid(n, o)) return 0;
   if (m > (int64_t)INT32_MAX - kBackPad - kFrontPad) return 0;
-  return make_layout(m, n, dict_size(o), o.precision == DISCORD_PREC_BF16X3).total;
+  return make_layout(m, n, dict_size(o), o.precision == DISCORD_PREC_BF16X3, o.znorm != 0).total;
 }
 
 int discord_prepare(const float* T, int64_t m, int32_t n, const discord_opts* opts, void* workspace,
@@ -335,7 +345,7 @@ int discord_prepare(const float* T, int64_t m, int32_t n, const discord_opts* op
   p->N = m - n + 1;
   p->opts = o;
   p->dict = dict_size(o);
-  p->L = make_layout(m, n, p->dict, o.precision == DISCORD_PREC_BF16X3);
+  p->L = make_layout(m, n, p->dict, o.precision == DISCORD_PREC_BF16X3, o.znorm != 0);
   auto bail = [&](int st) {
     discord_release(p);
     return st;
@@ -396,8 +406,12 @@ int discord_prepare(const float* T, int64_t m, int32_t n, const discord_opts* op
     p->sigma = hstats[1];
     if (!(p->sigma > 0.0)) return fail(p, DISCORD_ECONST, "sigma == 0");
     // row statistics, PAA -> SAX -> word ids, histogram, Cand, Index_Word
-    launch_row_stats(p->Tp(), p->N, n, p->at<double>(p->L.row_mean), p->at<double>(p->L.row_cnorm), s);
+    const bool zn = o.znorm != 0;
+    double* row_sigma = zn ? p->at<double>(p->L.row_sigma) : nullptr;
+    launch_row_stats(p->Tp(), p->N, n, p->at<double>(p->L.row_mean), p->at<double>(p->L.row_cnorm),
+                     row_sigma, s);
     launch_sax(p->Tp(), p->N, n, o.paa_w, o.alphabet, p->at<double>(p->L.stats),
+               zn ? p->at<double>(p->L.row_mean) : nullptr, row_sigma,
                p->at<int32_t>(p->L.words), p->at<int32_t>(p->L.hist), s);
     launch_cand(p->at<int32_t>(p->L.words), p->at<int32_t>(p->L.hist), p->N, p->dict,
                 p->at<int32_t>(p->L.minfreq), p->at<int32_t>(p->L.seg), p->at<int32_t>(p->L.cand),
@@ -406,12 +420,15 @@ int discord_prepare(const float* T, int64_t m, int32_t n, const discord_opts* op
                p->at<int32_t>(p->L.seg), p->at<int32_t>(p->L.csr_off),
                p->at<int32_t>(p->L.csr_mem), s);
     const bool mixed = o.precision == DISCORD_PREC_BF16X3;
-    if (mixed)
-      launch_row_stats32(p->Tp(), p->N, n, p->N + kRowPad, p->at<double>(p->L.row_mean),
+    // FP32 centres and scales: the split-BF16 operands, and under per-window
+    // normalisation also the FP32 scan's
+    float* r32 = zn ? p->at<float>(p->L.r32) : nullptr;
+    if (mixed || zn)
+      launch_row_stats32(p->Tp(), p->N, n, p->N + kRowPad, p->at<double>(p->L.row_mean), row_sigma,
                          p->at<double>(p->L.stats), p->at<float>(p->L.mu32),
-                         p->at<float>(p->L.smu32), p->at<float>(p->L.cn32), s);
+                         p->at<float>(p->L.smu32), p->at<float>(p->L.cn32), r32, s);
     if (mixed)
-      launch_split_blocks(p->Tp(), p->N, n, p->at<float>(p->L.mu32), p->at<float>(p->L.cn32),
+      launch_split_blocks(p->Tp(), p->N, n, p->at<float>(p->L.mu32), p->at<float>(p->L.cn32), r32,
                           p->at<uint4>(p->L.sblk), s);
     // the bucket column blocks serve only the PhiDD order (same-word columns first)
     const bool buckets = o.order == 1;
@@ -507,12 +524,26 @@ int discord_search(discord_plan p, discord_result* out) {
   J.n_survivors = n_surv;
   const MixedRows R{p->at<float>(p->L.mu32), p->at<float>(p->L.smu32), p->at<float>(p->L.cn32),
                     p->at<uint4>(p->L.sblk)};
+  const bool zn = p->opts.znorm != 0;
+  J.raise_sub = 0.0f;
+  if (zn && !mixed) {
+    J.zc = p->at<float>(p->L.mu32);
+    J.zr = p->at<float>(p->L.r32);
+  }
   if (mixed) {
     // The split-BF16 minima carry errors of order 2^-16 |a'||b'|, with no
     // simple relative bound; raising the best-so-far by a 2^-10 margin is a
     // heuristic only -- the FP64 certification below keeps the result exact
     // whatever the best-so-far was.
     J.raise_scale = (float)(1.0 - std::ldexp(1.0, -10));
+  } else if (zn) {
+    // Normalised FP32 form q_i + q_j - 2 C s_i s_j: C is a sum of n products of
+    // centred values, off by at most about (n + 2) 2^-24 n sigma_i sigma_j, and
+    // s_i s_j carries two more roundings; the distance is then off by less than
+    // 2.2 (n + 4) n 2^-24 + 16 n 2^-24 in absolute terms (the quantities are at
+    // most 4n), which completed rows subtract before raising the best-so-far.
+    J.raise_scale = 1.0f;
+    J.raise_sub = (float)((2.2 * (n + 4.0) * n + 16.0 * n) * std::ldexp(1.0, -24));
   } else {
     // A row whose scan completed has exact NN >= (its FP32 minimum) / (1 + gamma),
     // gamma = (n + 3) 2^-24 bounding the direct-form rounding; raising the
@@ -661,7 +692,7 @@ int discord_search(discord_plan p, discord_result* out) {
   uint32_t* unc_count = &sc->unc_count;
   uint32_t* relerr = &sc->relerr;
   int64_t* unc = p->at<int64_t>(p->L.unc);
-  launch_verify(p->Tp(), n, N, nn_wit, nn_approx, ex, unc, unc_count, relerr, s);
+  launch_verify(p->Tp(), n, N, zstats(p), nn_wit, nn_approx, ex, unc, unc_count, relerr, s);
   LAUNCH_OK(p, "verify");
   SearchScalars hsc;
   HIP_TRY(p, hipMemcpyAsync(&hsc, sc, sizeof(hsc), hipMemcpyDeviceToHost, s));
@@ -686,7 +717,7 @@ int discord_search(discord_plan p, discord_result* out) {
   r.nn_index = hex.j;
   r.d2 = hex.d2;
   r.distance_raw = std::sqrt(hex.d2);
-  r.distance = r.distance_raw / p->sigma;
+  r.distance = zn ? r.distance_raw : r.distance_raw / p->sigma;
   r.mu = p->mu;
   r.sigma = p->sigma;
   r.max_rel_err = (double)__builtin_bit_cast(float, hrel);
@@ -736,6 +767,7 @@ int64_t discord_plan_count(discord_plan p, int32_t field) {
     case DISCORD_FIELD_ROW_STATE:
     case DISCORD_FIELD_ROW_MEAN:
     case DISCORD_FIELD_ROW_CNORM: return p->N;
+    case DISCORD_FIELD_ROW_SIGMA: return p->opts.znorm ? p->N : DISCORD_EINVAL;
     case DISCORD_FIELD_HIST: return p->dict;
     case DISCORD_FIELD_CSR_OFFSETS: return p->dict + 1;
     case DISCORD_FIELD_CAND: return p->cand_count;
@@ -759,6 +791,7 @@ int discord_plan_copy(discord_plan p, int32_t field, void* host_dst, size_t byte
     case DISCORD_FIELD_ROW_STATE: off = p->L.row_state; break;
     case DISCORD_FIELD_ROW_MEAN: off = p->L.row_mean; elem = 8; break;
     case DISCORD_FIELD_ROW_CNORM: off = p->L.row_cnorm; elem = 8; break;
+    case DISCORD_FIELD_ROW_SIGMA: off = p->L.row_sigma; elem = 8; break;
     default: return DISCORD_EINVAL;
   }
   if (bytes < elem * (size_t)count) return DISCORD_EINVAL;

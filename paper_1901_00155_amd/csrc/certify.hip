@@ -13,7 +13,8 @@
 //
 // FP64 distances are the sequential sum over k = 0..n-1 of (a_k - b_k)^2 with a
 // separately rounded multiply and add (contraction off), i.e. the sum eq. (1)
-// defines, accumulated in the order it is written.
+// defines, accumulated in the order it is written; under per-window
+// normalisation a_k and b_k are the normalised window elements.
 #include <algorithm>
 
 #include "internal.hpp"
@@ -30,6 +31,32 @@ __device__ inline double d2_fp64(const float* __restrict__ T, int64_t i, int64_t
     s = s + d * d;
   }
   return s;
+}
+
+// Per-window normalisation: element k of window i is (t_{i+k} - mu_i) / sigma_i
+// (a correctly rounded FP64 division), or 0 for a flat window; the distance is
+// the same sequential sum over the normalised elements.
+__device__ inline double zval(const float* __restrict__ T, int64_t i, int k, double mu, double sg) {
+  return sg > 0.0 ? ((double)T[i + k] - mu) / sg : 0.0;
+}
+
+__device__ inline double d2_fp64_z(const float* __restrict__ T, int64_t i, int64_t j, int n,
+                                   ZStats z) {
+  const double mi = z.mu[i], si = z.sg[i], mj = z.mu[j], sj = z.sg[j];
+  double s = 0.0;
+  for (int k = 0; k < n; ++k) {
+    const double d = zval(T, i, k, mi, si) - zval(T, j, k, mj, sj);
+    s = s + d * d;
+  }
+  return s;
+}
+
+template <bool Z>
+__device__ inline double pair_d2(const float* __restrict__ T, int64_t i, int64_t j, int n, ZStats z) {
+  if constexpr (Z)
+    return d2_fp64_z(T, i, j, n, z);
+  else
+    return d2_fp64(T, i, j, n);
 }
 
 __device__ inline bool has_non_self(int64_t i, int64_t N, int n) {
@@ -154,7 +181,9 @@ __global__ void k_seed_row(const uint64_t* __restrict__ seed, int64_t* __restric
 }
 
 // Exact NN of rows[y] over the columns of chunk x: block min, lowest j on ties.
+template <bool Z>
 __global__ __launch_bounds__(256) void k_rows_nn_fp64(const float* __restrict__ T, int n, int64_t N,
+                                                      ZStats z,
                                                       const int64_t* __restrict__ rows,
                                                       int64_t nchunks,
                                                       double* __restrict__ part_d,
@@ -169,7 +198,7 @@ __global__ __launch_bounds__(256) void k_rows_nn_fp64(const float* __restrict__ 
   for (int64_t j = cb + threadIdx.x; j < ce; j += 256) {
     const int64_t dij = i > j ? i - j : j - i;
     if (dij < n) continue;
-    const double d = d2_fp64(T, i, j, n);
+    const double d = pair_d2<Z>(T, i, j, n, z);
     if (d < bd) {
       bd = d;
       bj = j;
@@ -245,7 +274,9 @@ __global__ void k_exact_from_rows(const int64_t* __restrict__ rows, const double
 }
 
 // Witness verification (see the file comment); appends failing rows.
+template <bool Z>
 __global__ __launch_bounds__(256) void k_verify(const float* __restrict__ T, int n, int64_t N,
+                                                ZStats z,
                                                 const int32_t* __restrict__ nn_witness,
                                                 const float* __restrict__ nn_approx,
                                                 const Exact* __restrict__ ex,
@@ -261,7 +292,7 @@ __global__ __launch_bounds__(256) void k_verify(const float* __restrict__ T, int
     const int32_t w = nn_witness[i];
     bool ok = false;
     if (w >= 0 && s >= 0) {
-      const double e = d2_fp64(T, i, w, n);
+      const double e = pair_d2<Z>(T, i, w, n, z);
       ok = (e < L) || (e == L && i > s);
       if (e > 0.0) rel = fmaxf(rel, (float)(fabs((double)nn_approx[i] - e) / e));
     }
@@ -353,12 +384,16 @@ void launch_seed_row(const uint64_t* seed_key, int64_t* rows_out, hipStream_t s)
 }
 
 void launch_rows_nn_fp64(const float* Tp, int n, int64_t N, const int64_t* rows, int64_t count,
-                         double* part_d, int64_t* part_j, double* out_d, int64_t* out_j,
+                         ZStats z, double* part_d, int64_t* part_j, double* out_d, int64_t* out_j,
                          hipStream_t s) {
   if (count <= 0) return;
   const int64_t nchunks = (N + kFp64Cols - 1) / kFp64Cols;
-  hipLaunchKernelGGL(k_rows_nn_fp64, dim3((unsigned)nchunks, (unsigned)count), dim3(256), 0, s, Tp,
-                     n, N, rows, nchunks, part_d, part_j);
+  if (z.sg)
+    hipLaunchKernelGGL(k_rows_nn_fp64<true>, dim3((unsigned)nchunks, (unsigned)count), dim3(256), 0,
+                       s, Tp, n, N, z, rows, nchunks, part_d, part_j);
+  else
+    hipLaunchKernelGGL(k_rows_nn_fp64<false>, dim3((unsigned)nchunks, (unsigned)count), dim3(256), 0,
+                       s, Tp, n, N, z, rows, nchunks, part_d, part_j);
   hipLaunchKernelGGL(k_rows_nn_reduce, dim3((unsigned)count), dim3(256), 0, s, part_d, part_j,
                      nchunks, out_d, out_j);
 }
@@ -369,11 +404,15 @@ void launch_exact_from_rows(const int64_t* rows, const double* d, const int64_t*
   hipLaunchKernelGGL(k_exact_from_rows, dim3(1), dim3(1), 0, s, rows, d, j, ex);
 }
 
-void launch_verify(const float* Tp, int n, int64_t N, const int32_t* nn_witness,
+void launch_verify(const float* Tp, int n, int64_t N, ZStats z, const int32_t* nn_witness,
                    const float* nn_approx, const Exact* ex, int64_t* uncertain,
                    uint32_t* uncertain_count, uint32_t* max_rel_err_bits, hipStream_t s) {
-  hipLaunchKernelGGL(k_verify, dim3(row_pass_blocks(N)), dim3(256), 0, s, Tp, n, N,
-                     nn_witness, nn_approx, ex, uncertain, uncertain_count, max_rel_err_bits);
+  if (z.sg)
+    hipLaunchKernelGGL(k_verify<true>, dim3(row_pass_blocks(N)), dim3(256), 0, s, Tp, n, N, z,
+                       nn_witness, nn_approx, ex, uncertain, uncertain_count, max_rel_err_bits);
+  else
+    hipLaunchKernelGGL(k_verify<false>, dim3(row_pass_blocks(N)), dim3(256), 0, s, Tp, n, N, z,
+                       nn_witness, nn_approx, ex, uncertain, uncertain_count, max_rel_err_bits);
 }
 
 void launch_merge_exact(const int64_t* rows, const double* d, const int64_t* j, int64_t count,

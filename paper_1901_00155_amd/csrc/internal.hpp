@@ -55,10 +55,15 @@ struct Exact {
 // ---- prep.hip -----------------------------------------------------------------
 void launch_stats(const float* Tp, int64_t m, double* partials, double* stats, int* bad,
                   hipStream_t s);
+// row_sigma: nullptr, or receives each row's standard deviation (per-window
+// normalisation)
 void launch_row_stats(const float* Tp, int64_t N, int n, double* row_mean, double* row_cnorm,
-                      hipStream_t s);
+                      double* row_sigma, hipStream_t s);
+// zmu/zsg: nullptr (the series normalised once by eq. (2)), or the row means and
+// standard deviations of per-window normalisation
 void launch_sax(const float* Tp, int64_t N, int n, int w, int alpha, const double* stats,
-                int32_t* words, int32_t* hist, hipStream_t s);
+                const double* zmu, const double* zsg, int32_t* words, int32_t* hist,
+                hipStream_t s);
 void launch_cand(const int32_t* words, const int32_t* hist, int64_t N, int dict,
                  int32_t* flags_scratch, int32_t* wave_counts, int32_t* cand, int32_t* cand_count,
                  hipStream_t s);
@@ -106,7 +111,13 @@ struct ScanJob {
   // early abandon against the best-so-far
   int32_t abandon;
   uint32_t* bsf;              // float bits of the best-so-far squared distance
-  float raise_scale;          // completed rows raise bsf to (their minimum) * raise_scale
+  float raise_scale;          // completed rows raise bsf to
+  float raise_sub;            //   max(0, (their minimum) * raise_scale - raise_sub)
+  // per-window normalisation (FP32 scan): row centres c_i and scales r_i =
+  // fp32(1 / sigma_i) (0: flat window), padded with zeros to N + 64; nullptr:
+  // distances between raw windows
+  const float* zc;
+  const float* zr;
   uint32_t* alive;            // per row group: bit r set while row r is searched
   uint32_t* done;             // per item: chunks finished (reset by the last one)
   int32_t* survivors;         // items left with live rows by a non-final launch
@@ -149,11 +160,14 @@ int mfma_row_blocks(int n, bool abandon);   // row blocks per MFMA work item
 // an A operand and as a B operand (1 KB each).  ceil(N/32) + 1 blocks.
 size_t mixed_block_bytes(int n);
 int64_t mixed_blocks(int64_t N);
+// r32: nullptr, or per-row scales of per-window normalisation (operands
+// (t - c) * r)
 void launch_split_blocks(const float* Tp, int64_t N, int n, const float* c32, const float* cn32,
-                         uint4* sblk, hipStream_t s);
+                         const float* r32, uint4* sblk, hipStream_t s);
+// row_sigma/r32: nullptr, or per-window normalisation (see prep.hip)
 void launch_row_stats32(const float* Tp, int64_t N, int n, int64_t padded, const double* row_mean,
-                        const double* stats, float* c32, float* smu32, float* cn32,
-                        hipStream_t s);
+                        const double* row_sigma, const double* stats, float* c32, float* smu32,
+                        float* cn32, float* r32, hipStream_t s);
 
 // ---- rank.hip -----------------------------------------------------------------
 // Items (item_rows consecutive rows each; alive masks per gsz rows) of `list`,
@@ -188,12 +202,18 @@ void launch_init_alive(uint32_t* alive, int64_t G, int64_t N, int gsz, hipStream
 void launch_seed_argmax(const uint64_t* best, const int32_t* row_state, int64_t N,
                         uint64_t* seed_key, hipStream_t s);
 void launch_seed_row(const uint64_t* seed_key, int64_t* rows_out, hipStream_t s);
+// FP64 distances of the certification.  zmu/zsg: nullptr (raw windows), or the
+// row means and standard deviations of per-window normalisation.
+struct ZStats {
+  const double* mu;
+  const double* sg;
+};
 void launch_rows_nn_fp64(const float* Tp, int n, int64_t N, const int64_t* rows, int64_t count,
-                         double* part_d, int64_t* part_j, double* out_d, int64_t* out_j,
+                         ZStats z, double* part_d, int64_t* part_j, double* out_d, int64_t* out_j,
                          hipStream_t s);
 void launch_exact_from_rows(const int64_t* rows, const double* d, const int64_t* j,
                             int64_t count, Exact* ex, hipStream_t s);
-void launch_verify(const float* Tp, int n, int64_t N, const int32_t* nn_witness,
+void launch_verify(const float* Tp, int n, int64_t N, ZStats z, const int32_t* nn_witness,
                    const float* nn_approx, const Exact* ex, int64_t* uncertain,
                    uint32_t* uncertain_count, uint32_t* max_rel_err_bits, hipStream_t s);
 void launch_merge_exact(const int64_t* rows, const double* d, const int64_t* j, int64_t count,

@@ -3,7 +3,8 @@
 //   stats     eq. (2): mean and standard deviation of the series, FP64, two-pass,
 //             fixed grid and fixed reduction tree (bit-reproducible run to run).
 //   row stats per-row mean and centred squared norm (FP64), used by the split-BF16
-//             scan and exposed for verification.
+//             scan and exposed for verification; with per-window normalisation
+//             also the row's standard deviation.
 //   sax       eqs. (3), (4), (9): PAA of each row on the z-normalised series, SAX
 //             symbols by the N(0,1) breakpoints, word id = lexicographic rank.
 //             One thread per row; the 256-bin word histogram (eq. 8) is built in
@@ -78,22 +79,28 @@ __global__ __launch_bounds__(256) void k_finish(const double* __restrict__ parti
   }
 }
 
+// Mean and centred squared norm of every row (FP64, sequential two-pass sums,
+// each multiply and add rounded on its own) and, for per-window normalisation,
+// the row's standard deviation sqrt(cnorm / n): eq. (2) over the window alone.
 __global__ __launch_bounds__(256) void k_row_stats(const float* __restrict__ T, int64_t N, int n,
                                                    double* __restrict__ mean,
-                                                   double* __restrict__ cnorm) {
+                                                   double* __restrict__ cnorm,
+                                                   double* __restrict__ sigma) {
+#pragma clang fp contract(off)
   const int64_t i = blockIdx.x * 256ll + threadIdx.x;
   if (i >= N) return;
   const float* x = T + i;
   double s = 0.0;
-  for (int k = 0; k < n; ++k) s += (double)x[k];
+  for (int k = 0; k < n; ++k) s = s + (double)x[k];
   const double mu = s / (double)n;
   double q = 0.0;
   for (int k = 0; k < n; ++k) {
     const double d = (double)x[k] - mu;
-    q += d * d;
+    q = q + d * d;
   }
   mean[i] = mu;
   cnorm[i] = q;
+  if (sigma) sigma[i] = sqrt(q / (double)n);
 }
 
 // FP32 row statistics of the split-BF16 scan.  The centre of row i is
@@ -103,31 +110,52 @@ __global__ __launch_bounds__(256) void k_row_stats(const float* __restrict__ T, 
 //         - n ((mu_a - c_a) - (mu_b - c_b))^2,
 // whose last term (below n * ulp(mu)^2) is dropped.  smu = sqrt(n) (mu - mu_T)
 // with mu_T the series mean.  Entries N .. N+pad-1 are zero.
+//
+// Per-window normalisation (sigma != nullptr): the operands are the centred
+// windows scaled by r_i = fp32(1 / sigma_i) (0 for a flat window), i.e. the
+// normalised windows up to the rounding of c_i and r_i; the mean term is gone
+// (every normalised window has mean 0), so smu = 0, and cnorm is the squared
+// norm of the FP32 operand values x_k = (t_{i+k} - c_i) * r_i, computed with
+// the same FP32 operations the split uses.  Both scans read c and r.
 __global__ __launch_bounds__(256) void k_row_stats32(const float* __restrict__ T, int64_t N, int n,
                                                      int64_t padded,
                                                      const double* __restrict__ mean,
+                                                     const double* __restrict__ sigma,
                                                      const double* __restrict__ stats,
                                                      float* __restrict__ c32,
                                                      float* __restrict__ smu32,
-                                                     float* __restrict__ cn32) {
+                                                     float* __restrict__ cn32,
+                                                     float* __restrict__ r32) {
   const int64_t i = blockIdx.x * 256ll + threadIdx.x;
   if (i >= padded) return;
   if (i >= N) {
     c32[i] = 0.0f;
     smu32[i] = 0.0f;
     cn32[i] = 0.0f;
+    if (r32) r32[i] = 0.0f;
     return;
   }
   const double mu = mean[i];
   const float c = (float)mu;
-  const double cd = (double)c;
   double q = 0.0;
-  for (int k = 0; k < n; ++k) {
-    const double d = (double)T[i + k] - cd;
-    q += d * d;
+  if (sigma) {
+    const double sg = sigma[i];
+    const float r = sg > 0.0 ? (float)(1.0 / sg) : 0.0f;
+    for (int k = 0; k < n; ++k) {
+      const float x = (T[i + k] - c) * r;
+      q += (double)x * (double)x;
+    }
+    r32[i] = r;
+    smu32[i] = 0.0f;
+  } else {
+    const double cd = (double)c;
+    for (int k = 0; k < n; ++k) {
+      const double d = (double)T[i + k] - cd;
+      q += d * d;
+    }
+    smu32[i] = (float)(sqrt((double)n) * (mu - stats[0]));
   }
   c32[i] = c;
-  smu32[i] = (float)(sqrt((double)n) * (mu - stats[0]));
   cn32[i] = (float)q;
 }
 
@@ -135,9 +163,15 @@ struct Breakpoints {
   double b[8];
 };
 
+// Z = false: PAA of the window on the series normalised by eq. (2) once;
+// Z = true: PAA of the window normalised on its own, element by element as
+// (t - mu_i) / sigma_i (a flat window gives zeros), then summed per segment.
+template <bool Z>
 __global__ __launch_bounds__(256) void k_sax(const float* __restrict__ T, int64_t N, int n, int w,
                                              int alpha, Breakpoints bp,
                                              const double* __restrict__ stats,
+                                             const double* __restrict__ zmu,
+                                             const double* __restrict__ zsg,
                                              int32_t* __restrict__ words,
                                              int32_t* __restrict__ hist) {
   __shared__ int32_t lh[kMaxWords];
@@ -145,15 +179,22 @@ __global__ __launch_bounds__(256) void k_sax(const float* __restrict__ T, int64_
   __syncthreads();
   const int64_t i = blockIdx.x * 256ll + threadIdx.x;
   if (i < N) {
-    const double mu = stats[0], sigma = stats[1];
+    const double mu = Z ? zmu[i] : stats[0], sigma = Z ? zsg[i] : stats[1];
     const float* x = T + i;
     int32_t code = 0;
     for (int s = 0; s < w; ++s) {
       const int a = (int)(((int64_t)s * n) / w), e = (int)(((int64_t)(s + 1) * n) / w);
       double acc = 0.0;
-      for (int k = a; k < e; ++k) acc += (double)x[k];
-      // mean of the segment on the normalised series: (mean(raw) - mu) / sigma
-      const double paa = (acc / (double)(e - a) - mu) / sigma;
+      double paa;
+      if (Z) {
+        if (sigma > 0.0)
+          for (int k = a; k < e; ++k) acc = acc + ((double)x[k] - mu) / sigma;
+        paa = acc / (double)(e - a);
+      } else {
+        for (int k = a; k < e; ++k) acc += (double)x[k];
+        // mean of the segment on the normalised series: (mean(raw) - mu) / sigma
+        paa = (acc / (double)(e - a) - mu) / sigma;
+      }
       int sym = 0;
       while (sym < alpha - 1 && paa >= bp.b[sym]) ++sym;   // beta_{k} <= paa < beta_{k+1}
       code = code * alpha + sym;
@@ -422,18 +463,18 @@ void launch_stats(const float* Tp, int64_t m, double* partials, double* stats, i
 }
 
 void launch_row_stats(const float* Tp, int64_t N, int n, double* row_mean, double* row_cnorm,
-                      hipStream_t s) {
+                      double* row_sigma, hipStream_t s) {
   const int64_t blocks = (N + 255) / 256;
   hipLaunchKernelGGL(k_row_stats, dim3((unsigned)blocks), dim3(256), 0, s, Tp, N, n, row_mean,
-                     row_cnorm);
+                     row_cnorm, row_sigma);
 }
 
 void launch_row_stats32(const float* Tp, int64_t N, int n, int64_t padded, const double* row_mean,
-                        const double* stats, float* c32, float* smu32, float* cn32,
-                        hipStream_t s) {
+                        const double* row_sigma, const double* stats, float* c32, float* smu32,
+                        float* cn32, float* r32, hipStream_t s) {
   const int64_t blocks = (padded + 255) / 256;
   hipLaunchKernelGGL(k_row_stats32, dim3((unsigned)blocks), dim3(256), 0, s, Tp, N, n, padded,
-                     row_mean, stats, c32, smu32, cn32);
+                     row_mean, row_sigma, stats, c32, smu32, cn32, r32);
 }
 
 // Breakpoints of eq. (4): beta_k = Phi^{-1}(k / alpha), computed on the host by
@@ -441,12 +482,17 @@ void launch_row_stats32(const float* Tp, int64_t N, int n, int64_t padded, const
 void sax_breakpoints(int alpha, double* out);
 
 void launch_sax(const float* Tp, int64_t N, int n, int w, int alpha, const double* stats,
-                int32_t* words, int32_t* hist, hipStream_t s) {
+                const double* zmu, const double* zsg, int32_t* words, int32_t* hist,
+                hipStream_t s) {
   Breakpoints bp{};
   sax_breakpoints(alpha, bp.b);
   const int64_t blocks = (N + 255) / 256;
-  hipLaunchKernelGGL(k_sax, dim3((unsigned)blocks), dim3(256), 0, s, Tp, N, n, w, alpha, bp,
-                     stats, words, hist);
+  if (zsg)
+    hipLaunchKernelGGL(k_sax<true>, dim3((unsigned)blocks), dim3(256), 0, s, Tp, N, n, w, alpha,
+                       bp, stats, zmu, zsg, words, hist);
+  else
+    hipLaunchKernelGGL(k_sax<false>, dim3((unsigned)blocks), dim3(256), 0, s, Tp, N, n, w, alpha,
+                       bp, stats, zmu, zsg, words, hist);
 }
 
 void launch_cand(const int32_t* words, const int32_t* hist, int64_t N, int dict,

@@ -96,6 +96,93 @@ __device__ __forceinline__ void block8x8(const float* __restrict__ x, const floa
   for (; p0 < n + TM - 1; p0 += 8) steps8<true>(acc, x, y, p0, n);  // rows finishing
 }
 
+// Per-window normalisation.  With x_{i,k} = (t_{i+k} - mu_i) / sigma_i, the
+// squared distance of two normalised windows is
+//     d^2 = q_i + q_j - 2 C_ij s_i s_j,   C_ij = sum_k (t_{i+k} - c_i)(t_{j+k} - c_j),
+// with s = 1 / sigma and q = n (s = q = 0 for a flat window, whose normalised
+// form is the zero vector); c = fp32(mu) differs from mu by less than an ulp,
+// which changes C by n (mu_i - c_i)(mu_j - c_j), far below its rounding error.
+// The centred products no longer share differences along diagonals, so the
+// block runs over k: per position 8 row and 8 column centrings and 64 FMAs,
+// 1.25 VALU ops per (pair, k) term.
+__device__ __forceinline__ void load16(const float* __restrict__ p, float (&v)[16]) {
+  const float4* q = reinterpret_cast<const float4*>(p);
+#pragma unroll
+  for (int h = 0; h < 4; ++h) {
+    const float4 f = q[h];
+    v[4 * h + 0] = f.x;
+    v[4 * h + 1] = f.y;
+    v[4 * h + 2] = f.z;
+    v[4 * h + 3] = f.w;
+  }
+}
+
+// positions k0 .. k0 + kn - 1 (kn <= 8, wave-uniform)
+template <bool TAIL>
+__device__ __forceinline__ void zsteps8(float (&acc)[TM][TN], const float* __restrict__ x,
+                                        const float* __restrict__ y, int k0, int kn,
+                                        const float (&cx)[TM], const float (&cy)[TN]) {
+  float xb[16], yb[16];
+  load16(x + k0, xb);
+  load16(y + k0, yb);
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    if (TAIL && u >= kn) break;
+    float xr[TM], yc[TN];
+#pragma unroll
+    for (int r = 0; r < TM; ++r) xr[r] = xb[u + r] - cx[r];
+#pragma unroll
+    for (int c = 0; c < TN; ++c) yc[c] = yb[u + c] - cy[c];
+#pragma unroll
+    for (int r = 0; r < TM; ++r)
+#pragma unroll
+      for (int c = 0; c < TN; ++c) acc[r][c] = __builtin_fmaf(xr[r], yc[c], acc[r][c]);
+  }
+}
+
+// acc[r][c] = approximate d^2 between normalised rows x + r and columns y + c.
+// x, y: 8-float aligned windows of the padded series; zx, zy: the same rows'
+// and columns' entries of the centre (zc) and scale (zr) arrays.
+__device__ __forceinline__ void block8x8_z(const float* __restrict__ x, const float* __restrict__ y,
+                                           int n, const float* __restrict__ zcx,
+                                           const float* __restrict__ zrx,
+                                           const float* __restrict__ zcy,
+                                           const float* __restrict__ zry, float (&acc)[TM][TN]) {
+  float cx[TM], sx[TM], cy[TN], sy[TN];
+#pragma unroll
+  for (int r = 0; r < TM; ++r) {
+    cx[r] = zcx[r];
+    sx[r] = zrx[r];
+  }
+  {
+    const float4* pc = reinterpret_cast<const float4*>(zcy);
+    const float4* ps = reinterpret_cast<const float4*>(zry);
+    const float4 c0 = pc[0], c1 = pc[1], s0 = ps[0], s1 = ps[1];
+    cy[0] = c0.x; cy[1] = c0.y; cy[2] = c0.z; cy[3] = c0.w;
+    cy[4] = c1.x; cy[5] = c1.y; cy[6] = c1.z; cy[7] = c1.w;
+    sy[0] = s0.x; sy[1] = s0.y; sy[2] = s0.z; sy[3] = s0.w;
+    sy[4] = s1.x; sy[5] = s1.y; sy[6] = s1.z; sy[7] = s1.w;
+  }
+#pragma unroll
+  for (int r = 0; r < TM; ++r)
+#pragma unroll
+    for (int c = 0; c < TN; ++c) acc[r][c] = 0.0f;
+  int k0 = 0;
+  for (; k0 + 8 <= n; k0 += 8) zsteps8<false>(acc, x, y, k0, 8, cx, cy);
+  if (k0 < n) zsteps8<true>(acc, x, y, k0, n - k0, cx, cy);
+  const float fn = (float)n;
+#pragma unroll
+  for (int r = 0; r < TM; ++r) {
+    const float qx = sx[r] > 0.0f ? fn : 0.0f;
+    const float m2s = -2.0f * sx[r];
+#pragma unroll
+    for (int c = 0; c < TN; ++c) {
+      const float qy = sy[c] > 0.0f ? fn : 0.0f;
+      acc[r][c] = fmaxf(__builtin_fmaf(m2s * sy[c], acc[r][c], qx + qy), 0.0f);
+    }
+  }
+}
+
 __device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
   for (int off = 32; off > 0; off >>= 1) {
     const uint64_t o = __shfl_xor(v, off, 64);
@@ -124,6 +211,7 @@ __device__ __forceinline__ uint64_t load_relaxed64(const uint64_t* p) {
 // each live row compares its running minimum with the device best-so-far and
 // leaves as soon as it is below (Algorithms 3-4); the leaving row keeps that
 // column as its witness.
+template <bool Z>
 __global__ __launch_bounds__(256) void k_scan_fp32(ScanJob J) {
   const int lane = threadIdx.x & 63;
   const int64_t item = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -188,7 +276,10 @@ __global__ __launch_bounds__(256) void k_scan_fp32(ScanJob J) {
                       : J.near_first ? spiral_block(sp, e - nb) : e - nb;
     const int32_t j0 = (int32_t)(q * TN);   // N < 2^31 (checked at prepare)
     float acc[TM][TN];
-    block8x8(x, J.Tp + j0, n, acc);
+    if constexpr (Z)
+      block8x8_z(x, J.Tp + j0, n, J.zc + i0, J.zr + i0, J.zc + j0, J.zr + j0, acc);
+    else
+      block8x8(x, J.Tp + j0, n, acc);
     // blocks inside the matrix and clear of the exclusion band need no mask:
     // each row's minimum over the 8 columns first, its column only on improvement
     const bool clean = in_seq && valid == 0xFFu && j0 + TN <= N &&
@@ -278,7 +369,8 @@ __global__ __launch_bounds__(256) void k_scan_fp32(ScanJob J) {
   if (final) {
     if (lane < TM && ((fin >> lane) & 1u)) {
       const uint64_t k = load_relaxed64(&J.best[i0 + lane]);
-      if (k != kEmptyMin) atomicMax(J.bsf, __builtin_bit_cast(uint32_t, key_dist(k) * J.raise_scale));
+      if (k != kEmptyMin)
+        atomicMax(J.bsf, __builtin_bit_cast(uint32_t, fmaxf(key_dist(k) * J.raise_scale - J.raise_sub, 0.0f)));
     }
   } else if (lane == 0) {
     J.survivors[atomicAdd(J.n_survivors, 1u)] = (int32_t)g;
@@ -291,7 +383,10 @@ void launch_scan_fp32(const ScanJob& J, hipStream_t s) {
   const int64_t items = J.n_groups * J.chunks;
   if (items <= 0) return;
   const int64_t blocks = (items + 3) / 4;
-  hipLaunchKernelGGL(k_scan_fp32, dim3((unsigned)blocks), dim3(256), 0, s, J);
+  if (J.zc)
+    hipLaunchKernelGGL(k_scan_fp32<true>, dim3((unsigned)blocks), dim3(256), 0, s, J);
+  else
+    hipLaunchKernelGGL(k_scan_fp32<false>, dim3((unsigned)blocks), dim3(256), 0, s, J);
 }
 
 }  // namespace dd

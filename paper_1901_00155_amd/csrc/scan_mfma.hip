@@ -4,6 +4,9 @@
 // rounding of the window means mu_a, mu_b) the squared Euclidean distance of
 // eq. (1) is, up to a term below n ulp(mu)^2,
 //     d^2 = |a - c_a|^2 + |b - c_b|^2 - 2 (a - c_a).(b - c_b) + n (mu_a - mu_b)^2 .
+// Under per-window normalisation the operands are the centred windows scaled by
+// fp32(1 / sigma) and the last term is zero (normalised windows have mean 0);
+// the kernels are the same, only the prepared operands and statistics differ.
 // The dot products run on v_mfma_f32_32x32x16_bf16 with each centred value
 // split as x = hi + lo (hi = bf16(x), lo = bf16(x - hi)) and
 // a'.b' ~ hi.hi + hi.lo + lo.hi, accumulated in FP32.  Centring first keeps
@@ -104,6 +107,7 @@ template <int KS>
 __global__ __launch_bounds__(256) void k_split_blocks(const float* __restrict__ Tp, int64_t nblk,
                                                       int n, const float* __restrict__ c32,
                                                       const float* __restrict__ cn32,
+                                                      const float* __restrict__ r32,
                                                       bf16x8* __restrict__ out) {
   const int64_t t = blockIdx.x * 256ll + threadIdx.x;
   const int64_t per_blk = (KS + 1) * 64;
@@ -117,10 +121,12 @@ __global__ __launch_bounds__(256) void k_split_blocks(const float* __restrict__ 
   if (s < KS) {
     const int k0 = 16 * s + 8 * h;
     const float c = c32[row];
+    // per-window normalisation scales the centred window (1 otherwise: exact)
+    const float r = r32 ? r32[row] : 1.0f;
     float v[8];
     load8(Tp + row + k0, v);
 #pragma unroll
-    for (int e = 0; e < 8; ++e) v[e] = (k0 + e < n) ? v[e] - c : 0.0f;
+    for (int e = 0; e < 8; ++e) v[e] = (k0 + e < n) ? (v[e] - c) * r : 0.0f;
     bf16x8 hi, lo;
     split8(v, hi, lo);
     blk[s * 128 + l] = hi;
@@ -465,7 +471,7 @@ __global__ __launch_bounds__(WAVES * 64, (KS <= 16 ? 2 : 1)) void k_scan_mfma(Sc
     if (final && h == 0 && ((fin >> rl) & 1u)) {
       const uint64_t k = load_relaxed64(&J.best[g[b] * BM + rl]);
       if (k != kEmptyMin)
-        atomicMax(J.bsf, __builtin_bit_cast(uint32_t, key_dist(k) * J.raise_scale));
+        atomicMax(J.bsf, __builtin_bit_cast(uint32_t, fmaxf(key_dist(k) * J.raise_scale - J.raise_sub, 0.0f)));
     }
   }
   if (final) return;
@@ -734,10 +740,10 @@ void launch_ks(const ScanJob& J, const MixedRows& R, hipStream_t s) {
 
 template <int KS>
 void launch_split(const float* Tp, int64_t nblk, int n, const float* c32, const float* cn32,
-                  uint4* sblk, hipStream_t s) {
+                  const float* r32, uint4* sblk, hipStream_t s) {
   const int64_t threads = nblk * (KS + 1) * 64;
   hipLaunchKernelGGL(k_split_blocks<KS>, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s,
-                     Tp, nblk, n, c32, cn32, reinterpret_cast<bf16x8*>(sblk));
+                     Tp, nblk, n, c32, cn32, r32, reinterpret_cast<bf16x8*>(sblk));
 }
 
 }  // namespace
@@ -767,11 +773,11 @@ bool launch_scan_mfma(const ScanJob& J, const MixedRows& R, hipStream_t s) {
 }
 
 void launch_split_blocks(const float* Tp, int64_t N, int n, const float* c32, const float* cn32,
-                         uint4* sblk, hipStream_t s) {
+                         const float* r32, uint4* sblk, hipStream_t s) {
   const int64_t nblk = mixed_blocks(N);
   switch ((n + 15) / 16) {
 #define DD_CASE(K) \
-  case K: launch_split<K>(Tp, nblk, n, c32, cn32, sblk, s); return;
+  case K: launch_split<K>(Tp, nblk, n, c32, cn32, r32, sblk, s); return;
     DD_KS_CASES(DD_CASE)
 #undef DD_CASE
     default: return;

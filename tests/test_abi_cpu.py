@@ -43,6 +43,19 @@ def test_opts_defaults_and_workspace(dd):
     assert dd.workspace_bytes(4096, 64) > 4 * 4096
     assert dd.workspace_bytes(100, 64) == 0            # m < 2n
     assert dd.workspace_bytes(4096, 64, paa_w=9) == 0  # bad option
+    assert o.znorm == 0                                 # eq. (2) over the whole series
+
+
+def test_znorm_option_workspace(dd):
+    """Per-window normalisation adds the FP64 row standard deviations and the
+    FP32 row scales (N + 64 entries) to the plan; other values are refused."""
+    m, n = 4096, 64
+    N = m - n + 1
+    base = dd.workspace_bytes(m, n)
+    z = dd.workspace_bytes(m, n, znorm=1)
+    assert z >= base + 8 * N + 4 * (N + 64)
+    assert dd.workspace_bytes(m, n, znorm=2) == 0
+    assert dd.workspace_bytes(m, n, znorm=-1) == 0
 
 
 def test_sax_breakpoints_match_oracle(dd):
