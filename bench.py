@@ -13,9 +13,11 @@ time (the scan's own count of evaluated non-self pairs).  Beside it: the time
 to discord, the brute-force-equivalent rate P(N, n) / time, the split-BF16
 MFMA search of the same input (`mixed`), the time to discord under each
 visiting order, full-scan rates of both precisions, the roofline of each scan
-kernel (kernel time from HIP events on the plan's stream), the serving stream
-(p50/p99 latency and throughput) and the FP64 CPU oracle timed on a bounded
-sample of the same workload on the host cores.
+kernel (kernel time from HIP events on the plan's stream), the m = 2^20, n = 256
+noisy walk in both precisions, per-window z-normalisation, the 10^7-point walk
+at windows of 512-2048, the serving stream (p50/p99 latency and throughput)
+and the FP64 CPU oracle timed on a bounded sample of the same workload on the
+host cores.
 """
 from __future__ import annotations
 
@@ -75,7 +77,7 @@ def traffic_for(precision: str, workload: str, mode: str):
     return rec.get("bytes_per_launch")
 
 
-def time_steps(dd, Td, n, precision, abandon, steps, warmup, order=2):
+def time_steps(dd, Td, n, precision, abandon, steps, warmup, order=2, znorm=False):
     import torch
     results = []
     stream = torch.cuda.current_stream()
@@ -84,7 +86,7 @@ def time_steps(dd, Td, n, precision, abandon, steps, warmup, order=2):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
         with dd.Plan(Td, n, precision=precision, abandon=abandon, order=order, stream=stream,
-                     torch_workspace=True) as p:
+                     torch_workspace=True, znorm=znorm) as p:
             r = p.search()
         if it >= warmup:
             results.append(r)
@@ -160,6 +162,84 @@ def serving(dd, workloads, precision="bf16x3", slots=4, budget=8 << 30, count=40
         "pairs_evaluated_total": float(sum(c["result"]["pairs_evaluated"] for c in ok)),
         "span_s": sm["span_s"], "generate_s": gen_s,
     }
+
+
+def noisy_block(dd, workloads):
+    """The mixed-precision configuration: m = 2^20 walk + N(0, 0.05), n = 256;
+    time to discord and full-scan rates of both precisions on the same input."""
+    import torch
+    w = workloads.noisy1m()
+    Td = torch.from_numpy(w.series).cuda()
+    N = w.m - w.n + 1
+    blk = {"workload": f"{w.name}: m={w.m} walk + N(0, 0.05) noise, window n={w.n}",
+           "brute_force_pairs": pair_count(N, w.n)}
+    ref = None
+    for prec in ("fp32", "bf16x3"):
+        so, ro = time_steps(dd, Td, w.n, prec, True, 3, 1)
+        y = ro[-1]
+        ref = ref or (int(y.index), y.d2)
+        assert (int(y.index), y.d2) == ref, "precisions disagree on noisy1m"
+        _, rf = time_steps(dd, Td, w.n, prec, False, 1, 0)
+        f = rf[-1]
+        assert int(f.index) == ref[0]
+        blk[prec] = {"time_to_discord_ms": so * 1e3, "index": int(y.index),
+                     "distance": float(y.distance),
+                     "max_rel_err_of_approx_nn": float(y.max_rel_err),
+                     "full_scan_ms": f.ms_scan,
+                     "full_scan_pairs_per_s": f.pairs_evaluated / (f.ms_scan * 1e-3),
+                     "full_scan_roofline_frac": roofline(w.n, prec, f.pairs_evaluated, f.ms_scan,
+                                                         None)["frac"]}
+        print(f"# noisy1m {prec}: {so * 1e3:.1f} ms to discord, full scan {f.ms_scan:.1f} ms",
+              file=sys.stderr, flush=True)
+    blk["bf16x3_full_scan_speedup_vs_fp32"] = (blk["fp32"]["full_scan_ms"]
+                                               / blk["bf16x3"]["full_scan_ms"])
+    blk["bf16x3_time_to_discord_speedup_vs_fp32"] = (blk["fp32"]["time_to_discord_ms"]
+                                                     / blk["bf16x3"]["time_to_discord_ms"])
+    return blk
+
+
+def znorm_block(dd, Td, w):
+    """Per-window z-normalisation (each window normalised on its own) on the
+    main workload: time to discord in both precisions."""
+    blk = {"workload": f"{w.name}, every window z-normalised on its own"}
+    ref = None
+    for prec in ("fp32", "bf16x3"):
+        so, ro = time_steps(dd, Td, w.n, prec, True, 3, 1, znorm=True)
+        y = ro[-1]
+        ref = ref or (int(y.index), y.d2)
+        assert (int(y.index), y.d2) == ref, "precisions disagree under znorm"
+        blk[prec] = {"time_to_discord_ms": so * 1e3, "index": int(y.index),
+                     "distance": float(y.distance), "pairs_evaluated": float(y.pairs_evaluated),
+                     "max_rel_err_of_approx_nn": float(y.max_rel_err)}
+        print(f"# znorm {prec}: {so * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    return blk
+
+
+def long_window_block(dd, workloads, windows=(512, 1024)):
+    """The paper's larger series and longer windows: a 10^7-point walk with
+    eight planted anomalies, time to discord per window (split-BF16 where the
+    window is within its limit, FP32 always)."""
+    import torch
+    blk = {}
+    for n in windows:
+        w = workloads.walk10m(n)
+        Td = torch.from_numpy(w.series).cuda()
+        row = {"m": w.m, "n": n, "brute_force_pairs": pair_count(w.m - n + 1, n)}
+        ref = None
+        for prec in ("fp32", "bf16x3"):
+            if prec == "bf16x3" and n > dd.MIXED_MAX_N:
+                continue
+            so, ro = time_steps(dd, Td, n, prec, True, 1, 0)   # library already warm
+            y = ro[-1]
+            ref = ref or (int(y.index), y.d2)
+            assert (int(y.index), y.d2) == ref, "precisions disagree on walk10m"
+            row[prec] = {"time_to_discord_ms": so * 1e3, "index": int(y.index),
+                         "distance": float(y.distance),
+                         "pairs_evaluated": float(y.pairs_evaluated)}
+            print(f"# walk10m n={n} {prec}: {so * 1e3:.1f} ms", file=sys.stderr, flush=True)
+        blk[w.name] = row
+        del Td
+    return blk
 
 
 def main():
@@ -294,6 +374,10 @@ def main():
             print(f"# full scan {prec}: {y.ms_scan:.1f} ms", file=sys.stderr, flush=True)
         full["bf16x3_speedup_vs_fp32"] = full["fp32"]["scan_ms"] / full["bf16x3"]["scan_ms"]
         out["full_scan"] = full
+        out["noisy1m"] = noisy_block(dd, workloads)
+        if abandon:
+            out["znorm"] = znorm_block(dd, Td, w)
+            out["long_windows"] = long_window_block(dd, workloads)
     if not args.no_serve:
         out["serving"] = serving(dd, workloads)
         sv = out["serving"]

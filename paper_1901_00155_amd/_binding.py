@@ -15,7 +15,8 @@ import numpy as np
 __all__ = [
     "load", "DiscordError", "Opts", "Result", "Plan", "search", "default_opts",
     "workspace_bytes", "strerror", "sax_breakpoints", "search_series",
-    "FIELD", "PREC_FP32", "PREC_BF16X3", "LIB_PATH", "EXPORTED", "Server", "ServerConfig",
+    "FIELD", "PREC_FP32", "PREC_BF16X3", "MIXED_MAX_N", "LIB_PATH", "EXPORTED", "Server",
+    "ServerConfig",
     "Request", "Completion", "ServerStats", "EXECUTOR_FN",
 ]
 
@@ -24,6 +25,7 @@ LIB_PATH = os.path.join(_HERE, "lib", "libdiscord.so")
 
 PREC_FP32 = 0
 PREC_BF16X3 = 1
+MIXED_MAX_N = 512   # DISCORD_MIXED_MAX_N: longest window of the split-BF16 scan
 _PREC = {"fp32": PREC_FP32, "bf16x3": PREC_BF16X3, PREC_FP32: PREC_FP32, PREC_BF16X3: PREC_BF16X3}
 
 FIELD = {

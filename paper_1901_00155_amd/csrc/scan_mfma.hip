@@ -486,16 +486,23 @@ __global__ __launch_bounds__(WAVES * 64, (KS <= 16 ? 2 : 1)) void k_scan_mfma(Sc
 
 // Full scans (no early abandon, matrix order, every item listed), software-
 // pipelined: the FP32 epilogue of column block s-1 runs while the MFMAs of
-// block s are in flight.  Two accumulator sets; three LDS stages (block s+1 is
-// loading while block s feeds the MFMAs and block s-1's column values feed the
-// epilogue), one barrier per step.  RB row blocks per wavefront, WAVES
-// wavefronts, MINW wavefronts per SIMD (launch bound).
-template <int KS, int RB, int WAVES, int MINW>
+// block s are in flight.  Two accumulator sets, one barrier per step.  Block
+// s+1 is loading while block s feeds the MFMAs and block s-1's column values
+// feed the epilogue, so the column values take three LDS stages; the operand
+// part of a block takes three stages too (NST = 3, each stage a whole block)
+// or, where three would not fit in LDS, two (NST = 2: block s+1 overwrites
+// block s-1, whose MFMAs finished before the previous step's barrier), with
+// the column values then in a ring of their own.  RB row blocks per
+// wavefront, WAVES wavefronts, MINW wavefronts per SIMD (launch bound).
+template <int KS, int RB, int WAVES, int MINW, int NST>
 __global__ __launch_bounds__(WAVES * 64, MINW) void k_scan_mfma_full(ScanJob J, MixedRows R) {
+  static_assert(NST == 2 || NST == 3, "two or three operand stages");
   extern __shared__ bf16x8 smem[];
   constexpr int SLOTS = Blk<KS>::SLOTS;
   constexpr int PER_T = (SLOTS + WAVES * 64 - 1) / (WAVES * 64);
-  constexpr int STAGE = SLOTS + 8;
+  // NST = 3: stage t = [block | its 8 column-value slots]; NST = 2: two block
+  // stages, then three 8-slot column-value stages
+  constexpr int STAGE = NST == 3 ? SLOTS + 8 : SLOTS;
   const bf16x8* __restrict__ S = reinterpret_cast<const bf16x8*>(R.sblk);
 
   const int lane = threadIdx.x & 63;
@@ -536,8 +543,16 @@ __global__ __launch_bounds__(WAVES * 64, MINW) void k_scan_mfma_full(ScanJob J, 
   const int64_t steps = e1 > e0 ? e1 - e0 : 0;
 
   typedef __attribute__((address_space(3))) void lds_void;
-  auto fetch = [&](int64_t q, bf16x8* dst) {
+  // step t's operand block and its 32 column values sqrt(n) (mean - mu)
+  auto stage = [&](int64_t t) { return smem + (t % NST) * STAGE; };
+  auto cvals = [&](int64_t t) {
+    return NST == 3 ? smem + (t % 3) * STAGE + SLOTS : smem + 2 * SLOTS + (t % 3) * 8;
+  };
+  // step t covers column block e0 + t
+  auto fetch = [&](int64_t t) {
+    const int64_t q = e0 + t;
     const bf16x8* src = S + q * SLOTS;
+    bf16x8* dst = stage(t);
 #pragma unroll
     for (int i = 0; i < PER_T; ++i) {
       const int w0 = i * WAVES * 64 + wv * 64;
@@ -545,10 +560,8 @@ __global__ __launch_bounds__(WAVES * 64, MINW) void k_scan_mfma_full(ScanJob J, 
         __builtin_amdgcn_global_load_lds(src + w0 + lane, (lds_void*)(dst + w0), 16, 0, 0);
     }
     if (wv == 0 && lane < 8)
-      __builtin_amdgcn_global_load_lds(R.smu + q * BN + 4 * lane, (lds_void*)(dst + SLOTS), 16, 0,
-                                       0);
+      __builtin_amdgcn_global_load_lds(R.smu + q * BN + 4 * lane, (lds_void*)cvals(t), 16, 0, 0);
   };
-  auto stage = [&](int64_t t) { return smem + (t % 3) * STAGE; };
 
   float rmin[RB];
   int32_t rj[RB];
@@ -579,11 +592,11 @@ __global__ __launch_bounds__(WAVES * 64, MINW) void k_scan_mfma_full(ScanJob J, 
   };
   // epilogue, first part (straight-line, so that it can be interleaved with the
   // MFMA chain of the next block): the 16 distances of this lane per row block
-  auto distances = [&](const floatx16 (&a)[RB], const bf16x8* buf, float (&d)[RB][16]) {
+  auto distances = [&](const floatx16 (&a)[RB], const bf16x8* cv, float (&d)[RB][16]) {
     float smc[16];
 #pragma unroll
     for (int qd = 0; qd < 4; ++qd) {
-      const float4 m = reinterpret_cast<const float4*>(buf + SLOTS)[2 * qd + h];
+      const float4 m = reinterpret_cast<const float4*>(cv)[2 * qd + h];
       smc[4 * qd + 0] = m.x; smc[4 * qd + 1] = m.y; smc[4 * qd + 2] = m.z; smc[4 * qd + 3] = m.w;
     }
 #pragma unroll
@@ -634,20 +647,20 @@ __global__ __launch_bounds__(WAVES * 64, MINW) void k_scan_mfma_full(ScanJob J, 
       }
     }
   };
-  auto epilogue = [&](const floatx16 (&a)[RB], int64_t q, const bf16x8* buf) {
+  auto epilogue = [&](const floatx16 (&a)[RB], int64_t t) {
     float d[RB][16];
-    distances(a, buf, d);
-    finish(d, q);
+    distances(a, cvals(t), d);
+    finish(d, e0 + t);
   };
   // step t >= 1: load block t+1, multiply block t into `cur` and compute block
   // t-1's distances from `prev` in one straight-line region (the scheduler is
   // asked to interleave the two), then finish block t-1
   auto step = [&](int64_t t, floatx16 (&cur)[RB], const floatx16 (&prev)[RB]) {
-    if (t + 1 < steps) fetch(e0 + t + 1, stage(t + 1));
+    if (t + 1 < steps) fetch(t + 1);
     float d[RB][16];
     __builtin_amdgcn_s_setprio(1);
     mma(cur, stage(t));
-    distances(prev, stage(t - 1), d);
+    distances(prev, cvals(t - 1), d);
 #pragma unroll
     for (int k = 0; k < 16 * RB; ++k) {
       __builtin_amdgcn_sched_group_barrier(0x008, 3, 0);   // 3 MFMA
@@ -660,9 +673,9 @@ __global__ __launch_bounds__(WAVES * 64, MINW) void k_scan_mfma_full(ScanJob J, 
 
   floatx16 acc0[RB], acc1[RB];
   if (steps > 0) {
-    fetch(e0, stage(0));
+    fetch(0);
     __syncthreads();
-    if (steps > 1) fetch(e0 + 1, stage(1));
+    if (steps > 1) fetch(1);
     mma(acc0, stage(0));
     __syncthreads();
   }
@@ -673,9 +686,9 @@ __global__ __launch_bounds__(WAVES * 64, MINW) void k_scan_mfma_full(ScanJob J, 
   }
   if (t < steps) {
     step(t, acc1, acc0);
-    epilogue(acc1, e0 + t, stage(t));
+    epilogue(acc1, t);
   } else if (steps > 0) {
-    epilogue(acc0, e0 + steps - 1, stage(steps - 1));
+    epilogue(acc0, steps - 1);
   }
 
 #pragma unroll
@@ -691,19 +704,20 @@ __global__ __launch_bounds__(WAVES * 64, MINW) void k_scan_mfma_full(ScanJob J, 
   if (lane == 0 && c64) atomicAdd(pair_slot(J.pairs), (unsigned long long)c64);
 }
 
-template <int KS, int RB, int WAVES, int MINW>
+template <int KS, int RB, int WAVES, int MINW, int NST>
 void launch_full_pipelined(const ScanJob& J, const MixedRows& R, hipStream_t s) {
   const int64_t blocks = J.n_groups * J.chunks;
   if (blocks <= 0) return;
-  const size_t lds = sizeof(bf16x8) * 3 * (Blk<KS>::SLOTS + 8);
+  const size_t lds = sizeof(bf16x8) * (NST * Blk<KS>::SLOTS + 3 * 8);
   static const bool attr_set = [lds] {
     if (lds > 65536)
-      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_scan_mfma_full<KS, RB, WAVES, MINW>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      (void)hipFuncSetAttribute(
+          reinterpret_cast<const void*>(&k_scan_mfma_full<KS, RB, WAVES, MINW, NST>),
+          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     return true;
   }();
   (void)attr_set;
-  hipLaunchKernelGGL((k_scan_mfma_full<KS, RB, WAVES, MINW>), dim3((unsigned)blocks),
+  hipLaunchKernelGGL((k_scan_mfma_full<KS, RB, WAVES, MINW, NST>), dim3((unsigned)blocks),
                      dim3(WAVES * 64), lds, s, J, R);
 }
 
@@ -728,10 +742,17 @@ void launch_kr(const ScanJob& J, const MixedRows& R, hipStream_t s) {
 
 template <int KS>
 void launch_ks(const ScanJob& J, const MixedRows& R, hipStream_t s) {
+  // full scans only (no abandon, matrix order, every item listed)
   if constexpr (KS > 8 && KS <= 16) {
     if (waves_for<KS>(J.abandon != 0) == 8) {
-      // full scans only: no abandon, matrix order, every item listed
-      launch_full_pipelined<KS, 1, 8, 2>(J, R, s);
+      launch_full_pipelined<KS, 1, 8, 2, 3>(J, R, s);
+      return;
+    }
+  }
+  if constexpr (KS > 16 && KS <= 18) {
+    if (!J.abandon) {
+      // two wavefronts per SIMD, two workgroups per CU (two operand stages each)
+      launch_full_pipelined<KS, 1, 4, 2, 2>(J, R, s);
       return;
     }
   }

@@ -8,7 +8,7 @@ GPU then read the same float32 values.
 
 The paper evaluates on two real series of 10^6 and 10^7 points (its dataset
 table, section 4.1) that are not available here; the workloads below are
-stand-ins with the same shape: long univariate series, windows of 64-512
+stand-ins with the same shape: long univariate series, windows of 64-2048
 samples, and a few planted anomalous windows.
 
 Workloads
@@ -19,6 +19,9 @@ Workloads
 ``noisy1m``   m=2^20 random walk plus N(0, 0.05) noise (seed 2), n=256, no anomaly.
 ``large4m``   m=2^22: three seeded sinusoids (periods 200-5000, log-uniform) plus a
               random walk plus N(0, 0.2) noise (seed 3), n=512, eight anomalies.
+``walk10m``   m=10^7 random walk plus N(0, 0.1) noise (seed 5), eight anomalies
+              cycling the three kinds, window n chosen by the caller (the
+              paper's windows 64-2048 on its 10^7-point series).
 ``serve``     4096 requests (seed 4): Poisson arrivals at 200 req/s, lengths
               log-uniform in [2^12, 2^18], n uniform over {64, 128, 256}, one
               anomaly each.
@@ -115,6 +118,17 @@ def large4m(seed: int = 3, m: int = 1 << 22, n: int = 512) -> Workload:
                     [(p, n, kd) for p, kd in zip(pos, kinds)], seed)
 
 
+def walk10m(n: int = 1024, seed: int = 5, m: int = 10 ** 7) -> Workload:
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.standard_normal(m)) + rng.normal(0.0, 0.1, m)
+    kinds = [ANOMALY_TYPES[i % 3] for i in range(8)]
+    pos = _positions(rng, m, n, len(kinds))
+    for p, kind in zip(pos, kinds):
+        _plant(t, rng, p, n, kind)
+    return Workload(f"walk10m_n{n}", t.astype(np.float32), n,
+                    [(p, n, kd) for p, kd in zip(pos, kinds)], seed)
+
+
 @dataclasses.dataclass
 class Request:
     arrival_s: float
@@ -153,5 +167,7 @@ def random_walk(m: int, seed: int, noise: float = 0.0) -> np.ndarray:
 
 
 def by_name(name: str) -> Workload:
+    if name.startswith("walk10m"):           # walk10m or walk10m_n<window>
+        return walk10m(int(name.split("_n")[1])) if "_n" in name else walk10m()
     return {"small": small, "walk1m": walk1m, "noisy1m": noisy1m,
             "large4m": large4m}[name]()

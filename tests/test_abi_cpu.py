@@ -101,3 +101,10 @@ def test_library_has_no_unresolved_internal_symbols(dd):
         pytest.skip("nm not available")
     out = subprocess.run([nm, "-uC", dd.LIB_PATH], capture_output=True, text=True, check=True).stdout
     assert "dd::" not in out, [ln for ln in out.splitlines() if "dd::" in ln]
+
+
+def test_binding_constants_match_header():
+    import re
+    from paper_1901_00155_amd import _binding as B
+    text = open(HEADER).read()
+    assert int(re.search(r"#define DISCORD_MIXED_MAX_N (\d+)", text).group(1)) == B.MIXED_MAX_N

@@ -109,8 +109,24 @@ def test_bf16x3_full_scan_profile(gpu, m, n):
 SMALL_CASES = [
     (16, 1, 0), (40, 3, 1), (64, 32, 2), (63, 21, 3), (100, 7, 4), (257, 9, 5), (300, 64, 6),
     (513, 100, 7), (1000, 1, 8), (1001, 333, 9), (2049, 17, 10), (3000, 128, 11),
-    (4100, 200, 12), (777, 259, 13), (4096, 64, 14), (1500, 512, 15),
+    (4100, 200, 12), (777, 259, 13), (4096, 64, 14), (1500, 512, 15), (2600, 280, 16),
 ]
+
+
+# the paper's longer windows (its 1024 and 2048): FP32 scan only (the split-BF16
+# scan stops at DISCORD_MIXED_MAX_N); a ragged window of 1500 as well
+LONG_CASES = [(3000, 1024, 19), (4500, 2048, 20), (3333, 1500, 21)]
+
+
+@pytest.mark.parametrize("m,n,seed", LONG_CASES)
+@pytest.mark.parametrize("mode", ["full", "abandon-matrix", "abandon-phidd", "abandon-near"])
+def test_long_windows_match_oracle(gpu, m, n, seed, mode):
+    T = workloads.random_walk(m, seed=seed)
+    ref = oracle.discord(T, n)
+    order = {"full": 1, "abandon-matrix": 0, "abandon-phidd": 1, "abandon-near": 2}[mode]
+    with gpu.Plan(T, n, abandon=mode != "full", order=order, precision="fp32") as p:
+        r = p.search()
+    _assert_same(r, ref, (m, n, seed, mode))
 
 
 @pytest.mark.parametrize("m,n,seed", SMALL_CASES)
