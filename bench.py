@@ -14,8 +14,9 @@ to discord, the brute-force-equivalent rate P(N, n) / time, the split-BF16
 MFMA search of the same input (`mixed`), the time to discord under each
 visiting order, full-scan rates of both precisions, the roofline of each scan
 kernel (kernel time from HIP events on the plan's stream), the m = 2^20, n = 256
-noisy walk in both precisions, per-window z-normalisation, the 10^7-point walk
-at windows of 512-2048, the serving stream (p50/p99 latency and throughput)
+noisy walk in both precisions, per-window z-normalisation, time to discord
+against the number of compute units (CU-limited streams), the 10^7-point walk
+at windows of 512 and 1024, the serving stream (p50/p99 latency and throughput)
 and the FP64 CPU oracle timed on a bounded sample of the same workload on the
 host cores.
 """
@@ -242,6 +243,35 @@ def long_window_block(dd, workloads, windows=(512, 1024)):
     return blk
 
 
+def scalability_block(dd, Td, w, cu_counts=(8, 16, 32, 64, 128, 256)):
+    """Time to discord against the number of compute units the search may use
+    (CU-limited streams), the GPU form of the paper's scalability study:
+    speedup s(k) = T(k0) / T(k) and efficiency e(k) = s(k) k0 / k from the
+    smallest count k0 (one CU per die of the device at k0 = 8)."""
+    blk = {"workload": w.name, "cu_counts": list(cu_counts), "base_cus": cu_counts[0]}
+    for prec in ("fp32", "bf16x3"):
+        rows = []
+        for k in cu_counts:
+            with dd.CULimitedStream(k) as cs:
+                ts = []
+                for it in range(3):
+                    t = time.perf_counter()
+                    with dd.Plan(Td, w.n, precision=prec, stream=cs) as p:
+                        r = p.search()
+                    ts.append(time.perf_counter() - t)
+            rows.append({"cus": k, "time_to_discord_ms": min(ts[1:]) * 1e3, "index": int(r.index),
+                         "pairs_evaluated": float(r.pairs_evaluated)})
+            print(f"# scalability {prec} {k} CUs: {rows[-1]['time_to_discord_ms']:.1f} ms",
+                  file=sys.stderr, flush=True)
+        t0 = rows[0]["time_to_discord_ms"]
+        for row in rows:
+            row["speedup"] = t0 / row["time_to_discord_ms"]
+            row["efficiency"] = row["speedup"] * cu_counts[0] / row["cus"]
+        assert len({row["index"] for row in rows}) == 1, "CU counts disagree"
+        blk[prec] = rows
+    return blk
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -377,6 +407,7 @@ def main():
         out["noisy1m"] = noisy_block(dd, workloads)
         if abandon:
             out["znorm"] = znorm_block(dd, Td, w)
+            out["scalability"] = scalability_block(dd, Td, w)
             out["long_windows"] = long_window_block(dd, workloads)
     if not args.no_serve:
         out["serving"] = serving(dd, workloads)

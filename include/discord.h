@@ -199,6 +199,35 @@ int discord_plan_copy(discord_plan plan, int32_t field, void* host_dst, size_t b
 int discord_rows_nn_fp64(discord_plan plan, const int64_t* rows, int64_t count,
                          double* d2_out, int64_t* j_out);
 
+/* ---- compute-unit-limited streams (scalability study) ----------------------
+ * The paper reports speedup and parallel efficiency against the number of
+ * cores it runs on (section 4, its scalability experiments).  On the GPU the
+ * unit is the compute unit (CU): a search on a stream from
+ * discord_stream_create_cu_limited runs every kernel on `cus` CUs of the
+ * current device only, so timing the same search at several CU counts gives
+ * that study.
+ *
+ * discord_cu_mask (host only, no device call) writes the CU mask used:
+ * `cus` bits spread evenly over the device's `xccs` accelerator dies, so
+ * that every die keeps cus / xccs CUs whether the runtime assigns mask bit b
+ * to die b / (total_cus / xccs) (contiguous) or to die b % xccs
+ * (interleaved).  Mask bit b is bit b % 32 of words[b / 32].
+ * Requires xccs >= 1, total_cus a multiple of xccs with (total_cus / xccs) a
+ * multiple of xccs, cus a multiple of xccs with 1 <= cus <= total_cus, and
+ * nwords >= ceil(total_cus / 32).  Returns the number of words written, or
+ * EINVAL.
+ *
+ * discord_stream_create_cu_limited creates such a stream (default priority,
+ * non-blocking) on the current device, reads its mask back and checks that it
+ * holds exactly `cus` CUs.  Returns OK, EINVAL (sizes as above, with the
+ * device's CU and die counts), or EDEVICE (the runtime refused the mask or
+ * changed it; no stream is left behind).  The caller owns the stream and
+ * releases it with discord_stream_destroy (which synchronises it first). */
+int discord_cu_mask(int32_t total_cus, int32_t xccs, int32_t cus, uint32_t* words,
+                    int32_t nwords);
+int discord_stream_create_cu_limited(int32_t cus, void** stream_out);
+int discord_stream_destroy(void* stream);
+
 /* ---- serving ---------------------------------------------------------------
  * The paper has no serving layer; this is a request loop around the same
  * prepare + search path.  Requests (T, m, n) of uneven size are queued in

@@ -16,7 +16,7 @@ __all__ = [
     "load", "DiscordError", "Opts", "Result", "Plan", "search", "default_opts",
     "workspace_bytes", "strerror", "sax_breakpoints", "search_series",
     "FIELD", "PREC_FP32", "PREC_BF16X3", "MIXED_MAX_N", "LIB_PATH", "EXPORTED", "Server",
-    "ServerConfig",
+    "ServerConfig", "cu_mask", "CULimitedStream",
     "Request", "Completion", "ServerStats", "EXECUTOR_FN",
 ]
 
@@ -42,6 +42,7 @@ EXPORTED = [
     "discord_search_series", "discord_plan_count", "discord_plan_copy", "discord_rows_nn_fp64",
     "discord_server_create", "discord_server_create_with_executor", "discord_server_submit",
     "discord_server_poll", "discord_server_get_stats", "discord_server_destroy",
+    "discord_cu_mask", "discord_stream_create_cu_limited", "discord_stream_destroy",
 ]
 
 
@@ -156,6 +157,12 @@ def load():
     lib.discord_plan_copy.restype = ctypes.c_int
     lib.discord_rows_nn_fp64.argtypes = [vp, vp, i64, vp, vp]
     lib.discord_rows_nn_fp64.restype = ctypes.c_int
+    lib.discord_cu_mask.argtypes = [i32, i32, i32, ctypes.POINTER(ctypes.c_uint32), i32]
+    lib.discord_cu_mask.restype = ctypes.c_int
+    lib.discord_stream_create_cu_limited.argtypes = [i32, ctypes.POINTER(vp)]
+    lib.discord_stream_create_cu_limited.restype = ctypes.c_int
+    lib.discord_stream_destroy.argtypes = [vp]
+    lib.discord_stream_destroy.restype = ctypes.c_int
     lib.discord_server_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]
     lib.discord_server_create.restype = ctypes.c_int
     lib.discord_server_create_with_executor.argtypes = [ctypes.POINTER(ServerConfig), EXECUTOR_FN,
@@ -224,6 +231,41 @@ def _series_ptr(T):
     return a.ctypes.data, a.size, a, None
 
 
+def cu_mask(total_cus: int, xccs: int, cus: int) -> list:
+    """The CU mask of a stream limited to `cus` CUs (discord_cu_mask), as 32-bit
+    words; host only."""
+    lib = load()
+    nw = (total_cus + 31) // 32
+    buf = (ctypes.c_uint32 * max(nw, 1))()
+    got = lib.discord_cu_mask(total_cus, xccs, cus, buf, nw)
+    _check(got if got < 0 else 0)
+    return list(buf[:got])
+
+
+class CULimitedStream:
+    """A HIP stream whose kernels run on `cus` compute units of the current
+    device only (discord_stream_create_cu_limited); pass it as `stream=`.
+    `handle` is the hipStream_t."""
+
+    def __init__(self, cus: int):
+        lib = load()
+        h = ctypes.c_void_p()
+        _check(lib.discord_stream_create_cu_limited(int(cus), ctypes.byref(h)))
+        self.cus = int(cus)
+        self.handle = h.value
+
+    def close(self):
+        if self.handle:
+            h, self.handle = self.handle, None
+            _check(load().discord_stream_destroy(h))
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
 class Plan:
     """A prepared series (discord_prepare) that can be searched repeatedly."""
 
@@ -242,6 +284,8 @@ class Plan:
             stream = tstream
         elif hasattr(stream, "cuda_stream"):
             stream = stream.cuda_stream
+        elif isinstance(stream, CULimitedStream):
+            stream = stream.handle
         self._ws = None
         ws_ptr, ws_bytes = None, 0
         if torch_workspace:

@@ -830,4 +830,64 @@ int discord_sax_breakpoints(int32_t alpha, double* out) {
   return DISCORD_OK;
 }
 
+int discord_cu_mask(int32_t total_cus, int32_t xccs, int32_t cus, uint32_t* words,
+                    int32_t nwords) {
+  if (!words || xccs < 1 || total_cus < 1 || total_cus % xccs != 0) return DISCORD_EINVAL;
+  const int32_t per = total_cus / xccs;   // CUs per die
+  if (per % xccs != 0 || cus < 1 || cus > total_cus || cus % xccs != 0) return DISCORD_EINVAL;
+  const int32_t used = (total_cus + 31) / 32;
+  if (nwords < used) return DISCORD_EINVAL;
+  std::memset(words, 0, sizeof(uint32_t) * (size_t)used);
+  const int32_t j = cus / xccs;           // CUs kept per die
+  std::vector<int32_t> taken((size_t)xccs);
+  for (int32_t x = 0; x < xccs; ++x) {
+    // block x holds bits x * per .. x * per + per - 1; take j of them whose
+    // residues mod xccs are (x + t) mod xccs, t = 0 .. j - 1, each residue's
+    // bits in ascending order (per / xccs of them per residue, j <= per)
+    std::fill(taken.begin(), taken.end(), 0);
+    for (int32_t t = 0; t < j; ++t) {
+      const int32_t r = (x + t) % xccs;
+      const int32_t b = x * per + r + xccs * taken[(size_t)r]++;
+      words[b / 32] |= 1u << (b % 32);
+    }
+  }
+  return used;
+}
+
+int discord_stream_create_cu_limited(int32_t cus, void** stream_out) {
+  if (!stream_out) return DISCORD_EINVAL;
+  *stream_out = nullptr;
+  int dev = 0, total = 0, xccs = 1;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&total, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return DISCORD_EDEVICE;
+  if (hipDeviceGetAttribute(&xccs, hipDeviceAttributeNumberOfXccs, dev) != hipSuccess || xccs < 1)
+    xccs = 1;
+  std::vector<uint32_t> mask((size_t)(total + 31) / 32);
+  const int used = discord_cu_mask(total, xccs, cus, mask.data(), (int32_t)mask.size());
+  if (used < 0) return used;
+  hipStream_t s = nullptr;
+  if (hipExtStreamCreateWithCUMask(&s, (uint32_t)used, mask.data()) != hipSuccess || !s)
+    return DISCORD_EDEVICE;
+  std::vector<uint32_t> back(mask.size(), 0);
+  int got = -1;
+  if (hipExtStreamGetCUMask(s, (uint32_t)back.size(), back.data()) == hipSuccess) {
+    got = 0;
+    for (uint32_t w : back) got += __builtin_popcount(w);
+  }
+  if (got != cus) {
+    (void)hipStreamDestroy(s);
+    return DISCORD_EDEVICE;
+  }
+  *stream_out = s;
+  return DISCORD_OK;
+}
+
+int discord_stream_destroy(void* stream) {
+  if (!stream) return DISCORD_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  const bool ok = hipStreamSynchronize(s) == hipSuccess;
+  return (hipStreamDestroy(s) == hipSuccess && ok) ? DISCORD_OK : DISCORD_EDEVICE;
+}
+
 }  // extern "C"

@@ -108,3 +108,29 @@ def test_binding_constants_match_header():
     from paper_1901_00155_amd import _binding as B
     text = open(HEADER).read()
     assert int(re.search(r"#define DISCORD_MIXED_MAX_N (\d+)", text).group(1)) == B.MIXED_MAX_N
+
+
+@pytest.mark.parametrize("total,xccs", [(256, 8), (304, 8), (64, 2), (40, 1), (32, 4)])
+def test_cu_mask_is_balanced_over_dies(dd, total, xccs):
+    """Every die keeps cus / xccs CUs under both the contiguous (bit b on die
+    b // per) and the interleaved (bit b on die b % xccs) assignment, no bit
+    lies beyond the device's CUs, and no bit repeats."""
+    per = total // xccs
+    for cus in range(xccs, total + 1, xccs):
+        if per % xccs:
+            with pytest.raises(dd.DiscordError):
+                dd.cu_mask(total, xccs, cus)
+            return
+        words = dd.cu_mask(total, xccs, cus)
+        assert len(words) == (total + 31) // 32
+        bits = [b for b in range(32 * len(words)) if (words[b // 32] >> (b % 32)) & 1]
+        assert len(bits) == cus and max(bits) < total
+        for die in range(xccs):
+            assert sum(1 for b in bits if b // per == die) == cus // xccs
+            assert sum(1 for b in bits if b % xccs == die) == cus // xccs
+
+
+def test_cu_mask_rejects_bad_sizes(dd):
+    for args in [(256, 8, 0), (256, 8, 12), (256, 8, 264), (256, 0, 8), (250, 8, 8), (0, 1, 1)]:
+        with pytest.raises(dd.DiscordError):
+            dd.cu_mask(*args)

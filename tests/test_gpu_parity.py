@@ -309,3 +309,16 @@ def test_large4m_certificate_both_precisions(gpu):
         _certify(w, r, wit)
         out[precision] = (r.index, r.nn_index, r.d2)
     assert out["fp32"] == out["bf16x3"], out
+
+
+@pytest.mark.parametrize("cus", [8, 64])
+@pytest.mark.parametrize("precision", PRECS)
+def test_cu_limited_stream(gpu, cus, precision):
+    """A search on a stream limited to a few compute units (the scalability
+    study's streams) gives the oracle's answer."""
+    w = workloads.small()
+    ref = oracle.discord(w.series, w.n)
+    with gpu.CULimitedStream(cus) as cs:
+        with gpu.Plan(w.series, w.n, precision=precision, stream=cs) as p:
+            r = p.search()
+    _assert_same(r, ref)
