@@ -55,7 +55,7 @@ typedef enum {
 } discord_precision;
 
 /* Largest window the split-BF16 MFMA scan takes (ERANGE beyond it). */
-#define DISCORD_MIXED_MAX_N 512
+#define DISCORD_MIXED_MAX_N 2048
 
 typedef struct {
     int32_t precision;  /* discord_precision                                         */

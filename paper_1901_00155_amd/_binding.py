@@ -25,7 +25,7 @@ LIB_PATH = os.path.join(_HERE, "lib", "libdiscord.so")
 
 PREC_FP32 = 0
 PREC_BF16X3 = 1
-MIXED_MAX_N = 512   # DISCORD_MIXED_MAX_N: longest window of the split-BF16 scan
+MIXED_MAX_N = 2048  # DISCORD_MIXED_MAX_N: longest window of the split-BF16 scan
 _PREC = {"fp32": PREC_FP32, "bf16x3": PREC_BF16X3, PREC_FP32: PREC_FP32, PREC_BF16X3: PREC_BF16X3}
 
 FIELD = {

@@ -151,8 +151,10 @@ struct MixedRows {
   const uint4* sblk;
 };
 constexpr int kMixedBlock = 32;      // rows per MFMA row block = columns per column block
-constexpr int kMixedMaxN = DISCORD_MIXED_MAX_N;  // longest window of the split-BF16 scan (32 K-steps)
+constexpr int kMixedMaxN = DISCORD_MIXED_MAX_N;  // longest window of the split-BF16 scan (128 K-steps)
 bool launch_scan_mfma(const ScanJob& J, const MixedRows& R, hipStream_t s);
+// windows of 513..2048 (scan_mfma_long.hip); false for other windows
+bool launch_scan_mfma_long(const ScanJob& J, const MixedRows& R, hipStream_t s);
 int mfma_row_blocks(int n, bool abandon);   // row blocks per MFMA work item
 // The split subsequence matrix: for every block of 32 consecutive rows, KS+1
 // K-steps of 16 operand slots per lane (64 lanes): KS steps of the centred

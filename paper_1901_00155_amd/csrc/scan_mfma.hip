@@ -102,22 +102,24 @@ __device__ __forceinline__ uint64_t load_relaxed64(const uint64_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Preparation: one thread per (block, K-step slot, lane).
-template <int KS>
-__global__ __launch_bounds__(256) void k_split_blocks(const float* __restrict__ Tp, int64_t nblk,
-                                                      int n, const float* __restrict__ c32,
-                                                      const float* __restrict__ cn32,
-                                                      const float* __restrict__ r32,
-                                                      bf16x8* __restrict__ out) {
+// Preparation: one thread per (block, K-step slot, lane).  KS is a template
+// argument for windows up to 512 and a run-time value beyond (the body is the
+// same; the constant only makes the index arithmetic cheaper).
+__device__ __forceinline__ void split_blocks_body(int KS, const float* __restrict__ Tp,
+                                                  int64_t nblk, int n,
+                                                  const float* __restrict__ c32,
+                                                  const float* __restrict__ cn32,
+                                                  const float* __restrict__ r32,
+                                                  bf16x8* __restrict__ out) {
   const int64_t t = blockIdx.x * 256ll + threadIdx.x;
-  const int64_t per_blk = (KS + 1) * 64;
+  const int64_t per_blk = (int64_t)(KS + 1) * 64;
   if (t >= nblk * per_blk) return;
   const int64_t q = t / per_blk;
   const int r = (int)(t - q * per_blk);
   const int s = r >> 6, l = r & 63;
   const int64_t row = q * BM + (l & 31);
   const int h = l >> 5;
-  bf16x8* blk = out + q * Blk<KS>::SLOTS;
+  bf16x8* blk = out + q * ((int64_t)(KS + 1) * 128);
   if (s < KS) {
     const int k0 = 16 * s + 8 * h;
     const float c = c32[row];
@@ -146,6 +148,24 @@ __global__ __launch_bounds__(256) void k_split_blocks(const float* __restrict__ 
     blk[KS * 128 + l] = xa;        // extra step as an A (column) operand
     blk[KS * 128 + 64 + l] = xb;   // extra step as a B (row) operand
   }
+}
+
+template <int KS>
+__global__ __launch_bounds__(256) void k_split_blocks(const float* __restrict__ Tp, int64_t nblk,
+                                                      int n, const float* __restrict__ c32,
+                                                      const float* __restrict__ cn32,
+                                                      const float* __restrict__ r32,
+                                                      bf16x8* __restrict__ out) {
+  split_blocks_body(KS, Tp, nblk, n, c32, cn32, r32, out);
+}
+
+__global__ __launch_bounds__(256) void k_split_blocks_long(int KS, const float* __restrict__ Tp,
+                                                           int64_t nblk, int n,
+                                                           const float* __restrict__ c32,
+                                                           const float* __restrict__ cn32,
+                                                           const float* __restrict__ r32,
+                                                           bf16x8* __restrict__ out) {
+  split_blocks_body(KS, Tp, nblk, n, c32, cn32, r32, out);
 }
 
 // One workgroup per (item, chunk of its column sequence).  An item is a fixed
@@ -771,6 +791,7 @@ void launch_split(const float* Tp, int64_t nblk, int n, const float* c32, const 
 
 int mfma_row_blocks(int n, bool abandon) {
   const int ks = (n + 15) / 16;
+  if (ks > 32) return 1;   // windows beyond 512: one row block per workgroup
   const int waves = (ks > 8 && ks <= 16 && !abandon) ? 8 : 4;
   return waves * (ks <= 8 ? 2 : 1);
 }
@@ -789,7 +810,7 @@ bool launch_scan_mfma(const ScanJob& J, const MixedRows& R, hipStream_t s) {
   case K: launch_ks<K>(J, R, s); return true;
     DD_KS_CASES(DD_CASE)
 #undef DD_CASE
-    default: return false;
+    default: return launch_scan_mfma_long(J, R, s);   // windows of 513..2048
   }
 }
 
@@ -801,7 +822,13 @@ void launch_split_blocks(const float* Tp, int64_t N, int n, const float* c32, co
   case K: launch_split<K>(Tp, nblk, n, c32, cn32, r32, sblk, s); return;
     DD_KS_CASES(DD_CASE)
 #undef DD_CASE
-    default: return;
+    default: {
+      const int ks = (n + 15) / 16;
+      const int64_t threads = nblk * (ks + 1) * 64;
+      hipLaunchKernelGGL(k_split_blocks_long, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0,
+                         s, ks, Tp, nblk, n, c32, cn32, r32, reinterpret_cast<bf16x8*>(sblk));
+      return;
+    }
   }
 }
 

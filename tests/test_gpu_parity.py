@@ -113,18 +113,21 @@ SMALL_CASES = [
 ]
 
 
-# the paper's longer windows (its 1024 and 2048): FP32 scan only (the split-BF16
-# scan stops at DISCORD_MIXED_MAX_N); a ragged window of 1500 as well
-LONG_CASES = [(3000, 1024, 19), (4500, 2048, 20), (3333, 1500, 21)]
+# the paper's longer windows (its 1024 and 2048), a ragged 1500, and windows
+# on either side of the split-BF16 kernels' boundary at 512 / 528 (33 K-steps)
+# and at the longest window (128 K-steps, 32 per wavefront)
+LONG_CASES = [(3000, 1024, 19), (4500, 2048, 20), (3333, 1500, 21), (2000, 513, 22),
+              (2600, 528, 23), (5200, 2033, 24), (4000, 1100, 25), (3600, 700, 26)]
 
 
 @pytest.mark.parametrize("m,n,seed", LONG_CASES)
 @pytest.mark.parametrize("mode", ["full", "abandon-matrix", "abandon-phidd", "abandon-near"])
-def test_long_windows_match_oracle(gpu, m, n, seed, mode):
+@pytest.mark.parametrize("precision", PRECS)
+def test_long_windows_match_oracle(gpu, m, n, seed, mode, precision):
     T = workloads.random_walk(m, seed=seed)
     ref = oracle.discord(T, n)
     order = {"full": 1, "abandon-matrix": 0, "abandon-phidd": 1, "abandon-near": 2}[mode]
-    with gpu.Plan(T, n, abandon=mode != "full", order=order, precision="fp32") as p:
+    with gpu.Plan(T, n, abandon=mode != "full", order=order, precision=precision) as p:
         r = p.search()
     _assert_same(r, ref, (m, n, seed, mode))
 
@@ -238,7 +241,7 @@ def test_error_paths(gpu):
     with pytest.raises(gpu.DiscordError):
         gpu.Plan(np.arange(100, dtype=np.float32), 3, paa_w=9)
     with pytest.raises(gpu.DiscordError) as e:
-        gpu.Plan(workloads.random_walk(3000, seed=1), 600, precision="bf16x3")
+        gpu.Plan(workloads.random_walk(4300, seed=1), 2049, precision="bf16x3")
     assert e.value.status == -6
 
 

@@ -168,7 +168,7 @@ def test_submit_refusals(dd):
     assert sorted(c["tag"] for c in done) == [3, 4, 5]
     assert st["rejected"] == 4 and st["submitted"] == 3
     with dd.Server(1 << 30, slots=1, executor=lambda *a: 0, precision="bf16x3") as s:
-        assert s.submit(np.arange(4096, dtype=np.float32), 600, 0) == -6   # beyond the MFMA limit
+        assert s.submit(np.arange(4200, dtype=np.float32), 2049, 0) == -6   # beyond the MFMA limit
 
 
 def test_bad_config_is_refused(dd):
