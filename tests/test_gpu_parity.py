@@ -325,3 +325,18 @@ def test_cu_limited_stream(gpu, cus, precision):
         with gpu.Plan(w.series, w.n, precision=precision, stream=cs) as p:
             r = p.search()
     _assert_same(r, ref)
+
+
+def test_walk10m_long_window_certificate_both_precisions(gpu):
+    """m = 10^7 walk + N(0, 0.1), window n = 1024 (the paper's larger series
+    and one of its longer windows), eight planted anomalies: both precisions
+    give the same discord, certified in FP64 against every row's witness."""
+    w = workloads.walk10m(1024)
+    out = {}
+    for precision in PRECS:
+        with gpu.Plan(w.series, w.n, precision=precision) as p:
+            r = p.search()
+            wit = p.copy("nn_witness")
+        _certify(w, r, wit)
+        out[precision] = (r.index, r.nn_index, r.d2)
+    assert out["fp32"] == out["bf16x3"], out
