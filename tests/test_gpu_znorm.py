@@ -79,7 +79,9 @@ def test_row_sigma_needs_znorm(gpu):
 ZCASES = [
     (16, 1, 0), (40, 3, 1), (64, 32, 2), (100, 7, 4), (257, 9, 5), (300, 64, 6),
     (513, 100, 7), (1001, 333, 9), (2049, 17, 10), (3000, 128, 11),
-    (4100, 200, 12), (4096, 64, 14), (1500, 512, 15),
+    (4100, 200, 12), (4096, 64, 14), (1500, 512, 15), (2600, 280, 16),
+    # windows beyond 512 (the split-BF16 scan with K-steps split over wavefronts)
+    (2600, 528, 23), (3600, 700, 26), (4500, 2048, 20),
 ]
 
 
