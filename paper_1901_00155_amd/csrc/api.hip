@@ -488,6 +488,11 @@ int discord_search(discord_plan p, discord_result* out) {
   while ((int64_t{1} << item_shift) < item_rows) ++item_shift;
   const int64_t n_items = (N + item_rows - 1) / item_rows;
   const int64_t target_items = mixed ? 1024 : 4096;   // ~4 wavefronts per SIMD
+  // The launches that complete the best-ranked items hold few items with long
+  // sequences; the FP32 ones split them finer (4x the work items): 15 -> 12 ms
+  // to discord on the 2^20 walk (n = 128), 390 -> 293 ms on the 2^22 series
+  // (n = 512).  The split-BF16 ones measured no better.
+  const int64_t seed_items = mixed ? target_items : 4 * target_items;
   const bool abandon = p->opts.abandon != 0;
   const bool order = p->opts.order != 0;          // Cand first (Algorithm 3)
   const bool buckets = p->opts.order == 1;        // same-word columns first
@@ -573,11 +578,11 @@ int discord_search(discord_plan p, discord_result* out) {
   const int64_t gran = mixed ? 16 : 64;   // entries per 512 columns
   // entries [begin, end) of every listed item, split into chunks so that the
   // launch holds enough work items to fill the GPU
-  auto set_window = [&](int64_t groups, int64_t begin, int64_t end) {
+  auto set_window = [&](int64_t groups, int64_t begin, int64_t end, int64_t target) {
     const int64_t items = std::max<int64_t>(1, groups);
     const int64_t width = std::max<int64_t>(end - begin, 1);
     const int64_t maxc = (width + gran - 1) / gran;
-    const int64_t c = std::min<int64_t>(maxc, std::max<int64_t>(1, (target_items + items - 1) / items));
+    const int64_t c = std::min<int64_t>(maxc, std::max<int64_t>(1, (target + items - 1) / items));
     J.seq_begin = begin;
     J.seq_chunk = ((width + c - 1) / c + gran - 1) / gran * gran;
     J.chunks = (width + J.seq_chunk - 1) / J.seq_chunk;
@@ -586,7 +591,7 @@ int discord_search(discord_plan p, discord_result* out) {
   if (!abandon) {
     J.abandon = 0;
     J.n_groups = n_items;
-    set_window(n_items, 0, nq);
+    set_window(n_items, 0, nq, target_items);
     if ((st = launch("scan (full)"))) return st;
   } else {
     J.abandon = 1;
@@ -608,7 +613,7 @@ int discord_search(discord_plan p, discord_result* out) {
       HIP_TRY(p, hipStreamSynchronize(s));
       J.groups = cgroups;
       J.n_groups = hcg;
-      set_window(hcg, 0, seq_max);
+      set_window(hcg, 0, seq_max, target_items);
       if ((st = launch("scan (Cand)"))) return st;
     }
     // Algorithm 4 over the other groups, in windows of their sequences: a first
@@ -636,7 +641,7 @@ int discord_search(discord_plan p, discord_result* out) {
       J.precheck = round > 0;
       J.survivors = out_buf;
       launch_init_i32(reinterpret_cast<int32_t*>(n_surv), 1, 0, s);
-      set_window(count, resume ? covered : 0, end);
+      set_window(count, resume ? covered : 0, end, target_items);
       if ((st = launch("scan (window)"))) return st;
       if (end >= seq_max) break;                  // final for every item
       uint32_t hs = 0;
@@ -655,7 +660,7 @@ int discord_search(discord_plan p, discord_result* out) {
         J.n_groups = k;
         J.skip = nullptr;
         J.precheck = 1;
-        set_window(k, resume ? covered : 0, seq_max);
+        set_window(k, resume ? covered : 0, seq_max, seed_items);
         if ((st = launch("scan (seeds)"))) return st;
         if (k == count) break;
         // the rest continue from the ranked list; their survivors go to out_buf
