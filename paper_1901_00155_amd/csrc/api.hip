@@ -489,10 +489,11 @@ int discord_search(discord_plan p, discord_result* out) {
   const int64_t n_items = (N + item_rows - 1) / item_rows;
   const int64_t target_items = mixed ? 1024 : 4096;   // ~4 wavefronts per SIMD
   // The launches that complete the best-ranked items hold few items with long
-  // sequences; the FP32 ones split them finer (4x the work items): 15 -> 12 ms
-  // to discord on the 2^20 walk (n = 128), 390 -> 293 ms on the 2^22 series
-  // (n = 512).  The split-BF16 ones measured no better.
-  const int64_t seed_items = mixed ? target_items : 4 * target_items;
+  // sequences, so they are split finer: 4x the work items (FP32), 2x
+  // (split-BF16, which also completes 16 items instead of 8; below).  FP32:
+  // 15 -> 12 ms to discord on the 2^20 walk (n = 128), 390 -> 293 ms on the
+  // 2^22 series (n = 512); split-BF16: 10 -> 8.7 ms and 220 -> 123 ms.
+  const int64_t seed_items = (mixed ? 2 : 4) * target_items;
   const bool abandon = p->opts.abandon != 0;
   const bool order = p->opts.order != 0;          // Cand first (Algorithm 3)
   const bool buckets = p->opts.order == 1;        // same-word columns first
@@ -626,7 +627,7 @@ int discord_search(discord_plan p, discord_result* out) {
     // rows already below the best-so-far leave before any work.
     const bool resume = true;
     const int probe = p->opts.probe_steps > 0 ? p->opts.probe_steps : (near_first ? (mixed ? 4 : 2) : 16);
-    const int64_t seeds = mixed ? 8 : 128;      // items completed first after each ranking
+    const int64_t seeds = mixed ? 16 : 128;     // items completed first after each ranking
     int32_t* in = nullptr;                        // nullptr: all groups
     int32_t* out_buf = J.survivors;
     int32_t* spare = p->at<int32_t>(p->L.survivors2);
