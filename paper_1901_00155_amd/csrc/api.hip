@@ -627,11 +627,14 @@ int discord_search(discord_plan p, discord_result* out) {
     // rows already below the best-so-far leave before any work.
     const bool resume = true;
     const int probe = p->opts.probe_steps > 0 ? p->opts.probe_steps : (near_first ? (mixed ? 4 : 2) : 16);
-    // items completed first after each ranking; split-BF16 items beyond n = 512
-    // are single row blocks, and 64 of them measured best (1.26 -> 1.03 s at
-    // n = 600 and 5.1 -> 3.4 s at n = 1024 on the 10^7-point walk, against 16;
-    // 128 and 256 were slower)
-    const int64_t seeds = mixed ? ((n + 15) / 16 > 32 ? 64 : 16) : 128;
+    // items completed first after each ranking.  Split-BF16 items beyond
+    // n = 512 are single row blocks, and 64 of them measured best (1.26 -> 1.03 s
+    // at n = 600 and 5.1 -> 3.4 s at n = 1024 on the 10^7-point walk, against 16;
+    // 128 and 256 were slower).  FP32 groups: more for longer windows (n = 512 on
+    // the 2^22 series: 296 -> 277 ms with 256; n = 1024 on the 10^7-point walk:
+    // 3.2 -> 2.3 s with 512), 128 below 512 (256 was slower at n = 128).
+    const int64_t seeds = mixed ? ((n + 15) / 16 > 32 ? 64 : 16)
+                                : (n >= 1024 ? 512 : (n >= 512 ? 256 : 128));
     int32_t* in = nullptr;                        // nullptr: all groups
     int32_t* out_buf = J.survivors;
     int32_t* spare = p->at<int32_t>(p->L.survivors2);
