@@ -102,7 +102,8 @@ def roofline(n, precision, pairs, scan_ms, traffic):
     peak = PEAK_FP32_VECTOR_TFLOPS if precision == "fp32" else PEAK_BF16_MFMA_TFLOPS
     return {"bound": "alu" if precision == "fp32" else "mfma", "achieved": achieved,
             "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
-            "kernel": "k_scan_fp32" if precision == "fp32" else "k_scan_mfma",
+            "kernel": ("k_scan_fp32" if precision == "fp32"
+                       else "k_scan_mfma" if n <= 512 else "k_scan_mfma_long"),
             "flops_per_pair": scan_flops_per_pair(n, precision), "scan_ms": scan_ms}
 
 
