@@ -122,7 +122,7 @@ typedef struct discord_plan_s* discord_plan;
 
 /* Device bytes a plan for (m, n, opts) needs.  This is what discord_prepare
  * allocates (workspace == NULL) or requires of a caller workspace.  0 on
- * invalid arguments. */
+ * invalid arguments and on sizes discord_prepare refuses with ERANGE. */
 size_t discord_workspace_bytes(int64_t m, int32_t n, const discord_opts* opts);
 
 /* Preparation stage (Algorithm 2, first six steps).

@@ -323,6 +323,7 @@ size_t discord_workspace_bytes(int64_t m, int32_t n, const discord_opts* opts) {
   if (n >= 1 && o.paa_w >= 1 && o.paa_w <= 8 && o.paa_w > n) o.paa_w = n;
   if (n < 1 || m < 2 * (int64_t)n || !opts_valid(n, o)) return 0;
   if (m > (int64_t)INT32_MAX - kBackPad - kFrontPad) return 0;
+  if (o.precision == DISCORD_PREC_BF16X3 && n > kMixedMaxN) return 0;
   return make_layout(m, n, dict_size(o), o.precision == DISCORD_PREC_BF16X3, o.znorm != 0).total;
 }
 

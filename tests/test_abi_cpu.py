@@ -134,3 +134,19 @@ def test_cu_mask_rejects_bad_sizes(dd):
     for args in [(256, 8, 0), (256, 8, 12), (256, 8, 264), (256, 0, 8), (250, 8, 8), (0, 1, 1)]:
         with pytest.raises(dd.DiscordError):
             dd.cu_mask(*args)
+
+
+@pytest.mark.parametrize("m,n", [(4096, 64), (50000, 512), (50000, 600), (100000, 2048)])
+def test_split_bf16_workspace_holds_the_split_matrix(dd, m, n):
+    """A split-BF16 plan holds the split subsequence matrix: ceil(N/32) + 1
+    blocks of ceil(n/16) + 1 K-steps of 2 KiB (hi and lo, or the norm step's
+    two operand forms), on top of the FP32 plan; windows up to
+    DISCORD_MIXED_MAX_N are accepted and longer ones refused."""
+    N = m - n + 1
+    split = (-(-N // 32) + 1) * (-(-n // 16) + 1) * 2048
+    f32 = dd.workspace_bytes(m, n)
+    b16 = dd.workspace_bytes(m, n, precision="bf16x3")
+    assert f32 > 0 and b16 >= f32 + split
+    assert b16 - f32 < split + 64 * N + (1 << 20)     # nothing else of that size
+    assert dd.workspace_bytes(2 * (dd.MIXED_MAX_N + 1), dd.MIXED_MAX_N + 1,
+                              precision="bf16x3") == 0
