@@ -37,7 +37,9 @@
 extern "C" {
 #endif
 
-#define DISCORD_ABI_VERSION 1
+/* 2: discord_opts lost its unused `topk` field (the certification rescores
+ * every row's witness in FP64 instead of the k best candidates of some rows). */
+#define DISCORD_ABI_VERSION 2
 
 /* ---- status codes ------------------------------------------------------- */
 #define DISCORD_OK        0
@@ -67,11 +69,6 @@ typedef struct {
                            2: Cand rows first, then each row's columns nearest in
                               time first, alternating forward and backward
                            0: matrix order only                                    */
-    int32_t topk;       /* 1..32, validated but unused: instead of rescoring the k
-                           best approximate candidates of finalist rows, the FP64
-                           certification rescores every row's best candidate (its
-                           witness) and rescans in full every row that test cannot
-                           clear (see discord_search)                              */
     int32_t paa_w;      /* PAA segments w of eq. (3) (1..8; min(w, n) is used)       */
     int32_t alphabet;   /* SAX alphabet size |A| of eq. (4) (2..8, |A|^w <= 256)      */
     int32_t probe_steps;/* abandon mode: the first window of every row's column
@@ -92,8 +89,12 @@ typedef struct {
 } discord_opts;
 
 /* Defaults: FP32, abandon on, order 2 (Cand first, then near-first columns),
- * topk 16, w = |A| = 4 (section 3.1). */
+ * w = |A| = 4 (section 3.1). */
 void discord_default_opts(discord_opts* opts);
+
+/* DISCORD_ABI_VERSION of the library actually loaded (a binding checks it
+ * against the header it was written for). */
+int32_t discord_abi_version(void);
 
 /* ---- result -------------------------------------------------------------- */
 typedef struct {

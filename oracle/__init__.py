@@ -14,8 +14,8 @@ Contents (each function cites the passage of the paper it follows):
   ``sax_words``        eqs. (3), (4), (9): PAA -> SAX -> word id per row (C)
   ``np_discord``       independent NumPy brute force (all pairs at once)
   ``int_discord``      exact-integer enumerator in pure Python ints
-  ``alg1``             Algorithm 1 (DiscordDiscovery) with any visiting order
-  ``phidd``            Algorithms 2-4 (PhiDD: PotentialDiscord + RefineDiscord)
+  ``alg1``             abandoning search (Algorithm 1) with any visiting order
+  ``phidd``            the same search in PhiDD's visiting orders (Algorithms 2-4)
   ``breakpoints``, ``freq_cand``, ``index_word``   SAX helpers of section 3.1
 """
 from .oracle import *  # noqa: F401,F403

@@ -144,6 +144,36 @@ static int row_nn(const float *T, int64_t m, int32_t n, int64_t i, double *dout,
     return bj >= 0;
 }
 
+/* The same minimum for one row with its columns shared among threads: each
+ * thread scans a contiguous ascending range of j and keeps its first minimum;
+ * merging takes the smallest distance and, among equal ones, the lowest j, so
+ * the result is the sequential loop's.  Used where a single row of a long
+ * series is asked for. */
+static int row_nn_cols(const float *T, int64_t m, int32_t n, int64_t i, double *dout,
+                       int64_t *jout, const double *zmu, const double *zsg, int threads)
+{
+    int64_t N = m - n + 1;
+    double best = INFINITY;
+    int64_t bj = -1;
+    if (threads < 1) threads = 1;
+#pragma omp parallel num_threads(threads)
+    {
+        double lb = INFINITY;
+        int64_t lj = -1;
+#pragma omp for schedule(static)
+        for (int64_t j = 0; j < N; ++j) {
+            if (llabs(i - j) < n) continue;
+            double d = pair_any(T, m, n, i, j, zmu, zsg);
+            if (d < lb) { lb = d; lj = j; }
+        }
+#pragma omp critical
+        if (lj >= 0 && (bj < 0 || lb < best || (lb == best && lj < bj))) { best = lb; bj = lj; }
+    }
+    *dout = best;
+    *jout = bj;
+    return bj >= 0;
+}
+
 /* Window statistics for the *_z entry points (NULL on allocation failure). */
 static int zstats_alloc(const float *T, int64_t m, int32_t n, double **mu, double **sg)
 {
@@ -160,6 +190,11 @@ static int rows_nn_any(const float *T, int64_t m, int32_t n, const int64_t *rows
                        const double *zsg)
 {
     if (threads < 1) threads = 1;
+    if (count < threads) {   /* few rows: share each row's columns instead */
+        for (int64_t r = 0; r < count; ++r)
+            row_nn_cols(T, m, n, rows[r], &nn_d2[r], &nn_j[r], zmu, zsg, threads);
+        return ORC_OK;
+    }
 #pragma omp parallel for schedule(dynamic, 1) num_threads(threads)
     for (int64_t r = 0; r < count; ++r)
         row_nn(T, m, n, rows[r], &nn_d2[r], &nn_j[r], zmu, zsg);
@@ -254,7 +289,7 @@ static int64_t witness_any(const float *T, int64_t m, int32_t n, int64_t idx, co
     int64_t N = m - n + 1;
     if (idx < 0 || idx >= N) return ORC_EINVAL;
     double dd; int64_t jj;
-    if (!row_nn(T, m, n, idx, &dd, &jj, zmu, zsg)) return ORC_EINVAL;
+    if (!row_nn_cols(T, m, n, idx, &dd, &jj, zmu, zsg, threads)) return ORC_EINVAL;
     *nn_of_idx = dd;
     /* part (ii) is checked against the exact NN of idx; the caller compares its
        claimed distance with *nn_of_idx */

@@ -437,100 +437,83 @@ def int_discord(values, n: int):
     return best_i, pj[best_i], prof[best_i], prof
 
 
-def _d2_seq(t, n, i, j):
-    """eq. (1) squared, sequential Python-float sum (same order as the C code)."""
-    s = 0.0
-    for k in range(n):
-        d = t[i + k] - t[j + k]
-        s = s + d * d
-    return s
+def _pair_table(T, n: int) -> np.ndarray:
+    """Squared distance of eq. (1) for every pair of windows, FP64.  np.cumsum
+    adds strictly left to right, so its last entry is the sequential sum over
+    k = 0..n-1, the value the C brute force computes (small inputs only:
+    N x N x n doubles)."""
+    t = np.asarray(T, dtype=np.float32).astype(np.float64)
+    W = np.lib.stride_tricks.sliding_window_view(t, n)
+    diff = W[:, None, :] - W[None, :, :]
+    return np.cumsum(diff * diff, axis=2)[:, :, -1]
 
 
-def _better(mn, i, bsf, pos):
-    """Lowest-index tie rule applied to Algorithm 1's bsf update."""
-    return pos < 0 or mn > bsf or (mn == bsf and i < pos)
+def _pruned_search(D, n: int, outer, inner):
+    """Exact discord search with early abandon, over a table of all squared
+    distances (section 2.2).  A row's non-self columns are taken in the order
+    ``inner(i)``; the row is abandoned at the first distance strictly below
+    the best-so-far (it cannot be the discord, since its NN is smaller still),
+    so the distances evaluated for it are those up to and including that one.
+    A row that is not abandoned has its NN as the minimum over all of them and
+    replaces the best-so-far when larger (lowest index on equal values).  The
+    best-so-far starts at 0 with no position.  Returns (index, d2, evaluated)."""
+    N = D.shape[0]
+    bsf, pos, evals = 0.0, -1, 0
+    for i in outer:
+        i = int(i)
+        cols = np.array([int(j) for j in inner(i) if abs(i - int(j)) >= n], dtype=np.int64)
+        if cols.size == 0:
+            continue                                   # no non-self match: no NN
+        d = D[i, cols]
+        below = np.flatnonzero(d < bsf)
+        if below.size:
+            evals += int(below[0]) + 1
+            continue
+        evals += cols.size
+        nn = float(d.min())
+        if pos < 0 or nn > bsf or (nn == bsf and i < pos):
+            bsf, pos = nn, i
+    return pos, bsf, evals
 
 
 def alg1(T, n: int, outer=None, inner=None, count: list | None = None):
-    """Algorithm 1 (HOTSAX DiscordDiscovery, section 2.2) on raw values with
-    squared distances: for each row i in the ``outer`` order scan the non-self j
-    in the ``inner(i)`` order, leave the row as soon as a distance below the
-    best-so-far appears, otherwise update the best-so-far with the row's NN.
-    Returns (index, d2).  ``count`` (a one-element list) receives the number of
-    distances evaluated."""
-    t = [float(v) for v in np.asarray(T, dtype=np.float32)]
-    m = len(t)
-    N = m - n + 1
+    """HOTSAX discord search (Algorithm 1, section 2.2) for any visiting order:
+    rows in the ``outer`` order, each row's columns in the ``inner(i)`` order
+    (matrix order by default), early abandon against the best-so-far, squared
+    distances on raw values.  Returns (index, d2); ``count`` (a one-element
+    list) receives the number of distances evaluated."""
+    D = _pair_table(T, n)
+    N = D.shape[0]
     outer = range(N) if outer is None else outer
-    bsf, pos, evals = 0.0, -1, 0
-    for i in outer:
-        mn = math.inf
-        abandoned = False
-        for j in (inner(i) if inner else range(N)):
-            if abs(i - j) < n:
-                continue
-            d = _d2_seq(t, n, i, j)
-            evals += 1
-            if d < bsf:
-                abandoned = True
-                break
-            if d < mn:
-                mn = d
-        if abandoned or mn == math.inf:
-            continue
-        if _better(mn, i, bsf, pos):
-            bsf, pos = mn, i
+    pos, bsf, evals = _pruned_search(D, n, outer, inner if inner else (lambda i: range(N)))
     if count is not None:
         count.append(evals)
     return pos, bsf
 
 
 def phidd(T, n: int, w: int = 4, alpha: int = 4, count: list | None = None):
-    """Algorithms 2-4 (PhiDD, section 3.2), sequential, on raw values.
-    Preparation: SAX words, Cand (eq. 7), Index_Word (eq. 10).  Search:
-    PotentialDiscord over Cand, then RefineDiscord over the other rows; each row
-    scans its own word's members first (Index_Word order), then every other row
-    in matrix order, leaving the row on a distance below the best-so-far.
+    """PhiDD (Algorithms 2-4, section 3.2), sequential, on raw values.  The
+    preparation gives SAX words, Cand (eq. 7) and Index_Word (eq. 10); the
+    method is then the abandoning search above with PhiDD's visiting orders:
+    rows of Cand first (PotentialDiscord), then every other row
+    (RefineDiscord); each row's columns start with the members of its own word
+    (Index_Word) and continue with every other column in matrix order.
     Returns (index, d2)."""
-    t = [float(v) for v in np.asarray(T, dtype=np.float32)]
-    m = len(t)
-    N = m - n + 1
+    D = _pair_table(T, n)
+    N = D.shape[0]
     words = sax_words(T, n, w, alpha)
     hist, cand = freq_cand(words, alpha ** w)
     offsets, members = index_word(words, alpha ** w)
-    bsf, pos, evals = 0.0, -1, 0
-
-    def scan(i):
-        nonlocal evals
-        wd = words[i]
-        bucket = members[offsets[wd]:offsets[wd + 1]]
-        mn = math.inf
-        for j in bucket:                      # same-word subsequences first
-            if abs(i - j) < n:
-                continue
-            d = _d2_seq(t, n, i, int(j))
-            evals += 1
-            if d < bsf:
-                return None
-            mn = min(mn, d)
-        for j in range(N):                    # then the rest, matrix order
-            if words[j] == wd or abs(i - j) < n:
-                continue
-            d = _d2_seq(t, n, i, j)
-            evals += 1
-            if d < bsf:
-                return None
-            mn = min(mn, d)
-        return mn
-
     in_cand = np.zeros(N, dtype=bool)
     in_cand[cand] = True
-    for i in list(cand) + [r for r in range(N) if not in_cand[r]]:
-        mn = scan(int(i))
-        if mn is None or mn == math.inf:
-            continue
-        if _better(mn, int(i), bsf, pos):
-            bsf, pos = mn, int(i)
+    outer = np.concatenate([cand, np.flatnonzero(~in_cand)])
+
+    def inner(i):
+        wd = words[i]
+        same = members[offsets[wd]:offsets[wd + 1]]
+        return np.concatenate([same, np.flatnonzero(words != wd)])
+
+    pos, bsf, evals = _pruned_search(D, n, outer, inner)
     if count is not None:
         count.append(evals)
     return pos, bsf

@@ -15,7 +15,7 @@ import numpy as np
 __all__ = [
     "load", "DiscordError", "Opts", "Result", "Plan", "search", "default_opts",
     "workspace_bytes", "strerror", "sax_breakpoints", "search_series",
-    "FIELD", "PREC_FP32", "PREC_BF16X3", "MIXED_MAX_N", "LIB_PATH", "EXPORTED", "Server",
+    "FIELD", "PREC_FP32", "PREC_BF16X3", "MIXED_MAX_N", "ABI_VERSION", "LIB_PATH", "EXPORTED", "Server",
     "ServerConfig", "cu_mask", "CULimitedStream",
     "Request", "Completion", "ServerStats", "EXECUTOR_FN",
 ]
@@ -26,6 +26,7 @@ LIB_PATH = os.path.join(_HERE, "lib", "libdiscord.so")
 PREC_FP32 = 0
 PREC_BF16X3 = 1
 MIXED_MAX_N = 2048  # DISCORD_MIXED_MAX_N: longest window of the split-BF16 scan
+ABI_VERSION = 2     # DISCORD_ABI_VERSION of the header these structures mirror
 _PREC = {"fp32": PREC_FP32, "bf16x3": PREC_BF16X3, PREC_FP32: PREC_FP32, PREC_BF16X3: PREC_BF16X3}
 
 FIELD = {
@@ -37,7 +38,7 @@ FIELD = {
 
 # every symbol the public header declares (checked by the CPU tests)
 EXPORTED = [
-    "discord_default_opts", "discord_workspace_bytes", "discord_prepare", "discord_search",
+    "discord_default_opts", "discord_abi_version", "discord_workspace_bytes", "discord_prepare", "discord_search",
     "discord_release", "discord_strerror", "discord_plan_error", "discord_sax_breakpoints",
     "discord_search_series", "discord_plan_count", "discord_plan_copy", "discord_rows_nn_fp64",
     "discord_server_create", "discord_server_create_with_executor", "discord_server_submit",
@@ -54,8 +55,7 @@ class DiscordError(RuntimeError):
 
 class Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("abandon", ctypes.c_int32),
-                ("order", ctypes.c_int32), ("topk", ctypes.c_int32),
-                ("paa_w", ctypes.c_int32), ("alphabet", ctypes.c_int32),
+                ("order", ctypes.c_int32), ("paa_w", ctypes.c_int32), ("alphabet", ctypes.c_int32),
                 ("probe_steps", ctypes.c_int32), ("znorm", ctypes.c_int32)]
 
 
@@ -131,6 +131,12 @@ def load():
                            "(there is no CPU fallback)")
     lib = ctypes.CDLL(LIB_PATH)
     vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+    lib.discord_abi_version.argtypes = []
+    lib.discord_abi_version.restype = i32
+    got = lib.discord_abi_version()
+    if got != ABI_VERSION:
+        raise RuntimeError(f"{LIB_PATH} has ABI version {got}, this binding expects "
+                           f"{ABI_VERSION}: rebuild it with __graft_entry__.build()")
     lib.discord_default_opts.argtypes = [ctypes.POINTER(Opts)]
     lib.discord_default_opts.restype = None
     lib.discord_workspace_bytes.argtypes = [i64, i32, ctypes.POINTER(Opts)]
@@ -269,12 +275,12 @@ class CULimitedStream:
 class Plan:
     """A prepared series (discord_prepare) that can be searched repeatedly."""
 
-    def __init__(self, T, n: int, precision="fp32", abandon=True, order=2, topk=16,
+    def __init__(self, T, n: int, precision="fp32", abandon=True, order=2,
                  paa_w=4, alphabet=4, probe_steps=0, znorm=False, stream=None,
                  torch_workspace=False):
         lib = load()
         self.opts = default_opts(precision=precision, abandon=int(bool(abandon)),
-                                 order=int(order), topk=topk, paa_w=paa_w,
+                                 order=int(order), paa_w=paa_w,
                                  alphabet=alphabet, probe_steps=probe_steps,
                                  znorm=int(bool(znorm)))
         ptr, m, self._keep, tstream = _series_ptr(T)

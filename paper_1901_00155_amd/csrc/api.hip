@@ -143,7 +143,6 @@ bool opts_valid(int32_t n, const discord_opts& o) {
   if (o.abandon != 0 && o.abandon != 1) return false;
   if (o.order < 0 || o.order > 2) return false;
   if (o.znorm != 0 && o.znorm != 1) return false;
-  if (o.topk < 1 || o.topk > 32) return false;
   (void)n;
   if (o.paa_w < 1 || o.paa_w > 8) return false;
   if (o.alphabet < 2 || o.alphabet > 8) return false;
@@ -295,10 +294,11 @@ void discord_default_opts(discord_opts* o) {
   o->precision = DISCORD_PREC_FP32;
   o->abandon = 1;
   o->order = 2;
-  o->topk = 16;
   o->paa_w = 4;
   o->alphabet = 4;
 }
+
+int32_t discord_abi_version(void) { return DISCORD_ABI_VERSION; }
 
 const char* discord_strerror(int status) {
   switch (status) {

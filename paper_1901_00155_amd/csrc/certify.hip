@@ -4,7 +4,9 @@
 //
 // Why this is exact.  Let L be the exact NN (squared) of some row s.  Every row
 // i carries a witness w(i), a non-self column found by the approximate scan
-// (its approximate argmin, or the column that made it leave early).  Its NN is
+// (its approximate argmin, or the column that made it leave early).  The
+// verification checks that w(i) is a column of the matrix and a non-self match
+// (|i - w(i)| >= n) itself, so it does not trust the scans' masks.  Its NN is
 // at most e(i) = d^2(i, w(i)) computed exactly here.  If e(i) < L, or e(i) = L
 // and i > s, row i cannot be the discord under the lowest-index rule.  The rows
 // that fail this test get their exact NN by a full FP64 row scan, and the final
@@ -291,7 +293,11 @@ __global__ __launch_bounds__(256) void k_verify(const float* __restrict__ T, int
     if (i == s || !has_non_self(i, N, n)) continue;
     const int32_t w = nn_witness[i];
     bool ok = false;
-    if (w >= 0 && s >= 0) {
+    // a witness clears its row only if it is a column of the matrix and a
+    // non-self match of the row (|i - w| >= n); anything else sends the row to
+    // the exact rescan, so the certificate does not rest on the scans' masks
+    const int64_t gap = i > (int64_t)w ? i - (int64_t)w : (int64_t)w - i;
+    if (w >= 0 && (int64_t)w < N && gap >= n && s >= 0) {
       const double e = pair_d2<Z>(T, i, w, n, z);
       ok = (e < L) || (e == L && i > s);
       if (e > 0.0) rel = fmaxf(rel, (float)(fabs((double)nn_approx[i] - e) / e));

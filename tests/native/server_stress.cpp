@@ -90,7 +90,6 @@ int main() {
   cfg.opts.precision = DISCORD_PREC_FP32;
   cfg.opts.abandon = 1;
   cfg.opts.order = 1;
-  cfg.opts.topk = 16;
   cfg.opts.paa_w = 4;
   cfg.opts.alphabet = 4;
   discord_server s = nullptr;

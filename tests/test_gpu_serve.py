@@ -70,6 +70,36 @@ def test_mix_matches_oracle_on_short_series(gpu, precision):
         assert got["distance"] == pytest.approx(ref["distance"], rel=1e-9, abs=0)
 
 
+@pytest.mark.parametrize("precision", PRECS)
+def test_mix_certified_by_oracle_on_long_series(gpu, precision):
+    """Served requests of 2^13 < m <= 2^18 samples, too long for the oracle's
+    brute force: each result from the mix equals the same request run alone on
+    a plan, and the witness array of that run is the oracle's FP64 certificate
+    of the (index, d2) the server returned; the neighbour is the oracle's exact
+    argmin of that row."""
+    dd = gpu
+    reqs = [r for r in workloads.serve_requests(seed=31, count=400, rate_hz=200.0, log2_min=12,
+                                                log2_max=18) if r.series.size > 1 << 13][:16]
+    assert len(reqs) == 16 and max(r.series.size for r in reqs) > 1 << 16
+    with dd.Server(8 << 30, slots=4, precision=precision) as s:
+        for r in reqs:
+            assert s.submit(r.series, r.n, r.tag) == 0
+        mix = _drain(s, len(reqs))
+    for r in reqs:
+        c = mix[r.tag]
+        assert c["status"] == 0, c["detail"]
+        got = c["result"]
+        with dd.Plan(r.series, r.n, precision=precision) as p:
+            a = p.search()
+            wit = p.copy("nn_witness")
+        assert (a.index, a.nn_index, a.d2) == (got["index"], got["nn_index"], got["d2"]), r.tag
+        bad, first, nn = oracle.witness_check(r.series, r.n, got["index"], got["d2"], wit)
+        assert bad == 0, (r.tag, first)
+        assert got["d2"] == pytest.approx(nn, rel=1e-9, abs=0)
+        d, j = oracle.rows_nn(r.series, r.n, [got["index"]])
+        assert j[0] == got["nn_index"] and d[0] == nn
+
+
 def test_failing_requests_do_not_disturb_the_mix(gpu):
     dd = gpu
     reqs = _requests(count=8, seed=11, log2_max=14)

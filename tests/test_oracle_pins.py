@@ -52,6 +52,36 @@ def test_exhaustive_integer_enumeration(seed):
         assert npo["index"] == i_idx and npo["d2"] == float(i_d2)
 
 
+@pytest.mark.parametrize("seed", range(6))
+def test_rows_nn_exhaustive_integer(seed):
+    """The C oracle's exact nearest non-self match of chosen rows (the rescan it
+    and the certificate use) against exact integer enumeration: for every row
+    of tiny integer series, the minimum squared distance and its lowest column,
+    with rows shared among threads and with one row's columns shared."""
+    rng = np.random.default_rng(150 + seed)
+    m = int(rng.integers(10, 40))
+    T = _rand_int_series(rng, m, -5, 6)
+    v = T.astype(int).tolist()
+    for n in range(1, m // 2 + 1):
+        N = m - n + 1
+        rows = np.arange(N, dtype=np.int64)
+        d, j = oracle.rows_nn(T, n, rows, threads=2)
+        # one row at a time with more threads than rows: the columns are shared
+        d1, j1 = zip(*(oracle.rows_nn(T, n, [i], threads=3) for i in range(N)))
+        assert np.array_equal(np.concatenate(d1), d) and np.array_equal(np.concatenate(j1), j)
+        for i in range(N):
+            best, arg = None, -1
+            for c in range(N):
+                if abs(i - c) < n:
+                    continue
+                e = sum((v[i + k] - v[c + k]) ** 2 for k in range(n))
+                if best is None or e < best:
+                    best, arg = e, c
+            assert j[i] == arg, (m, n, i)
+            if arg >= 0:
+                assert d[i] == float(best), (m, n, i)
+
+
 # --------------------------------------------------------------------------- P2
 @pytest.mark.parametrize("seed", range(6))
 def test_window_one_reduces_to_sorting(seed):

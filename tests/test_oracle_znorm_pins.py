@@ -209,13 +209,16 @@ def test_z_sax_words(n, w, alpha):
     X = np.where(sd > 0, (W - mu) / np.where(sd > 0, sd, 1.0), 0.0)
     bp = oracle.breakpoints(alpha)
     code = np.zeros(X.shape[0], dtype=np.int64)
+    near = np.zeros(X.shape[0], dtype=bool)     # some PAA value within 1e-12 of a breakpoint
     for s in range(w):
         a, b = (s * n) // w, ((s + 1) * n) // w
         paa = X[:, a:b].sum(axis=1) / (b - a)
         code = code * alpha + np.searchsorted(bp, paa, side="right")
-    # rounding can move a PAA value across a breakpoint only within ~1e-15
+        near |= np.min(np.abs(paa[:, None] - bp[None, :]), axis=1) <= 1e-12
+    # the two sums round differently, which can move a PAA value across a
+    # breakpoint only when it lies within rounding distance of it
     diff = np.flatnonzero(words != code)
-    assert diff.size <= 2, diff
+    assert np.all(near[diff]), diff[~near[diff]]
     mid = sum((alpha // 2) * alpha ** (w - 1 - s) for s in range(w))
     assert words[400] == mid
 
