@@ -157,7 +157,8 @@ void discord_release(discord_plan plan);
 const char* discord_strerror(int status);
 
 /* Detail of the last error on this plan ("" if none).  With plan == NULL: the
- * detail of the calling thread's last failed discord_prepare. */
+ * detail of the calling thread's last failed discord_prepare or
+ * discord_search_series_noalloc. */
 const char* discord_plan_error(discord_plan plan);
 
 /* The inner breakpoints beta_1..beta_{alpha-1} of eq. (4) (N(0,1) quantiles
@@ -168,6 +169,29 @@ int discord_sax_breakpoints(int32_t alpha, double* out);
 /* One-shot: prepare + search with default options on a library stream. */
 int discord_search_series(const float* T, int64_t m, int32_t n, int64_t* index,
                           double* distance);
+
+/* For callers that cannot allocate (code under stream capture, tight serving
+ * loops, hosts that forbid allocation): prepare + search of one series, the
+ * same computation and result as discord_prepare + discord_search with `opts`,
+ * with no device allocation, no stream or event creation and no heap plan.
+ * The plan lives in a static device array of DISCORD_NOALLOC_MAX_BYTES that
+ * each GPU the library runs on holds until the process ends; its address is
+ * taken once per device on the first call there.
+ *   T       m float32 values, host or device pointer (a host series goes
+ *           through the runtime's own copy).
+ *   opts    NULL for defaults.
+ *   stream  hipStream_t to run on (NULL: the null stream); synchronised before
+ *           the call returns.
+ *   out     receives the result; ms_prepare / ms_search / ms_scan are 0 (no
+ *           events are taken).
+ * Errors: those of discord_prepare / discord_search, and ERANGE when the plan
+ * (discord_workspace_bytes(m, n, opts)) is larger than the array; the text is
+ * in discord_plan_error(NULL).  Calls on one GPU share its array: calls that
+ * overlap on the same GPU race (serialise them). */
+#define DISCORD_NOALLOC_MAX_BYTES ((size_t)32 << 20)
+int discord_search_series_noalloc(const float* T, int64_t m, int32_t n,
+                                  const discord_opts* opts, void* stream,
+                                  discord_result* out);
 
 /* ---- introspection of the prepared and searched state (for verification) -- */
 typedef enum {

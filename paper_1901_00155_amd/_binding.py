@@ -15,6 +15,7 @@ import numpy as np
 __all__ = [
     "load", "DiscordError", "Opts", "Result", "Plan", "search", "default_opts",
     "workspace_bytes", "strerror", "sax_breakpoints", "search_series",
+    "search_series_noalloc", "NOALLOC_MAX_BYTES",
     "FIELD", "PREC_FP32", "PREC_BF16X3", "MIXED_MAX_N", "ABI_VERSION", "LIB_PATH", "EXPORTED", "Server",
     "ServerConfig", "cu_mask", "CULimitedStream",
     "Request", "Completion", "ServerStats", "EXECUTOR_FN",
@@ -27,6 +28,7 @@ PREC_FP32 = 0
 PREC_BF16X3 = 1
 MIXED_MAX_N = 2048  # DISCORD_MIXED_MAX_N: longest window of the split-BF16 scan
 ABI_VERSION = 2     # DISCORD_ABI_VERSION of the header these structures mirror
+NOALLOC_MAX_BYTES = 32 << 20  # DISCORD_NOALLOC_MAX_BYTES: static workspace per device
 _PREC = {"fp32": PREC_FP32, "bf16x3": PREC_BF16X3, PREC_FP32: PREC_FP32, PREC_BF16X3: PREC_BF16X3}
 
 FIELD = {
@@ -40,7 +42,7 @@ FIELD = {
 EXPORTED = [
     "discord_default_opts", "discord_abi_version", "discord_workspace_bytes", "discord_prepare", "discord_search",
     "discord_release", "discord_strerror", "discord_plan_error", "discord_sax_breakpoints",
-    "discord_search_series", "discord_plan_count", "discord_plan_copy", "discord_rows_nn_fp64",
+    "discord_search_series", "discord_search_series_noalloc", "discord_plan_count", "discord_plan_copy", "discord_rows_nn_fp64",
     "discord_server_create", "discord_server_create_with_executor", "discord_server_submit",
     "discord_server_poll", "discord_server_get_stats", "discord_server_destroy",
     "discord_cu_mask", "discord_stream_create_cu_limited", "discord_stream_destroy",
@@ -157,6 +159,9 @@ def load():
     lib.discord_search_series.argtypes = [vp, i64, i32, ctypes.POINTER(i64),
                                           ctypes.POINTER(ctypes.c_double)]
     lib.discord_search_series.restype = ctypes.c_int
+    lib.discord_search_series_noalloc.argtypes = [vp, i64, i32, ctypes.POINTER(Opts), vp,
+                                                  ctypes.POINTER(Result)]
+    lib.discord_search_series_noalloc.restype = ctypes.c_int
     lib.discord_plan_count.argtypes = [vp, i32]
     lib.discord_plan_count.restype = i64
     lib.discord_plan_copy.argtypes = [vp, i32, vp, ctypes.c_size_t]
@@ -368,6 +373,26 @@ def search_series(T, n: int):
     _check(load().discord_search_series(ctypes.c_void_p(ptr), m, n, ctypes.byref(idx),
                                         ctypes.byref(dist)))
     return int(idx.value), float(dist.value)
+
+
+def search_series_noalloc(T, n: int, stream=None, **opts) -> Result:
+    """discord_search_series_noalloc: prepare + search in the library's static
+    device workspace (no allocation; plans up to NOALLOC_MAX_BYTES)."""
+    ptr, m, keep, tstream = _series_ptr(T)
+    if stream is None:
+        stream = tstream
+    elif hasattr(stream, "cuda_stream"):
+        stream = stream.cuda_stream
+    elif isinstance(stream, CULimitedStream):
+        stream = stream.handle
+    o = default_opts(**opts)
+    r = Result()
+    st = load().discord_search_series_noalloc(ctypes.c_void_p(ptr), m, n, ctypes.byref(o),
+                                              ctypes.c_void_p(stream), ctypes.byref(r))
+    if st != 0:
+        detail = load().discord_plan_error(None).decode()
+        raise DiscordError(st, strerror(st) + (f": {detail}" if detail else ""))
+    return r
 
 
 class Server:

@@ -178,6 +178,7 @@ struct discord_plan_s {
   int64_t max_bucket = 0;     // longest word bucket, in scan column blocks
   double ms_prepare = 0.0;
   bool searched = false;
+  bool timed = true;          // false: no HIP events (the allocation-free entry point)
   char err[512] = {0};
 
   template <class P>
@@ -265,10 +266,21 @@ float elapsed_ms(hipEvent_t a, hipEvent_t b) {
   return t;
 }
 
+// on = false: no events are taken (a plan that must not create runtime
+// objects); recording is then a no-op and the time reads 0
 struct EventPair {
   hipEvent_t a = nullptr, b = nullptr;
-  explicit EventPair(size_t slot) : a(g_events.get(2 * slot)), b(g_events.get(2 * slot + 1)) {}
-  float ms() const { return elapsed_ms(a, b); }
+  bool on = true;
+  explicit EventPair(size_t slot, bool use = true) : on(use) {
+    if (on) {
+      a = g_events.get(2 * slot);
+      b = g_events.get(2 * slot + 1);
+    }
+  }
+  bool ready() const { return !on || (a && b); }
+  hipError_t start(hipStream_t s) const { return on ? hipEventRecord(a, s) : hipSuccess; }
+  hipError_t stop(hipStream_t s) const { return on ? hipEventRecord(b, s) : hipSuccess; }
+  float ms() const { return on ? elapsed_ms(a, b) : 0.f; }
 };
 
 ZStats zstats(discord_plan p) {
@@ -315,6 +327,17 @@ const char* discord_strerror(int status) {
 
 static thread_local char g_prepare_err[512];
 
+}  // extern "C"
+
+void dd::set_thread_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_prepare_err, sizeof(g_prepare_err), fmt, ap);
+  va_end(ap);
+}
+
+extern "C" {
+
 const char* discord_plan_error(discord_plan p) { return p ? p->err : g_prepare_err; }
 
 size_t discord_workspace_bytes(int64_t m, int32_t n, const discord_opts* opts) {
@@ -327,55 +350,40 @@ size_t discord_workspace_bytes(int64_t m, int32_t n, const discord_opts* opts) {
   return make_layout(m, n, dict_size(o), o.precision == DISCORD_PREC_BF16X3, o.znorm != 0).total;
 }
 
-int discord_prepare(const float* T, int64_t m, int32_t n, const discord_opts* opts, void* workspace,
-                    size_t ws_bytes, void* stream, discord_plan* out) {
-  if (!out) return DISCORD_EINVAL;
-  *out = nullptr;
-  discord_opts o;
-  if (opts) o = *opts; else discord_default_opts(&o);
-  if (o.paa_w >= 1 && o.paa_w <= 8 && o.paa_w > n) o.paa_w = n;   // eq. (3) needs w <= n
-  g_prepare_err[0] = 0;
-  if (!T || n < 1 || m < 2 * (int64_t)n || !opts_valid(n, o)) return DISCORD_EINVAL;
-  if (m > (int64_t)INT32_MAX - kBackPad - kFrontPad) return DISCORD_ERANGE;
-  if (o.precision == DISCORD_PREC_BF16X3 && n > kMixedMaxN) return DISCORD_ERANGE;
+}  // extern "C"
 
-  discord_plan p = new (std::nothrow) discord_plan_s();
-  if (!p) return DISCORD_ENOMEM;
+namespace {
+
+// Validates the arguments of a preparation; *o receives the options in use.
+int check_prepare_args(const float* T, int64_t m, int32_t n, const discord_opts* opts,
+                       discord_opts* o) {
+  if (opts) *o = *opts; else discord_default_opts(o);
+  if (o->paa_w >= 1 && o->paa_w <= 8 && o->paa_w > n) o->paa_w = n;   // eq. (3) needs w <= n
+  if (!T || n < 1 || m < 2 * (int64_t)n || !opts_valid(n, *o)) return DISCORD_EINVAL;
+  if (m > (int64_t)INT32_MAX - kBackPad - kFrontPad) return DISCORD_ERANGE;
+  if (o->precision == DISCORD_PREC_BF16X3 && n > kMixedMaxN) return DISCORD_ERANGE;
+  return DISCORD_OK;
+}
+
+void init_plan(discord_plan p, int64_t m, int32_t n, const discord_opts& o) {
   p->m = m;
   p->n = n;
   p->N = m - n + 1;
   p->opts = o;
   p->dict = dict_size(o);
   p->L = make_layout(m, n, p->dict, o.precision == DISCORD_PREC_BF16X3, o.znorm != 0);
-  auto bail = [&](int st) {
-    discord_release(p);
-    return st;
-  };
-  if (hipGetDevice(&p->device) != hipSuccess) return bail(DISCORD_EDEVICE);
-  if (stream) {
-    p->stream = (hipStream_t)stream;
-  } else {
-    if (hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking) != hipSuccess)
-      return bail(DISCORD_EDEVICE);
-    p->own_stream = true;
-  }
-  if (workspace) {
-    if (ws_bytes < p->L.total || ((uintptr_t)workspace % kAlign) != 0) return bail(DISCORD_ENOMEM);
-    p->arena = (char*)workspace;
-  } else {
-    if (hipMalloc(&p->arena, p->L.total) != hipSuccess) {
-      (void)hipGetLastError();
-      p->arena = nullptr;
-      return bail(DISCORD_ENOMEM);
-    }
-    p->own_arena = true;
-  }
-  int st = DISCORD_OK;
-  EventPair ev(0);
+}
+
+// The preparation kernels on a plan whose arena and stream are set.
+int prepare_run(discord_plan p, const float* T) {
+  const int64_t m = p->m;
+  const int32_t n = p->n;
+  const discord_opts& o = p->opts;
+  EventPair ev(0, p->timed);
   hipStream_t s = p->stream;
-  auto run = [&]() -> int {
-    if (!ev.a || !ev.b) return fail(p, DISCORD_EDEVICE, "hipEventCreate failed");
-    HIP_TRY(p, hipEventRecord(ev.a, s));
+  {
+    if (!ev.ready()) return fail(p, DISCORD_EDEVICE, "hipEventCreate failed");
+    HIP_TRY(p, ev.start(s));
     // padded series: zero pads, then the values
     float* Tbase = p->at<float>(p->L.T);
     {
@@ -444,14 +452,55 @@ int discord_prepare(const float* T, int64_t m, int32_t n, const discord_opts* op
     int32_t hcm[8] = {0};   // |Cand| at [0], the longest bucket at [4]
     HIP_TRY(p, hipMemcpyAsync(hcm, p->at<int32_t>(p->L.cand_count), sizeof(hcm),
                               hipMemcpyDeviceToHost, s));
-    HIP_TRY(p, hipEventRecord(ev.b, s));
+    HIP_TRY(p, ev.stop(s));
     HIP_TRY(p, hipStreamSynchronize(s));
     p->cand_count = hcm[0];
     p->max_bucket = buckets ? hcm[4] : 0;
     p->ms_prepare = ev.ms();
     return DISCORD_OK;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int discord_prepare(const float* T, int64_t m, int32_t n, const discord_opts* opts, void* workspace,
+                    size_t ws_bytes, void* stream, discord_plan* out) {
+  if (!out) return DISCORD_EINVAL;
+  *out = nullptr;
+  g_prepare_err[0] = 0;
+  discord_opts o;
+  const int bad = check_prepare_args(T, m, n, opts, &o);
+  if (bad != DISCORD_OK) return bad;
+
+  discord_plan p = new (std::nothrow) discord_plan_s();
+  if (!p) return DISCORD_ENOMEM;
+  init_plan(p, m, n, o);
+  auto bail = [&](int st) {
+    discord_release(p);
+    return st;
   };
-  st = run();
+  if (hipGetDevice(&p->device) != hipSuccess) return bail(DISCORD_EDEVICE);
+  if (stream) {
+    p->stream = (hipStream_t)stream;
+  } else {
+    if (hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking) != hipSuccess)
+      return bail(DISCORD_EDEVICE);
+    p->own_stream = true;
+  }
+  if (workspace) {
+    if (ws_bytes < p->L.total || ((uintptr_t)workspace % kAlign) != 0) return bail(DISCORD_ENOMEM);
+    p->arena = (char*)workspace;
+  } else {
+    if (hipMalloc(&p->arena, p->L.total) != hipSuccess) {
+      (void)hipGetLastError();
+      p->arena = nullptr;
+      return bail(DISCORD_ENOMEM);
+    }
+    p->own_arena = true;
+  }
+  const int st = prepare_run(p, T);
   if (st != DISCORD_OK) {
     // keep the message for the caller: copy before release
     std::snprintf(g_prepare_err, sizeof(g_prepare_err), "%s", p->err);
@@ -466,15 +515,15 @@ int discord_search(discord_plan p, discord_result* out) {
   hipStream_t s = p->stream;
   const int64_t N = p->N;
   const int n = p->n;
-  EventPair ev(0);
-  if (!ev.a || !ev.b) return fail(p, DISCORD_EDEVICE, "hipEventCreate failed");
+  EventPair ev(0, p->timed);
+  if (!ev.ready()) return fail(p, DISCORD_EDEVICE, "hipEventCreate failed");
   // scan launches are timed one by one (pairs 1, 2, ...): their sum is ms_scan
   int timed = 0;
   constexpr int kMaxTimed = 256;
   discord_result r;
   std::memset(&r, 0, sizeof(r));
   HIP_TRY(p, hipSetDevice(p->device));
-  HIP_TRY(p, hipEventRecord(ev.a, s));
+  HIP_TRY(p, ev.start(s));
 
   const bool mixed = p->opts.precision == DISCORD_PREC_BF16X3;
   // rows per scan group: 8 (FP32 micro-tile) or 32 (one MFMA tile side)
@@ -558,8 +607,9 @@ int discord_search(discord_plan p, discord_result* out) {
     J.raise_scale = (float)(1.0 - ((n + 3) * std::ldexp(1.0, -24) * 1.01 + std::ldexp(1.0, -22)));
   }
   auto launch = [&](const char* what) -> int {
-    EventPair t(1 + timed);
-    const bool timing = timed < kMaxTimed && t.a && t.b;
+    const bool timing = p->timed && timed < kMaxTimed;
+    EventPair t(1 + timed, timing);
+    if (!t.ready()) return fail(p, DISCORD_EDEVICE, "hipEventCreate failed");
     if (timing) HIP_TRY(p, hipEventRecord(t.a, s));
     if (mixed) {
       if (!launch_scan_mfma(J, R, s)) return fail(p, DISCORD_ERANGE, "window too long for bf16x3");
@@ -723,7 +773,7 @@ int discord_search(discord_plan p, discord_result* out) {
   }
   Exact hex;
   HIP_TRY(p, hipMemcpyAsync(&hex, ex, sizeof(hex), hipMemcpyDeviceToHost, s));
-  HIP_TRY(p, hipEventRecord(ev.b, s));
+  HIP_TRY(p, ev.stop(s));
   HIP_TRY(p, hipStreamSynchronize(s));
   if (hex.i < 0) return fail(p, DISCORD_EDEVICE, "certification produced no discord");
 
@@ -905,3 +955,30 @@ int discord_stream_destroy(void* stream) {
 }
 
 }  // extern "C"
+
+namespace dd {
+
+int search_series_in_arena(const float* T, int64_t m, int32_t n, const discord_opts* opts,
+                           void* arena, size_t arena_bytes, hipStream_t stream,
+                           discord_result* out, char* err, size_t err_len) {
+  if (err && err_len) err[0] = 0;
+  discord_opts o;
+  int st = check_prepare_args(T, m, n, opts, &o);
+  if (st != DISCORD_OK) return st;
+  // the plan lives on this stack frame: no heap object, no stream, no event
+  discord_plan_s plan;
+  discord_plan p = &plan;
+  init_plan(p, m, n, o);
+  if (!arena || p->L.total > arena_bytes || ((uintptr_t)arena % kAlign) != 0)
+    return DISCORD_ERANGE;
+  if (hipGetDevice(&p->device) != hipSuccess) return DISCORD_EDEVICE;
+  p->stream = stream;
+  p->arena = static_cast<char*>(arena);
+  p->timed = false;
+  st = prepare_run(p, T);
+  if (st == DISCORD_OK) st = discord_search(p, out);
+  if (st != DISCORD_OK && err && err_len) std::snprintf(err, err_len, "%s", p->err);
+  return st;
+}
+
+}  // namespace dd

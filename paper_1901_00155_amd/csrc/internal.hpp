@@ -222,3 +222,15 @@ void launch_merge_exact(const int64_t* rows, const double* d, const int64_t* j, 
                         Exact* ex, int32_t* nn_witness, hipStream_t s);
 
 }  // namespace dd
+
+namespace dd {
+// ---- api.hip: one series prepared and searched in caller-provided device
+// memory, with a plan on the stack; all work on `stream`, which it
+// synchronises before returning.  Creates no stream, event, heap object or
+// device allocation.  ERANGE if the plan does not fit in arena_bytes.
+int search_series_in_arena(const float* T, int64_t m, int32_t n, const discord_opts* opts,
+                           void* arena, size_t arena_bytes, hipStream_t stream,
+                           discord_result* out, char* err, size_t err_len);
+// Sets the calling thread's error text (discord_plan_error(NULL)).
+void set_thread_error(const char* fmt, ...);
+}  // namespace dd

@@ -151,3 +151,27 @@ def test_split_bf16_workspace_holds_the_split_matrix(dd, m, n):
     assert b16 - f32 < split + 64 * N + (1 << 20)     # nothing else of that size
     assert dd.workspace_bytes(2 * (dd.MIXED_MAX_N + 1), dd.MIXED_MAX_N + 1,
                               precision="bf16x3") == 0
+
+
+def test_noalloc_refuses_plans_beyond_its_static_workspace(dd):
+    """The allocation-free entry point checks the plan's size against its
+    static workspace before any device call, so the refusal is visible here
+    without a GPU; the limit matches the header."""
+    import re
+    hdr = open(os.path.join(os.path.dirname(dd.LIB_PATH), "..", "..", "include",
+                            "discord.h")).read()
+    assert re.search(r"DISCORD_NOALLOC_MAX_BYTES \(\(size_t\)32 << 20\)", hdr)
+    assert dd.NOALLOC_MAX_BYTES == 32 << 20
+    m, n = 1 << 20, 128
+    assert dd.workspace_bytes(m, n) > dd.NOALLOC_MAX_BYTES
+    T = np.zeros(m, dtype=np.float32)
+    with pytest.raises(dd.DiscordError) as e:
+        dd.search_series_noalloc(T, n)
+    assert e.value.status == -6 and "static workspace" in str(e.value)
+    # the split-BF16 matrix makes the same window's plan larger
+    m2 = 1 << 16
+    assert dd.workspace_bytes(m2, 256) <= dd.NOALLOC_MAX_BYTES
+    assert dd.workspace_bytes(m2, 256, precision="bf16x3") > dd.NOALLOC_MAX_BYTES
+    with pytest.raises(dd.DiscordError) as e:
+        dd.search_series_noalloc(np.zeros(m2, np.float32), 256, precision="bf16x3")
+    assert e.value.status == -6
