@@ -72,8 +72,13 @@ struct Layout {
       best, nn_approx, nn_wit, row_state, row_mean, row_cnorm, rows, part_d, part_j, out_d,
       out_j, exact, unc, srch, pair_slots, alive, done, survivors, survivors2, score, rank_hist, gflags,
       cand_groups, bgrp_cnt, bgrp_off, bgrp, max_bucket, mu32, smu32, cn32, r32, row_sigma, sblk,
-      total;
+      ctl, wins, total;
 };
+
+// work descriptors of one search: the Cand launch and two per round (window,
+// completion); rounds grow the window 2x at least, so a sequence of 2^31
+// entries needs fewer than 40
+constexpr int kMaxWins = 128;
 
 Layout make_layout(int64_t m, int32_t n, int dict, bool mixed, bool znorm) {
   const int64_t N = m - n + 1;
@@ -114,6 +119,8 @@ Layout make_layout(int64_t m, int32_t n, int dict, bool mixed, bool znorm) {
   L.unc = take(sizeof(int64_t) * N);
   const int64_t G = (N + kRowGroup - 1) / kRowGroup;
   L.srch = take(sizeof(SearchScalars));
+  L.ctl = take(sizeof(SearchCtl));
+  L.wins = take(sizeof(WinDesc) * kMaxWins);
   L.pair_slots = take(sizeof(uint64_t) * kPairSlots * kPairStride);
   L.alive = take(sizeof(uint32_t) * G);
   L.done = take(sizeof(uint32_t) * G);
@@ -652,31 +659,18 @@ int discord_search(discord_plan p, discord_result* out) {
     J.bgrp_off = p->at<int32_t>(p->L.bgrp_off);
     J.bgrp = p->at<int32_t>(p->L.bgrp);
     J.near_first = near_first;
-    int32_t hcg = 0;
-    if (order && p->cand_count > 0) {
-      // Algorithm 3: the row groups holding Cand rows, each scanned over its
-      // whole sequence, split into chunks to fill the GPU
-      int32_t* cgroups = p->at<int32_t>(p->L.cand_groups);
-      int32_t* n_cg = &sc->n_cand_groups;
-      launch_cand_group_flags(p->at<int32_t>(p->L.cand), p->at<int32_t>(p->L.cand_count),
-                              p->cand_count, item_shift, gflags, s);
-      launch_compact_flags(gflags, n_items, p->at<int32_t>(p->L.seg), cgroups, n_cg, s);
-      HIP_TRY(p, hipMemcpyAsync(&hcg, n_cg, sizeof(hcg), hipMemcpyDeviceToHost, s));
-      HIP_TRY(p, hipStreamSynchronize(s));
-      J.groups = cgroups;
-      J.n_groups = hcg;
-      set_window(hcg, 0, seq_max, target_items);
-      if ((st = launch("scan (Cand)"))) return st;
-    }
-    // Algorithm 4 over the other groups, in windows of their sequences: a first
-    // window of probe_steps x 512 columns for every group; then the groups with
-    // rows still live continue.  PhiDD and matrix order: one more launch over
-    // the rest of the sequence.  Near-first order: the survivors are ranked by
-    // their rows' published minima, the best-ranked are completed at once (to
-    // raise the best-so-far), and the rest continue in windows twice (four times,
-    // on short sequences) as long each time.  Every launch resumes an item where its previous window ended, and
-    // rows already below the best-so-far leave before any work.
-    const bool resume = true;
+    // The whole loop is enqueued now and decided on the device (control.hip):
+    // a Cand launch (Algorithm 3), then rounds of Algorithm 4 over every other
+    // item -- a window of each listed item's sequence; for the near-first order
+    // a ranking of the survivors, the best-ranked completed at once (to raise
+    // the best-so-far) and the rest continuing in a window `growth` times
+    // longer; for the other orders the survivors finish in a second window.
+    // Every launch resumes an item where its previous window ended, and rows
+    // already below the best-so-far leave before any work.  The host mirrors
+    // the window sizes to know how many rounds the sequences allow; a loop
+    // that ends sooner leaves the remaining launches without work.
+    SearchCtl* ctl = p->at<SearchCtl>(p->L.ctl);
+    WinDesc* wins = p->at<WinDesc>(p->L.wins);
     const int probe = p->opts.probe_steps > 0 ? p->opts.probe_steps : (near_first ? (mixed ? 4 : 2) : 16);
     // items completed first after each ranking.  Split-BF16 items beyond
     // n = 512 are single row blocks, and 64 of them measured best (1.26 -> 1.03 s
@@ -686,55 +680,76 @@ int discord_search(discord_plan p, discord_result* out) {
     // 3.2 -> 2.3 s with 512), 128 below 512 (256 was slower at n = 128).
     const int64_t seeds = mixed ? ((n + 15) / 16 > 32 ? 64 : 16)
                                 : (n >= 1024 ? 512 : (n >= 512 ? 256 : 128));
-    int32_t* in = nullptr;                        // nullptr: all groups
-    int32_t* out_buf = J.survivors;
-    int32_t* spare = p->at<int32_t>(p->L.survivors2);
-    int64_t count = n_items;
-    int64_t covered = 0;                          // entries already seen by every listed item
-    int64_t width = (int64_t)probe * gran;
+    // windows double on long sequences and grow 4x on short ones (fewer
+    // rounds where a round costs little work)
+    const int64_t growth = seq_max >= (int64_t{1} << 15) ? 2 : 4;
+    const CtlParams P{seq_max, gran, target_items, seed_items, seeds, growth, near_first ? 1 : 0};
+    // A launch whose work is decided on the device gets a grid sized for the
+    // most work its descriptor can hold, at most `cap` work items (beyond, its
+    // wavefronts or workgroups stride over the work).
+    const int64_t cap = mixed ? 16384 : 65536;
+    auto grid_work = [&](int64_t items_max, int64_t width_max, int64_t target) {
+      const int64_t maxc = (std::max<int64_t>(width_max, 1) + gran - 1) / gran;
+      return std::min(cap, std::min(items_max * maxc, items_max + target));
+    };
+    int nw = 0;
+    const bool cand = order && p->cand_count > 0;
+    if (cand) {
+      // Algorithm 3: the items holding Cand rows, each over its whole sequence
+      launch_cand_group_flags(p->at<int32_t>(p->L.cand), p->at<int32_t>(p->L.cand_count),
+                              p->cand_count, item_shift, gflags, s);
+      launch_compact_flags(gflags, n_items, p->at<int32_t>(p->L.seg),
+                           p->at<int32_t>(p->L.cand_groups), &sc->n_cand_groups, s);
+    }
+    const int64_t width0 = (int64_t)probe * gran;
+    launch_ctl_start(ctl, n_items, width0, &sc->n_cand_groups, cand ? &wins[nw] : nullptr, P, s);
+    if (cand) {
+      J.win = &wins[nw++];
+      J.groups = p->at<int32_t>(p->L.cand_groups);
+      J.skip = nullptr;
+      J.precheck = 0;
+      J.max_work = grid_work(std::min<int64_t>(n_items, p->cand_count), seq_max, target_items);
+      if ((st = launch("scan (Cand)"))) return st;
+    }
+    int32_t* const lists[2] = {p->at<int32_t>(p->L.survivors), p->at<int32_t>(p->L.survivors2)};
+    int32_t* const spare = lists[1];
+    int64_t covered = 0, width = width0;   // the device's window sizes while its loop runs
     for (int round = 0;; ++round) {
       const int64_t end = std::min<int64_t>(seq_max, covered + width);
-      J.groups = in;
-      J.n_groups = count;
-      J.skip = (round == 0 && order && hcg > 0) ? gflags : nullptr;
+      if (nw + 2 > kMaxWins) return fail(p, DISCORD_EDEVICE, "search needs too many rounds");
+      WinDesc* w = &wins[nw++];
+      launch_ctl_window(ctl, w, n_surv, P, s);
+      J.win = w;
+      J.groups = round == 0 ? nullptr : (near_first ? spare : lists[(round - 1) & 1]);
+      J.skip = (round == 0 && cand) ? gflags : nullptr;
       J.precheck = round > 0;
-      J.survivors = out_buf;
-      launch_init_i32(reinterpret_cast<int32_t*>(n_surv), 1, 0, s);
-      set_window(count, resume ? covered : 0, end, target_items);
+      J.survivors = near_first ? lists[0] : lists[round & 1];
+      J.max_work = grid_work(n_items, end - covered, target_items);
       if ((st = launch("scan (window)"))) return st;
       if (end >= seq_max) break;                  // final for every item
-      uint32_t hs = 0;
-      HIP_TRY(p, hipMemcpyAsync(&hs, n_surv, sizeof(hs), hipMemcpyDeviceToHost, s));
-      HIP_TRY(p, hipStreamSynchronize(s));
-      if (hs == 0) break;
+      launch_ctl_after(ctl, n_surv, P, s);
       covered = end;
-      count = hs;
-      if (near_first) {
-        // rank the survivors into `spare`, complete the best-ranked
-        launch_rank_groups(out_buf, count, item_rows, gsz, alive, best, N, p->at<uint32_t>(p->L.score),
-                           p->at<uint32_t>(p->L.rank_hist), spare, s);
-        LAUNCH_OK(p, "rank");
-        const int64_t k = std::min<int64_t>(count, seeds);
-        J.groups = spare;
-        J.n_groups = k;
-        J.skip = nullptr;
-        J.precheck = 1;
-        set_window(k, resume ? covered : 0, seq_max, seed_items);
-        if ((st = launch("scan (seeds)"))) return st;
-        if (k == count) break;
-        // the rest continue from the ranked list; their survivors go to out_buf
-        // again (its previous contents were consumed by the ranking)
-        in = spare + k;
-        count -= k;
-        // windows double on long sequences and grow 4x on short ones (fewer
-        // rounds, each a host round trip, where a round costs little work)
-        width *= seq_max >= (int64_t{1} << 15) ? 2 : 4;
-      } else {
-        in = out_buf;
-        std::swap(out_buf, spare);
+      if (!near_first) {
         width = seq_max;
+        continue;
       }
+      // rank the survivors into `spare`, complete the best-ranked; the rest
+      // continue from the ranked list
+      launch_rank_groups(lists[0], &ctl->count, n_items, item_rows, gsz, alive, best, N,
+                         p->at<uint32_t>(p->L.score), p->at<uint32_t>(p->L.rank_hist), spare, s);
+      LAUNCH_OK(p, "rank");
+      WinDesc* ws = &wins[nw++];
+      launch_ctl_seeds(ctl, ws, P, s);
+      J.win = ws;
+      J.groups = spare;
+      J.skip = nullptr;
+      J.precheck = 1;
+      J.max_work = grid_work(std::min<int64_t>(seeds, n_items), seq_max - covered, seed_items);
+      if ((st = launch("scan (seeds)"))) return st;
+      launch_ctl_post(ctl, P, s);
+      width *= growth;
     }
+    J.win = nullptr;
   }
 
   // ---- certification in FP64 ---------------------------------------------------
@@ -758,23 +773,36 @@ int discord_search(discord_plan p, discord_result* out) {
   int64_t* unc = p->at<int64_t>(p->L.unc);
   launch_verify(p->Tp(), n, N, zstats(p), nn_wit, nn_approx, ex, unc, unc_count, relerr, s);
   LAUNCH_OK(p, "verify");
+  // the first rows the witnesses could not clear (usually none) are rescanned
+  // before the one readback; more than that continue below in host-sized batches
+  constexpr int64_t kDevRows = 8;
+  launch_rows_nn_fp64(p->Tp(), n, N, unc, kDevRows, zstats(p), p->at<double>(p->L.part_d),
+                      p->at<int64_t>(p->L.part_j), p->at<double>(p->L.out_d),
+                      p->at<int64_t>(p->L.out_j), s, unc_count);
+  launch_merge_exact(unc, p->at<double>(p->L.out_d), p->at<int64_t>(p->L.out_j), kDevRows, ex,
+                     nn_wit, s, unc_count);
+  LAUNCH_OK(p, "rescan");
   SearchScalars hsc;
-  HIP_TRY(p, hipMemcpyAsync(&hsc, sc, sizeof(hsc), hipMemcpyDeviceToHost, s));
-  HIP_TRY(p, hipStreamSynchronize(s));
-  const uint32_t hunc = hsc.unc_count, hrel = hsc.relerr, hab = hsc.n_aband;
-  const uint64_t hpairs = hsc.pairs;
-  for (int64_t b = 0; b < (int64_t)hunc; b += kFp64BatchRows) {
-    const int64_t c = std::min<int64_t>(kFp64BatchRows, (int64_t)hunc - b);
-    st = rows_nn_batch(p, unc + b, c);
-    if (st) return st;
-    launch_merge_exact(unc + b, p->at<double>(p->L.out_d), p->at<int64_t>(p->L.out_j), c, ex,
-                       nn_wit, s);
-    LAUNCH_OK(p, "merge_exact");
-  }
   Exact hex;
+  HIP_TRY(p, hipMemcpyAsync(&hsc, sc, sizeof(hsc), hipMemcpyDeviceToHost, s));
   HIP_TRY(p, hipMemcpyAsync(&hex, ex, sizeof(hex), hipMemcpyDeviceToHost, s));
   HIP_TRY(p, ev.stop(s));
   HIP_TRY(p, hipStreamSynchronize(s));
+  const uint32_t hunc = hsc.unc_count, hrel = hsc.relerr, hab = hsc.n_aband;
+  const uint64_t hpairs = hsc.pairs;
+  if ((int64_t)hunc > kDevRows) {
+    for (int64_t b = kDevRows; b < (int64_t)hunc; b += kFp64BatchRows) {
+      const int64_t c = std::min<int64_t>(kFp64BatchRows, (int64_t)hunc - b);
+      st = rows_nn_batch(p, unc + b, c);
+      if (st) return st;
+      launch_merge_exact(unc + b, p->at<double>(p->L.out_d), p->at<int64_t>(p->L.out_j), c, ex,
+                         nn_wit, s);
+      LAUNCH_OK(p, "merge_exact");
+    }
+    HIP_TRY(p, hipMemcpyAsync(&hex, ex, sizeof(hex), hipMemcpyDeviceToHost, s));
+    HIP_TRY(p, ev.stop(s));
+    HIP_TRY(p, hipStreamSynchronize(s));
+  }
   if (hex.i < 0) return fail(p, DISCORD_EDEVICE, "certification produced no discord");
 
   r.index = hex.i;

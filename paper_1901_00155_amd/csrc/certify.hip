@@ -189,9 +189,11 @@ __global__ __launch_bounds__(256) void k_rows_nn_fp64(const float* __restrict__ 
                                                       const int64_t* __restrict__ rows,
                                                       int64_t nchunks,
                                                       double* __restrict__ part_d,
-                                                      int64_t* __restrict__ part_j) {
+                                                      int64_t* __restrict__ part_j,
+                                                      const uint32_t* __restrict__ count) {
   __shared__ double sd[256];
   __shared__ int64_t sj[256];
+  if (count && (int64_t)blockIdx.y >= (int64_t)*count) return;   // row beyond the device count
   const int64_t i = rows[blockIdx.y];
   const int64_t cb = (int64_t)blockIdx.x * kFp64Cols;
   const int64_t ce = min<int64_t>(N, cb + kFp64Cols);
@@ -231,9 +233,11 @@ __global__ __launch_bounds__(256) void k_rows_nn_fp64(const float* __restrict__ 
 __global__ __launch_bounds__(256) void k_rows_nn_reduce(const double* __restrict__ part_d,
                                                         const int64_t* __restrict__ part_j,
                                                         int64_t nchunks, double* __restrict__ out_d,
-                                                        int64_t* __restrict__ out_j) {
+                                                        int64_t* __restrict__ out_j,
+                                                        const uint32_t* __restrict__ count) {
   __shared__ double sd[256];
   __shared__ int64_t sj[256];
+  if (count && (int64_t)blockIdx.x >= (int64_t)*count) return;
   double bd = __builtin_inf();
   int64_t bj = -1;
   const double* pd = part_d + blockIdx.x * nchunks;
@@ -314,7 +318,9 @@ __global__ __launch_bounds__(256) void k_verify(const float* __restrict__ T, int
 // witness array is a complete certificate.
 __global__ void k_merge_exact(const int64_t* __restrict__ rows, const double* __restrict__ d,
                               const int64_t* __restrict__ j, int64_t count, Exact* __restrict__ ex,
-                              int32_t* __restrict__ nn_witness) {
+                              int32_t* __restrict__ nn_witness,
+                              const uint32_t* __restrict__ dev_count) {
+  if (dev_count) count = min<int64_t>(count, (int64_t)*dev_count);
   for (int64_t k = threadIdx.x; k < count; k += blockDim.x)
     if (j[k] >= 0) nn_witness[rows[k]] = (int32_t)j[k];
   if (threadIdx.x != 0) return;
@@ -391,17 +397,17 @@ void launch_seed_row(const uint64_t* seed_key, int64_t* rows_out, hipStream_t s)
 
 void launch_rows_nn_fp64(const float* Tp, int n, int64_t N, const int64_t* rows, int64_t count,
                          ZStats z, double* part_d, int64_t* part_j, double* out_d, int64_t* out_j,
-                         hipStream_t s) {
+                         hipStream_t s, const uint32_t* dev_count) {
   if (count <= 0) return;
   const int64_t nchunks = (N + kFp64Cols - 1) / kFp64Cols;
   if (z.sg)
     hipLaunchKernelGGL(k_rows_nn_fp64<true>, dim3((unsigned)nchunks, (unsigned)count), dim3(256), 0,
-                       s, Tp, n, N, z, rows, nchunks, part_d, part_j);
+                       s, Tp, n, N, z, rows, nchunks, part_d, part_j, dev_count);
   else
     hipLaunchKernelGGL(k_rows_nn_fp64<false>, dim3((unsigned)nchunks, (unsigned)count), dim3(256), 0,
-                       s, Tp, n, N, z, rows, nchunks, part_d, part_j);
+                       s, Tp, n, N, z, rows, nchunks, part_d, part_j, dev_count);
   hipLaunchKernelGGL(k_rows_nn_reduce, dim3((unsigned)count), dim3(256), 0, s, part_d, part_j,
-                     nchunks, out_d, out_j);
+                     nchunks, out_d, out_j, dev_count);
 }
 
 void launch_exact_from_rows(const int64_t* rows, const double* d, const int64_t* j, int64_t count,
@@ -422,8 +428,9 @@ void launch_verify(const float* Tp, int n, int64_t N, ZStats z, const int32_t* n
 }
 
 void launch_merge_exact(const int64_t* rows, const double* d, const int64_t* j, int64_t count,
-                        Exact* ex, int32_t* nn_witness, hipStream_t s) {
-  hipLaunchKernelGGL(k_merge_exact, dim3(1), dim3(64), 0, s, rows, d, j, count, ex, nn_witness);
+                        Exact* ex, int32_t* nn_witness, hipStream_t s, const uint32_t* dev_count) {
+  hipLaunchKernelGGL(k_merge_exact, dim3(1), dim3(64), 0, s, rows, d, j, count, ex, nn_witness,
+                     dev_count);
 }
 
 }  // namespace dd

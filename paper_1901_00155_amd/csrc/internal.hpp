@@ -90,6 +90,18 @@ void launch_max_bucket(const int32_t* goff, int dict, int32_t* out, hipStream_t 
 // chunks that run in parallel; when that reaches the end of an item's sequence
 // the launch is final for it and its rows still live are complete, else they
 // are appended to `survivors` for a later launch that resumes at the next entry.
+// The work of one scan launch when the search decides it on the device: the
+// control kernels (control.hip) write it from the counts the previous launches
+// left, and the scan reads it instead of ScanJob's own n_groups, chunks,
+// seq_begin and seq_chunk; its item list starts at groups + list_off.
+struct WinDesc {
+  int64_t n_groups;
+  int64_t chunks;
+  int64_t seq_begin;
+  int64_t seq_chunk;
+  int64_t list_off;
+};
+
 struct ScanJob {
   const float* Tp;            // padded series (t_0 at Tp[0])
   int32_t n;
@@ -125,7 +137,24 @@ struct ScanJob {
   uint64_t* best;             // per row: packed (approximate distance, column) minimum
   uint64_t* pairs;            // pair distances evaluated (non-self, in range), counted in
                               // kPairSlots slots kPairStride words apart (see pair_slot)
+  // nullptr: the fields above describe the launch's work and the grid covers
+  // it; else the work is read from here and the launch's grid (sized for the
+  // most work the descriptor can hold) strides over it
+  const WinDesc* win;
+  int64_t max_work;           // work items (item x chunk) the grid is sized for
 };
+
+// Reads the device-side work descriptor into J (kernels call it first).
+__device__ __forceinline__ void apply_win(ScanJob& J) {
+  if (J.win) {
+    const WinDesc w = *J.win;
+    J.n_groups = w.n_groups;
+    J.chunks = w.chunks;
+    J.seq_begin = w.seq_begin;
+    J.seq_chunk = w.seq_chunk;
+    if (J.groups) J.groups += w.list_off;
+  }
+}
 void launch_scan_fp32(const ScanJob& J, hipStream_t s);
 
 // The pair counter is spread over slots on cache lines of their own, chosen by
@@ -171,15 +200,59 @@ void launch_row_stats32(const float* Tp, int64_t N, int n, int64_t padded, const
                         const double* row_sigma, const double* stats, float* c32, float* smu32,
                         float* cn32, float* r32, hipStream_t s);
 
+// ---- control.hip ----------------------------------------------------------------
+// The loop of an early-abandon search, decided on the device.  The host
+// enqueues a fixed sequence of launches (it depends only on the plan's sizes
+// and options); one-thread control kernels between them turn the counts the
+// scans leave behind into the next launch's work (WinDesc).  count == 0 means
+// the loop is over: every later launch then finds no work.
+struct SearchCtl {
+  int64_t count;    // items listed for the next window (0: done)
+  int64_t covered;  // sequence entries every listed item has already seen
+  int64_t width;    // entries of the next window
+  int64_t in_off;   // first entry of the next window's item list
+  int64_t end;      // end of the current window
+  int64_t k;        // items of the current completion launch
+};
+struct CtlParams {
+  int64_t seq_max;      // longest column sequence (entries)
+  int64_t gran;         // entries per 512 columns (the chunk granule)
+  int64_t target;       // work items a window launch aims at
+  int64_t seed_target;  // work items a completion launch aims at
+  int64_t seeds;        // best-ranked items completed after each ranking
+  int64_t growth;       // window growth per round
+  int32_t near_first;   // 1: rank and complete between windows; 0: two windows only
+};
+// entries [begin, end) of `items` items, split into chunks so that the launch
+// holds about `target` work items (the host computes the same split for the
+// launches whose counts it knows)
+void set_window_host(WinDesc* w, int64_t items, int64_t begin, int64_t end, int64_t target,
+                     int64_t gran);
+// ctl := (count, 0, width, 0); with cand_count: the Cand launch covers the whole
+// sequence of *cand_count items
+void launch_ctl_start(SearchCtl* ctl, int64_t count, int64_t width, const int32_t* cand_count,
+                      WinDesc* cand_win, const CtlParams& P, hipStream_t s);
+// the next window: entries [covered, covered + width) of the listed items;
+// clears the survivor count
+void launch_ctl_window(SearchCtl* ctl, WinDesc* win, uint32_t* n_surv, const CtlParams& P,
+                       hipStream_t s);
+// after a window: the loop ends when the sequences are done or no item has a
+// live row; else the survivors are the next list
+void launch_ctl_after(SearchCtl* ctl, const uint32_t* n_surv, const CtlParams& P, hipStream_t s);
+// the best-ranked min(count, seeds) items, completed over the rest of their sequences
+void launch_ctl_seeds(SearchCtl* ctl, WinDesc* win, const CtlParams& P, hipStream_t s);
+// after the completion launch: the rest continue in a window `growth` times longer
+void launch_ctl_post(SearchCtl* ctl, const CtlParams& P, hipStream_t s);
+
 // ---- rank.hip -----------------------------------------------------------------
-// Items (item_rows consecutive rows each; alive masks per gsz rows) of `list`,
-// in descending order of the largest published minimum of a live row (score
-// and hist are scratch: count and rank_hist_bins() entries).
+// The *count items (item_rows consecutive rows each; alive masks per gsz rows)
+// of `list`, in descending order of the largest published minimum of a live row
+// (score and hist are scratch: max_count and rank_hist_bins() entries).  The
+// count is read on the device; the grids are sized for max_count.
 size_t rank_hist_bins();
-void launch_rank_groups(const int32_t* list, int64_t count, int64_t item_rows, int gsz,
-                        const uint32_t* alive,
-                        const uint64_t* best, int64_t N, uint32_t* score, uint32_t* hist,
-                        int32_t* out, hipStream_t s);
+void launch_rank_groups(const int32_t* list, const int64_t* count, int64_t max_count,
+                        int64_t item_rows, int gsz, const uint32_t* alive, const uint64_t* best,
+                        int64_t N, uint32_t* score, uint32_t* hist, int32_t* out, hipStream_t s);
 
 // ---- certify.hip --------------------------------------------------------------
 // Fills of several buffers (32- or 64-bit elements) in one launch.
@@ -210,16 +283,19 @@ struct ZStats {
   const double* mu;
   const double* sg;
 };
+// dev_count (optional): only the first min(count, *dev_count) rows are rescanned
+// (a batch sized on the host, filled to a count known only on the device)
 void launch_rows_nn_fp64(const float* Tp, int n, int64_t N, const int64_t* rows, int64_t count,
                          ZStats z, double* part_d, int64_t* part_j, double* out_d, int64_t* out_j,
-                         hipStream_t s);
+                         hipStream_t s, const uint32_t* dev_count = nullptr);
 void launch_exact_from_rows(const int64_t* rows, const double* d, const int64_t* j,
                             int64_t count, Exact* ex, hipStream_t s);
 void launch_verify(const float* Tp, int n, int64_t N, ZStats z, const int32_t* nn_witness,
                    const float* nn_approx, const Exact* ex, int64_t* uncertain,
                    uint32_t* uncertain_count, uint32_t* max_rel_err_bits, hipStream_t s);
 void launch_merge_exact(const int64_t* rows, const double* d, const int64_t* j, int64_t count,
-                        Exact* ex, int32_t* nn_witness, hipStream_t s);
+                        Exact* ex, int32_t* nn_witness, hipStream_t s,
+                        const uint32_t* dev_count = nullptr);
 
 }  // namespace dd
 

@@ -34,10 +34,12 @@ __device__ __forceinline__ uint32_t row_score(const uint32_t* __restrict__ alive
 
 // Small items (up to 64 rows): one thread per item.
 __global__ __launch_bounds__(256) void k_group_score(const int32_t* __restrict__ list,
-                                                     int64_t count, int64_t item_rows, int gsz,
+                                                     const int64_t* __restrict__ count_p,
+                                                     int64_t item_rows, int gsz,
                                                      const uint32_t* __restrict__ alive,
                                                      const uint64_t* __restrict__ best, int64_t N,
                                                      uint32_t* __restrict__ score) {
+  const int64_t count = *count_p;
   const int64_t k = blockIdx.x * 256ll + threadIdx.x;
   if (k >= count) return;
   const int64_t r0 = (int64_t)list[k] * item_rows;
@@ -51,10 +53,12 @@ __global__ __launch_bounds__(256) void k_group_score(const int32_t* __restrict__
 
 // Large items: one wavefront per item, its lanes striding over the rows.
 __global__ __launch_bounds__(256) void k_group_score_wave(const int32_t* __restrict__ list,
-                                                          int64_t count, int64_t item_rows, int gsz,
+                                                          const int64_t* __restrict__ count_p,
+                                                          int64_t item_rows, int gsz,
                                                           const uint32_t* __restrict__ alive,
                                                           const uint64_t* __restrict__ best,
                                                           int64_t N, uint32_t* __restrict__ score) {
+  const int64_t count = *count_p;
   const int64_t k = blockIdx.x * 4ll + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (k >= count) return;
@@ -73,7 +77,10 @@ __global__ __launch_bounds__(256) void k_group_score_wave(const int32_t* __restr
 }
 
 __global__ __launch_bounds__(256) void k_rank_hist(const uint32_t* __restrict__ score,
-                                                   int64_t count, uint32_t* __restrict__ hist) {
+                                                   const int64_t* __restrict__ count_p,
+                                                   uint32_t* __restrict__ hist) {
+  const int64_t count = *count_p;
+  if ((int64_t)blockIdx.x * 256 >= count) return;
   __shared__ uint32_t h[kBins];
   for (int b = threadIdx.x; b < kBins; b += 256) h[b] = 0;
   __syncthreads();
@@ -116,8 +123,11 @@ __global__ __launch_bounds__(1024) void k_rank_offsets(uint32_t* __restrict__ hi
 // rather than one per item.
 __global__ __launch_bounds__(256) void k_rank_scatter(const int32_t* __restrict__ list,
                                                       const uint32_t* __restrict__ score,
-                                                      int64_t count, uint32_t* __restrict__ cursor,
+                                                      const int64_t* __restrict__ count_p,
+                                                      uint32_t* __restrict__ cursor,
                                                       int32_t* __restrict__ out) {
+  const int64_t count = *count_p;
+  if ((int64_t)blockIdx.x * 256 >= count) return;
   __shared__ uint32_t local[kBins];
   __shared__ uint32_t base[kBins];
   for (int b = threadIdx.x; b < kBins; b += 256) local[b] = 0;
@@ -139,16 +149,15 @@ __global__ __launch_bounds__(256) void k_rank_scatter(const int32_t* __restrict_
 
 size_t rank_hist_bins() { return kBins; }
 
-void launch_rank_groups(const int32_t* list, int64_t count, int64_t item_rows, int gsz,
-                        const uint32_t* alive,
-                        const uint64_t* best, int64_t N, uint32_t* score, uint32_t* hist,
-                        int32_t* out, hipStream_t s) {
-  if (count <= 0) return;
-  const unsigned blocks = (unsigned)((count + 255) / 256);
+void launch_rank_groups(const int32_t* list, const int64_t* count, int64_t max_count,
+                        int64_t item_rows, int gsz, const uint32_t* alive, const uint64_t* best,
+                        int64_t N, uint32_t* score, uint32_t* hist, int32_t* out, hipStream_t s) {
+  if (max_count <= 0) return;
+  const unsigned blocks = (unsigned)((max_count + 255) / 256);
   launch_init_i32(reinterpret_cast<int32_t*>(hist), kBins, 0, s);
   if (item_rows > 64)
-    hipLaunchKernelGGL(k_group_score_wave, dim3((unsigned)((count + 3) / 4)), dim3(256), 0, s, list,
-                       count, item_rows, gsz, alive, best, N, score);
+    hipLaunchKernelGGL(k_group_score_wave, dim3((unsigned)((max_count + 3) / 4)), dim3(256), 0, s,
+                       list, count, item_rows, gsz, alive, best, N, score);
   else
     hipLaunchKernelGGL(k_group_score, dim3(blocks), dim3(256), 0, s, list, count, item_rows, gsz,
                        alive, best, N, score);

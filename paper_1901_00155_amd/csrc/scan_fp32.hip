@@ -212,10 +212,7 @@ __device__ __forceinline__ uint64_t load_relaxed64(const uint64_t* p) {
 // leaves as soon as it is below (Algorithms 3-4); the leaving row keeps that
 // column as its witness.
 template <bool Z>
-__global__ __launch_bounds__(256) void k_scan_fp32(ScanJob J) {
-  const int lane = threadIdx.x & 63;
-  const int64_t item = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (item >= J.n_groups * J.chunks) return;
+__device__ __forceinline__ void scan_item(const ScanJob& J, int64_t item, int lane) {
   const int64_t li = item / J.chunks;
   const int64_t ch = item - li * J.chunks;
   const int64_t g = __builtin_amdgcn_readfirstlane((int)(J.groups ? J.groups[li] : li));
@@ -377,10 +374,25 @@ __global__ __launch_bounds__(256) void k_scan_fp32(ScanJob J) {
   }
 }
 
+// Each wavefront takes work items (item, chunk) blockIdx.x * 4 + wave, then
+// strides by the grid's wavefront count: a grid sized for the work gives every
+// work item its own wavefront, a smaller one (the device-decided launches,
+// sized for the most work they can hold) takes several per wavefront.
+template <bool Z>
+__global__ __launch_bounds__(256) void k_scan_fp32(ScanJob Jarg) {
+  ScanJob J = Jarg;
+  apply_win(J);
+  const int lane = threadIdx.x & 63;
+  const int64_t total = J.n_groups * J.chunks;
+  for (int64_t item = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); item < total;
+       item += (int64_t)gridDim.x * 4)
+    scan_item<Z>(J, item, lane);
+}
+
 }  // namespace
 
 void launch_scan_fp32(const ScanJob& J, hipStream_t s) {
-  const int64_t items = J.n_groups * J.chunks;
+  const int64_t items = J.win ? J.max_work : J.n_groups * J.chunks;
   if (items <= 0) return;
   const int64_t blocks = (items + 3) / 4;
   if (J.zc)

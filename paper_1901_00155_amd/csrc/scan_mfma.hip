@@ -175,8 +175,7 @@ __global__ __launch_bounds__(256) void k_split_blocks_long(int KS, const float* 
 // blocks in matrix order or near-first (spiral.hpp) around the item's rows,
 // one 32-column block per step.
 template <int KS, int RB, int WAVES>
-__global__ __launch_bounds__(WAVES * 64, (KS <= 16 ? 2 : 1)) void k_scan_mfma(ScanJob J,
-                                                                             MixedRows R) {
+__device__ __forceinline__ void scan_item(const ScanJob& J, const MixedRows& R, int64_t wi) {
   // two stages, each a column block (Blk<KS>::SLOTS slots) followed by the
   // block's 32 column values sqrt(n) (mean - mu) (8 slots)
   extern __shared__ bf16x8 smem[];
@@ -195,8 +194,8 @@ __global__ __launch_bounds__(WAVES * 64, (KS <= 16 ? 2 : 1)) void k_scan_mfma(Sc
   const int h = lane >> 5;
   const int rl = lane & 31;
   const int64_t per_item = WAVES * RB;
-  const int64_t li = blockIdx.x / J.chunks;
-  const int64_t ch = blockIdx.x - li * J.chunks;
+  const int64_t li = wi / J.chunks;
+  const int64_t ch = wi - li * J.chunks;
   if (li >= J.n_groups) return;
   const int64_t N = J.N;
   const int n = J.n;
@@ -504,6 +503,26 @@ __global__ __launch_bounds__(WAVES * 64, (KS <= 16 ? 2 : 1)) void k_scan_mfma(Sc
   }
 }
 
+// One workgroup per work item (item, chunk) blockIdx.x, then striding by the
+// grid size (the device-decided launches are sized for the most work they can
+// hold).  Between two items every wavefront waits for its own copies into LDS
+// (a sweep that ended early can leave the next block's copy in flight) and
+// for the others to finish reading, before the next item's copies start.
+template <int KS, int RB, int WAVES>
+__global__ __launch_bounds__(WAVES * 64, (KS <= 16 ? 2 : 1)) void k_scan_mfma(ScanJob Jarg,
+                                                                             MixedRows R) {
+  ScanJob J = Jarg;
+  apply_win(J);
+  const int64_t total = J.n_groups * J.chunks;
+  for (int64_t wi = blockIdx.x; wi < total; wi += gridDim.x) {
+    scan_item<KS, RB, WAVES>(J, R, wi);
+    if (wi + gridDim.x < total) {
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+    }
+  }
+}
+
 // Full scans (no early abandon, matrix order, every item listed), software-
 // pipelined: the FP32 epilogue of column block s-1 runs while the MFMAs of
 // block s are in flight.  Two accumulator sets, one barrier per step.  Block
@@ -743,7 +762,7 @@ void launch_full_pipelined(const ScanJob& J, const MixedRows& R, hipStream_t s) 
 
 template <int KS, int RB, int WAVES>
 void launch_kr(const ScanJob& J, const MixedRows& R, hipStream_t s) {
-  const int64_t blocks = J.n_groups * J.chunks;
+  const int64_t blocks = J.win ? J.max_work : J.n_groups * J.chunks;
   if (blocks <= 0) return;
   const size_t lds = sizeof(bf16x8) * 2 * (Blk<KS>::SLOTS + 8);
   // the LDS opt-in is per kernel and set once per process; the initialisation of a

@@ -41,7 +41,7 @@ __device__ __forceinline__ uint64_t load_relaxed64(const uint64_t* p) {
 // One workgroup per (item, chunk of its column sequence); an item is one row
 // block.  KSP: K-steps per wavefront, with 4 * KSP >= KS > 4 * (KSP - 1).
 template <int KSP>
-__global__ __launch_bounds__(W * 64, 1) void k_scan_mfma_long(ScanJob J, MixedRows R) {
+__device__ __forceinline__ void scan_item(const ScanJob& J, const MixedRows& R, int64_t wi) {
   __shared__ float4 part[W][4][64];          // partial accumulators, 16 KiB
   __shared__ uint32_t live_of[2][W];         // per step parity: each wavefront's live rows
   __shared__ uint32_t tail[W + 1];
@@ -56,8 +56,8 @@ __global__ __launch_bounds__(W * 64, 1) void k_scan_mfma_long(ScanJob J, MixedRo
   const int64_t SLOTS = (int64_t)(KS + 1) * 128;   // 16-byte slots per block
   const int k0 = wv * KSP;                          // this wavefront's first K-step
   const int kw = min(KSP, KS - k0);                 // >= 1 (KS > 4 (KSP - 1))
-  const int64_t li = blockIdx.x / J.chunks;
-  const int64_t ch = blockIdx.x - li * J.chunks;
+  const int64_t li = wi / J.chunks;
+  const int64_t ch = wi - li * J.chunks;
   if (li >= J.n_groups) return;
   const int64_t N = J.N;
   const int64_t g = __builtin_amdgcn_readfirstlane((int)(J.groups ? J.groups[li] : li));
@@ -309,9 +309,24 @@ __global__ __launch_bounds__(W * 64, 1) void k_scan_mfma_long(ScanJob J, MixedRo
   }
 }
 
+// One workgroup per work item, striding by the grid size as in scan_mfma.hip.
+template <int KSP>
+__global__ __launch_bounds__(W * 64, 1) void k_scan_mfma_long(ScanJob Jarg, MixedRows R) {
+  ScanJob J = Jarg;
+  apply_win(J);
+  const int64_t total = J.n_groups * J.chunks;
+  for (int64_t wi = blockIdx.x; wi < total; wi += gridDim.x) {
+    scan_item<KSP>(J, R, wi);
+    if (wi + gridDim.x < total) {
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+    }
+  }
+}
+
 template <int KSP>
 void launch_long(const ScanJob& J, const MixedRows& R, hipStream_t s) {
-  const int64_t blocks = J.n_groups * J.chunks;
+  const int64_t blocks = J.win ? J.max_work : J.n_groups * J.chunks;
   if (blocks <= 0) return;
   hipLaunchKernelGGL(k_scan_mfma_long<KSP>, dim3((unsigned)blocks), dim3(W * 64), 0, s, J, R);
 }
