@@ -150,6 +150,18 @@ int discord_prepare(const float* T, int64_t m, int32_t n, const discord_opts* op
  * is relied on. */
 int discord_search(discord_plan plan, discord_result* out);
 
+/* The same search, run from a HIP graph: the first call on a plan captures the
+ * whole search (every launch, the device-side decisions between them and the
+ * readback of the answer; nothing in it waits for the host) and later calls
+ * replay it, so a resident plan searched again costs one graph launch and one
+ * synchronisation.  Same result as discord_search, bit for bit.  The graph
+ * and a small pinned readback block belong to the plan (freed by
+ * discord_release).  ms_scan is 0 (no per-launch events inside the graph);
+ * ms_search brackets the graph launch.  Errors: those of discord_search, and
+ * EDEVICE if capture or instantiation fails (the plan stays usable with
+ * discord_search). */
+int discord_search_graph(discord_plan plan, discord_result* out);
+
 /* Frees the plan and the device memory it owns.  NULL is ignored. */
 void discord_release(discord_plan plan);
 

@@ -41,7 +41,7 @@ FIELD = {
 # every symbol the public header declares (checked by the CPU tests)
 EXPORTED = [
     "discord_default_opts", "discord_abi_version", "discord_workspace_bytes", "discord_prepare", "discord_search",
-    "discord_release", "discord_strerror", "discord_plan_error", "discord_sax_breakpoints",
+    "discord_release", "discord_search_graph", "discord_strerror", "discord_plan_error", "discord_sax_breakpoints",
     "discord_search_series", "discord_search_series_noalloc", "discord_plan_count", "discord_plan_copy", "discord_rows_nn_fp64",
     "discord_server_create", "discord_server_create_with_executor", "discord_server_submit",
     "discord_server_poll", "discord_server_get_stats", "discord_server_destroy",
@@ -148,6 +148,8 @@ def load():
     lib.discord_prepare.restype = ctypes.c_int
     lib.discord_search.argtypes = [vp, ctypes.POINTER(Result)]
     lib.discord_search.restype = ctypes.c_int
+    lib.discord_search_graph.argtypes = [vp, ctypes.POINTER(Result)]
+    lib.discord_search_graph.restype = ctypes.c_int
     lib.discord_release.argtypes = [vp]
     lib.discord_release.restype = None
     lib.discord_strerror.argtypes = [ctypes.c_int]
@@ -318,6 +320,13 @@ class Plan:
     def search(self) -> Result:
         r = Result()
         _check(load().discord_search(self._h, ctypes.byref(r)), self._h)
+        return r
+
+    def search_graph(self) -> Result:
+        """discord_search_graph: captured into a HIP graph on the first call,
+        replayed afterwards."""
+        r = Result()
+        _check(load().discord_search_graph(self._h, ctypes.byref(r)), self._h)
         return r
 
     def count(self, field: str) -> int:

@@ -186,6 +186,8 @@ struct discord_plan_s {
   double ms_prepare = 0.0;
   bool searched = false;
   bool timed = true;          // false: no HIP events (the allocation-free entry point)
+  hipGraphExec_t gexec = nullptr;   // the search captured by discord_search_graph
+  void* hout = nullptr;             // pinned block the captured search reads back into
   char err[512] = {0};
 
   template <class P>
@@ -517,20 +519,37 @@ int discord_prepare(const float* T, int64_t m, int32_t n, const discord_opts* op
   return DISCORD_OK;
 }
 
-int discord_search(discord_plan p, discord_result* out) {
-  if (!p || !out) return DISCORD_EINVAL;
+}  // extern "C"
+
+namespace {
+
+// What one search reads back: its counters and the certified answer.
+struct HostOut {
+  SearchScalars sc;
+  Exact ex;
+};
+
+constexpr int64_t kDevRows = 8;   // uncertain rows rescanned before the readback
+
+// One search in flight.  timed: scan launches timed so far (event pairs 1,
+// 2, ...: their sum is ms_scan); events are taken only if the plan is timed
+// and the search is not being captured into a graph.
+struct SearchRun {
+  HostOut* h = nullptr;
+  bool events = true;
+  int timed = 0;
+};
+
+// Enqueues the whole search on the plan's stream, up to the copies of its
+// counters and answer into run.h; nothing here waits for the device, so the
+// sequence can also be captured into a graph.
+int search_enqueue(discord_plan p, SearchRun& run) {
   hipStream_t s = p->stream;
   const int64_t N = p->N;
   const int n = p->n;
-  EventPair ev(0, p->timed);
-  if (!ev.ready()) return fail(p, DISCORD_EDEVICE, "hipEventCreate failed");
-  // scan launches are timed one by one (pairs 1, 2, ...): their sum is ms_scan
-  int timed = 0;
+  int& timed = run.timed;
   constexpr int kMaxTimed = 256;
-  discord_result r;
-  std::memset(&r, 0, sizeof(r));
   HIP_TRY(p, hipSetDevice(p->device));
-  HIP_TRY(p, ev.start(s));
 
   const bool mixed = p->opts.precision == DISCORD_PREC_BF16X3;
   // rows per scan group: 8 (FP32 micro-tile) or 32 (one MFMA tile side)
@@ -614,7 +633,7 @@ int discord_search(discord_plan p, discord_result* out) {
     J.raise_scale = (float)(1.0 - ((n + 3) * std::ldexp(1.0, -24) * 1.01 + std::ldexp(1.0, -22)));
   }
   auto launch = [&](const char* what) -> int {
-    const bool timing = p->timed && timed < kMaxTimed;
+    const bool timing = run.events && timed < kMaxTimed;
     EventPair t(1 + timed, timing);
     if (!t.ready()) return fail(p, DISCORD_EDEVICE, "hipEventCreate failed");
     if (timing) HIP_TRY(p, hipEventRecord(t.a, s));
@@ -774,26 +793,41 @@ int discord_search(discord_plan p, discord_result* out) {
   launch_verify(p->Tp(), n, N, zstats(p), nn_wit, nn_approx, ex, unc, unc_count, relerr, s);
   LAUNCH_OK(p, "verify");
   // the first rows the witnesses could not clear (usually none) are rescanned
-  // before the one readback; more than that continue below in host-sized batches
-  constexpr int64_t kDevRows = 8;
+  // before the one readback; more than that continue in host-sized batches
   launch_rows_nn_fp64(p->Tp(), n, N, unc, kDevRows, zstats(p), p->at<double>(p->L.part_d),
                       p->at<int64_t>(p->L.part_j), p->at<double>(p->L.out_d),
                       p->at<int64_t>(p->L.out_j), s, unc_count);
   launch_merge_exact(unc, p->at<double>(p->L.out_d), p->at<int64_t>(p->L.out_j), kDevRows, ex,
                      nn_wit, s, unc_count);
   LAUNCH_OK(p, "rescan");
-  SearchScalars hsc;
-  Exact hex;
-  HIP_TRY(p, hipMemcpyAsync(&hsc, sc, sizeof(hsc), hipMemcpyDeviceToHost, s));
-  HIP_TRY(p, hipMemcpyAsync(&hex, ex, sizeof(hex), hipMemcpyDeviceToHost, s));
-  HIP_TRY(p, ev.stop(s));
-  HIP_TRY(p, hipStreamSynchronize(s));
-  const uint32_t hunc = hsc.unc_count, hrel = hsc.relerr, hab = hsc.n_aband;
-  const uint64_t hpairs = hsc.pairs;
+  HIP_TRY(p, hipMemcpyAsync(&run.h->sc, sc, sizeof(SearchScalars), hipMemcpyDeviceToHost, s));
+  HIP_TRY(p, hipMemcpyAsync(&run.h->ex, ex, sizeof(Exact), hipMemcpyDeviceToHost, s));
+  return DISCORD_OK;
+}
+
+// After the copies of search_enqueue have landed: the uncertain rows beyond the
+// device batch (rare) are rescanned here, then the result is filled in.
+// `ev` brackets the search for ms_search (its stop is recorded again after
+// the extra rescans).
+int search_finish(discord_plan p, SearchRun& run, const EventPair& ev, discord_result* out) {
+  hipStream_t s = p->stream;
+  const int64_t N = p->N;
+  const int n = p->n;
+  SearchScalars* sc = p->at<SearchScalars>(p->L.srch);
+  Exact* ex = p->at<Exact>(p->L.exact);
+  int32_t* nn_wit = p->at<int32_t>(p->L.nn_wit);
+  int64_t* unc = p->at<int64_t>(p->L.unc);
+  (void)sc;
+  (void)N;
+  (void)n;
+  const HostOut& h = *run.h;
+  const uint32_t hunc = h.sc.unc_count, hrel = h.sc.relerr, hab = h.sc.n_aband;
+  const uint64_t hpairs = h.sc.pairs;
+  Exact hex = h.ex;
   if ((int64_t)hunc > kDevRows) {
     for (int64_t b = kDevRows; b < (int64_t)hunc; b += kFp64BatchRows) {
       const int64_t c = std::min<int64_t>(kFp64BatchRows, (int64_t)hunc - b);
-      st = rows_nn_batch(p, unc + b, c);
+      const int st = rows_nn_batch(p, unc + b, c);
       if (st) return st;
       launch_merge_exact(unc + b, p->at<double>(p->L.out_d), p->at<int64_t>(p->L.out_j), c, ex,
                          nn_wit, s);
@@ -805,6 +839,9 @@ int discord_search(discord_plan p, discord_result* out) {
   }
   if (hex.i < 0) return fail(p, DISCORD_EDEVICE, "certification produced no discord");
 
+  discord_result r;
+  std::memset(&r, 0, sizeof(r));
+  const bool zn = p->opts.znorm != 0;
   r.index = hex.i;
   r.nn_index = hex.j;
   r.d2 = hex.d2;
@@ -821,15 +858,88 @@ int discord_search(discord_plan p, discord_result* out) {
   r.cand_rows = (uint64_t)p->cand_count;
   r.ms_prepare = p->ms_prepare;
   r.ms_search = ev.ms();
-  for (int k = 0; k < timed; ++k) r.ms_scan += EventPair(1 + k).ms();
+  for (int k = 0; k < run.timed; ++k) r.ms_scan += EventPair(1 + k).ms();
   p->searched = true;
   *out = r;
   return DISCORD_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+int discord_search(discord_plan p, discord_result* out) {
+  if (!p || !out) return DISCORD_EINVAL;
+  EventPair ev(0, p->timed);
+  if (!ev.ready()) return fail(p, DISCORD_EDEVICE, "hipEventCreate failed");
+  HIP_TRY(p, hipSetDevice(p->device));
+  HIP_TRY(p, ev.start(p->stream));
+  HostOut h;
+  SearchRun run;
+  run.h = &h;
+  run.events = p->timed;
+  int st = search_enqueue(p, run);
+  if (st != DISCORD_OK) return st;
+  HIP_TRY(p, ev.stop(p->stream));
+  HIP_TRY(p, hipStreamSynchronize(p->stream));
+  return search_finish(p, run, ev, out);
+}
+
+int discord_search_graph(discord_plan p, discord_result* out) {
+  if (!p || !out) return DISCORD_EINVAL;
+  HIP_TRY(p, hipSetDevice(p->device));
+  hipStream_t s = p->stream;
+  if (!p->hout) {
+    void* h = nullptr;
+    if (hipHostMalloc(&h, sizeof(HostOut), hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(p, DISCORD_ENOMEM, "hipHostMalloc of the graph's readback block failed");
+    }
+    p->hout = h;
+  }
+  HostOut* h = static_cast<HostOut*>(p->hout);
+  if (!p->gexec) {
+    // capture once: the sequence depends only on the plan, and every launch's
+    // work is decided on the device, so the same graph serves every search
+    SearchRun cap;
+    cap.h = h;
+    cap.events = false;
+    HIP_TRY(p, hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+    const int st = search_enqueue(p, cap);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(s, &g);
+    if (st != DISCORD_OK || e != hipSuccess || !g) {
+      if (g) (void)hipGraphDestroy(g);
+      (void)hipGetLastError();
+      return st != DISCORD_OK ? st
+                              : fail(p, DISCORD_EDEVICE, "stream capture failed: %s",
+                                     hipGetErrorString(e));
+    }
+    const hipError_t ei = hipGraphInstantiate(&p->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) {
+      p->gexec = nullptr;
+      (void)hipGetLastError();
+      return fail(p, DISCORD_EDEVICE, "hipGraphInstantiate failed: %s", hipGetErrorString(ei));
+    }
+  }
+  EventPair ev(0, p->timed);
+  if (!ev.ready()) return fail(p, DISCORD_EDEVICE, "hipEventCreate failed");
+  HIP_TRY(p, ev.start(s));
+  HIP_TRY(p, hipGraphLaunch(p->gexec, s));
+  HIP_TRY(p, ev.stop(s));
+  HIP_TRY(p, hipStreamSynchronize(s));
+  SearchRun run;
+  run.h = h;
+  run.events = false;
+  return search_finish(p, run, ev, out);
+}
+
 void discord_release(discord_plan p) {
   if (!p) return;
   if (p->stream) (void)hipStreamSynchronize(p->stream);
+  if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+  if (p->hout) (void)hipHostFree(p->hout);
   if (p->own_arena && p->arena) (void)hipFree(p->arena);
   if (p->own_stream && p->stream) (void)hipStreamDestroy(p->stream);
   delete p;
