@@ -72,12 +72,12 @@ struct Layout {
       best, nn_approx, nn_wit, row_state, row_mean, row_cnorm, rows, part_d, part_j, out_d,
       out_j, exact, unc, srch, pair_slots, alive, done, survivors, survivors2, score, rank_hist, gflags,
       cand_groups, bgrp_cnt, bgrp_off, bgrp, max_bucket, mu32, smu32, cn32, r32, row_sigma, sblk,
-      ctl, wins, total;
+      ctl, wins, lb, lb_range, lb_bmin, lb_bmax, total;
 };
 
-// work descriptors of one search: the Cand launch and two per round (window,
-// completion); rounds grow the window 2x at least, so a sequence of 2^31
-// entries needs fewer than 40
+// work descriptors of one search: the Cand launch and up to three per round
+// (window, two completion stages); rounds grow the window 2x at least, so a
+// sequence of 2^31 entries needs fewer than 40 rounds
 constexpr int kMaxWins = 128;
 
 Layout make_layout(int64_t m, int32_t n, int dict, bool mixed, bool znorm) {
@@ -141,6 +141,12 @@ Layout make_layout(int64_t m, int32_t n, int dict, bool mixed, bool znorm) {
   L.row_sigma = take(znorm ? sizeof(double) * N : 0);
   // the split subsequence matrix of the MFMA scan, resident for the plan's life
   L.sblk = take(mixed ? (size_t)mixed_blocks(N) * mixed_block_bytes(n) : 0);
+  // the mean-gap bound of every row's NN (global normalisation only: under
+  // per-window normalisation every window has mean 0)
+  L.lb = take(znorm ? 0 : sizeof(float) * N);
+  L.lb_range = take(znorm ? 0 : sizeof(uint64_t) * 2);
+  L.lb_bmin = take(znorm ? 0 : sizeof(int32_t) * bound_bins());
+  L.lb_bmax = take(znorm ? 0 : sizeof(int32_t) * bound_bins());
   L.total = off;
   return L;
 }
@@ -428,6 +434,10 @@ int prepare_run(discord_plan p, const float* T) {
     double* row_sigma = zn ? p->at<double>(p->L.row_sigma) : nullptr;
     launch_row_stats(p->Tp(), p->N, n, p->at<double>(p->L.row_mean), p->at<double>(p->L.row_cnorm),
                      row_sigma, s);
+    if (!zn)
+      launch_row_bound(p->at<double>(p->L.row_mean), p->N, n, p->at<uint64_t>(p->L.lb_range),
+                       p->at<int32_t>(p->L.lb_bmin), p->at<int32_t>(p->L.lb_bmax),
+                       p->at<float>(p->L.lb), s);
     launch_sax(p->Tp(), p->N, n, o.paa_w, o.alphabet, p->at<double>(p->L.stats),
                zn ? p->at<double>(p->L.row_mean) : nullptr, row_sigma,
                p->at<int32_t>(p->L.words), p->at<int32_t>(p->L.hist), s);
@@ -702,7 +712,9 @@ int search_enqueue(discord_plan p, SearchRun& run) {
     // windows double on long sequences and grow 4x on short ones (fewer
     // rounds where a round costs little work)
     const int64_t growth = seq_max >= (int64_t{1} << 15) ? 2 : 4;
-    const CtlParams P{seq_max, gran, target_items, seed_items, seeds, growth, near_first ? 1 : 0};
+    const int64_t seeds2 = 0;
+    const CtlParams P{seq_max, gran,   target_items,         seed_items,
+                      seeds,   seeds2, growth,               near_first ? 1 : 0};
     // A launch whose work is decided on the device gets a grid sized for the
     // most work its descriptor can hold, at most `cap` work items (beyond, its
     // wavefronts or workgroups stride over the work).
@@ -732,15 +744,43 @@ int search_enqueue(discord_plan p, SearchRun& run) {
     }
     int32_t* const lists[2] = {p->at<int32_t>(p->L.survivors), p->at<int32_t>(p->L.survivors2)};
     int32_t* const spare = lists[1];
+    // Near-first order, global normalisation: before the first window, the
+    // items whose rows have the largest mean-gap bound of their NN (bound.hip)
+    // are completed, which puts the best-so-far near its final value.  Their
+    // items are then skipped by the first window, like the Cand items.  16
+    // FP32 groups / 2 split-BF16 items measured best among 1..64 (time to
+    // discord, FP32 / split-BF16: 2^20 walk n = 128 12.3 -> 8.3 / 8.2 -> 5.5 ms;
+    // 2^20 noisy walk n = 256 22.9 -> 10.3 / 12.1 -> 5.1 ms; 2^22 series
+    // n = 512 277 -> 65 / 126 -> 31 ms).
+    const int64_t bound_seeds = (near_first && !zn) ? std::min<int64_t>(n_items, mixed ? 2 : 16) : 0;
+    if (bound_seeds > 0) {
+      launch_item_bound(p->at<float>(p->L.lb), N, item_rows, n_items, p->at<uint32_t>(p->L.score),
+                        s);
+      launch_rank_scores(nullptr, &ctl->count, n_items, p->at<uint32_t>(p->L.score),
+                         p->at<uint32_t>(p->L.rank_hist), spare, s);
+      LAUNCH_OK(p, "bound ranking");
+      WinDesc wd{};
+      set_window_host(&wd, bound_seeds, 0, seq_max, seed_items, gran);
+      J.win = nullptr;
+      J.groups = spare;
+      J.n_groups = bound_seeds;
+      J.chunks = wd.chunks;
+      J.seq_begin = 0;
+      J.seq_chunk = wd.seq_chunk;
+      J.skip = cand ? gflags : nullptr;
+      J.precheck = 1;
+      if ((st = launch("scan (bound seeds)"))) return st;
+      launch_flag_items(spare, bound_seeds, gflags, s);
+    }
     int64_t covered = 0, width = width0;   // the device's window sizes while its loop runs
     for (int round = 0;; ++round) {
       const int64_t end = std::min<int64_t>(seq_max, covered + width);
-      if (nw + 2 > kMaxWins) return fail(p, DISCORD_EDEVICE, "search needs too many rounds");
+      if (nw + 3 > kMaxWins) return fail(p, DISCORD_EDEVICE, "search needs too many rounds");
       WinDesc* w = &wins[nw++];
       launch_ctl_window(ctl, w, n_surv, P, s);
       J.win = w;
       J.groups = round == 0 ? nullptr : (near_first ? spare : lists[(round - 1) & 1]);
-      J.skip = (round == 0 && cand) ? gflags : nullptr;
+      J.skip = (round == 0 && (cand || bound_seeds > 0)) ? gflags : nullptr;
       J.precheck = round > 0;
       J.survivors = near_first ? lists[0] : lists[round & 1];
       J.max_work = grid_work(n_items, end - covered, target_items);
@@ -757,14 +797,17 @@ int search_enqueue(discord_plan p, SearchRun& run) {
       launch_rank_groups(lists[0], &ctl->count, n_items, item_rows, gsz, alive, best, N,
                          p->at<uint32_t>(p->L.score), p->at<uint32_t>(p->L.rank_hist), spare, s);
       LAUNCH_OK(p, "rank");
-      WinDesc* ws = &wins[nw++];
-      launch_ctl_seeds(ctl, ws, P, s);
-      J.win = ws;
-      J.groups = spare;
-      J.skip = nullptr;
-      J.precheck = 1;
-      J.max_work = grid_work(std::min<int64_t>(seeds, n_items), seq_max - covered, seed_items);
-      if ((st = launch("scan (seeds)"))) return st;
+      for (int stage = 0; stage < (seeds2 > 0 ? 2 : 1); ++stage) {
+        WinDesc* ws = &wins[nw++];
+        launch_ctl_seeds(ctl, ws, P, stage, s);
+        J.win = ws;
+        J.groups = spare;
+        J.skip = nullptr;
+        J.precheck = 1;
+        J.max_work = grid_work(std::min<int64_t>(stage ? seeds2 : seeds, n_items), seq_max - covered,
+                               seed_items);
+        if ((st = launch("scan (seeds)"))) return st;
+      }
       launch_ctl_post(ctl, P, s);
       width *= growth;
     }

@@ -1,0 +1,178 @@
+// bound.hip -- a cheap lower bound of every row's nearest-neighbour distance,
+// used to choose which rows the search completes first.
+//
+// For windows a, b of length n with means mu_a, mu_b, the squared distance of
+// eq. (1) splits into the centred part and the mean part,
+//     |a - b|^2 = |(a - mu_a) - (b - mu_b)|^2 + n (mu_a - mu_b)^2 ,
+// so d^2(i, j) >= n (mu_i - mu_j)^2 and NN(i) >= n min_j (mu_i - mu_j)^2 over
+// the non-self j (|i - j| >= n).  A window whose mean lies where the series is
+// rarely seen (apart from its own neighbourhood) therefore has a large NN, and
+// the discord, the row with the largest NN, tends to be among the rows with
+// the largest bound.  Completing those rows first raises the best-so-far close
+// to its final value before the bulk of the rows are searched.  The bound only
+// orders work: the search's result never depends on it.
+//
+// Evaluation: the row means are binned (B bins over [min, max]); each bin keeps
+// its smallest and largest row index.  Bin c holds a non-self match of row i
+// exactly when max_c >= i + n or min_c <= i - n, so the first such bin at
+// distance d from row i's own bin bounds the nearest non-self mean below by
+// (d - 1) bin widths.
+#include "internal.hpp"
+
+namespace dd {
+namespace {
+
+constexpr int kBoundBins = 65536;
+constexpr int kBoundReach = 4096;   // bins searched on each side before giving up
+
+// order-preserving map of doubles to unsigned integers
+__device__ __forceinline__ uint64_t ordered(double x) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, x);
+  return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
+}
+__device__ __forceinline__ double unordered(uint64_t u) {
+  return __builtin_bit_cast(double, (u >> 63) ? (u & 0x7FFFFFFFFFFFFFFFull) : ~u);
+}
+
+__global__ __launch_bounds__(256) void k_mean_range(const double* __restrict__ mu, int64_t N,
+                                                    uint64_t* __restrict__ range) {
+  __shared__ uint64_t lo_s[4], hi_s[4];
+  uint64_t lo = ~0ull, hi = 0;
+  for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < N; i += (int64_t)gridDim.x * 256) {
+    const uint64_t u = ordered(mu[i]);
+    lo = u < lo ? u : lo;
+    hi = u > hi ? u : hi;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint64_t a = __shfl_xor(lo, off, 64), b = __shfl_xor(hi, off, 64);
+    lo = a < lo ? a : lo;
+    hi = b > hi ? b : hi;
+  }
+  if ((threadIdx.x & 63) == 0) {
+    lo_s[threadIdx.x >> 6] = lo;
+    hi_s[threadIdx.x >> 6] = hi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < 4; ++w) {
+      lo = lo_s[w] < lo ? lo_s[w] : lo;
+      hi = hi_s[w] > hi ? hi_s[w] : hi;
+    }
+    atomicMin((unsigned long long*)&range[0], (unsigned long long)lo);
+    atomicMax((unsigned long long*)&range[1], (unsigned long long)hi);
+  }
+}
+
+struct Bins {
+  double lo, inv_width, width;
+};
+
+__device__ __forceinline__ Bins bins_of(const uint64_t* __restrict__ range) {
+  const double lo = unordered(range[0]), hi = unordered(range[1]);
+  const double span = hi - lo;
+  Bins b;
+  b.lo = lo;
+  b.width = span > 0.0 ? span / kBoundBins : 1.0;
+  b.inv_width = span > 0.0 ? kBoundBins / span : 0.0;
+  return b;
+}
+
+__device__ __forceinline__ int bin_of(const Bins& b, double x) {
+  const double t = (x - b.lo) * b.inv_width;
+  const int k = t > 0.0 ? (int)t : 0;
+  return k < kBoundBins - 1 ? k : kBoundBins - 1;
+}
+
+__global__ __launch_bounds__(256) void k_bin_rows(const double* __restrict__ mu, int64_t N,
+                                                  const uint64_t* __restrict__ range,
+                                                  int32_t* __restrict__ bmin,
+                                                  int32_t* __restrict__ bmax) {
+  const Bins b = bins_of(range);
+  for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < N; i += (int64_t)gridDim.x * 256) {
+    const int k = bin_of(b, mu[i]);
+    atomicMin(&bmin[k], (int32_t)i);
+    atomicMax(&bmax[k], (int32_t)i);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_row_bound(const double* __restrict__ mu, int64_t N, int n,
+                                                   const uint64_t* __restrict__ range,
+                                                   const int32_t* __restrict__ bmin,
+                                                   const int32_t* __restrict__ bmax,
+                                                   float* __restrict__ lb) {
+  const Bins b = bins_of(range);
+  for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < N; i += (int64_t)gridDim.x * 256) {
+    const int k = bin_of(b, mu[i]);
+    const int64_t lo_row = i - n, hi_row = i + n;   // non-self: j <= lo_row or j >= hi_row
+    int d = 0;
+    for (; d <= kBoundReach; ++d) {
+      const int c0 = k - d, c1 = k + d;
+      const bool ok0 = c0 >= 0 && (bmax[c0] >= hi_row || bmin[c0] <= lo_row);
+      const bool ok1 = c1 < kBoundBins && (bmax[c1] >= hi_row || bmin[c1] <= lo_row);
+      if (ok0 || ok1 || (c0 < 0 && c1 >= kBoundBins)) break;
+    }
+    const double gap = (d > 1 ? d - 1 : 0) * b.width;
+    lb[i] = (float)(n * gap * gap);
+  }
+}
+
+// item score: the largest bound among the item's rows (non-negative floats
+// order like their bit patterns)
+__global__ __launch_bounds__(256) void k_item_bound(const float* __restrict__ lb, int64_t N,
+                                                    int64_t item_rows, int64_t n_items,
+                                                    uint32_t* __restrict__ score) {
+  for (int64_t t = blockIdx.x * 256ll + threadIdx.x; t < n_items; t += (int64_t)gridDim.x * 256) {
+    const int64_t r0 = t * item_rows, r1 = min<int64_t>(N, r0 + item_rows);
+    uint32_t s = 0;
+    for (int64_t i = r0; i < r1; ++i) {
+      const uint32_t v = __builtin_bit_cast(uint32_t, lb[i]);
+      s = v > s ? v : s;
+    }
+    score[t] = s;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_flag_items(const int32_t* __restrict__ list, int64_t count,
+                                                    int32_t* __restrict__ flags) {
+  const int64_t t = blockIdx.x * 256ll + threadIdx.x;
+  if (t < count) flags[list[t]] = 1;
+}
+
+unsigned blocks_for(int64_t count) {
+  const int64_t b = (count + 255) / 256;
+  return (unsigned)(b < 1 ? 1 : (b > 1024 ? 1024 : b));
+}
+
+}  // namespace
+
+size_t bound_bins() { return kBoundBins; }
+
+void launch_row_bound(const double* row_mean, int64_t N, int n, uint64_t* range, int32_t* bmin,
+                      int32_t* bmax, float* lb, hipStream_t s) {
+  const FillOp fills[] = {
+      {range, 1, ~0ull, 1},
+      {range + 1, 1, 0, 1},
+      {bmin, kBoundBins, 0x7FFFFFFF, 0},
+      {bmax, kBoundBins, 0xFFFFFFFFu, 0},
+  };
+  launch_fill_many(fills, 4, s);
+  hipLaunchKernelGGL(k_mean_range, dim3(blocks_for(N)), dim3(256), 0, s, row_mean, N, range);
+  hipLaunchKernelGGL(k_bin_rows, dim3(blocks_for(N)), dim3(256), 0, s, row_mean, N, range, bmin,
+                     bmax);
+  hipLaunchKernelGGL(k_row_bound, dim3(blocks_for(N)), dim3(256), 0, s, row_mean, N, n, range,
+                     bmin, bmax, lb);
+}
+
+void launch_item_bound(const float* lb, int64_t N, int64_t item_rows, int64_t n_items,
+                       uint32_t* score, hipStream_t s) {
+  hipLaunchKernelGGL(k_item_bound, dim3(blocks_for(n_items)), dim3(256), 0, s, lb, N, item_rows,
+                     n_items, score);
+}
+
+void launch_flag_items(const int32_t* list, int64_t count, int32_t* flags, hipStream_t s) {
+  if (count > 0)
+    hipLaunchKernelGGL(k_flag_items, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, list,
+                       count, flags);
+}
+
+}  // namespace dd

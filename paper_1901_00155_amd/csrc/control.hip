@@ -44,6 +44,7 @@ __global__ void k_ctl_start(SearchCtl* ctl, int64_t count, int64_t width,
   ctl->in_off = 0;
   ctl->end = 0;
   ctl->k = 0;
+  ctl->k2 = 0;
   if (cand_win) set_window(cand_win, *cand_count, 0, P.seq_max, P.target, P.gran, 0);
 }
 
@@ -68,22 +69,31 @@ __global__ void k_ctl_after(SearchCtl* ctl, const uint32_t* n_surv, CtlParams P)
   if (!P.near_first) ctl->width = P.seq_max;   // the survivors finish in one more window
 }
 
-__global__ void k_ctl_seeds(SearchCtl* ctl, WinDesc* win, CtlParams P) {
+__global__ void k_ctl_seeds(SearchCtl* ctl, WinDesc* win, CtlParams P, int stage) {
   const int64_t c = ctl->count;
-  const int64_t k = c < P.seeds ? c : P.seeds;
-  set_window(win, k, ctl->covered, P.seq_max, P.seed_target, P.gran, 0);
-  ctl->k = k;
+  if (stage == 0) {
+    const int64_t k = c < P.seeds ? c : P.seeds;
+    set_window(win, k, ctl->covered, P.seq_max, P.seed_target, P.gran, 0);
+    ctl->k = k;
+    ctl->k2 = 0;
+  } else {
+    const int64_t rest = c - ctl->k;
+    const int64_t k2 = rest < P.seeds2 ? rest : P.seeds2;
+    set_window(win, k2, ctl->covered, P.seq_max, P.seed_target, P.gran, ctl->k);
+    ctl->k2 = k2;
+  }
 }
 
 __global__ void k_ctl_post(SearchCtl* ctl, CtlParams P) {
   const int64_t c = ctl->count;
   if (c == 0) return;
-  if (ctl->k >= c) {   // the ranked list was completed whole
+  const int64_t done = ctl->k + ctl->k2;
+  if (done >= c) {   // the ranked list was completed whole
     ctl->count = 0;
     return;
   }
-  ctl->in_off = ctl->k;
-  ctl->count = c - ctl->k;
+  ctl->in_off = done;
+  ctl->count = c - done;
   ctl->width *= P.growth;
 }
 
@@ -109,8 +119,9 @@ void launch_ctl_after(SearchCtl* ctl, const uint32_t* n_surv, const CtlParams& P
   hipLaunchKernelGGL(k_ctl_after, dim3(1), dim3(1), 0, s, ctl, n_surv, P);
 }
 
-void launch_ctl_seeds(SearchCtl* ctl, WinDesc* win, const CtlParams& P, hipStream_t s) {
-  hipLaunchKernelGGL(k_ctl_seeds, dim3(1), dim3(1), 0, s, ctl, win, P);
+void launch_ctl_seeds(SearchCtl* ctl, WinDesc* win, const CtlParams& P, int stage,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_ctl_seeds, dim3(1), dim3(1), 0, s, ctl, win, P, stage);
 }
 
 void launch_ctl_post(SearchCtl* ctl, const CtlParams& P, hipStream_t s) {

@@ -142,7 +142,7 @@ __global__ __launch_bounds__(256) void k_rank_scatter(const int32_t* __restrict_
   for (int b = threadIdx.x; b < kBins; b += 256)
     if (local[b]) base[b] = atomicAdd(&cursor[b], local[b]);
   __syncthreads();
-  if (k < count) out[base[bin] + pos] = list[k];
+  if (k < count) out[base[bin] + pos] = list ? list[k] : (int32_t)k;
 }
 
 }  // namespace
@@ -161,6 +161,15 @@ void launch_rank_groups(const int32_t* list, const int64_t* count, int64_t max_c
   else
     hipLaunchKernelGGL(k_group_score, dim3(blocks), dim3(256), 0, s, list, count, item_rows, gsz,
                        alive, best, N, score);
+  launch_rank_scores(list, count, max_count, score, hist, out, s, false);
+}
+
+void launch_rank_scores(const int32_t* list, const int64_t* count, int64_t max_count,
+                        const uint32_t* score, uint32_t* hist, int32_t* out, hipStream_t s,
+                        bool clear_hist) {
+  if (max_count <= 0) return;
+  const unsigned blocks = (unsigned)((max_count + 255) / 256);
+  if (clear_hist) launch_init_i32(reinterpret_cast<int32_t*>(hist), kBins, 0, s);
   hipLaunchKernelGGL(k_rank_hist, dim3(std::min(blocks, 1024u)), dim3(256), 0, s, score, count,
                      hist);
   hipLaunchKernelGGL(k_rank_offsets, dim3(1), dim3(1024), 0, s, hist);
