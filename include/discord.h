@@ -218,9 +218,15 @@ typedef enum {
     DISCORD_FIELD_ROW_STATE   = 7,  /* int32[N]    0 not scanned, 1 full scan, 2 abandoned */
     DISCORD_FIELD_ROW_MEAN    = 8,  /* double[N]   mean of each row (FP64)              */
     DISCORD_FIELD_ROW_CNORM   = 9,  /* double[N]   centred squared norm of each row     */
-    DISCORD_FIELD_ROW_SIGMA   = 10  /* double[N]   standard deviation of each row, FP64,
+    DISCORD_FIELD_ROW_SIGMA   = 10, /* double[N]   standard deviation of each row, FP64,
                                        sqrt(ROW_CNORM / n) (opts.znorm = 1 plans only;
                                        EINVAL otherwise)                                */
+    DISCORD_FIELD_ROW_BOUND   = 11  /* float[N]    a lower bound of each row's NN d^2: n
+                                       times the squared gap from its mean to the means
+                                       of its non-self rows, at bin resolution; the
+                                       search completes the rows with the largest bound
+                                       first (opts.znorm = 0 plans only; EINVAL
+                                       otherwise)                                       */
 } discord_field;
 
 /* Number of elements of a field (Cand length after prepare; N or table sizes

@@ -36,6 +36,7 @@ FIELD = {
     "csr_offsets": (3, np.int32), "csr_members": (4, np.int32),
     "nn_approx": (5, np.float32), "nn_witness": (6, np.int32), "row_state": (7, np.int32),
     "row_mean": (8, np.float64), "row_cnorm": (9, np.float64), "row_sigma": (10, np.float64),
+    "row_bound": (11, np.float32),
 }
 
 # every symbol the public header declares (checked by the CPU tests)

@@ -72,12 +72,12 @@ struct Layout {
       best, nn_approx, nn_wit, row_state, row_mean, row_cnorm, rows, part_d, part_j, out_d,
       out_j, exact, unc, srch, pair_slots, alive, done, survivors, survivors2, score, rank_hist, gflags,
       cand_groups, bgrp_cnt, bgrp_off, bgrp, max_bucket, mu32, smu32, cn32, r32, row_sigma, sblk,
-      ctl, wins, lb, lb_range, lb_bmin, lb_bmax, total;
+      ctl, wins, lb, lb_range, lb_bmin, lb_bmax, bflags, total;
 };
 
-// work descriptors of one search: the Cand launch and up to three per round
-// (window, two completion stages); rounds grow the window 2x at least, so a
-// sequence of 2^31 entries needs fewer than 40 rounds
+// work descriptors of one search: the Cand launch and one per round; rounds
+// grow the window 2x at least, so a sequence of 2^31 entries needs fewer than
+// 40 rounds
 constexpr int kMaxWins = 128;
 
 Layout make_layout(int64_t m, int32_t n, int dict, bool mixed, bool znorm) {
@@ -129,6 +129,7 @@ Layout make_layout(int64_t m, int32_t n, int dict, bool mixed, bool znorm) {
   L.score = take(sizeof(uint32_t) * G);
   L.rank_hist = take(sizeof(uint32_t) * rank_hist_bins());
   L.gflags = take(sizeof(int32_t) * G);
+  L.bflags = take(sizeof(int32_t) * G);
   L.cand_groups = take(sizeof(int32_t) * G);
   L.bgrp_cnt = take(sizeof(int32_t) * kMaxWords);
   L.bgrp_off = take(sizeof(int32_t) * (kMaxWords + 1));
@@ -574,11 +575,9 @@ int search_enqueue(discord_plan p, SearchRun& run) {
   while ((int64_t{1} << item_shift) < item_rows) ++item_shift;
   const int64_t n_items = (N + item_rows - 1) / item_rows;
   const int64_t target_items = mixed ? 1024 : 4096;   // ~4 wavefronts per SIMD
-  // The launches that complete the best-ranked items hold few items with long
-  // sequences, so they are split finer: 4x the work items (FP32), 2x
-  // (split-BF16, which also completes 16 items instead of 8; below).  FP32:
-  // 15 -> 12 ms to discord on the 2^20 walk (n = 128), 390 -> 293 ms on the
-  // 2^22 series (n = 512); split-BF16: 10 -> 8.7 ms and 220 -> 123 ms.
+  // The launch that completes the bound-ranked items holds few items with
+  // long sequences, so it is split finer: 4x the work items (FP32), 2x
+  // (split-BF16).
   const int64_t seed_items = (mixed ? 2 : 4) * target_items;
   const bool abandon = p->opts.abandon != 0;
   const bool order = p->opts.order != 0;          // Cand first (Algorithm 3)
@@ -599,8 +598,9 @@ int search_enqueue(discord_plan p, SearchRun& run) {
         {pairs, (int64_t)kPairSlots * kPairStride, 0, 1},
         {p->at<uint32_t>(p->L.done), G, 0, 0},
         {gflags, G, 0, 0},
+        {p->at<int32_t>(p->L.bflags), G, 0, 0},
     };
-    launch_fill_many(fills, abandon ? 5 : 3, s);
+    launch_fill_many(fills, abandon ? 6 : 3, s);
   }
   // ---- approximate scan (Algorithms 3 and 4) ----------------------------------
   ScanJob J{};
@@ -689,32 +689,25 @@ int search_enqueue(discord_plan p, SearchRun& run) {
     J.bgrp = p->at<int32_t>(p->L.bgrp);
     J.near_first = near_first;
     // The whole loop is enqueued now and decided on the device (control.hip):
-    // a Cand launch (Algorithm 3), then rounds of Algorithm 4 over every other
-    // item -- a window of each listed item's sequence; for the near-first order
-    // a ranking of the survivors, the best-ranked completed at once (to raise
-    // the best-so-far) and the rest continuing in a window `growth` times
-    // longer; for the other orders the survivors finish in a second window.
-    // Every launch resumes an item where its previous window ended, and rows
-    // already below the best-so-far leave before any work.  The host mirrors
-    // the window sizes to know how many rounds the sequences allow; a loop
-    // that ends sooner leaves the remaining launches without work.
+    // for the near-first order first the items with the largest mean-gap
+    // bound, then a Cand launch (Algorithm 3), then rounds of Algorithm 4 over
+    // every other item -- a window of each listed item's sequence, the items
+    // with rows still live continuing in a window `growth` times longer (for
+    // the other orders the survivors finish in a second window).  Every launch
+    // resumes an item where its previous window ended, and rows already below
+    // the best-so-far leave before any work.  The host mirrors the window
+    // sizes to know how many rounds the sequences allow; a loop that ends
+    // sooner leaves the remaining launches without work.
     SearchCtl* ctl = p->at<SearchCtl>(p->L.ctl);
     WinDesc* wins = p->at<WinDesc>(p->L.wins);
-    const int probe = p->opts.probe_steps > 0 ? p->opts.probe_steps : (near_first ? (mixed ? 4 : 2) : 16);
-    // items completed first after each ranking.  Split-BF16 items beyond
-    // n = 512 are single row blocks, and 64 of them measured best (1.26 -> 1.03 s
-    // at n = 600 and 5.1 -> 3.4 s at n = 1024 on the 10^7-point walk, against 16;
-    // 128 and 256 were slower).  FP32 groups: more for longer windows (n = 512 on
-    // the 2^22 series: 296 -> 277 ms with 256; n = 1024 on the 10^7-point walk:
-    // 3.2 -> 2.3 s with 512), 128 below 512 (256 was slower at n = 128).
-    const int64_t seeds = mixed ? ((n + 15) / 16 > 32 ? 64 : 16)
-                                : (n >= 1024 ? 512 : (n >= 512 ? 256 : 128));
-    // windows double on long sequences and grow 4x on short ones (fewer
-    // rounds where a round costs little work)
-    const int64_t growth = seq_max >= (int64_t{1} << 15) ? 2 : 4;
-    const int64_t seeds2 = 0;
-    const CtlParams P{seq_max, gran,   target_items,         seed_items,
-                      seeds,   seeds2, growth,               near_first ? 1 : 0};
+    // first window: 2 (FP32) / 2 (split-BF16) steps of 512 columns in the
+    // near-first order (split-BF16: 4 -> 2 took the 2^20 walk 4.6 -> 4.1 ms)
+    const int probe = p->opts.probe_steps > 0 ? p->opts.probe_steps : (near_first ? 2 : 16);
+    // windows grow 4x, 2x on sequences of 2^20 entries and more (measured
+    // with the bound-ranked items completed first: FP32 2^20 walk 6.6 -> 6.2
+    // ms with 4x; FP32 10^7-point walk n = 1024 613 -> 559 ms with 2x)
+    const int64_t growth = seq_max >= (int64_t{1} << 20) ? 2 : 4;
+    const CtlParams P{seq_max, gran, target_items, growth, near_first ? 1 : 0};
     // A launch whose work is decided on the device gets a grid sized for the
     // most work its descriptor can hold, at most `cap` work items (beyond, its
     // wavefronts or workgroups stride over the work).
@@ -733,26 +726,23 @@ int search_enqueue(discord_plan p, SearchRun& run) {
                            p->at<int32_t>(p->L.cand_groups), &sc->n_cand_groups, s);
     }
     const int64_t width0 = (int64_t)probe * gran;
-    launch_ctl_start(ctl, n_items, width0, &sc->n_cand_groups, cand ? &wins[nw] : nullptr, P, s);
-    if (cand) {
-      J.win = &wins[nw++];
-      J.groups = p->at<int32_t>(p->L.cand_groups);
-      J.skip = nullptr;
-      J.precheck = 0;
-      J.max_work = grid_work(std::min<int64_t>(n_items, p->cand_count), seq_max, target_items);
-      if ((st = launch("scan (Cand)"))) return st;
-    }
+    WinDesc* cand_win = cand ? &wins[nw++] : nullptr;
+    launch_ctl_start(ctl, n_items, width0, &sc->n_cand_groups, cand_win, P, s);
+    // survivor lists: round r lists its survivors in lists[r & 1]; the bound
+    // ranking goes to lists[1] before the first round
     int32_t* const lists[2] = {p->at<int32_t>(p->L.survivors), p->at<int32_t>(p->L.survivors2)};
     int32_t* const spare = lists[1];
-    // Near-first order, global normalisation: before the first window, the
-    // items whose rows have the largest mean-gap bound of their NN (bound.hip)
-    // are completed, which puts the best-so-far near its final value.  Their
-    // items are then skipped by the first window, like the Cand items.  16
-    // FP32 groups / 2 split-BF16 items measured best among 1..64 (time to
-    // discord, FP32 / split-BF16: 2^20 walk n = 128 12.3 -> 8.3 / 8.2 -> 5.5 ms;
-    // 2^20 noisy walk n = 256 22.9 -> 10.3 / 12.1 -> 5.1 ms; 2^22 series
-    // n = 512 277 -> 65 / 126 -> 31 ms).
+    // Near-first order, global normalisation: first of all, the items whose
+    // rows have the largest mean-gap bound of their NN (bound.hip) are
+    // completed, which puts the best-so-far near its final value; the Cand
+    // rows and every later window then leave early against it.  These items
+    // are skipped by the Cand launch and the first window.  16 FP32 groups / 2
+    // split-BF16 items measured best among 1..64 (time to discord, FP32 /
+    // split-BF16: 2^20 walk n = 128 12.3 -> 8.3 / 8.2 -> 5.5 ms; 2^20 noisy walk
+    // n = 256 22.9 -> 10.3 / 12.1 -> 5.1 ms; 2^22 series n = 512 277 -> 65 /
+    // 126 -> 31 ms, with these items searched after Cand).
     const int64_t bound_seeds = (near_first && !zn) ? std::min<int64_t>(n_items, mixed ? 2 : 16) : 0;
+    int32_t* bflags = p->at<int32_t>(p->L.bflags);
     if (bound_seeds > 0) {
       launch_item_bound(p->at<float>(p->L.lb), N, item_rows, n_items, p->at<uint32_t>(p->L.score),
                         s);
@@ -767,49 +757,38 @@ int search_enqueue(discord_plan p, SearchRun& run) {
       J.chunks = wd.chunks;
       J.seq_begin = 0;
       J.seq_chunk = wd.seq_chunk;
-      J.skip = cand ? gflags : nullptr;
-      J.precheck = 1;
+      J.skip = nullptr;
+      J.precheck = 0;
       if ((st = launch("scan (bound seeds)"))) return st;
       launch_flag_items(spare, bound_seeds, gflags, s);
+      launch_flag_items(spare, bound_seeds, bflags, s);
+    }
+    if (cand) {
+      // Algorithm 3: the items holding Cand rows, each over its whole sequence
+      J.win = cand_win;
+      J.groups = p->at<int32_t>(p->L.cand_groups);
+      J.skip = bound_seeds > 0 ? bflags : nullptr;
+      J.precheck = 0;
+      J.max_work = grid_work(std::min<int64_t>(n_items, p->cand_count), seq_max, target_items);
+      if ((st = launch("scan (Cand)"))) return st;
     }
     int64_t covered = 0, width = width0;   // the device's window sizes while its loop runs
     for (int round = 0;; ++round) {
       const int64_t end = std::min<int64_t>(seq_max, covered + width);
-      if (nw + 3 > kMaxWins) return fail(p, DISCORD_EDEVICE, "search needs too many rounds");
+      if (nw + 1 > kMaxWins) return fail(p, DISCORD_EDEVICE, "search needs too many rounds");
       WinDesc* w = &wins[nw++];
       launch_ctl_window(ctl, w, n_surv, P, s);
       J.win = w;
-      J.groups = round == 0 ? nullptr : (near_first ? spare : lists[(round - 1) & 1]);
+      J.groups = round == 0 ? nullptr : lists[(round - 1) & 1];
       J.skip = (round == 0 && (cand || bound_seeds > 0)) ? gflags : nullptr;
       J.precheck = round > 0;
-      J.survivors = near_first ? lists[0] : lists[round & 1];
+      J.survivors = lists[round & 1];
       J.max_work = grid_work(n_items, end - covered, target_items);
       if ((st = launch("scan (window)"))) return st;
       if (end >= seq_max) break;                  // final for every item
       launch_ctl_after(ctl, n_surv, P, s);
       covered = end;
-      if (!near_first) {
-        width = seq_max;
-        continue;
-      }
-      // rank the survivors into `spare`, complete the best-ranked; the rest
-      // continue from the ranked list
-      launch_rank_groups(lists[0], &ctl->count, n_items, item_rows, gsz, alive, best, N,
-                         p->at<uint32_t>(p->L.score), p->at<uint32_t>(p->L.rank_hist), spare, s);
-      LAUNCH_OK(p, "rank");
-      for (int stage = 0; stage < (seeds2 > 0 ? 2 : 1); ++stage) {
-        WinDesc* ws = &wins[nw++];
-        launch_ctl_seeds(ctl, ws, P, stage, s);
-        J.win = ws;
-        J.groups = spare;
-        J.skip = nullptr;
-        J.precheck = 1;
-        J.max_work = grid_work(std::min<int64_t>(stage ? seeds2 : seeds, n_items), seq_max - covered,
-                               seed_items);
-        if ((st = launch("scan (seeds)"))) return st;
-      }
-      launch_ctl_post(ctl, P, s);
-      width *= growth;
+      width = near_first ? width * growth : seq_max;
     }
     J.win = nullptr;
   }
@@ -1013,6 +992,7 @@ int64_t discord_plan_count(discord_plan p, int32_t field) {
     case DISCORD_FIELD_ROW_MEAN:
     case DISCORD_FIELD_ROW_CNORM: return p->N;
     case DISCORD_FIELD_ROW_SIGMA: return p->opts.znorm ? p->N : DISCORD_EINVAL;
+    case DISCORD_FIELD_ROW_BOUND: return p->opts.znorm ? DISCORD_EINVAL : p->N;
     case DISCORD_FIELD_HIST: return p->dict;
     case DISCORD_FIELD_CSR_OFFSETS: return p->dict + 1;
     case DISCORD_FIELD_CAND: return p->cand_count;
@@ -1037,6 +1017,7 @@ int discord_plan_copy(discord_plan p, int32_t field, void* host_dst, size_t byte
     case DISCORD_FIELD_ROW_MEAN: off = p->L.row_mean; elem = 8; break;
     case DISCORD_FIELD_ROW_CNORM: off = p->L.row_cnorm; elem = 8; break;
     case DISCORD_FIELD_ROW_SIGMA: off = p->L.row_sigma; elem = 8; break;
+    case DISCORD_FIELD_ROW_BOUND: off = p->L.lb; break;
     default: return DISCORD_EINVAL;
   }
   if (bytes < elem * (size_t)count) return DISCORD_EINVAL;

@@ -12,18 +12,19 @@
 // to its final value before the bulk of the rows are searched.  The bound only
 // orders work: the search's result never depends on it.
 //
-// Evaluation: the row means are binned (B bins over [min, max]); each bin keeps
-// its smallest and largest row index.  Bin c holds a non-self match of row i
-// exactly when max_c >= i + n or min_c <= i - n, so the first such bin at
-// distance d from row i's own bin bounds the nearest non-self mean below by
-// (d - 1) bin widths.
+// Evaluation: the row means are binned (B bins over [min, max], about 16 rows
+// per bin on average, B <= 65536); each bin keeps its smallest and largest row
+// index.  Bin c holds a non-self match of row i exactly when max_c >= i + n or
+// min_c <= i - n, so the first such bin at distance d from row i's own bin
+// bounds the nearest non-self mean below by (d - 1) bin widths.  With bins
+// that dense, a row leaves the outward search after a bin or two unless its
+// level is rare, which is what the bound is for.
 #include "internal.hpp"
 
 namespace dd {
 namespace {
 
-constexpr int kBoundBins = 65536;
-constexpr int kBoundReach = 4096;   // bins searched on each side before giving up
+constexpr int kBoundBins = 65536;   // most bins (the scratch arrays' size)
 
 // order-preserving map of doubles to unsigned integers
 __device__ __forceinline__ uint64_t ordered(double x) {
@@ -65,29 +66,31 @@ __global__ __launch_bounds__(256) void k_mean_range(const double* __restrict__ m
 
 struct Bins {
   double lo, inv_width, width;
+  int count;
 };
 
-__device__ __forceinline__ Bins bins_of(const uint64_t* __restrict__ range) {
+__device__ __forceinline__ Bins bins_of(const uint64_t* __restrict__ range, int count) {
   const double lo = unordered(range[0]), hi = unordered(range[1]);
   const double span = hi - lo;
   Bins b;
   b.lo = lo;
-  b.width = span > 0.0 ? span / kBoundBins : 1.0;
-  b.inv_width = span > 0.0 ? kBoundBins / span : 0.0;
+  b.width = span > 0.0 ? span / count : 1.0;
+  b.inv_width = span > 0.0 ? count / span : 0.0;
+  b.count = count;
   return b;
 }
 
 __device__ __forceinline__ int bin_of(const Bins& b, double x) {
   const double t = (x - b.lo) * b.inv_width;
   const int k = t > 0.0 ? (int)t : 0;
-  return k < kBoundBins - 1 ? k : kBoundBins - 1;
+  return k < b.count - 1 ? k : b.count - 1;
 }
 
 __global__ __launch_bounds__(256) void k_bin_rows(const double* __restrict__ mu, int64_t N,
-                                                  const uint64_t* __restrict__ range,
+                                                  const uint64_t* __restrict__ range, int nbins,
                                                   int32_t* __restrict__ bmin,
                                                   int32_t* __restrict__ bmax) {
-  const Bins b = bins_of(range);
+  const Bins b = bins_of(range, nbins);
   for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < N; i += (int64_t)gridDim.x * 256) {
     const int k = bin_of(b, mu[i]);
     atomicMin(&bmin[k], (int32_t)i);
@@ -96,20 +99,20 @@ __global__ __launch_bounds__(256) void k_bin_rows(const double* __restrict__ mu,
 }
 
 __global__ __launch_bounds__(256) void k_row_bound(const double* __restrict__ mu, int64_t N, int n,
-                                                   const uint64_t* __restrict__ range,
+                                                   const uint64_t* __restrict__ range, int nbins,
                                                    const int32_t* __restrict__ bmin,
                                                    const int32_t* __restrict__ bmax,
                                                    float* __restrict__ lb) {
-  const Bins b = bins_of(range);
+  const Bins b = bins_of(range, nbins);
   for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < N; i += (int64_t)gridDim.x * 256) {
     const int k = bin_of(b, mu[i]);
     const int64_t lo_row = i - n, hi_row = i + n;   // non-self: j <= lo_row or j >= hi_row
     int d = 0;
-    for (; d <= kBoundReach; ++d) {
+    for (;; ++d) {
       const int c0 = k - d, c1 = k + d;
       const bool ok0 = c0 >= 0 && (bmax[c0] >= hi_row || bmin[c0] <= lo_row);
-      const bool ok1 = c1 < kBoundBins && (bmax[c1] >= hi_row || bmin[c1] <= lo_row);
-      if (ok0 || ok1 || (c0 < 0 && c1 >= kBoundBins)) break;
+      const bool ok1 = c1 < nbins && (bmax[c1] >= hi_row || bmin[c1] <= lo_row);
+      if (ok0 || ok1 || (c0 < 0 && c1 >= nbins)) break;
     }
     const double gap = (d > 1 ? d - 1 : 0) * b.width;
     lb[i] = (float)(n * gap * gap);
@@ -149,18 +152,20 @@ size_t bound_bins() { return kBoundBins; }
 
 void launch_row_bound(const double* row_mean, int64_t N, int n, uint64_t* range, int32_t* bmin,
                       int32_t* bmax, float* lb, hipStream_t s) {
+  int nbins = 64;   // a power of two near N / 16, within [64, kBoundBins]
+  while (nbins < kBoundBins && (int64_t)nbins * 16 < N) nbins *= 2;
   const FillOp fills[] = {
       {range, 1, ~0ull, 1},
       {range + 1, 1, 0, 1},
-      {bmin, kBoundBins, 0x7FFFFFFF, 0},
-      {bmax, kBoundBins, 0xFFFFFFFFu, 0},
+      {bmin, nbins, 0x7FFFFFFF, 0},
+      {bmax, nbins, 0xFFFFFFFFu, 0},
   };
   launch_fill_many(fills, 4, s);
   hipLaunchKernelGGL(k_mean_range, dim3(blocks_for(N)), dim3(256), 0, s, row_mean, N, range);
-  hipLaunchKernelGGL(k_bin_rows, dim3(blocks_for(N)), dim3(256), 0, s, row_mean, N, range, bmin,
-                     bmax);
+  hipLaunchKernelGGL(k_bin_rows, dim3(blocks_for(N)), dim3(256), 0, s, row_mean, N, range, nbins,
+                     bmin, bmax);
   hipLaunchKernelGGL(k_row_bound, dim3(blocks_for(N)), dim3(256), 0, s, row_mean, N, n, range,
-                     bmin, bmax, lb);
+                     nbins, bmin, bmax, lb);
 }
 
 void launch_item_bound(const float* lb, int64_t N, int64_t item_rows, int64_t n_items,

@@ -3,9 +3,7 @@
 // Algorithms 3 and 4 visit rows, and each row's columns, in some order and
 // stop a row at its first distance below the best-so-far.  On the GPU every
 // item (a fixed set of consecutive rows) walks its column sequence in windows:
-// the first window for every item, then, after each window, the items that
-// still have a live row are ranked (rank.hip), the best-ranked are completed
-// over the rest of their sequences (raising the best-so-far), and the others
+// the first window for every item, then the items that still have a live row
 // continue in a longer window.  Which items a launch covers and how they are
 // split into chunks depends on how many survived the previous launch, a count
 // that exists only on the device.  These one-thread kernels turn those counts
@@ -43,8 +41,6 @@ __global__ void k_ctl_start(SearchCtl* ctl, int64_t count, int64_t width,
   ctl->width = width;
   ctl->in_off = 0;
   ctl->end = 0;
-  ctl->k = 0;
-  ctl->k2 = 0;
   if (cand_win) set_window(cand_win, *cand_count, 0, P.seq_max, P.target, P.gran, 0);
 }
 
@@ -66,35 +62,9 @@ __global__ void k_ctl_after(SearchCtl* ctl, const uint32_t* n_surv, CtlParams P)
   ctl->covered = ctl->end;
   ctl->count = hs;
   ctl->in_off = 0;
-  if (!P.near_first) ctl->width = P.seq_max;   // the survivors finish in one more window
-}
-
-__global__ void k_ctl_seeds(SearchCtl* ctl, WinDesc* win, CtlParams P, int stage) {
-  const int64_t c = ctl->count;
-  if (stage == 0) {
-    const int64_t k = c < P.seeds ? c : P.seeds;
-    set_window(win, k, ctl->covered, P.seq_max, P.seed_target, P.gran, 0);
-    ctl->k = k;
-    ctl->k2 = 0;
-  } else {
-    const int64_t rest = c - ctl->k;
-    const int64_t k2 = rest < P.seeds2 ? rest : P.seeds2;
-    set_window(win, k2, ctl->covered, P.seq_max, P.seed_target, P.gran, ctl->k);
-    ctl->k2 = k2;
-  }
-}
-
-__global__ void k_ctl_post(SearchCtl* ctl, CtlParams P) {
-  const int64_t c = ctl->count;
-  if (c == 0) return;
-  const int64_t done = ctl->k + ctl->k2;
-  if (done >= c) {   // the ranked list was completed whole
-    ctl->count = 0;
-    return;
-  }
-  ctl->in_off = done;
-  ctl->count = c - done;
-  ctl->width *= P.growth;
+  // near-first: the next window `growth` times longer; else the survivors
+  // finish in one more window
+  ctl->width = P.near_first ? ctl->width * P.growth : P.seq_max;
 }
 
 }  // namespace
@@ -117,15 +87,6 @@ void launch_ctl_window(SearchCtl* ctl, WinDesc* win, uint32_t* n_surv, const Ctl
 
 void launch_ctl_after(SearchCtl* ctl, const uint32_t* n_surv, const CtlParams& P, hipStream_t s) {
   hipLaunchKernelGGL(k_ctl_after, dim3(1), dim3(1), 0, s, ctl, n_surv, P);
-}
-
-void launch_ctl_seeds(SearchCtl* ctl, WinDesc* win, const CtlParams& P, int stage,
-                      hipStream_t s) {
-  hipLaunchKernelGGL(k_ctl_seeds, dim3(1), dim3(1), 0, s, ctl, win, P, stage);
-}
-
-void launch_ctl_post(SearchCtl* ctl, const CtlParams& P, hipStream_t s) {
-  hipLaunchKernelGGL(k_ctl_post, dim3(1), dim3(1), 0, s, ctl, P);
 }
 
 }  // namespace dd

@@ -212,18 +212,13 @@ struct SearchCtl {
   int64_t width;    // entries of the next window
   int64_t in_off;   // first entry of the next window's item list
   int64_t end;      // end of the current window
-  int64_t k;        // items of the round's first completion launch
-  int64_t k2;       // items of its second completion launch
 };
 struct CtlParams {
   int64_t seq_max;      // longest column sequence (entries)
   int64_t gran;         // entries per 512 columns (the chunk granule)
   int64_t target;       // work items a window launch aims at
-  int64_t seed_target;  // work items a completion launch aims at
-  int64_t seeds;        // best-ranked items completed first after each ranking
-  int64_t seeds2;       // the next best-ranked, completed after them (0: none)
   int64_t growth;       // window growth per round
-  int32_t near_first;   // 1: rank and complete between windows; 0: two windows only
+  int32_t near_first;   // 1: windows grow by `growth`; 0: the second window ends the sequences
 };
 // entries [begin, end) of `items` items, split into chunks so that the launch
 // holds about `target` work items (the host computes the same split for the
@@ -239,13 +234,8 @@ void launch_ctl_start(SearchCtl* ctl, int64_t count, int64_t width, const int32_
 void launch_ctl_window(SearchCtl* ctl, WinDesc* win, uint32_t* n_surv, const CtlParams& P,
                        hipStream_t s);
 // after a window: the loop ends when the sequences are done or no item has a
-// live row; else the survivors are the next list
+// live row; else the survivors are the next list and the window grows
 void launch_ctl_after(SearchCtl* ctl, const uint32_t* n_surv, const CtlParams& P, hipStream_t s);
-// completion launches over the rest of the items' sequences: stage 0 the
-// best-ranked min(count, seeds) items, stage 1 the next min(count - k, seeds2)
-void launch_ctl_seeds(SearchCtl* ctl, WinDesc* win, const CtlParams& P, int stage, hipStream_t s);
-// after the completion launch: the rest continue in a window `growth` times longer
-void launch_ctl_post(SearchCtl* ctl, const CtlParams& P, hipStream_t s);
 
 // ---- bound.hip ----------------------------------------------------------------
 // lb[i] <= NN(i): n times the squared gap from row i's mean to the nearest mean
@@ -261,17 +251,11 @@ void launch_item_bound(const float* lb, int64_t N, int64_t item_rows, int64_t n_
 void launch_flag_items(const int32_t* list, int64_t count, int32_t* flags, hipStream_t s);
 
 // ---- rank.hip -----------------------------------------------------------------
-// The *count items (item_rows consecutive rows each; alive masks per gsz rows)
-// of `list`, in descending order of the largest published minimum of a live row
-// (score and hist are scratch: max_count and rank_hist_bins() entries).  The
-// count is read on the device; the grids are sized for max_count.
+// A descending counting sort of the *count entries of `list` (nullptr: 0, 1,
+// ...) by score[k] (the bits of a non-negative float; hist is scratch of
+// rank_hist_bins() entries, cleared first when clear_hist).  The count is read
+// on the device; the grids are sized for max_count.
 size_t rank_hist_bins();
-void launch_rank_groups(const int32_t* list, const int64_t* count, int64_t max_count,
-                        int64_t item_rows, int gsz, const uint32_t* alive, const uint64_t* best,
-                        int64_t N, uint32_t* score, uint32_t* hist, int32_t* out, hipStream_t s);
-// The same descending counting sort of the *count entries of `list` (nullptr:
-// 0, 1, ...) by the given score[k] (the bits of a non-negative float); with
-// clear_hist the histogram is cleared first.
 void launch_rank_scores(const int32_t* list, const int64_t* count, int64_t max_count,
                         const uint32_t* score, uint32_t* hist, int32_t* out, hipStream_t s,
                         bool clear_hist = true);

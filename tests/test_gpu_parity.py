@@ -361,3 +361,22 @@ def _walk10m(n):
         _W10M.clear()
         _W10M[n] = workloads.walk10m(n)
     return _W10M[n]
+
+
+@pytest.mark.parametrize("m,n,seed", [(3000, 37, 1), (4096, 64, 2), (20000, 128, 3), (9000, 700, 4)])
+def test_row_bound_below_exact_nn(gpu, m, n, seed):
+    """The mean-gap bound that orders the search is a true lower bound of every
+    row's exact NN (oracle profile), and it is not vacuous: the rows with the
+    largest bound are near the top of the NN profile."""
+    T = workloads.random_walk(m, seed=700 + seed)
+    ref = oracle.discord(T, n, profile=True)
+    prof = ref["profile"]
+    with gpu.Plan(T, n) as p:
+        lb = p.copy("row_bound").astype(np.float64)
+        r = p.search()
+    has = np.isfinite(prof)
+    assert np.all(lb[has] <= prof[has] * (1 + 1e-6) + 1e-9)
+    assert lb.max() > 0
+    top = np.argsort(-lb)[:16]
+    assert np.max(prof[top]) >= np.quantile(prof[has], 0.75)
+    assert r.index == ref["index"]
