@@ -117,6 +117,9 @@ typedef struct {
     double   ms_prepare;      /* device time of discord_prepare (HIP events)         */
     double   ms_search;       /* device time of discord_search (HIP events)          */
     double   ms_scan;         /* of which: the approximate scan launches, summed     */
+    uint64_t scan_launches;   /* scan launches enqueued (the device-decided search
+                                 enqueues a fixed number; those past the end of its
+                                 loop find no work)                                 */
 } discord_result;
 
 typedef struct discord_plan_s* discord_plan;

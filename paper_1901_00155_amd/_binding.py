@@ -71,7 +71,7 @@ class Result(ctypes.Structure):
                 ("pairs_evaluated", ctypes.c_uint64), ("rows_rescored", ctypes.c_uint64),
                 ("rows_abandoned", ctypes.c_uint64), ("cand_rows", ctypes.c_uint64),
                 ("ms_prepare", ctypes.c_double), ("ms_search", ctypes.c_double),
-                ("ms_scan", ctypes.c_double)]
+                ("ms_scan", ctypes.c_double), ("scan_launches", ctypes.c_uint64)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -75,9 +75,9 @@ struct Layout {
       ctl, wins, lb, lb_range, lb_bmin, lb_bmax, bflags, total;
 };
 
-// work descriptors of one search: the Cand launch and one per round; rounds
-// grow the window 2x at least, so a sequence of 2^31 entries needs fewer than
-// 40 rounds
+// work descriptors of one search: the Cand and bound launches and one or two
+// per round (window, completion); rounds grow the window 2x at least, so a
+// sequence of 2^31 entries needs fewer than 40 rounds
 constexpr int kMaxWins = 128;
 
 Layout make_layout(int64_t m, int32_t n, int dict, bool mixed, bool znorm) {
@@ -194,6 +194,7 @@ struct discord_plan_s {
   bool searched = false;
   bool timed = true;          // false: no HIP events (the allocation-free entry point)
   hipGraphExec_t gexec = nullptr;   // the search captured by discord_search_graph
+  int glaunches = 0;                // scan launches in that graph
   void* hout = nullptr;             // pinned block the captured search reads back into
   char err[512] = {0};
 
@@ -390,95 +391,125 @@ void init_plan(discord_plan p, int64_t m, int32_t n, const discord_opts& o) {
   p->L = make_layout(m, n, p->dict, o.precision == DISCORD_PREC_BF16X3, o.znorm != 0);
 }
 
-// The preparation kernels on a plan whose arena and stream are set.
-int prepare_run(discord_plan p, const float* T) {
+// What a plan reads back to the host: the preparation's statistics and
+// counts, and the search's counters and certified answer.
+struct HostOut {
+  SearchScalars sc;
+  Exact ex;
+  double stats[8];   // eq. (2): mean, sigma (as laid out on the device) ...
+  int32_t bad[4];    // ... followed by the NaN/Inf flag
+  int32_t cand[8];   // |Cand| at [0], the longest bucket at [4]
+};
+static_assert(offsetof(HostOut, bad) == offsetof(HostOut, stats) + sizeof(double) * 8,
+              "the statistics block and the flag are copied as one");
+
+// The preparation kernels on a plan whose arena and stream are set, with no
+// host synchronisation: on a series with NaN/Inf or sigma = 0 they run on
+// meaningless values (every index they form stays in range), and the search
+// loop stops at once (control.hip) -- the error is reported from the readback.
+int prepare_enqueue(discord_plan p, const float* T) {
   const int64_t m = p->m;
   const int32_t n = p->n;
   const discord_opts& o = p->opts;
+  hipStream_t s = p->stream;
+  // padded series: zero pads, then the values
+  float* Tbase = p->at<float>(p->L.T);
+  {
+    const FillOp fills[] = {
+        {Tbase, kFrontPad, 0, 0},
+        {Tbase + kFrontPad + m, kBackPad, 0, 0},
+        {p->at<int32_t>(p->L.bad), 4, 0, 0},
+        {p->at<int32_t>(p->L.hist), kMaxWords, 0, 0},
+    };
+    launch_fill_many(fills, 4, s);
+  }
+  const hipMemcpyKind kind = is_device_pointer(T) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  HIP_TRY(p, hipMemcpyAsync(p->Tp(), T, sizeof(float) * m, kind, s));
+  // eq. (2)
+  launch_stats(p->Tp(), m, p->at<double>(p->L.partials), p->at<double>(p->L.stats),
+               p->at<int32_t>(p->L.bad), s);
+  LAUNCH_OK(p, "stats");
+  // row statistics, the mean-gap bound, PAA -> SAX -> word ids, histogram,
+  // Cand, Index_Word
+  const bool zn = o.znorm != 0;
+  double* row_sigma = zn ? p->at<double>(p->L.row_sigma) : nullptr;
+  launch_row_stats(p->Tp(), p->N, n, p->at<double>(p->L.row_mean), p->at<double>(p->L.row_cnorm),
+                   row_sigma, s);
+  if (!zn)
+    launch_row_bound(p->at<double>(p->L.row_mean), p->N, n, p->at<uint64_t>(p->L.lb_range),
+                     p->at<int32_t>(p->L.lb_bmin), p->at<int32_t>(p->L.lb_bmax),
+                     p->at<float>(p->L.lb), s);
+  launch_sax(p->Tp(), p->N, n, o.paa_w, o.alphabet, p->at<double>(p->L.stats),
+             zn ? p->at<double>(p->L.row_mean) : nullptr, row_sigma,
+             p->at<int32_t>(p->L.words), p->at<int32_t>(p->L.hist), s);
+  launch_cand(p->at<int32_t>(p->L.words), p->at<int32_t>(p->L.hist), p->N, p->dict,
+              p->at<int32_t>(p->L.minfreq), p->at<int32_t>(p->L.seg), p->at<int32_t>(p->L.cand),
+              p->at<int32_t>(p->L.cand_count), s);
+  launch_csr(p->at<int32_t>(p->L.words), p->at<int32_t>(p->L.hist), p->N, p->dict,
+             p->at<int32_t>(p->L.seg), p->at<int32_t>(p->L.csr_off),
+             p->at<int32_t>(p->L.csr_mem), s);
+  const bool mixed = o.precision == DISCORD_PREC_BF16X3;
+  // FP32 centres and scales: the split-BF16 operands, and under per-window
+  // normalisation also the FP32 scan's
+  float* r32 = zn ? p->at<float>(p->L.r32) : nullptr;
+  if (mixed || zn)
+    launch_row_stats32(p->Tp(), p->N, n, p->N + kRowPad, p->at<double>(p->L.row_mean), row_sigma,
+                       p->at<double>(p->L.stats), p->at<float>(p->L.mu32),
+                       p->at<float>(p->L.smu32), p->at<float>(p->L.cn32), r32, s);
+  if (mixed)
+    launch_split_blocks(p->Tp(), p->N, n, p->at<float>(p->L.mu32), p->at<float>(p->L.cn32), r32,
+                        p->at<uint4>(p->L.sblk), s);
+  // the bucket column blocks serve only the PhiDD order (same-word columns first)
+  if (o.order == 1) {
+    launch_bucket_groups(p->at<int32_t>(p->L.csr_off), p->at<int32_t>(p->L.csr_mem), p->dict,
+                         mixed ? 5 : 3,
+                         p->at<int32_t>(p->L.bgrp_cnt), p->at<int32_t>(p->L.bgrp_off),
+                         p->at<int32_t>(p->L.bgrp), s);
+    launch_max_bucket(p->at<int32_t>(p->L.bgrp_off), p->dict, p->at<int32_t>(p->L.max_bucket), s);
+  }
+  LAUNCH_OK(p, "prepare kernels");
+  p->cand_count = -1;   // on the device only, until a readback
+  p->max_bucket = -1;
+  return DISCORD_OK;
+}
+
+// Copies of the preparation's statistics and counts into h.
+int prepare_readback(discord_plan p, HostOut* h) {
+  hipStream_t s = p->stream;
+  HIP_TRY(p, hipMemcpyAsync(h->stats, p->at<double>(p->L.stats),
+                            sizeof(double) * 8 + sizeof(int32_t) * 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(p, hipMemcpyAsync(h->cand, p->at<int32_t>(p->L.cand_count), sizeof(h->cand),
+                            hipMemcpyDeviceToHost, s));
+  return DISCORD_OK;
+}
+
+// After the copies of prepare_readback have landed: the errors of eq. (2) and
+// the counts the host uses.
+int prepare_check(discord_plan p, const HostOut& h) {
+  if (h.bad[0]) return fail(p, DISCORD_EINVAL, "series holds NaN or Inf");
+  p->mu = h.stats[0];
+  p->sigma = h.stats[1];
+  if (!(p->sigma > 0.0)) return fail(p, DISCORD_ECONST, "sigma == 0");
+  p->cand_count = h.cand[0];
+  p->max_bucket = p->opts.order == 1 ? h.cand[4] : 0;
+  return DISCORD_OK;
+}
+
+// The preparation of discord_prepare: the kernels and one synchronisation.
+int prepare_run(discord_plan p, const float* T) {
   EventPair ev(0, p->timed);
   hipStream_t s = p->stream;
-  {
-    if (!ev.ready()) return fail(p, DISCORD_EDEVICE, "hipEventCreate failed");
-    HIP_TRY(p, ev.start(s));
-    // padded series: zero pads, then the values
-    float* Tbase = p->at<float>(p->L.T);
-    {
-      const FillOp fills[] = {
-          {Tbase, kFrontPad, 0, 0},
-          {Tbase + kFrontPad + m, kBackPad, 0, 0},
-          {p->at<int32_t>(p->L.bad), 4, 0, 0},
-          {p->at<int32_t>(p->L.hist), kMaxWords, 0, 0},
-      };
-      launch_fill_many(fills, 4, s);
-    }
-    const hipMemcpyKind kind = is_device_pointer(T) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-    HIP_TRY(p, hipMemcpyAsync(p->Tp(), T, sizeof(float) * m, kind, s));
-    // eq. (2)
-    launch_stats(p->Tp(), m, p->at<double>(p->L.partials), p->at<double>(p->L.stats),
-                 p->at<int32_t>(p->L.bad), s);
-    LAUNCH_OK(p, "stats");
-    struct {
-      double stats[8];
-      int32_t bad[4];
-    } hs;   // the statistics block followed by the flag, as laid out on the device
-    static_assert(sizeof(hs) == sizeof(double) * 8 + sizeof(int32_t) * 4, "layout");
-    HIP_TRY(p, hipMemcpyAsync(&hs, p->at<double>(p->L.stats), sizeof(hs), hipMemcpyDeviceToHost, s));
-    HIP_TRY(p, hipStreamSynchronize(s));
-    const double* hstats = hs.stats;
-    const int32_t hbad = hs.bad[0];
-    if (hbad) return fail(p, DISCORD_EINVAL, "series holds NaN or Inf");
-    p->mu = hstats[0];
-    p->sigma = hstats[1];
-    if (!(p->sigma > 0.0)) return fail(p, DISCORD_ECONST, "sigma == 0");
-    // row statistics, PAA -> SAX -> word ids, histogram, Cand, Index_Word
-    const bool zn = o.znorm != 0;
-    double* row_sigma = zn ? p->at<double>(p->L.row_sigma) : nullptr;
-    launch_row_stats(p->Tp(), p->N, n, p->at<double>(p->L.row_mean), p->at<double>(p->L.row_cnorm),
-                     row_sigma, s);
-    if (!zn)
-      launch_row_bound(p->at<double>(p->L.row_mean), p->N, n, p->at<uint64_t>(p->L.lb_range),
-                       p->at<int32_t>(p->L.lb_bmin), p->at<int32_t>(p->L.lb_bmax),
-                       p->at<float>(p->L.lb), s);
-    launch_sax(p->Tp(), p->N, n, o.paa_w, o.alphabet, p->at<double>(p->L.stats),
-               zn ? p->at<double>(p->L.row_mean) : nullptr, row_sigma,
-               p->at<int32_t>(p->L.words), p->at<int32_t>(p->L.hist), s);
-    launch_cand(p->at<int32_t>(p->L.words), p->at<int32_t>(p->L.hist), p->N, p->dict,
-                p->at<int32_t>(p->L.minfreq), p->at<int32_t>(p->L.seg), p->at<int32_t>(p->L.cand),
-                p->at<int32_t>(p->L.cand_count), s);
-    launch_csr(p->at<int32_t>(p->L.words), p->at<int32_t>(p->L.hist), p->N, p->dict,
-               p->at<int32_t>(p->L.seg), p->at<int32_t>(p->L.csr_off),
-               p->at<int32_t>(p->L.csr_mem), s);
-    const bool mixed = o.precision == DISCORD_PREC_BF16X3;
-    // FP32 centres and scales: the split-BF16 operands, and under per-window
-    // normalisation also the FP32 scan's
-    float* r32 = zn ? p->at<float>(p->L.r32) : nullptr;
-    if (mixed || zn)
-      launch_row_stats32(p->Tp(), p->N, n, p->N + kRowPad, p->at<double>(p->L.row_mean), row_sigma,
-                         p->at<double>(p->L.stats), p->at<float>(p->L.mu32),
-                         p->at<float>(p->L.smu32), p->at<float>(p->L.cn32), r32, s);
-    if (mixed)
-      launch_split_blocks(p->Tp(), p->N, n, p->at<float>(p->L.mu32), p->at<float>(p->L.cn32), r32,
-                          p->at<uint4>(p->L.sblk), s);
-    // the bucket column blocks serve only the PhiDD order (same-word columns first)
-    const bool buckets = o.order == 1;
-    if (buckets) {
-      launch_bucket_groups(p->at<int32_t>(p->L.csr_off), p->at<int32_t>(p->L.csr_mem), p->dict,
-                           mixed ? 5 : 3,
-                           p->at<int32_t>(p->L.bgrp_cnt), p->at<int32_t>(p->L.bgrp_off),
-                           p->at<int32_t>(p->L.bgrp), s);
-      launch_max_bucket(p->at<int32_t>(p->L.bgrp_off), p->dict, p->at<int32_t>(p->L.max_bucket), s);
-    }
-    LAUNCH_OK(p, "prepare kernels");
-    int32_t hcm[8] = {0};   // |Cand| at [0], the longest bucket at [4]
-    HIP_TRY(p, hipMemcpyAsync(hcm, p->at<int32_t>(p->L.cand_count), sizeof(hcm),
-                              hipMemcpyDeviceToHost, s));
-    HIP_TRY(p, ev.stop(s));
-    HIP_TRY(p, hipStreamSynchronize(s));
-    p->cand_count = hcm[0];
-    p->max_bucket = buckets ? hcm[4] : 0;
-    p->ms_prepare = ev.ms();
-    return DISCORD_OK;
-  }
+  if (!ev.ready()) return fail(p, DISCORD_EDEVICE, "hipEventCreate failed");
+  HIP_TRY(p, ev.start(s));
+  int st = prepare_enqueue(p, T);
+  if (st != DISCORD_OK) return st;
+  HostOut h;
+  if ((st = prepare_readback(p, &h)) != DISCORD_OK) return st;
+  HIP_TRY(p, ev.stop(s));
+  HIP_TRY(p, hipStreamSynchronize(s));
+  if ((st = prepare_check(p, h)) != DISCORD_OK) return st;
+  p->ms_prepare = ev.ms();
+  return DISCORD_OK;
 }
 
 }  // namespace
@@ -534,12 +565,6 @@ int discord_prepare(const float* T, int64_t m, int32_t n, const discord_opts* op
 
 namespace {
 
-// What one search reads back: its counters and the certified answer.
-struct HostOut {
-  SearchScalars sc;
-  Exact ex;
-};
-
 constexpr int64_t kDevRows = 8;   // uncertain rows rescanned before the readback
 
 // One search in flight.  timed: scan launches timed so far (event pairs 1,
@@ -549,6 +574,7 @@ struct SearchRun {
   HostOut* h = nullptr;
   bool events = true;
   int timed = 0;
+  int launches = 0;   // scan launches enqueued
 };
 
 // Enqueues the whole search on the plan's stream, up to the copies of its
@@ -644,6 +670,7 @@ int search_enqueue(discord_plan p, SearchRun& run) {
   }
   auto launch = [&](const char* what) -> int {
     const bool timing = run.events && timed < kMaxTimed;
+    ++run.launches;
     EventPair t(1 + timed, timing);
     if (!t.ready()) return fail(p, DISCORD_EDEVICE, "hipEventCreate failed");
     if (timing) HIP_TRY(p, hipEventRecord(t.a, s));
@@ -662,6 +689,7 @@ int search_enqueue(discord_plan p, SearchRun& run) {
   // Sequence entries are column groups of 8 (FP32) or blocks of 32 (MFMA); a
   // sequence is at most the word bucket plus every column block.
   const int64_t nq = (N + (mixed ? kMixedBlock : kColBlock) - 1) / (mixed ? kMixedBlock : kColBlock);
+  if (buckets && p->max_bucket < 0) return fail(p, DISCORD_EDEVICE, "bucket sizes not read back");
   const int64_t seq_max = nq + (buckets ? p->max_bucket : 0);
   const int64_t gran = mixed ? 16 : 64;   // entries per 512 columns
   // entries [begin, end) of every listed item, split into chunks so that the
@@ -700,14 +728,30 @@ int search_enqueue(discord_plan p, SearchRun& run) {
     // sooner leaves the remaining launches without work.
     SearchCtl* ctl = p->at<SearchCtl>(p->L.ctl);
     WinDesc* wins = p->at<WinDesc>(p->L.wins);
-    // first window: 2 (FP32) / 2 (split-BF16) steps of 512 columns in the
-    // near-first order (split-BF16: 4 -> 2 took the 2^20 walk 4.6 -> 4.1 ms)
-    const int probe = p->opts.probe_steps > 0 ? p->opts.probe_steps : (near_first ? 2 : 16);
+    // Ranked rounds (near-first order under per-window normalisation, where
+    // the mean-gap bound is zero): after each window the items still searched
+    // are ranked by the largest published minimum of a live row, the
+    // best-ranked are completed at once to raise the best-so-far, and the rest
+    // continue.  With the bound-ranked items completed first (global
+    // normalisation) the best-so-far is already near its final value and these
+    // completions only cost time (FP32 2^20 walk 8.0 -> 6.6 ms without them).
+    const bool ranked = near_first && zn;
+    // first window: 2 steps of 512 columns in the near-first order (4 for
+    // split-BF16 in ranked rounds; without them 2 took the 2^20 walk 4.6 ->
+    // 4.1 ms)
+    const int probe = p->opts.probe_steps > 0 ? p->opts.probe_steps
+                                              : (near_first ? ((ranked && mixed) ? 4 : 2) : 16);
     // windows grow 4x, 2x on sequences of 2^20 entries and more (measured
     // with the bound-ranked items completed first: FP32 2^20 walk 6.6 -> 6.2
-    // ms with 4x; FP32 10^7-point walk n = 1024 613 -> 559 ms with 2x)
-    const int64_t growth = seq_max >= (int64_t{1} << 20) ? 2 : 4;
-    const CtlParams P{seq_max, gran, target_items, growth, near_first ? 1 : 0};
+    // ms with 4x; FP32 10^7-point walk n = 1024 613 -> 559 ms with 2x); in
+    // ranked rounds 2x from 2^15 entries
+    const int64_t growth = seq_max >= (int64_t{1} << (ranked ? 15 : 20)) ? 2 : 4;
+    // ranked rounds: items completed after each ranking (split-BF16 items
+    // beyond n = 512 are single row blocks, 64 of them; FP32 groups: more for
+    // longer windows)
+    const int64_t seeds = mixed ? ((n + 15) / 16 > 32 ? 64 : 16)
+                                : (n >= 1024 ? 512 : (n >= 512 ? 256 : 128));
+    const CtlParams P{seq_max, gran, target_items, seed_items, growth, seeds, near_first ? 1 : 0};
     // A launch whose work is decided on the device gets a grid sized for the
     // most work its descriptor can hold, at most `cap` work items (beyond, its
     // wavefronts or workgroups stride over the work).
@@ -717,17 +761,24 @@ int search_enqueue(discord_plan p, SearchRun& run) {
       return std::min(cap, std::min(items_max * maxc, items_max + target));
     };
     int nw = 0;
-    const bool cand = order && p->cand_count > 0;
+    // |Cand| is known on the host after discord_prepare; in a request run as
+    // one sequence (prepare and search together) it exists only on the device
+    const bool cand_known = p->cand_count >= 0;
+    const bool cand = order && (!cand_known || p->cand_count > 0);
+    const int64_t cand_max = cand_known ? std::min<int64_t>(n_items, p->cand_count) : n_items;
     if (cand) {
       // Algorithm 3: the items holding Cand rows, each over its whole sequence
       launch_cand_group_flags(p->at<int32_t>(p->L.cand), p->at<int32_t>(p->L.cand_count),
-                              p->cand_count, item_shift, gflags, s);
+                              cand_known ? p->cand_count : N, item_shift, gflags, s);
       launch_compact_flags(gflags, n_items, p->at<int32_t>(p->L.seg),
                            p->at<int32_t>(p->L.cand_groups), &sc->n_cand_groups, s);
     }
     const int64_t width0 = (int64_t)probe * gran;
+    const int64_t bound_seeds = (near_first && !zn) ? std::min<int64_t>(n_items, mixed ? 2 : 16) : 0;
     WinDesc* cand_win = cand ? &wins[nw++] : nullptr;
-    launch_ctl_start(ctl, n_items, width0, &sc->n_cand_groups, cand_win, P, s);
+    WinDesc* bound_win = bound_seeds > 0 ? &wins[nw++] : nullptr;
+    launch_ctl_start(ctl, n_items, width0, &sc->n_cand_groups, cand_win, bound_seeds, bound_win,
+                     p->at<double>(p->L.stats), p->at<int32_t>(p->L.bad), P, s);
     // survivor lists: round r lists its survivors in lists[r & 1]; the bound
     // ranking goes to lists[1] before the first round
     int32_t* const lists[2] = {p->at<int32_t>(p->L.survivors), p->at<int32_t>(p->L.survivors2)};
@@ -741,7 +792,6 @@ int search_enqueue(discord_plan p, SearchRun& run) {
     // split-BF16: 2^20 walk n = 128 12.3 -> 8.3 / 8.2 -> 5.5 ms; 2^20 noisy walk
     // n = 256 22.9 -> 10.3 / 12.1 -> 5.1 ms; 2^22 series n = 512 277 -> 65 /
     // 126 -> 31 ms, with these items searched after Cand).
-    const int64_t bound_seeds = (near_first && !zn) ? std::min<int64_t>(n_items, mixed ? 2 : 16) : 0;
     int32_t* bflags = p->at<int32_t>(p->L.bflags);
     if (bound_seeds > 0) {
       launch_item_bound(p->at<float>(p->L.lb), N, item_rows, n_items, p->at<uint32_t>(p->L.score),
@@ -749,19 +799,14 @@ int search_enqueue(discord_plan p, SearchRun& run) {
       launch_rank_scores(nullptr, &ctl->count, n_items, p->at<uint32_t>(p->L.score),
                          p->at<uint32_t>(p->L.rank_hist), spare, s);
       LAUNCH_OK(p, "bound ranking");
-      WinDesc wd{};
-      set_window_host(&wd, bound_seeds, 0, seq_max, seed_items, gran);
-      J.win = nullptr;
+      J.win = bound_win;
       J.groups = spare;
-      J.n_groups = bound_seeds;
-      J.chunks = wd.chunks;
-      J.seq_begin = 0;
-      J.seq_chunk = wd.seq_chunk;
+      J.max_work = grid_work(bound_seeds, seq_max, seed_items);
       J.skip = nullptr;
       J.precheck = 0;
       if ((st = launch("scan (bound seeds)"))) return st;
-      launch_flag_items(spare, bound_seeds, gflags, s);
-      launch_flag_items(spare, bound_seeds, bflags, s);
+      launch_flag_items(spare, bound_seeds, bound_win, gflags, s);
+      launch_flag_items(spare, bound_seeds, bound_win, bflags, s);
     }
     if (cand) {
       // Algorithm 3: the items holding Cand rows, each over its whole sequence
@@ -769,26 +814,42 @@ int search_enqueue(discord_plan p, SearchRun& run) {
       J.groups = p->at<int32_t>(p->L.cand_groups);
       J.skip = bound_seeds > 0 ? bflags : nullptr;
       J.precheck = 0;
-      J.max_work = grid_work(std::min<int64_t>(n_items, p->cand_count), seq_max, target_items);
+      J.max_work = grid_work(cand_max, seq_max, target_items);
       if ((st = launch("scan (Cand)"))) return st;
     }
     int64_t covered = 0, width = width0;   // the device's window sizes while its loop runs
     for (int round = 0;; ++round) {
       const int64_t end = std::min<int64_t>(seq_max, covered + width);
-      if (nw + 1 > kMaxWins) return fail(p, DISCORD_EDEVICE, "search needs too many rounds");
+      if (nw + 2 > kMaxWins) return fail(p, DISCORD_EDEVICE, "search needs too many rounds");
       WinDesc* w = &wins[nw++];
       launch_ctl_window(ctl, w, n_surv, P, s);
       J.win = w;
-      J.groups = round == 0 ? nullptr : lists[(round - 1) & 1];
+      // lists: ranked rounds read the ranked list (`spare`, past its completed
+      // head) and always list survivors in lists[0]; otherwise the lists alternate
+      J.groups = round == 0 ? nullptr : (ranked ? spare : lists[(round - 1) & 1]);
       J.skip = (round == 0 && (cand || bound_seeds > 0)) ? gflags : nullptr;
       J.precheck = round > 0;
-      J.survivors = lists[round & 1];
+      J.survivors = ranked ? lists[0] : lists[round & 1];
       J.max_work = grid_work(n_items, end - covered, target_items);
       if ((st = launch("scan (window)"))) return st;
       if (end >= seq_max) break;                  // final for every item
       launch_ctl_after(ctl, n_surv, P, s);
       covered = end;
       width = near_first ? width * growth : seq_max;
+      if (ranked) {
+        launch_rank_groups(lists[0], &ctl->count, n_items, item_rows, gsz, alive, best, N,
+                           p->at<uint32_t>(p->L.score), p->at<uint32_t>(p->L.rank_hist), spare, s);
+        LAUNCH_OK(p, "rank");
+        WinDesc* ws = &wins[nw++];
+        launch_ctl_seeds(ctl, ws, P, s);
+        J.win = ws;
+        J.groups = spare;
+        J.skip = nullptr;
+        J.precheck = 1;
+        J.max_work = grid_work(std::min<int64_t>(seeds, n_items), seq_max - covered, seed_items);
+        if ((st = launch("scan (seeds)"))) return st;
+        launch_ctl_post(ctl, s);
+      }
     }
     J.win = nullptr;
   }
@@ -881,6 +942,7 @@ int search_finish(discord_plan p, SearchRun& run, const EventPair& ev, discord_r
   r.ms_prepare = p->ms_prepare;
   r.ms_search = ev.ms();
   for (int k = 0; k < run.timed; ++k) r.ms_scan += EventPair(1 + k).ms();
+  r.scan_launches = (uint64_t)run.launches;
   p->searched = true;
   *out = r;
   return DISCORD_OK;
@@ -937,6 +999,7 @@ int discord_search_graph(discord_plan p, discord_result* out) {
                               : fail(p, DISCORD_EDEVICE, "stream capture failed: %s",
                                      hipGetErrorString(e));
     }
+    p->glaunches = cap.launches;
     const hipError_t ei = hipGraphInstantiate(&p->gexec, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (ei != hipSuccess) {
@@ -954,6 +1017,7 @@ int discord_search_graph(discord_plan p, discord_result* out) {
   SearchRun run;
   run.h = h;
   run.events = false;
+  run.launches = p->glaunches;
   return search_finish(p, run, ev, out);
 }
 
@@ -1137,8 +1201,28 @@ int search_series_in_arena(const float* T, int64_t m, int32_t n, const discord_o
   p->stream = stream;
   p->arena = static_cast<char*>(arena);
   p->timed = false;
-  st = prepare_run(p, T);
-  if (st == DISCORD_OK) st = discord_search(p, out);
+  if (o.order == 1) {
+    // the PhiDD order's sequences need the bucket sizes on the host first
+    st = prepare_run(p, T);
+    if (st == DISCORD_OK) st = discord_search(p, out);
+  } else {
+    // preparation and search as one sequence with one synchronisation; the
+    // statistics of eq. (2) are checked from the same readback
+    HostOut h;
+    SearchRun run;
+    run.h = &h;
+    run.events = false;
+    st = prepare_enqueue(p, T);
+    if (st == DISCORD_OK) st = search_enqueue(p, run);
+    if (st == DISCORD_OK) st = prepare_readback(p, &h);
+    if (st == DISCORD_OK && hipStreamSynchronize(stream) != hipSuccess)
+      st = fail(p, DISCORD_EDEVICE, "hipStreamSynchronize failed");
+    if (st == DISCORD_OK) st = prepare_check(p, h);
+    if (st == DISCORD_OK) {
+      EventPair none(0, false);
+      st = search_finish(p, run, none, out);
+    }
+  }
   if (st != DISCORD_OK && err && err_len) std::snprintf(err, err_len, "%s", p->err);
   return st;
 }

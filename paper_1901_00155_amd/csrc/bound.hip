@@ -135,10 +135,14 @@ __global__ __launch_bounds__(256) void k_item_bound(const float* __restrict__ lb
   }
 }
 
+// only the first min(count, win->n_groups) entries: the list holds that many
+// (none when the device loop stopped before it began)
 __global__ __launch_bounds__(256) void k_flag_items(const int32_t* __restrict__ list, int64_t count,
+                                                    const WinDesc* __restrict__ win,
                                                     int32_t* __restrict__ flags) {
   const int64_t t = blockIdx.x * 256ll + threadIdx.x;
-  if (t < count) flags[list[t]] = 1;
+  const int64_t c = win->n_groups < count ? win->n_groups : count;
+  if (t < c) flags[list[t]] = 1;
 }
 
 unsigned blocks_for(int64_t count) {
@@ -174,10 +178,11 @@ void launch_item_bound(const float* lb, int64_t N, int64_t item_rows, int64_t n_
                      n_items, score);
 }
 
-void launch_flag_items(const int32_t* list, int64_t count, int32_t* flags, hipStream_t s) {
+void launch_flag_items(const int32_t* list, int64_t count, const WinDesc* win, int32_t* flags,
+                       hipStream_t s) {
   if (count > 0)
     hipLaunchKernelGGL(k_flag_items, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, list,
-                       count, flags);
+                       count, win, flags);
 }
 
 }  // namespace dd

@@ -35,13 +35,20 @@ __host__ __device__ inline void set_window(WinDesc* w, int64_t items, int64_t be
 }
 
 __global__ void k_ctl_start(SearchCtl* ctl, int64_t count, int64_t width,
-                            const int32_t* cand_count, WinDesc* cand_win, CtlParams P) {
-  ctl->count = count;
+                            const int32_t* cand_count, WinDesc* cand_win, int64_t bound_items,
+                            WinDesc* bound_win, const double* stats, const int32_t* bad,
+                            CtlParams P) {
+  // eq. (2) undefined (sigma = 0) or the series not finite: nothing to search
+  const bool go = !bad[0] && stats[1] > 0.0;
+  ctl->count = go ? count : 0;
   ctl->covered = 0;
   ctl->width = width;
   ctl->in_off = 0;
   ctl->end = 0;
-  if (cand_win) set_window(cand_win, *cand_count, 0, P.seq_max, P.target, P.gran, 0);
+  ctl->k = 0;
+  if (cand_win) set_window(cand_win, go ? *cand_count : 0, 0, P.seq_max, P.target, P.gran, 0);
+  if (bound_win)
+    set_window(bound_win, go ? bound_items : 0, 0, P.seq_max, P.seed_target, P.gran, 0);
 }
 
 __global__ void k_ctl_window(SearchCtl* ctl, WinDesc* win, uint32_t* n_surv, CtlParams P) {
@@ -67,6 +74,24 @@ __global__ void k_ctl_after(SearchCtl* ctl, const uint32_t* n_surv, CtlParams P)
   ctl->width = P.near_first ? ctl->width * P.growth : P.seq_max;
 }
 
+__global__ void k_ctl_seeds(SearchCtl* ctl, WinDesc* win, CtlParams P) {
+  const int64_t c = ctl->count;
+  const int64_t k = c < P.seeds ? c : P.seeds;
+  set_window(win, k, ctl->covered, P.seq_max, P.seed_target, P.gran, 0);
+  ctl->k = k;
+}
+
+__global__ void k_ctl_post(SearchCtl* ctl) {
+  const int64_t c = ctl->count;
+  if (c == 0) return;
+  if (ctl->k >= c) {   // the ranked list was completed whole
+    ctl->count = 0;
+    return;
+  }
+  ctl->in_off = ctl->k;
+  ctl->count = c - ctl->k;
+}
+
 }  // namespace
 
 void set_window_host(WinDesc* w, int64_t items, int64_t begin, int64_t end, int64_t target,
@@ -75,9 +100,10 @@ void set_window_host(WinDesc* w, int64_t items, int64_t begin, int64_t end, int6
 }
 
 void launch_ctl_start(SearchCtl* ctl, int64_t count, int64_t width, const int32_t* cand_count,
-                      WinDesc* cand_win, const CtlParams& P, hipStream_t s) {
+                      WinDesc* cand_win, int64_t bound_items, WinDesc* bound_win,
+                      const double* stats, const int32_t* bad, const CtlParams& P, hipStream_t s) {
   hipLaunchKernelGGL(k_ctl_start, dim3(1), dim3(1), 0, s, ctl, count, width, cand_count, cand_win,
-                     P);
+                     bound_items, bound_win, stats, bad, P);
 }
 
 void launch_ctl_window(SearchCtl* ctl, WinDesc* win, uint32_t* n_surv, const CtlParams& P,
@@ -87,6 +113,14 @@ void launch_ctl_window(SearchCtl* ctl, WinDesc* win, uint32_t* n_surv, const Ctl
 
 void launch_ctl_after(SearchCtl* ctl, const uint32_t* n_surv, const CtlParams& P, hipStream_t s) {
   hipLaunchKernelGGL(k_ctl_after, dim3(1), dim3(1), 0, s, ctl, n_surv, P);
+}
+
+void launch_ctl_seeds(SearchCtl* ctl, WinDesc* win, const CtlParams& P, hipStream_t s) {
+  hipLaunchKernelGGL(k_ctl_seeds, dim3(1), dim3(1), 0, s, ctl, win, P);
+}
+
+void launch_ctl_post(SearchCtl* ctl, hipStream_t s) {
+  hipLaunchKernelGGL(k_ctl_post, dim3(1), dim3(1), 0, s, ctl);
 }
 
 }  // namespace dd

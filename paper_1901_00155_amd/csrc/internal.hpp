@@ -212,12 +212,15 @@ struct SearchCtl {
   int64_t width;    // entries of the next window
   int64_t in_off;   // first entry of the next window's item list
   int64_t end;      // end of the current window
+  int64_t k;        // items of the round's completion launch (ranked rounds)
 };
 struct CtlParams {
   int64_t seq_max;      // longest column sequence (entries)
   int64_t gran;         // entries per 512 columns (the chunk granule)
   int64_t target;       // work items a window launch aims at
+  int64_t seed_target;  // work items the launch completing the bound-ranked items aims at
   int64_t growth;       // window growth per round
+  int64_t seeds;        // ranked rounds: best-ranked items completed after each window
   int32_t near_first;   // 1: windows grow by `growth`; 0: the second window ends the sequences
 };
 // entries [begin, end) of `items` items, split into chunks so that the launch
@@ -225,10 +228,14 @@ struct CtlParams {
 // launches whose counts it knows)
 void set_window_host(WinDesc* w, int64_t items, int64_t begin, int64_t end, int64_t target,
                      int64_t gran);
-// ctl := (count, 0, width, 0); with cand_count: the Cand launch covers the whole
-// sequence of *cand_count items
+// ctl := (count, 0, width, 0); cand_win (if given): the Cand launch covers the
+// whole sequence of *cand_count items; bound_win (if given): the launch that
+// completes bound_items items.  A series that eq. (2) rejects (bad[0] set, or
+// stats[1] = sigma not > 0) ends the loop before it starts: count = 0 and both
+// launches empty.
 void launch_ctl_start(SearchCtl* ctl, int64_t count, int64_t width, const int32_t* cand_count,
-                      WinDesc* cand_win, const CtlParams& P, hipStream_t s);
+                      WinDesc* cand_win, int64_t bound_items, WinDesc* bound_win,
+                      const double* stats, const int32_t* bad, const CtlParams& P, hipStream_t s);
 // the next window: entries [covered, covered + width) of the listed items;
 // clears the survivor count
 void launch_ctl_window(SearchCtl* ctl, WinDesc* win, uint32_t* n_surv, const CtlParams& P,
@@ -236,6 +243,11 @@ void launch_ctl_window(SearchCtl* ctl, WinDesc* win, uint32_t* n_surv, const Ctl
 // after a window: the loop ends when the sequences are done or no item has a
 // live row; else the survivors are the next list and the window grows
 void launch_ctl_after(SearchCtl* ctl, const uint32_t* n_surv, const CtlParams& P, hipStream_t s);
+// ranked rounds: after the survivors were ranked, the best-ranked
+// min(count, seeds) items are completed over the rest of their sequences ...
+void launch_ctl_seeds(SearchCtl* ctl, WinDesc* win, const CtlParams& P, hipStream_t s);
+// ... and the rest continue from the ranked list in the next window
+void launch_ctl_post(SearchCtl* ctl, hipStream_t s);
 
 // ---- bound.hip ----------------------------------------------------------------
 // lb[i] <= NN(i): n times the squared gap from row i's mean to the nearest mean
@@ -247,8 +259,11 @@ void launch_row_bound(const double* row_mean, int64_t N, int n, uint64_t* range,
 // score[t] = bits of the largest lb over item t's rows (item_rows rows each)
 void launch_item_bound(const float* lb, int64_t N, int64_t item_rows, int64_t n_items,
                        uint32_t* score, hipStream_t s);
-// flags[list[t]] = 1 for t < count
-void launch_flag_items(const int32_t* list, int64_t count, int32_t* flags, hipStream_t s);
+// flags[list[t]] = 1 for t < min(count, win->n_groups): the items a launch
+// described by `win` covered (the list may hold fewer valid entries than
+// count when the device decided on less work)
+void launch_flag_items(const int32_t* list, int64_t count, const WinDesc* win, int32_t* flags,
+                       hipStream_t s);
 
 // ---- rank.hip -----------------------------------------------------------------
 // A descending counting sort of the *count entries of `list` (nullptr: 0, 1,
@@ -256,6 +271,12 @@ void launch_flag_items(const int32_t* list, int64_t count, int32_t* flags, hipSt
 // rank_hist_bins() entries, cleared first when clear_hist).  The count is read
 // on the device; the grids are sized for max_count.
 size_t rank_hist_bins();
+// The *count items of `list` (item_rows consecutive rows each; alive masks per
+// gsz rows) by the largest published minimum of a live row (score is scratch
+// of max_count entries).
+void launch_rank_groups(const int32_t* list, const int64_t* count, int64_t max_count,
+                        int64_t item_rows, int gsz, const uint32_t* alive, const uint64_t* best,
+                        int64_t N, uint32_t* score, uint32_t* hist, int32_t* out, hipStream_t s);
 void launch_rank_scores(const int32_t* list, const int64_t* count, int64_t max_count,
                         const uint32_t* score, uint32_t* hist, int32_t* out, hipStream_t s,
                         bool clear_hist = true);
@@ -308,8 +329,10 @@ void launch_merge_exact(const int64_t* rows, const double* d, const int64_t* j, 
 namespace dd {
 // ---- api.hip: one series prepared and searched in caller-provided device
 // memory, with a plan on the stack; all work on `stream`, which it
-// synchronises before returning.  Creates no stream, event, heap object or
-// device allocation.  ERANGE if the plan does not fit in arena_bytes.
+// synchronises before returning (once: preparation and search are enqueued as
+// one sequence, except for the PhiDD order, whose sequences need the bucket
+// sizes on the host).  Creates no stream, event, heap object or device
+// allocation.  ERANGE if the plan does not fit in arena_bytes.
 int search_series_in_arena(const float* T, int64_t m, int32_t n, const discord_opts* opts,
                            void* arena, size_t arena_bytes, hipStream_t stream,
                            discord_result* out, char* err, size_t err_len);

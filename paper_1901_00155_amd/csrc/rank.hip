@@ -1,7 +1,12 @@
 // rank.hip -- items in descending order of a score, most promising first.
 //
 // The search ranks its items by the mean-gap bound of their rows' NN
-// (bound.hip) to choose which to complete first.  The items are put in
+// (bound.hip) to choose which to complete first.  Under per-window
+// normalisation, where that bound is zero, it ranks the items still searched
+// after each window instead: each live row has a published minimum over the
+// columns seen so far, an upper bound of its NN, and an item scores the
+// largest such bound among its live rows (+inf for a row that has seen no
+// column yet).  The items are put in
 // descending score order by a counting sort on the top 12 bits of the score's
 // IEEE pattern (non-negative floats order like their bits; bins are 1/16 of an
 // octave wide); the order within a bin is arbitrary and, like every visiting
@@ -15,6 +20,63 @@ namespace {
 
 constexpr int kBins = 4096;
 constexpr int kBinShift = 19;   // 31 value bits -> 12-bit bin
+
+__device__ __forceinline__ uint32_t load_relaxed(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint32_t row_score(const uint32_t* __restrict__ alive,
+                                              const uint64_t* __restrict__ best, int64_t i,
+                                              int gsz) {
+  if (!((load_relaxed(&alive[i / gsz]) >> (i % gsz)) & 1u)) return 0;
+  const uint64_t key = best[i];
+  const uint32_t bits = key == kEmptyMin ? 0x7F800000u : (uint32_t)(key >> 32);
+  return bits > 0x7F800000u ? 0 : bits;   // not a non-negative number: rank last
+}
+
+// Small items (up to 64 rows): one thread per item.
+__global__ __launch_bounds__(256) void k_group_score(const int32_t* __restrict__ list,
+                                                     const int64_t* __restrict__ count_p,
+                                                     int64_t item_rows, int gsz,
+                                                     const uint32_t* __restrict__ alive,
+                                                     const uint64_t* __restrict__ best, int64_t N,
+                                                     uint32_t* __restrict__ score) {
+  const int64_t count = *count_p;
+  const int64_t k = blockIdx.x * 256ll + threadIdx.x;
+  if (k >= count) return;
+  const int64_t r0 = (int64_t)list[k] * item_rows;
+  uint32_t s = 0;
+  for (int64_t i = r0; i < r0 + item_rows && i < N; ++i) {
+    const uint32_t b = row_score(alive, best, i, gsz);
+    s = b > s ? b : s;
+  }
+  score[k] = s;
+}
+
+// Large items: one wavefront per item, its lanes striding over the rows.
+__global__ __launch_bounds__(256) void k_group_score_wave(const int32_t* __restrict__ list,
+                                                          const int64_t* __restrict__ count_p,
+                                                          int64_t item_rows, int gsz,
+                                                          const uint32_t* __restrict__ alive,
+                                                          const uint64_t* __restrict__ best,
+                                                          int64_t N, uint32_t* __restrict__ score) {
+  const int64_t count = *count_p;
+  const int64_t k = blockIdx.x * 4ll + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (k >= count) return;
+  const int64_t r0 = (int64_t)list[k] * item_rows;
+  const int64_t r1 = min<int64_t>(N, r0 + item_rows);
+  uint32_t s = 0;
+  for (int64_t i = r0 + lane; i < r1; i += 64) {
+    const uint32_t b = row_score(alive, best, i, gsz);
+    s = b > s ? b : s;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint32_t o = __shfl_xor(s, off, 64);
+    s = o > s ? o : s;
+  }
+  if (lane == 0) score[k] = s;
+}
 
 __global__ __launch_bounds__(256) void k_rank_hist(const uint32_t* __restrict__ score,
                                                    const int64_t* __restrict__ count_p,
@@ -88,6 +150,20 @@ __global__ __launch_bounds__(256) void k_rank_scatter(const int32_t* __restrict_
 }  // namespace
 
 size_t rank_hist_bins() { return kBins; }
+
+void launch_rank_groups(const int32_t* list, const int64_t* count, int64_t max_count,
+                        int64_t item_rows, int gsz, const uint32_t* alive, const uint64_t* best,
+                        int64_t N, uint32_t* score, uint32_t* hist, int32_t* out, hipStream_t s) {
+  if (max_count <= 0) return;
+  const unsigned blocks = (unsigned)((max_count + 255) / 256);
+  if (item_rows > 64)
+    hipLaunchKernelGGL(k_group_score_wave, dim3((unsigned)((max_count + 3) / 4)), dim3(256), 0, s,
+                       list, count, item_rows, gsz, alive, best, N, score);
+  else
+    hipLaunchKernelGGL(k_group_score, dim3(blocks), dim3(256), 0, s, list, count, item_rows, gsz,
+                       alive, best, N, score);
+  launch_rank_scores(list, count, max_count, score, hist, out, s);
+}
 
 void launch_rank_scores(const int32_t* list, const int64_t* count, int64_t max_count,
                         const uint32_t* score, uint32_t* hist, int32_t* out, hipStream_t s,

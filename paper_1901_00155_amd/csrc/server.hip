@@ -1,8 +1,10 @@
 // server.hip -- the GPU executor of the serving loop and discord_server_create.
 //
 // One device arena of the configured budget is allocated once; every admitted
-// request prepares and searches inside its own block of it (discord_prepare with
-// a caller workspace), so no device allocation happens per request.  Each slot
+// request prepares and searches inside its own block of it, so no device
+// allocation happens per request.  A request's preparation and search are
+// enqueued as one sequence (every decision of the search taken on the device)
+// and the worker synchronises once, when the answer is on the host.  Each slot
 // owns a HIP stream of default priority and a pinned host staging buffer: the
 // series is copied into the staging buffer and from there to the device
 // asynchronously on the slot's stream.  The kernels of different slots run
@@ -62,16 +64,12 @@ int hip_execute(void* ctx, const discord_request* rq, const discord_opts* opts,
     S.capacity = cap;
   }
   std::memcpy(S.staging, rq->T, sizeof(float) * rq->m);
-  discord_plan plan = nullptr;
-  int st = discord_prepare(S.staging, rq->m, rq->n, opts, rq->workspace, rq->ws_bytes, S.stream,
-                           &plan);
-  if (st != DISCORD_OK) {
-    set_detail(detail, detail_len, "prepare", discord_plan_error(nullptr));
-    return st;
-  }
-  st = discord_search(plan, out);
-  if (st != DISCORD_OK) set_detail(detail, detail_len, "search", discord_plan_error(plan));
-  discord_release(plan);
+  // preparation and search enqueued as one sequence on the slot's stream,
+  // with one synchronisation; the plan lives on this worker's stack
+  char err[256];
+  const int st = dd::search_series_in_arena(S.staging, rq->m, rq->n, opts, rq->workspace,
+                                            rq->ws_bytes, S.stream, out, err, sizeof(err));
+  if (st != DISCORD_OK) set_detail(detail, detail_len, "request", err);
   return st;
 }
 
