@@ -90,7 +90,7 @@ def walk1m(seed: int = 1, m: int = 1 << 20, n: int = 128) -> Workload:
     pos = _positions(rng, m, n, len(kinds))
     for p, kind in zip(pos, kinds):
         _plant(t, rng, p, n, kind)
-    return Workload("walk1m", t.astype(np.float32), n,
+    return Workload("walk1m" if n == 128 else f"walk1m_n{n}", t.astype(np.float32), n,
                     [(p, n, kd) for p, kd in zip(pos, kinds)], seed)
 
 
@@ -169,5 +169,7 @@ def random_walk(m: int, seed: int, noise: float = 0.0) -> np.ndarray:
 def by_name(name: str) -> Workload:
     if name.startswith("walk10m"):           # walk10m or walk10m_n<window>
         return walk10m(int(name.split("_n")[1])) if "_n" in name else walk10m()
+    if name.startswith("walk1m_n"):          # the 2^20 walk searched with another window
+        return walk1m(n=int(name.split("_n")[1]))
     return {"small": small, "walk1m": walk1m, "noisy1m": noisy1m,
             "large4m": large4m}[name]()
