@@ -16,7 +16,7 @@ visiting order, full-scan rates of both precisions, the roofline of each scan
 kernel (kernel time from HIP events on the plan's stream), the m = 2^20, n = 256
 noisy walk in both precisions, per-window z-normalisation, time to discord
 against the number of compute units (CU-limited streams), the 10^7-point walk
-at windows of 512 and 1024, the serving stream (p50/p99 latency and throughput,
+at windows of 1024 and 2048, the serving stream (p50/p99 latency and throughput,
 at its 200 req/s and replayed 8x faster to saturate the server) and the FP64
 CPU oracle: the whole m = 4096 case in full, and a bounded sample of rows of
 the main workload, on the host cores.
@@ -48,7 +48,15 @@ PAPER_CONTEXT = {
     "hotsax_corei5_scd1m_n128_s": 147600.0,
 }
 
-SCAN_SOURCES = {"fp32": "scan_fp32.hip", "bf16x3": "scan_mfma.hip"}
+SCAN_SOURCES = {"k_scan_fp32": "scan_fp32.hip", "k_scan_mfma": "scan_mfma.hip",
+                "k_scan_mfma_long": "scan_mfma_long.hip"}
+
+
+def scan_kernel(n: int, precision: str) -> str:
+    """The scan kernel a search of window n runs in this precision."""
+    if precision == "fp32":
+        return "k_scan_fp32"
+    return "k_scan_mfma" if n <= 512 else "k_scan_mfma_long"
 
 
 def pair_count(N: int, n: int) -> int:
@@ -61,12 +69,12 @@ def scan_flops_per_pair(n: int, precision: str) -> float:
     return 3.0 * n if precision == "fp32" else 6.0 * n
 
 
-def source_sha(precision: str) -> str:
-    p = os.path.join(ROOT, "paper_1901_00155_amd", "csrc", SCAN_SOURCES[precision])
+def source_sha(kernel: str) -> str:
+    p = os.path.join(ROOT, "paper_1901_00155_amd", "csrc", SCAN_SOURCES[kernel])
     return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
 
 
-def traffic_for(precision: str, workload: str, mode: str):
+def traffic_for(precision: str, workload: str, mode: str, n: int):
     """HBM bytes of the scan launches of one search, from the committed
     rocprofv3 PMC summary, if it was taken on the current kernel source; else
     None."""
@@ -75,7 +83,7 @@ def traffic_for(precision: str, workload: str, mode: str):
         rec = json.load(open(p))[f"{precision}/{workload}/{mode}"]
     except (OSError, KeyError, ValueError):
         return None
-    if rec.get("source_sha") != source_sha(precision):
+    if rec.get("source_sha") != source_sha(scan_kernel(n, precision)):
         return None
     return rec.get("bytes_per_search")
 
@@ -109,8 +117,7 @@ def roofline(n, precision, pairs, scan_ms, traffic, launches=None):
     peak = PEAK_FP32_VECTOR_TFLOPS if precision == "fp32" else PEAK_BF16_MFMA_TFLOPS
     return {"bound": "alu" if precision == "fp32" else "mfma", "achieved": achieved,
             "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
-            "kernel": ("k_scan_fp32" if precision == "fp32"
-                       else "k_scan_mfma" if n <= 512 else "k_scan_mfma_long"),
+            "kernel": scan_kernel(n, precision),
             "flops_per_pair": scan_flops_per_pair(n, precision), "scan_ms": scan_ms,
             "launches": launches}
 
@@ -249,7 +256,7 @@ def znorm_block(dd, Td, w):
     return blk
 
 
-def long_window_block(dd, workloads, windows=(512, 1024)):
+def long_window_block(dd, workloads, windows=(1024, 2048)):
     """The paper's larger series and longer windows: a 10^7-point walk with
     eight planted anomalies, time to discord per window (split-BF16 where the
     window is within its limit, FP32 always)."""
@@ -374,7 +381,7 @@ def main():
                     "rows_abandoned": int(r.rows_abandoned),
                     "max_rel_err_of_approx_nn": float(r.max_rel_err)},
         "roofline": roofline(n, args.precision, pairs, scan_ms,
-                             traffic_for(args.precision, w.name, mode),
+                             traffic_for(args.precision, w.name, mode, n),
                              launches=int(np.mean([x.scan_launches for x in res]))),
         "paper_context": PAPER_CONTEXT,
     }
@@ -389,7 +396,7 @@ def main():
             "precision": other, "time_to_discord_ms": s2 * 1e3, "pairs_per_s": p2 / s2,
             "brute_force_equiv_pairs_per_s": P / s2, "speedup_vs_step": sec / s2,
             "max_rel_err_of_approx_nn": float(x.max_rel_err),
-            "roofline": roofline(n, other, p2, sm2, traffic_for(other, w.name, mode))}
+            "roofline": roofline(n, other, p2, sm2, traffic_for(other, w.name, mode, n))}
         print(f"# {other} step {s2 * 1e3:.2f} ms", file=sys.stderr, flush=True)
         if abandon:
             # the paper's visiting order (PhiDD: Cand first, same-word columns first)

@@ -456,13 +456,14 @@ int prepare_enqueue(discord_plan p, const float* T) {
     launch_row_stats32(p->Tp(), p->N, n, p->N + kRowPad, p->at<double>(p->L.row_mean), row_sigma,
                        p->at<double>(p->L.stats), p->at<float>(p->L.mu32),
                        p->at<float>(p->L.smu32), p->at<float>(p->L.cn32), r32, s);
-  if (mixed)
+  if (mixed && !mixed_long(n))   // longer windows take their operands from the series
     launch_split_blocks(p->Tp(), p->N, n, p->at<float>(p->L.mu32), p->at<float>(p->L.cn32), r32,
                         p->at<uint4>(p->L.sblk), s);
   // the bucket column blocks serve only the PhiDD order (same-word columns first)
   if (o.order == 1) {
+    // (bucket entries are the scan's column blocks: 8, 32 or 128 columns)
     launch_bucket_groups(p->at<int32_t>(p->L.csr_off), p->at<int32_t>(p->L.csr_mem), p->dict,
-                         mixed ? 5 : 3,
+                         mixed ? (mixed_long(n) ? 7 : 5) : 3,
                          p->at<int32_t>(p->L.bgrp_cnt), p->at<int32_t>(p->L.bgrp_off),
                          p->at<int32_t>(p->L.bgrp), s);
     launch_max_bucket(p->at<int32_t>(p->L.bgrp_off), p->dict, p->at<int32_t>(p->L.max_bucket), s);
@@ -640,9 +641,10 @@ int search_enqueue(discord_plan p, SearchRun& run) {
   J.done = p->at<uint32_t>(p->L.done);
   J.survivors = p->at<int32_t>(p->L.survivors);
   J.n_survivors = n_surv;
-  const MixedRows R{p->at<float>(p->L.mu32), p->at<float>(p->L.smu32), p->at<float>(p->L.cn32),
-                    p->at<uint4>(p->L.sblk)};
   const bool zn = p->opts.znorm != 0;
+  const MixedRows R{p->at<float>(p->L.mu32), p->at<float>(p->L.smu32), p->at<float>(p->L.cn32),
+                    mixed_long(n) ? nullptr : p->at<uint4>(p->L.sblk),
+                    zn ? p->at<float>(p->L.r32) : nullptr};
   J.raise_sub = 0.0f;
   if (zn && !mixed) {
     J.zc = p->at<float>(p->L.mu32);
@@ -686,12 +688,14 @@ int search_enqueue(discord_plan p, SearchRun& run) {
     }
     return DISCORD_OK;
   };
-  // Sequence entries are column groups of 8 (FP32) or blocks of 32 (MFMA); a
-  // sequence is at most the word bucket plus every column block.
-  const int64_t nq = (N + (mixed ? kMixedBlock : kColBlock) - 1) / (mixed ? kMixedBlock : kColBlock);
+  // Sequence entries are column groups of 8 (FP32), blocks of 32 (MFMA) or
+  // of 128 (MFMA, windows beyond 512); a sequence is at most the word bucket
+  // plus every column block.
+  const int64_t col_w = mixed ? (mixed_long(n) ? kMixedLongCols : kMixedBlock) : kColBlock;
+  const int64_t nq = (N + col_w - 1) / col_w;
   if (buckets && p->max_bucket < 0) return fail(p, DISCORD_EDEVICE, "bucket sizes not read back");
   const int64_t seq_max = nq + (buckets ? p->max_bucket : 0);
-  const int64_t gran = mixed ? 16 : 64;   // entries per 512 columns
+  const int64_t gran = 512 / col_w;   // entries per 512 columns
   // entries [begin, end) of every listed item, split into chunks so that the
   // launch holds enough work items to fill the GPU
   auto set_window = [&](int64_t groups, int64_t begin, int64_t end, int64_t target) {
@@ -746,11 +750,9 @@ int search_enqueue(discord_plan p, SearchRun& run) {
     // ms with 4x; FP32 10^7-point walk n = 1024 613 -> 559 ms with 2x); in
     // ranked rounds 2x from 2^15 entries
     const int64_t growth = seq_max >= (int64_t{1} << (ranked ? 15 : 20)) ? 2 : 4;
-    // ranked rounds: items completed after each ranking (split-BF16 items
-    // beyond n = 512 are single row blocks, 64 of them; FP32 groups: more for
-    // longer windows)
-    const int64_t seeds = mixed ? ((n + 15) / 16 > 32 ? 64 : 16)
-                                : (n >= 1024 ? 512 : (n >= 512 ? 256 : 128));
+    // ranked rounds: items completed after each ranking (split-BF16: 16
+    // workgroup items; FP32 groups: more for longer windows)
+    const int64_t seeds = mixed ? 16 : (n >= 1024 ? 512 : (n >= 512 ? 256 : 128));
     const CtlParams P{seq_max, gran, target_items, seed_items, growth, seeds, near_first ? 1 : 0};
     // A launch whose work is decided on the device gets a grid sized for the
     // most work its descriptor can hold, at most `cap` work items (beyond, its
@@ -774,7 +776,10 @@ int search_enqueue(discord_plan p, SearchRun& run) {
                            p->at<int32_t>(p->L.cand_groups), &sc->n_cand_groups, s);
     }
     const int64_t width0 = (int64_t)probe * gran;
-    const int64_t bound_seeds = (near_first && !zn) ? std::min<int64_t>(n_items, mixed ? 2 : 16) : 0;
+    // (8 items of 128 rows for windows beyond 512: 10^7-point walk n = 2048
+    // 1290 -> 420 ms, n = 1024 113 -> 109 ms against 2)
+    const int64_t bound_seeds =
+        (near_first && !zn) ? std::min<int64_t>(n_items, mixed ? (mixed_long(n) ? 8 : 2) : 16) : 0;
     WinDesc* cand_win = cand ? &wins[nw++] : nullptr;
     WinDesc* bound_win = bound_seeds > 0 ? &wins[nw++] : nullptr;
     launch_ctl_start(ctl, n_items, width0, &sc->n_cand_groups, cand_win, bound_seeds, bound_win,

@@ -177,13 +177,17 @@ struct MixedRows {
   const float* mu;
   const float* smu;
   const float* cnorm;
-  const uint4* sblk;
+  const uint4* sblk;      // the split subsequence matrix (windows up to 512; else nullptr)
+  const float* r;         // per-window normalisation scales, or nullptr
 };
 constexpr int kMixedBlock = 32;      // rows per MFMA row block = columns per column block
 constexpr int kMixedMaxN = DISCORD_MIXED_MAX_N;  // longest window of the split-BF16 scan (128 K-steps)
 bool launch_scan_mfma(const ScanJob& J, const MixedRows& R, hipStream_t s);
-// windows of 513..2048 (scan_mfma_long.hip); false for other windows
+// windows of 513..2048 (scan_mfma_long.hip): operands built from the series,
+// items of 128 rows, steps of 128 columns; false for other windows
 bool launch_scan_mfma_long(const ScanJob& J, const MixedRows& R, hipStream_t s);
+bool mixed_long(int n);                     // the window takes scan_mfma_long.hip
+constexpr int kMixedLongCols = 128;         // columns per sequence entry of that scan
 int mfma_row_blocks(int n, bool abandon);   // row blocks per MFMA work item
 // The split subsequence matrix: for every block of 32 consecutive rows, KS+1
 // K-steps of 16 operand slots per lane (64 lanes): KS steps of the centred

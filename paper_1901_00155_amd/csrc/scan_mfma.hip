@@ -159,15 +159,6 @@ __global__ __launch_bounds__(256) void k_split_blocks(const float* __restrict__ 
   split_blocks_body(KS, Tp, nblk, n, c32, cn32, r32, out);
 }
 
-__global__ __launch_bounds__(256) void k_split_blocks_long(int KS, const float* __restrict__ Tp,
-                                                           int64_t nblk, int n,
-                                                           const float* __restrict__ c32,
-                                                           const float* __restrict__ cn32,
-                                                           const float* __restrict__ r32,
-                                                           bf16x8* __restrict__ out) {
-  split_blocks_body(KS, Tp, nblk, n, c32, cn32, r32, out);
-}
-
 // One workgroup per (item, chunk of its column sequence).  An item is a fixed
 // set of WAVES * RB consecutive row blocks (the list holds item numbers), so
 // its sequence is the same in every launch and a search can resume it: the
@@ -815,12 +806,14 @@ void launch_split(const float* Tp, int64_t nblk, int n, const float* c32, const 
 
 int mfma_row_blocks(int n, bool abandon) {
   const int ks = (n + 15) / 16;
-  if (ks > 32) return 1;   // windows beyond 512: one row block per workgroup
+  if (ks > 32) return 4;   // windows beyond 512: 128 rows per workgroup (scan_mfma_long.hip)
   const int waves = (ks > 8 && ks <= 16 && !abandon) ? 8 : 4;
   return waves * ((ks <= 8 && !abandon) ? 2 : 1);
 }
 
-size_t mixed_block_bytes(int n) { return (size_t)(((n + 15) / 16) + 1) * 128 * 16; }
+size_t mixed_block_bytes(int n) {
+  return mixed_long(n) ? 0 : (size_t)(((n + 15) / 16) + 1) * 128 * 16;
+}
 
 int64_t mixed_blocks(int64_t N) { return (N + BM - 1) / BM + 1; }
 
@@ -846,13 +839,8 @@ void launch_split_blocks(const float* Tp, int64_t N, int n, const float* c32, co
   case K: launch_split<K>(Tp, nblk, n, c32, cn32, r32, sblk, s); return;
     DD_KS_CASES(DD_CASE)
 #undef DD_CASE
-    default: {
-      const int ks = (n + 15) / 16;
-      const int64_t threads = nblk * (ks + 1) * 64;
-      hipLaunchKernelGGL(k_split_blocks_long, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0,
-                         s, ks, Tp, nblk, n, c32, cn32, r32, reinterpret_cast<bf16x8*>(sblk));
-      return;
-    }
+    default:
+      return;   // longer windows build their operands from the series (scan_mfma_long.hip)
   }
 }
 

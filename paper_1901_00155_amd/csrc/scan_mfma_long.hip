@@ -1,23 +1,43 @@
-// scan_mfma_long.hip -- split-BF16 pair-distance scan for windows of 513..2048.
+// scan_mfma_long.hip -- split-BF16 pair-distance scan for windows of 513..2048,
+// with the operands taken from the series itself.
 //
-// The arithmetic is that of scan_mfma.hip: centred windows split as hi + lo
-// bf16, a'.b' ~ hi.hi + hi.lo + lo.hi on v_mfma_f32_32x32x16_bf16, one extra
-// K-step folding in the norms, d^2 = acc + (sqrt(n) (mu_a - mu_b))^2, and every
-// decision certified in FP64 afterwards.  What changes is where the operands
-// live.  A row block's operands take 8 VGPRs per K-step, so beyond 32 K-steps
-// (n = 512) one wavefront cannot hold them.  Here the K-steps of ONE row block
-// are split over the 4 wavefronts of a workgroup: wavefront w keeps steps
-// w*KSP .. w*KSP + KSP - 1 in registers for the whole sweep (KSP <= 32) and
-// reads the same steps of each column block straight from global memory (the
-// column blocks are read by every row block in turn, so they are served by L2
-// in matrix order and near-first order alike).  Each wavefront's partial 32x32
-// accumulator goes through LDS; wavefront w then sums the four partials of the
-// accumulator elements 4w..4w+3 (columns j0 + 8w + 4h + 0..3 of row rl, in the
-// lane layout of the 32x32 result) and keeps the running minimum of those
-// columns.  Early abandon, survivors and the best-so-far follow the short-window
-// kernel; the live-row mask is made uniform over the workgroup after every
-// step (a row leaves as soon as any wavefront finds a column below the
-// best-so-far).
+// The windows of a series are shifted copies of one another: element k of
+// window i is t_{i+k}.  A 32 x 16 MFMA operand whose row r and K-index k hold
+// x_{i0 + r + k} therefore reads, in lane (r, h), the 8 consecutive values
+// x_{i0 + r + 16 s + 8 h + 0..7} of one array x.  Such operands are built in
+// LDS from a short stretch of the series, instead of being read from a
+// per-window matrix of n values per row.  For a workgroup's 128 rows and a
+// step's 128 columns that stretch is 16 KS + 128 values each (KS = ceil(n/16)
+// K-steps).  Every entry p of the LDS array holds the 8 values starting at p
+// (hi and lo bf16 halves, 16 bytes each).  So every operand is one aligned
+// ds_read_b128, and the 64 lanes of a read touch consecutive entries.
+//
+// Centring.  A window cannot be centred on its own mean here (that would give
+// every window its own copy of the values again), so the values of a
+// workgroup's rows are centred on one offset C_R, the FP32 mean of the
+// middle row, and a step's columns on C_C likewise:
+//   x'_k = t_{i+k} - C_R,  y'_k = t_{j+k} - C_C,   P = x'.y'.
+// With m_i = c_i - C_R and m_j = c_j - C_C (c the FP32 window means) the
+// centred product is a.b = P - n m_i m_j, up to terms of order n ulp(mu) m.
+// Eq. (1)'s squared distance is then
+//   d^2 = |a|^2 + |b|^2 - 2 P + 2 n m_i m_j + n (mu_i - mu_j)^2 ,
+// and under per-window normalisation (scales r = 1/sigma)
+//   d^2 = |a r_i|^2 + |b r_j|^2 - 2 r_i r_j (P - n m_i m_j) .
+// Within a workgroup the window means differ little from the offsets, so
+// |x'| stays close to |a| and the split products keep the ~2^-16 |a||b|
+// error of the short-window kernel; as there, every decision is certified in
+// FP64 afterwards.
+//
+// Work sharing.  An item is 4 row blocks of 32 consecutive rows (128 rows),
+// one per wavefront.  A step is 128 consecutive columns, in 4 blocks of 32.
+// Wavefront w multiplies its row block by the 4 column blocks, which makes
+// four 32x32 accumulators.  At K-step s, column block c needs the column
+// operand at offset 16 (s + 2c), so one operand serves 4 (block, step) pairs.
+// Each K-step reads one new column operand and one row operand (hi and lo)
+// for 12 MFMAs.  Steps visit 128-column super-blocks: the item's word bucket
+// first (same-word columns, Algorithm 4), then outward from the item's rows
+// (spiral.hpp), or in matrix order.  Early abandon, survivors and the
+// best-so-far follow scan_mfma.hip.
 #include "internal.hpp"
 
 namespace dd {
@@ -26,9 +46,22 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
-constexpr int BM = 32;
-constexpr int BN = 32;
-constexpr int W = 4;   // wavefronts per workgroup, one K-part each
+constexpr int BM = 32;          // rows per row block
+constexpr int W = 4;            // wavefronts = row blocks per item
+constexpr int TR = W * BM;      // rows per item
+constexpr int CB = 4;           // column blocks per step
+constexpr int TC = CB * BM;     // columns per step
+constexpr int THREADS = W * 64;
+
+// LDS entries of one stretch: rows/columns 0..127 at K-steps 0..KS-1 reach
+// entry 127 + 16 (KS - 1) + 8 (then 7 more values inside the entry)
+__host__ __device__ constexpr int stretch_entries(int ks) { return 16 * ks + 128; }
+
+// dynamic LDS: two stretches (hi and lo entries each), then the step's
+// column statistics (3 x 128 floats)
+__host__ __device__ constexpr size_t lds_bytes(int ks) {
+  return (size_t)2 * stretch_entries(ks) * 2 * sizeof(bf16x8) + 3 * TC * sizeof(float);
+}
 
 __device__ __forceinline__ uint32_t load_relaxed(const uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -38,14 +71,44 @@ __device__ __forceinline__ uint64_t load_relaxed64(const uint64_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// One workgroup per (item, chunk of its column sequence); an item is one row
-// block.  KSP: K-steps per wavefront, with 4 * KSP >= KS > 4 * (KSP - 1).
-template <int KSP>
-__device__ __forceinline__ void scan_item(const ScanJob& J, const MixedRows& R, int64_t wi) {
-  __shared__ float4 part[W][4][64];          // partial accumulators, 16 KiB
-  __shared__ uint32_t live_of[2][W];         // per step parity: each wavefront's live rows
+// entries p = 0 .. L-1 of a stretch starting at series index `base`:
+// hi/lo halves of (t_{base+p+e} - C), e = 0..7.  Reads t up to base + L + 6,
+// inside the zero pad after the series for every base <= N - 1.
+__device__ __forceinline__ void build_stretch(const float* __restrict__ Tp, int64_t base, float C,
+                                              int L, bf16x8* __restrict__ eh,
+                                              bf16x8* __restrict__ el) {
+  for (int p = threadIdx.x; p < L; p += THREADS) {
+    const float* src = Tp + base + p;
+    float4 a, b;
+    __builtin_memcpy(&a, src, 16);
+    __builtin_memcpy(&b, src + 4, 16);
+    const float v[8] = {a.x - C, a.y - C, a.z - C, a.w - C, b.x - C, b.y - C, b.z - C, b.w - C};
+    bf16x8 hi, lo;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const __bf16 x = (__bf16)v[e];
+      hi[e] = x;
+      lo[e] = (__bf16)(v[e] - (float)x);
+    }
+    eh[p] = hi;
+    el[p] = lo;
+  }
+}
+
+__device__ __forceinline__ bf16x8 mask_bf16(bf16x8 x, uint4 m) {
+  uint4 u = __builtin_bit_cast(uint4, x);
+  u.x &= m.x;
+  u.y &= m.y;
+  u.z &= m.z;
+  u.w &= m.w;
+  return __builtin_bit_cast(bf16x8, u);
+}
+
+template <bool Z>
+__device__ __forceinline__ void scan_item(const ScanJob& J, const MixedRows& R, int64_t wi,
+                                          bf16x8* smem) {
+  __shared__ uint32_t wave_live[2 * W];
   __shared__ uint32_t tail[W + 1];
-  const bf16x8* __restrict__ S = reinterpret_cast<const bf16x8*>(R.sblk);
 
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
@@ -53,74 +116,60 @@ __device__ __forceinline__ void scan_item(const ScanJob& J, const MixedRows& R, 
   const int rl = lane & 31;
   const int n = J.n;
   const int KS = (n + 15) / 16;
-  const int64_t SLOTS = (int64_t)(KS + 1) * 128;   // 16-byte slots per block
-  const int k0 = wv * KSP;                          // this wavefront's first K-step
-  const int kw = min(KSP, KS - k0);                 // >= 1 (KS > 4 (KSP - 1))
+  const int L = stretch_entries(KS);
+  bf16x8* const rEh = smem;              // row stretch
+  bf16x8* const rEl = smem + L;
+  bf16x8* const cEh = smem + 2 * L;      // column stretch of the current step
+  bf16x8* const cEl = smem + 3 * L;
+  float* const cst = reinterpret_cast<float*>(smem + 4 * L);   // cn | m | smu or r
+
   const int64_t li = wi / J.chunks;
   const int64_t ch = wi - li * J.chunks;
   if (li >= J.n_groups) return;
   const int64_t N = J.N;
-  const int64_t g = __builtin_amdgcn_readfirstlane((int)(J.groups ? J.groups[li] : li));
-  if (J.skip && J.skip[g]) return;
+  const int64_t item = __builtin_amdgcn_readfirstlane((int)(J.groups ? J.groups[li] : li));
+  if (J.skip && J.skip[item]) return;
+  const int64_t r_first = item * TR;
+
+  // ---- this wavefront's row block and its live rows ---------------------------
+  const int64_t g = item * W + wv;
   const int64_t r0 = g * BM;
-  const int64_t rows = min<int64_t>(BM, N - r0);
-  const uint32_t valid = rows >= 32 ? 0xFFFFFFFFu : ((1u << rows) - 1u);
-  uint32_t live =
-      J.abandon ? __builtin_amdgcn_readfirstlane(load_relaxed(&J.alive[g]) & valid) : valid;
-  if (J.abandon && J.precheck && live) {
-    // rows whose minimum over the columns of earlier launches is already below
-    // the best-so-far cannot be the discord: they leave with that witness
-    // (every wavefront takes the same decision from the same values)
-    const float bs = __builtin_bit_cast(float, load_relaxed(J.bsf));
-    bool below = false;
-    if (h == 0 && ((live >> rl) & 1u)) {
-      const uint64_t k = load_relaxed64(&J.best[r0 + rl]);
-      below = k != kEmptyMin && key_dist(k) < bs;
-    }
-    const uint32_t dead = (uint32_t)(__ballot(below) & 0xFFFFFFFFull);
-    if (dead) {
-      if (lane == 0) atomicAnd(&J.alive[g], ~dead);
-      live &= ~dead;
-    }
-  }
-
-  // one live mask for the workgroup before the sweep: each wavefront read the
-  // masks on its own, and another chunk of the item may have changed them
-  if (lane == 0) live_of[1][wv] = live;
-  __syncthreads();
-#pragma unroll
-  for (int w = 0; w < W; ++w) live &= live_of[1][w];
-
-  // ---- this wavefront's K-part of the row operands, scaled by -2 --------------
-  const bf16x8* rblk = S + g * SLOTS;
-  const __bf16 m2 = (__bf16)(-2.0f);
-  bf16x8 bh[KSP], bl[KSP], bx;
-#pragma unroll
-  for (int s = 0; s < KSP; ++s) {
-    if (s < kw) {
-      bh[s] = rblk[(int64_t)(k0 + s) * 128 + lane] * m2;
-      bl[s] = rblk[(int64_t)(k0 + s) * 128 + 64 + lane] * m2;
-    } else {
-      bh[s] = bl[s] = bf16x8{};
+  uint32_t valid = 0, live = 0;
+  if (r0 < N) {
+    const int64_t rows = min<int64_t>(BM, N - r0);
+    valid = rows >= 32 ? 0xFFFFFFFFu : ((1u << rows) - 1u);
+    live = J.abandon ? __builtin_amdgcn_readfirstlane(load_relaxed(&J.alive[g]) & valid) : valid;
+    if (J.abandon && J.precheck && live) {
+      // rows whose minimum over the columns of earlier launches is already
+      // below the best-so-far cannot be the discord: they leave with that witness
+      const float bs = __builtin_bit_cast(float, load_relaxed(J.bsf));
+      bool below = false;
+      if (h == 0 && ((live >> rl) & 1u)) {
+        const uint64_t k = load_relaxed64(&J.best[r0 + rl]);
+        below = k != kEmptyMin && key_dist(k) < bs;
+      }
+      const uint32_t dead = (uint32_t)(__ballot(below) & 0xFFFFFFFFull);
+      if (dead) {
+        if (lane == 0) atomicAnd(&J.alive[g], ~dead);
+        live &= ~dead;
+      }
     }
   }
-  bx = rblk[(int64_t)KS * 128 + 64 + lane] * m2;   // norm step (wavefront 0 uses it)
-  const float smr = R.smu[r0 + rl];
 
   // ---- column sequence (uniform over the workgroup) ---------------------------
   int64_t nb = 0, b0 = 0;
   if (J.words) {
-    const int wd = J.words[r0];
+    const int wd = J.words[r_first];
     b0 = J.bgrp_off[wd];
     nb = J.bgrp_off[wd + 1] - b0;
   }
-  const int64_t NQ = (N + BN - 1) / BN;
+  const int64_t NQ = (N + TC - 1) / TC;
   Spiral sp{0, -1, NQ, 0};
-  if (J.near_first) sp = make_spiral(r0, r0 + BM, n, NQ, BN);
+  if (J.near_first) sp = make_spiral(r_first, r_first + TR, n, NQ, TC);
   const int64_t len = nb + spiral_count(sp);
   const int64_t e0 = J.seq_begin + ch * J.seq_chunk;
   const int64_t e1 = min<int64_t>(len, e0 + J.seq_chunk);
-  int64_t steps = (e1 > e0 && live) ? e1 - e0 : 0;
+  int64_t steps = e1 > e0 ? e1 - e0 : 0;
   const bool final = J.seq_begin + J.chunks * J.seq_chunk >= len;
   auto block_of = [&](int64_t s) -> int64_t {
     const int64_t e = e0 + s;
@@ -128,144 +177,208 @@ __device__ __forceinline__ void scan_item(const ScanJob& J, const MixedRows& R, 
                   : spiral_block(sp, e - nb);
   };
 
+  // workgroup-wide: is any row still live?
+  if (lane == 0) wave_live[wv] = live ? 1u : 0u;
+  __syncthreads();
+  bool wg_live = false;
+#pragma unroll
+  for (int w = 0; w < W; ++w) wg_live |= wave_live[w] != 0;
+  if (!wg_live) steps = 0;
+
+  // ---- the row stretch and the per-row terms -----------------------------------
+  const float CR = R.mu[min<int64_t>(r_first + TR / 2, N - 1)];
+  if (steps > 0) build_stretch(J.Tp, r_first, CR, L, rEh, rEl);
+  const int64_t irow = min<int64_t>(r0 + rl, N - 1);
+  const float ci = R.cnorm[irow];
+  const float mi = R.mu[irow] - CR;
+  // raw: gi = 2 n m_i, xi = smu_i; normalised: gi = -n m_i, xi = -2 r_i
+  const float gi = Z ? -(float)n * mi : 2.0f * (float)n * mi;
+  const float xi = Z ? -2.0f * R.r[irow] : R.smu[irow];
+  // the last K-step holds window elements 16 (KS - 1) + 8 h + e; those >= n
+  // are zeroed in the row operand (bits of each bf16: all ones, or zero)
+  uint4 tail_mask;
+  {
+    const int lim = n - 16 * (KS - 1) - 8 * h;
+    uint32_t mw[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      mw[e] = (2 * e < lim ? 0x0000FFFFu : 0u) | (2 * e + 1 < lim ? 0xFFFF0000u : 0u);
+    tail_mask = make_uint4(mw[0], mw[1], mw[2], mw[3]);
+  }
+
   float rmin = __builtin_inff();
   int32_t rj = -1;
   uint32_t cnt = 0;
   const int32_t i = (int32_t)(r0 + rl);
-
-  // With PF > 0, column operands are read from global memory PF K-steps ahead
-  // of their MFMAs: step k of a block sits in slot k % PF, refilled with step
-  // k + PF once consumed; after a block's last MFMA is issued the first PF
-  // steps of the next block are requested, so their latency overlaps the
-  // epilogue.  The 64 registers this takes cost a wavefront per SIMD beyond 15
-  // K-steps per wavefront, which measured slower (0.11 vs 0.15 of the BF16 peak
-  // at n = 1024; 0.23 vs 0.19 at n = 600, where it keeps two), so there the
-  // operands are loaded where they are used.
-  constexpr int PF = KSP <= 15 ? 8 : 0;
-  constexpr int PFS = PF > 0 ? PF : 1;
-  bf16x8 pa[PFS], pl[PFS], px;
-  auto prefetch_head = [&](const bf16x8* cb) {
-    if constexpr (PF == 0) return;
-#pragma unroll
-    for (int k = 0; k < PF; ++k) {
-      if (k < kw) {
-        pa[k] = cb[(int64_t)(k0 + k) * 128 + lane];
-        pl[k] = cb[(int64_t)(k0 + k) * 128 + 64 + lane];
-      }
-    }
-    px = cb[(int64_t)KS * 128 + lane];
-  };
-  int64_t q_next = steps > 0 ? block_of(0) : 0;
-  if (steps > 0) prefetch_head(S + q_next * SLOTS);
+  const int32_t jlim = (int32_t)N;   // N < 2^31 (checked at prepare)
 
   for (int64_t s = 0; s < steps; ++s) {
-    const int64_t q = q_next;
-    const int32_t j0 = (int32_t)(q * BN);
-    const bf16x8* cblk = S + q * SLOTS;
-    if (s + 1 < steps) q_next = block_of(s + 1);
-    // ---- partial product over this wavefront's K-steps ------------------------
-    floatx16 acc;
+    // every wavefront has finished reading the previous step's columns (and
+    // the row stretch is complete before the first step)
+    __syncthreads();
+    if (s > 0) {
+      const uint32_t* flags = wave_live + (s & 1) * W;
+      bool any = false;
 #pragma unroll
-    for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
-    if (wv == 0)
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(PF > 0 ? px : cblk[(int64_t)KS * 128 + lane],
-                                                    bx, acc, 0, 0, 0);
+      for (int w = 0; w < W; ++w) any |= flags[w] != 0;
+      if (!any) break;
+    }
+    const int64_t q = block_of(s);
+    const int32_t j0 = (int32_t)(q * TC);
+    const float CC = R.mu[min<int64_t>(j0 + TC / 2, N - 1)];
+    build_stretch(J.Tp, j0, CC, L, cEh, cEl);
+    if (threadIdx.x < TC) {
+      const int32_t j = j0 + threadIdx.x;
+      const bool in = j < jlim;
+      cst[threadIdx.x] = in ? R.cnorm[j] : 0.0f;
+      cst[TC + threadIdx.x] = in ? R.mu[j] - CC : 0.0f;
+      cst[2 * TC + threadIdx.x] = in ? (Z ? R.r[j] : R.smu[j]) : 0.0f;
+    }
+    __syncthreads();
+
+    if (live) {
+      // ---- P = x'.y' for 32 rows x 128 columns ------------------------------------
+      floatx16 acc[CB];
 #pragma unroll
-    for (int k = 0; k < KSP; ++k) {
-      if (k < kw) {
-        bf16x8 ah, al;
-        if constexpr (PF > 0) {
-          ah = pa[k % PFS];
-          al = pl[k % PFS];
-          if (k + PF < kw) {
-            pa[k % PFS] = cblk[(int64_t)(k0 + k + PF) * 128 + lane];
-            pl[k % PFS] = cblk[(int64_t)(k0 + k + PF) * 128 + 64 + lane];
+      for (int c = 0; c < CB; ++c)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[c][v] = 0.0f;
+      const bf16x8* ch_ = cEh + rl + 8 * h;          // column operand u at ch_[16 u]
+      const bf16x8* cl_ = cEl + rl + 8 * h;
+      const bf16x8* rh_ = rEh + 32 * wv + rl + 8 * h;   // row operand s at rh_[16 s]
+      const bf16x8* rl_ = rEl + 32 * wv + rl + 8 * h;
+      bf16x8 oh[8], ol[8], bh[2], bl[2];   // column operands by u mod 8, row operands by s mod 2
+#pragma unroll
+      for (int u = 0; u < 7; ++u) {
+        oh[u] = ch_[16 * u];
+        ol[u] = cl_[16 * u];
+      }
+      bh[0] = rh_[0];
+      bl[0] = rl_[0];
+      for (int kb = 0; kb < KS; kb += 8) {
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          const int k = kb + t;
+          // operands of the next K-step: the column operand at u = k + 7 (its
+          // block 3) and the row operand.  The reads are unconditional (indices
+          // clamped into the stretch; past the last step they are not used), so
+          // that every K-step waits only for the previous step's reads.
+          {
+            const int un = min(k + 7, KS + 5);
+            const int rn = min(k + 1, KS - 1);
+            oh[(t + 7) & 7] = ch_[16 * un];
+            ol[(t + 7) & 7] = cl_[16 * un];
+            bh[(t + 1) & 1] = rh_[16 * rn];
+            bl[(t + 1) & 1] = rl_[16 * rn];
           }
-        } else {
-          ah = cblk[(int64_t)(k0 + k) * 128 + lane];
-          al = cblk[(int64_t)(k0 + k) * 128 + 64 + lane];
+          if (k < KS) {
+            if (k == KS - 1) {
+              bh[t & 1] = mask_bf16(bh[t & 1], tail_mask);
+              bl[t & 1] = mask_bf16(bl[t & 1], tail_mask);
+            }
+#pragma unroll
+            for (int c = 0; c < CB; ++c)
+              acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(oh[(t + 2 * c) & 7], bh[t & 1],
+                                                              acc[c], 0, 0, 0);
+#pragma unroll
+            for (int c = 0; c < CB; ++c)
+              acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(oh[(t + 2 * c) & 7], bl[t & 1],
+                                                              acc[c], 0, 0, 0);
+#pragma unroll
+            for (int c = 0; c < CB; ++c)
+              acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ol[(t + 2 * c) & 7], bh[t & 1],
+                                                              acc[c], 0, 0, 0);
+          }
         }
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[k], acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl[k], acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[k], acc, 0, 0, 0);
+      }
+
+      // ---- epilogue: distances of the 4 column blocks ------------------------------
+      // lane (rl, h), register v of block c: column j0 + 32 c + 8 (v / 4) + 4 h + v % 4
+#pragma unroll
+      for (int c = 0; c < CB; ++c) {
+        const int32_t jb = j0 + 32 * c;
+        const bool clean = (jb + BM <= jlim) && ((jb >= (int32_t)r0 + BM - 1 + n) ||
+                                                 (jb + BM - 1 + n <= (int32_t)r0));
+        float d[16];
+#pragma unroll
+        for (int qd = 0; qd < 4; ++qd) {
+          const int lc = 32 * c + 8 * qd + 4 * h;
+          const float4 cn = *reinterpret_cast<const float4*>(cst + lc);
+          const float4 mj = *reinterpret_cast<const float4*>(cst + TC + lc);
+          const float4 xj = *reinterpret_cast<const float4*>(cst + 2 * TC + lc);
+          const float cnv[4] = {cn.x, cn.y, cn.z, cn.w};
+          const float mjv[4] = {mj.x, mj.y, mj.z, mj.w};
+          const float xjv[4] = {xj.x, xj.y, xj.z, xj.w};
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const float P = acc[c][4 * qd + e];
+            const float base = ci + cnv[e];
+            if (Z) {
+              // |a r_i|^2 + |b r_j|^2 - 2 r_i r_j (P - n m_i m_j)
+              d[4 * qd + e] = __builtin_fmaf(xi * xjv[e], __builtin_fmaf(gi, mjv[e], P), base);
+            } else {
+              // |a|^2 + |b|^2 - 2 P + 2 n m_i m_j + (smu_i - smu_j)^2
+              const float u = xi - xjv[e];
+              const float t = __builtin_fmaf(u, u, __builtin_fmaf(gi, mjv[e], base));
+              d[4 * qd + e] = __builtin_fmaf(-2.0f, P, t);
+            }
+          }
+        }
+        if (!clean) {
+#pragma unroll
+          for (int v = 0; v < 16; ++v) {
+            const int32_t j = jb + 8 * (v >> 2) + 4 * h + (v & 3);
+            const int32_t dij = i > j ? i - j : j - i;
+            if (!(j < jlim && dij >= n)) d[v] = __builtin_inff();
+          }
+        }
+        float tmin = d[0];
+#pragma unroll
+        for (int v = 1; v < 16; ++v) tmin = fminf(tmin, d[v]);
+        if (tmin < rmin) {
+          int32_t jj = -1;
+#pragma unroll
+          for (int v = 15; v >= 0; --v)
+            if (d[v] == tmin) jj = jb + 8 * (v >> 2) + 4 * h + (v & 3);
+          rmin = tmin;
+          rj = jj;
+        }
+        if ((valid >> rl) & 1u) {
+          if (clean) {
+            cnt += 16;
+          } else {
+#pragma unroll
+            for (int v = 0; v < 16; ++v) cnt += d[v] < __builtin_inff();
+          }
+        }
+      }
+      // ---- early abandon ----------------------------------------------------------
+      if (J.abandon) {
+        const float bsf = __builtin_bit_cast(float, load_relaxed(J.bsf));
+        const float m = fminf(rmin, __shfl_xor(rmin, 32, 64));
+        const uint32_t dead = (uint32_t)(__ballot(m < bsf && h == 0) & 0xFFFFFFFFull) & live;
+        if (dead) {
+          uint64_t key = rj < 0 ? kEmptyMin : pack_min(fmaxf(rmin, 0.0f), (uint32_t)rj);
+          const uint64_t o = __shfl_xor(key, 32, 64);
+          key = o < key ? o : key;
+          if (h == 0 && ((dead >> rl) & 1u))
+            atomicMin((unsigned long long*)&J.best[r0 + rl], (unsigned long long)key);
+          if (lane == 0) atomicAnd(&J.alive[g], ~dead);
+          live &= ~dead;
+        }
+        if (J.chunks > 1) live &= __builtin_amdgcn_readfirstlane(load_relaxed(&J.alive[g]));
       }
     }
-    if (s + 1 < steps) prefetch_head(S + q_next * SLOTS);
-#pragma unroll
-    for (int c = 0; c < 4; ++c)
-      part[wv][c][lane] = make_float4(acc[4 * c], acc[4 * c + 1], acc[4 * c + 2], acc[4 * c + 3]);
-    __syncthreads();
-    // ---- this wavefront's 4 columns: sum of the partials, distance ------------
-    float4 t = part[0][wv][lane];
-#pragma unroll
-    for (int p = 1; p < W; ++p) {
-      const float4 x = part[p][wv][lane];
-      t.x += x.x; t.y += x.y; t.z += x.z; t.w += x.w;
-    }
-    const int32_t jc = j0 + 8 * wv + 4 * h;         // this lane's first column
-    const float4 sc = *reinterpret_cast<const float4*>(R.smu + jc);
-    float d[4];
-    {
-      float u;
-      u = smr - sc.x; d[0] = __builtin_fmaf(u, u, t.x);
-      u = smr - sc.y; d[1] = __builtin_fmaf(u, u, t.y);
-      u = smr - sc.z; d[2] = __builtin_fmaf(u, u, t.z);
-      u = smr - sc.w; d[3] = __builtin_fmaf(u, u, t.w);
-    }
-    const bool clean = (j0 + BN <= (int32_t)N) &&
-                       ((j0 >= (int32_t)r0 + BM - 1 + n) || (j0 + BN - 1 + n <= (int32_t)r0));
-    if (!clean) {
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int32_t j = jc + u;
-        const int32_t dij = i > j ? i - j : j - i;
-        if (!(j < (int32_t)N && dij >= n)) d[u] = __builtin_inff();
-      }
-    }
-    const float tmin = fminf(fminf(d[0], d[1]), fminf(d[2], d[3]));
-    if (tmin < rmin) {
-      int32_t jj = -1;
-#pragma unroll
-      for (int u = 3; u >= 0; --u)
-        if (d[u] == tmin) jj = jc + u;
-      rmin = tmin;
-      rj = jj;
-    }
-    if ((valid >> rl) & 1u) {
-      if (clean) {
-        cnt += 4;
-      } else {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) cnt += d[u] < __builtin_inff();
-      }
-    }
-    // ---- early abandon --------------------------------------------------------
-    if (J.abandon) {
-      const float bsf = __builtin_bit_cast(float, load_relaxed(J.bsf));
-      const float m = fminf(rmin, __shfl_xor(rmin, 32, 64));
-      const uint32_t dead = (uint32_t)(__ballot(m < bsf && h == 0) & 0xFFFFFFFFull) & live;
-      if (dead) {
-        uint64_t key = rj < 0 ? kEmptyMin : pack_min(fmaxf(rmin, 0.0f), (uint32_t)rj);
-        const uint64_t o = __shfl_xor(key, 32, 64);
-        key = o < key ? o : key;
-        if (h == 0 && ((dead >> rl) & 1u))
-          atomicMin((unsigned long long*)&J.best[r0 + rl], (unsigned long long)key);
-        if (lane == 0) atomicAnd(&J.alive[g], ~dead);
-        live &= ~dead;
-      }
-      if (J.chunks > 1) live &= __builtin_amdgcn_readfirstlane(load_relaxed(&J.alive[g]));
-    }
-    // ---- one live mask for the workgroup (the partials are read by now) --------
-    uint32_t* lv = live_of[s & 1];
-    if (lane == 0) lv[wv] = live;
-    __syncthreads();
-#pragma unroll
-    for (int w = 0; w < W; ++w) live &= lv[w];
-    if (!live) break;
+    // the next step's first barrier makes these flags visible; they alternate
+    // between two rows, read after that barrier and rewritten only after the
+    // following one
+    if (lane == 0) wave_live[((s + 1) & 1) * W + wv] = live ? 1u : 0u;
   }
 
   // ---- publish --------------------------------------------------------------------
-  {
+  if (valid) {
+    // (the split products can round a near-zero distance below zero; keys hold
+    // non-negative distances so that they order like the values)
     uint64_t key = rj < 0 ? kEmptyMin : pack_min(fmaxf(rmin, 0.0f), (uint32_t)rj);
     const uint64_t o = __shfl_xor(key, 32, 64);
     key = o < key ? o : key;
@@ -277,76 +390,88 @@ __device__ __forceinline__ void scan_item(const ScanJob& J, const MixedRows& R, 
   if (lane == 0 && c64) atomicAdd(pair_slot(J.pairs), (unsigned long long)c64);
   if (!J.abandon) return;
 
-  // every wavefront has published its columns' minima before any is read back
+  // the item's last chunk to finish decides: complete rows raise the
+  // best-so-far with their minimum over all launches; rows still live after a
+  // non-final launch make the item a survivor
   __threadfence();
-  __syncthreads();
+  __syncthreads();                              // every wavefront has published
   if (J.chunks > 1) {
-    // the item's last chunk to finish decides
     if (threadIdx.x == 0) {
-      const uint32_t prev = atomicAdd(&J.done[g], 1u);
+      const uint32_t prev = atomicAdd(&J.done[item], 1u);
       const bool last = prev + 1 == (uint32_t)J.chunks;
-      if (last) atomicExch(&J.done[g], 0u);   // ready for the next launch
+      if (last) atomicExch(&J.done[item], 0u);   // ready for the next launch
       tail[W] = last ? 1u : 0u;
     }
     __syncthreads();
     if (!tail[W]) return;
     __threadfence();
   }
-  if (wv != 0) return;
-  const uint32_t fin =
-      J.chunks > 1 ? __builtin_amdgcn_readfirstlane(load_relaxed(&J.alive[g])) & valid : live;
-  if (!fin) return;
+  uint32_t fin = 0;
+  if (valid)
+    fin = J.chunks > 1 ? __builtin_amdgcn_readfirstlane(load_relaxed(&J.alive[g])) & valid : live;
   if (final) {
-    // complete rows raise the best-so-far with their minimum over all launches
-    if (h == 0 && ((fin >> rl) & 1u)) {
+    if (fin && h == 0 && ((fin >> rl) & 1u)) {
       const uint64_t k = load_relaxed64(&J.best[r0 + rl]);
       if (k != kEmptyMin)
         atomicMax(J.bsf, __builtin_bit_cast(uint32_t,
                                             fmaxf(key_dist(k) * J.raise_scale - J.raise_sub, 0.0f)));
     }
-  } else if (lane == 0) {
-    J.survivors[atomicAdd(J.n_survivors, 1u)] = (int32_t)g;
+    return;
+  }
+  if (lane == 0) tail[wv] = fin ? 1u : 0u;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    bool any = false;
+    for (int w = 0; w < W; ++w) any |= tail[w] != 0;
+    if (any) J.survivors[atomicAdd(J.n_survivors, 1u)] = (int32_t)item;
   }
 }
 
-// One workgroup per work item, striding by the grid size as in scan_mfma.hip.
-template <int KSP>
-__global__ __launch_bounds__(W * 64, 1) void k_scan_mfma_long(ScanJob Jarg, MixedRows R) {
+// One workgroup per work item (item, chunk), striding by the grid size.  Every
+// wavefront finishes its LDS reads before the next item rebuilds the stretches.
+template <bool Z>
+__global__ __launch_bounds__(THREADS, 2) void k_scan_mfma_long(ScanJob Jarg, MixedRows R) {
+  extern __shared__ bf16x8 smem[];
   ScanJob J = Jarg;
   apply_win(J);
   const int64_t total = J.n_groups * J.chunks;
   for (int64_t wi = blockIdx.x; wi < total; wi += gridDim.x) {
-    scan_item<KSP>(J, R, wi);
-    if (wi + gridDim.x < total) {
-      __builtin_amdgcn_s_waitcnt(0);
-      __syncthreads();
-    }
+    scan_item<Z>(J, R, wi, smem);
+    if (wi + gridDim.x < total) __syncthreads();
   }
 }
 
-template <int KSP>
+template <bool Z>
 void launch_long(const ScanJob& J, const MixedRows& R, hipStream_t s) {
   const int64_t blocks = J.win ? J.max_work : J.n_groups * J.chunks;
   if (blocks <= 0) return;
-  hipLaunchKernelGGL(k_scan_mfma_long<KSP>, dim3((unsigned)blocks), dim3(W * 64), 0, s, J, R);
+  const size_t lds = lds_bytes((J.n + 15) / 16);
+  // the LDS opt-in is per kernel and set once per process, to the largest
+  // window's need; the initialisation of a function-local static is thread-safe
+  static const bool attr_set = [] {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_scan_mfma_long<Z>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds_bytes(kMixedMaxN / 16));
+    return true;
+  }();
+  (void)attr_set;
+  hipLaunchKernelGGL(k_scan_mfma_long<Z>, dim3((unsigned)blocks), dim3(THREADS), lds, s, J, R);
 }
 
 }  // namespace
 
-#define DD_KSP_CASES(X)                                                                       \
-  X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) X(17) X(18) X(19) X(20) X(21) X(22) X(23) \
-  X(24) X(25) X(26) X(27) X(28) X(29) X(30) X(31) X(32)
+bool mixed_long(int n) {
+  const int ks = (n + 15) / 16;
+  return ks > 32 && ks <= kMixedMaxN / 16;
+}
 
 bool launch_scan_mfma_long(const ScanJob& J, const MixedRows& R, hipStream_t s) {
-  const int ks = (J.n + 15) / 16;
-  if (ks <= 32 || ks > 4 * 32) return false;
-  switch ((ks + W - 1) / W) {
-#define DD_CASE(K) \
-  case K: launch_long<K>(J, R, s); return true;
-    DD_KSP_CASES(DD_CASE)
-#undef DD_CASE
-    default: return false;
-  }
+  if (!mixed_long(J.n)) return false;
+  if (R.r)
+    launch_long<true>(J, R, s);
+  else
+    launch_long<false>(J, R, s);
+  return true;
 }
 
 }  // namespace dd

@@ -143,12 +143,14 @@ def test_cu_mask_rejects_bad_sizes(dd):
 
 @pytest.mark.parametrize("m,n", [(4096, 64), (50000, 512), (50000, 600), (100000, 2048)])
 def test_split_bf16_workspace_holds_the_split_matrix(dd, m, n):
-    """A split-BF16 plan holds the split subsequence matrix: ceil(N/32) + 1
-    blocks of ceil(n/16) + 1 K-steps of 2 KiB (hi and lo, or the norm step's
-    two operand forms), on top of the FP32 plan; windows up to
-    DISCORD_MIXED_MAX_N are accepted and longer ones refused."""
+    """A split-BF16 plan with windows up to 512 holds the split subsequence
+    matrix: ceil(N/32) + 1 blocks of ceil(n/16) + 1 K-steps of 2 KiB (hi and lo,
+    or the norm step's two operand forms), on top of the FP32 plan.  Longer
+    windows build their operands from the series, so their plan is the FP32
+    plan plus O(N) row statistics.  Windows up to DISCORD_MIXED_MAX_N are
+    accepted and longer ones refused."""
     N = m - n + 1
-    split = (-(-N // 32) + 1) * (-(-n // 16) + 1) * 2048
+    split = (-(-N // 32) + 1) * (-(-n // 16) + 1) * 2048 if n <= 512 else 0
     f32 = dd.workspace_bytes(m, n)
     b16 = dd.workspace_bytes(m, n, precision="bf16x3")
     assert f32 > 0 and b16 >= f32 + split

@@ -80,7 +80,7 @@ ZCASES = [
     (16, 1, 0), (40, 3, 1), (64, 32, 2), (100, 7, 4), (257, 9, 5), (300, 64, 6),
     (513, 100, 7), (1001, 333, 9), (2049, 17, 10), (3000, 128, 11),
     (4100, 200, 12), (4096, 64, 14), (1500, 512, 15), (2600, 280, 16),
-    # windows beyond 512 (the split-BF16 scan with K-steps split over wavefronts)
+    # windows beyond 512 (the split-BF16 scan with operands built from the series)
     (2600, 528, 23), (3600, 700, 26), (4500, 2048, 20),
 ]
 
@@ -174,6 +174,26 @@ def test_znorm_fp32_full_scan_profile(gpu):
     assert np.all(np.abs(approx - ref["profile"]) <= bound)
     N = m - n + 1
     assert np.all(np.abs(np.arange(N) - wit) >= n)
+
+
+@pytest.mark.parametrize("m,n", [(3000, 64), (2600, 528), (3333, 1500), (4500, 2048)])
+def test_znorm_bf16x3_full_scan_profile(gpu, m, n):
+    """Split-BF16 normalised minima: within 2^-12 * 2n of the exact NN
+    (normalised windows have squared norm n, and the split products carry
+    ~2^-16 of |a'||b'|); witnesses are non-self and the result is certified."""
+    T = workloads.random_walk(m, seed=m + n)
+    ref = oracle.discord(T, n, profile=True, znorm=True)
+    with gpu.Plan(T, n, precision="bf16x3", abandon=False, znorm=True) as p:
+        r = p.search()
+        approx = p.copy("nn_approx").astype(np.float64)
+        wit = p.copy("nn_witness")
+    _assert_same(r, ref)
+    prof = ref["profile"]
+    fin = np.isfinite(prof)   # rows with no non-self match: infinite on both sides
+    assert np.array_equal(np.isfinite(approx), fin)
+    assert np.all(np.abs(approx[fin] - prof[fin]) <= 2.0 ** -12 * 2 * n)
+    N = m - n + 1
+    assert np.all(np.abs(np.arange(N) - wit)[fin] >= n)
 
 
 def _certify_z(w, r, wit):
