@@ -48,15 +48,12 @@ PAPER_CONTEXT = {
     "hotsax_corei5_scd1m_n128_s": 147600.0,
 }
 
-SCAN_SOURCES = {"k_scan_fp32": "scan_fp32.hip", "k_scan_mfma": "scan_mfma.hip",
-                "k_scan_mfma_long": "scan_mfma_long.hip"}
+SCAN_SOURCES = {"k_scan_fp32": "scan_fp32.hip", "k_scan_mfma": "scan_mfma.hip"}
 
 
 def scan_kernel(n: int, precision: str) -> str:
     """The scan kernel a search of window n runs in this precision."""
-    if precision == "fp32":
-        return "k_scan_fp32"
-    return "k_scan_mfma" if n <= 512 else "k_scan_mfma_long"
+    return "k_scan_fp32" if precision == "fp32" else "k_scan_mfma"
 
 
 def pair_count(N: int, n: int) -> int:

@@ -71,7 +71,7 @@ struct Layout {
   size_t T, stats, partials, bad, words, hist, minfreq, cand, cand_count, seg, csr_off, csr_mem,
       best, nn_approx, nn_wit, row_state, row_mean, row_cnorm, rows, part_d, part_j, out_d,
       out_j, exact, unc, srch, pair_slots, alive, done, survivors, survivors2, score, rank_hist, gflags,
-      cand_groups, bgrp_cnt, bgrp_off, bgrp, max_bucket, mu32, smu32, cn32, r32, row_sigma, sblk,
+      cand_groups, bgrp_cnt, bgrp_off, bgrp, max_bucket, mu32, smu32, cn32, r32, row_sigma,
       ctl, wins, lb, lb_range, lb_bmin, lb_bmax, bflags, total;
 };
 
@@ -140,8 +140,6 @@ Layout make_layout(int64_t m, int32_t n, int dict, bool mixed, bool znorm) {
   // per-window normalisation: FP64 row standard deviations, FP32 row scales
   L.r32 = take(znorm ? sizeof(float) * (N + kRowPad) : 0);
   L.row_sigma = take(znorm ? sizeof(double) * N : 0);
-  // the split subsequence matrix of the MFMA scan, resident for the plan's life
-  L.sblk = take(mixed ? (size_t)mixed_blocks(N) * mixed_block_bytes(n) : 0);
   // the mean-gap bound of every row's NN (global normalisation only: under
   // per-window normalisation every window has mean 0)
   L.lb = take(znorm ? 0 : sizeof(float) * N);
@@ -456,14 +454,11 @@ int prepare_enqueue(discord_plan p, const float* T) {
     launch_row_stats32(p->Tp(), p->N, n, p->N + kRowPad, p->at<double>(p->L.row_mean), row_sigma,
                        p->at<double>(p->L.stats), p->at<float>(p->L.mu32),
                        p->at<float>(p->L.smu32), p->at<float>(p->L.cn32), r32, s);
-  if (mixed && !mixed_long(n))   // longer windows take their operands from the series
-    launch_split_blocks(p->Tp(), p->N, n, p->at<float>(p->L.mu32), p->at<float>(p->L.cn32), r32,
-                        p->at<uint4>(p->L.sblk), s);
   // the bucket column blocks serve only the PhiDD order (same-word columns first)
   if (o.order == 1) {
-    // (bucket entries are the scan's column blocks: 8, 32 or 128 columns)
+    // (bucket entries are the scan's column blocks: 8 or 128 columns)
     launch_bucket_groups(p->at<int32_t>(p->L.csr_off), p->at<int32_t>(p->L.csr_mem), p->dict,
-                         mixed ? (mixed_long(n) ? 7 : 5) : 3,
+                         mixed ? 7 : 3,
                          p->at<int32_t>(p->L.bgrp_cnt), p->at<int32_t>(p->L.bgrp_off),
                          p->at<int32_t>(p->L.bgrp), s);
     launch_max_bucket(p->at<int32_t>(p->L.bgrp_off), p->dict, p->at<int32_t>(p->L.max_bucket), s);
@@ -594,7 +589,7 @@ int search_enqueue(discord_plan p, SearchRun& run) {
   const int gsz = mixed ? kMixedBlock : kRowGroup;
   const int64_t G = (N + gsz - 1) / gsz;
   // row groups per work item: one wavefront (FP32) or one workgroup (MFMA)
-  const int rb = mixed ? mfma_row_blocks(n, p->opts.abandon != 0) : 1;
+  const int rb = mixed ? kMixedItemBlocks : 1;
   // the unit of the scan's lists: one row group (FP32) or one workgroup's fixed
   // set of rb row blocks (MFMA)
   const int64_t item_rows = (int64_t)gsz * rb;
@@ -643,7 +638,6 @@ int search_enqueue(discord_plan p, SearchRun& run) {
   J.n_survivors = n_surv;
   const bool zn = p->opts.znorm != 0;
   const MixedRows R{p->at<float>(p->L.mu32), p->at<float>(p->L.smu32), p->at<float>(p->L.cn32),
-                    mixed_long(n) ? nullptr : p->at<uint4>(p->L.sblk),
                     zn ? p->at<float>(p->L.r32) : nullptr};
   J.raise_sub = 0.0f;
   if (zn && !mixed) {
@@ -688,10 +682,9 @@ int search_enqueue(discord_plan p, SearchRun& run) {
     }
     return DISCORD_OK;
   };
-  // Sequence entries are column groups of 8 (FP32), blocks of 32 (MFMA) or
-  // of 128 (MFMA, windows beyond 512); a sequence is at most the word bucket
-  // plus every column block.
-  const int64_t col_w = mixed ? (mixed_long(n) ? kMixedLongCols : kMixedBlock) : kColBlock;
+  // Sequence entries are column groups of 8 (FP32) or blocks of 128 (MFMA); a
+  // sequence is at most the word bucket plus every column block.
+  const int64_t col_w = mixed ? kMixedCols : kColBlock;
   const int64_t nq = (N + col_w - 1) / col_w;
   if (buckets && p->max_bucket < 0) return fail(p, DISCORD_EDEVICE, "bucket sizes not read back");
   const int64_t seq_max = nq + (buckets ? p->max_bucket : 0);
@@ -776,10 +769,12 @@ int search_enqueue(discord_plan p, SearchRun& run) {
                            p->at<int32_t>(p->L.cand_groups), &sc->n_cand_groups, s);
     }
     const int64_t width0 = (int64_t)probe * gran;
-    // (8 items of 128 rows for windows beyond 512: 10^7-point walk n = 2048
-    // 1290 -> 420 ms, n = 1024 113 -> 109 ms against 2)
+    // split-BF16: 2 items of 128 rows up to n = 512, 8 beyond (time to
+    // discord: 2^20 walk n = 128 3.25 ms with 2, 3.35 with 8; 10^7-point walk
+    // n = 2048 420 ms with 8, 1290 with 2; n = 1024 109 / 113 ms)
     const int64_t bound_seeds =
-        (near_first && !zn) ? std::min<int64_t>(n_items, mixed ? (mixed_long(n) ? 8 : 2) : 16) : 0;
+        (near_first && !zn) ? std::min<int64_t>(n_items, mixed ? ((n + 15) / 16 > 32 ? 8 : 2) : 16)
+                            : 0;
     WinDesc* cand_win = cand ? &wins[nw++] : nullptr;
     WinDesc* bound_win = bound_seeds > 0 ? &wins[nw++] : nullptr;
     launch_ctl_start(ctl, n_items, width0, &sc->n_cand_groups, cand_win, bound_seeds, bound_win,
@@ -792,11 +787,10 @@ int search_enqueue(discord_plan p, SearchRun& run) {
     // rows have the largest mean-gap bound of their NN (bound.hip) are
     // completed, which puts the best-so-far near its final value; the Cand
     // rows and every later window then leave early against it.  These items
-    // are skipped by the Cand launch and the first window.  16 FP32 groups / 2
-    // split-BF16 items measured best among 1..64 (time to discord, FP32 /
-    // split-BF16: 2^20 walk n = 128 12.3 -> 8.3 / 8.2 -> 5.5 ms; 2^20 noisy walk
-    // n = 256 22.9 -> 10.3 / 12.1 -> 5.1 ms; 2^22 series n = 512 277 -> 65 /
-    // 126 -> 31 ms, with these items searched after Cand).
+    // are skipped by the Cand launch and the first window.  16 FP32 groups
+    // measured best among 1..64 (time to discord against none: 2^20 walk
+    // n = 128 12.3 -> 8.3 ms; 2^20 noisy walk n = 256 22.9 -> 10.3 ms; 2^22
+    // series n = 512 277 -> 65 ms, with these items searched after Cand).
     int32_t* bflags = p->at<int32_t>(p->L.bflags);
     if (bound_seeds > 0) {
       launch_item_bound(p->at<float>(p->L.lb), N, item_rows, n_items, p->at<uint32_t>(p->L.score),

@@ -18,7 +18,7 @@ LIBDIR = os.path.join(PKG, "lib")
 LIB = os.path.join(LIBDIR, "libdiscord.so")
 OBJDIR = os.path.join(ROOT, "_build", "obj")
 
-SOURCES = ["scan_mfma.hip", "scan_mfma_long.hip", "prep.hip", "scan_fp32.hip", "certify.hip",
+SOURCES = ["scan_mfma.hip", "prep.hip", "scan_fp32.hip", "certify.hip",
            "control.hip", "bound.hip",
            "rank.hip", "api.hip", "noalloc.hip", "server.hip", "server_core.cpp"]
 

@@ -171,34 +171,21 @@ void launch_sum_pairs(const uint64_t* slots, uint64_t* total, hipStream_t s);
 // ---- scan_mfma.hip ------------------------------------------------------------
 // Row statistics of the split-BF16 scan (FP32, padded with zeros to N + 64):
 // mu = fp32 row mean (the centre), smu = sqrt(n) (mean - series mean),
-// cnorm = squared norm about the centre.  sblk is the split subsequence matrix
-// in MFMA operand layout (see mixed_block_bytes).
+// cnorm = squared norm about the centre, r = per-window normalisation scales
+// (nullptr: distances between raw windows).  The operands are built from the
+// padded series (ScanJob::Tp).
 struct MixedRows {
   const float* mu;
   const float* smu;
   const float* cnorm;
-  const uint4* sblk;      // the split subsequence matrix (windows up to 512; else nullptr)
-  const float* r;         // per-window normalisation scales, or nullptr
+  const float* r;
 };
-constexpr int kMixedBlock = 32;      // rows per MFMA row block = columns per column block
+constexpr int kMixedBlock = 32;      // rows per MFMA row block (one alive mask)
+constexpr int kMixedItemBlocks = 4;  // row blocks per work item (one per wavefront)
+constexpr int kMixedCols = 128;      // columns per step = per sequence entry
 constexpr int kMixedMaxN = DISCORD_MIXED_MAX_N;  // longest window of the split-BF16 scan (128 K-steps)
+// false for windows beyond kMixedMaxN
 bool launch_scan_mfma(const ScanJob& J, const MixedRows& R, hipStream_t s);
-// windows of 513..2048 (scan_mfma_long.hip): operands built from the series,
-// items of 128 rows, steps of 128 columns; false for other windows
-bool launch_scan_mfma_long(const ScanJob& J, const MixedRows& R, hipStream_t s);
-bool mixed_long(int n);                     // the window takes scan_mfma_long.hip
-constexpr int kMixedLongCols = 128;         // columns per sequence entry of that scan
-int mfma_row_blocks(int n, bool abandon);   // row blocks per MFMA work item
-// The split subsequence matrix: for every block of 32 consecutive rows, KS+1
-// K-steps of 16 operand slots per lane (64 lanes): KS steps of the centred
-// window (hi then lo, 1 KB each) and one extra step holding the norm terms as
-// an A operand and as a B operand (1 KB each).  ceil(N/32) + 1 blocks.
-size_t mixed_block_bytes(int n);
-int64_t mixed_blocks(int64_t N);
-// r32: nullptr, or per-row scales of per-window normalisation (operands
-// (t - c) * r)
-void launch_split_blocks(const float* Tp, int64_t N, int n, const float* c32, const float* cn32,
-                         const float* r32, uint4* sblk, hipStream_t s);
 // row_sigma/r32: nullptr, or per-window normalisation (see prep.hip)
 void launch_row_stats32(const float* Tp, int64_t N, int n, int64_t padded, const double* row_mean,
                         const double* row_sigma, const double* stats, float* c32, float* smu32,
