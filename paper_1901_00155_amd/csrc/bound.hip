@@ -18,13 +18,20 @@
 // min_c <= i - n, so the first such bin at distance d from row i's own bin
 // bounds the nearest non-self mean below by (d - 1) bin widths.  With bins
 // that dense, a row leaves the outward search after a bin or two unless its
-// level is rare, which is what the bound is for.
+// level is rare, which is what the bound is for.  Groups of 256 bins keep the
+// smallest and largest row index of their bins as well, so the search crosses
+// a group without a match in one step: a row at a rare level checks at most
+// a few hundred bins and groups on either side instead of tens of thousands
+// of bins.
 #include "internal.hpp"
 
 namespace dd {
 namespace {
 
-constexpr int kBoundBins = 65536;   // most bins (the scratch arrays' size)
+constexpr int kBoundBins = 65536;   // most bins
+constexpr int kGroup = 256;         // bins per group
+// scratch arrays: the bins, then their groups from index kBoundBins on
+constexpr int kBoundSlots = kBoundBins + kBoundBins / kGroup;
 
 // order-preserving map of doubles to unsigned integers
 __device__ __forceinline__ uint64_t ordered(double x) {
@@ -98,6 +105,68 @@ __global__ __launch_bounds__(256) void k_bin_rows(const double* __restrict__ mu,
   }
 }
 
+// group g's smallest / largest row index over its bins (one workgroup each;
+// the last group may be partial, and fewer than kGroup bins make one group)
+__global__ __launch_bounds__(kGroup) void k_bin_groups(int nbins, int32_t* __restrict__ bmin,
+                                                       int32_t* __restrict__ bmax) {
+  __shared__ int32_t lo_s[kGroup / 64], hi_s[kGroup / 64];
+  const int c = blockIdx.x * kGroup + threadIdx.x;
+  int32_t lo = c < nbins ? bmin[c] : 0x7FFFFFFF, hi = c < nbins ? bmax[c] : -1;
+  for (int off = 32; off > 0; off >>= 1) {
+    lo = min(lo, __shfl_xor(lo, off, 64));
+    hi = max(hi, __shfl_xor(hi, off, 64));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    lo_s[threadIdx.x >> 6] = lo;
+    hi_s[threadIdx.x >> 6] = hi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kGroup / 64; ++w) {
+      lo = min(lo, lo_s[w]);
+      hi = max(hi, hi_s[w]);
+    }
+    bmin[kBoundBins + blockIdx.x] = lo;
+    bmax[kBoundBins + blockIdx.x] = hi;
+  }
+}
+
+// Does slot c (a bin, or a group at kBoundBins + g) hold a non-self row?
+__device__ __forceinline__ bool holds_match(const int32_t* __restrict__ bmin,
+                                            const int32_t* __restrict__ bmax, int c,
+                                            int64_t lo_row, int64_t hi_row) {
+  return bmax[c] >= hi_row || bmin[c] <= lo_row;
+}
+
+// The nearest bin at distance < limit from bin k (going down if dir < 0, up
+// otherwise) holding a non-self row: its distance, or `limit` if none.
+__device__ int nearest_match(const int32_t* __restrict__ bmin, const int32_t* __restrict__ bmax,
+                             int nbins, int k, int dir, int limit, int64_t lo_row,
+                             int64_t hi_row) {
+  int c = k;
+  // the rest of k's group, bin by bin
+  const int gedge = dir < 0 ? k / kGroup * kGroup : min(nbins, (k / kGroup + 1) * kGroup) - 1;
+  for (;; c += dir) {
+    const int d = dir < 0 ? k - c : c - k;
+    if (d >= limit) return limit;
+    if (holds_match(bmin, bmax, c, lo_row, hi_row)) return d;
+    if (c == gedge) break;
+  }
+  // whole groups; the first that holds a match is searched bin by bin
+  const int ngroups = (nbins + kGroup - 1) / kGroup;
+  for (int g = k / kGroup + dir; g >= 0 && g < ngroups; g += dir) {
+    const int first = dir < 0 ? (g + 1) * kGroup - 1 : g * kGroup;
+    if ((dir < 0 ? k - first : first - k) >= limit) return limit;
+    if (!holds_match(bmin, bmax, kBoundBins + g, lo_row, hi_row)) continue;
+    for (c = first;; c += dir) {
+      const int d = dir < 0 ? k - c : c - k;
+      if (d >= limit) return limit;
+      if (holds_match(bmin, bmax, c, lo_row, hi_row)) return d;
+    }
+  }
+  return limit;
+}
+
 __global__ __launch_bounds__(256) void k_row_bound(const double* __restrict__ mu, int64_t N, int n,
                                                    const uint64_t* __restrict__ range, int nbins,
                                                    const int32_t* __restrict__ bmin,
@@ -107,13 +176,13 @@ __global__ __launch_bounds__(256) void k_row_bound(const double* __restrict__ mu
   for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < N; i += (int64_t)gridDim.x * 256) {
     const int k = bin_of(b, mu[i]);
     const int64_t lo_row = i - n, hi_row = i + n;   // non-self: j <= lo_row or j >= hi_row
-    int d = 0;
-    for (;; ++d) {
-      const int c0 = k - d, c1 = k + d;
-      const bool ok0 = c0 >= 0 && (bmax[c0] >= hi_row || bmin[c0] <= lo_row);
-      const bool ok1 = c1 < nbins && (bmax[c1] >= hi_row || bmin[c1] <= lo_row);
-      if (ok0 || ok1 || (c0 < 0 && c1 >= nbins)) break;
-    }
+    // the nearest matching bin on either side; with none at all (a row without
+    // non-self matches) the distance to the farther end of the bins
+    const int none = max(k + 1, nbins - k);
+    const int dd = nearest_match(bmin, bmax, nbins, k, -1, min(k + 1, none), lo_row, hi_row);
+    const int limit_up = dd <= k ? dd : none;
+    const int du = nearest_match(bmin, bmax, nbins, k, 1, min(nbins - k, limit_up), lo_row, hi_row);
+    int d = min(dd <= k ? dd : none, du < nbins - k ? du : none);
     const double gap = (d > 1 ? d - 1 : 0) * b.width;
     lb[i] = (float)(n * gap * gap);
   }
@@ -145,14 +214,15 @@ __global__ __launch_bounds__(256) void k_flag_items(const int32_t* __restrict__ 
   if (t < c) flags[list[t]] = 1;
 }
 
-unsigned blocks_for(int64_t count) {
+// blocks of 256 threads for `count` items, at most `cap` (threads then stride)
+unsigned blocks_for(int64_t count, int64_t cap = 1024) {
   const int64_t b = (count + 255) / 256;
-  return (unsigned)(b < 1 ? 1 : (b > 1024 ? 1024 : b));
+  return (unsigned)(b < 1 ? 1 : (b > cap ? cap : b));
 }
 
 }  // namespace
 
-size_t bound_bins() { return kBoundBins; }
+size_t bound_bins() { return kBoundSlots; }
 
 void launch_row_bound(const double* row_mean, int64_t N, int n, uint64_t* range, int32_t* bmin,
                       int32_t* bmax, float* lb, hipStream_t s) {
@@ -166,9 +236,13 @@ void launch_row_bound(const double* row_mean, int64_t N, int n, uint64_t* range,
   };
   launch_fill_many(fills, 4, s);
   hipLaunchKernelGGL(k_mean_range, dim3(blocks_for(N)), dim3(256), 0, s, row_mean, N, range);
-  hipLaunchKernelGGL(k_bin_rows, dim3(blocks_for(N)), dim3(256), 0, s, row_mean, N, range, nbins,
+  hipLaunchKernelGGL(k_bin_rows, dim3(blocks_for(N, 4096)), dim3(256), 0, s, row_mean, N, range, nbins,
                      bmin, bmax);
-  hipLaunchKernelGGL(k_row_bound, dim3(blocks_for(N)), dim3(256), 0, s, row_mean, N, n, range,
+  hipLaunchKernelGGL(k_bin_groups, dim3((unsigned)((nbins + kGroup - 1) / kGroup)), dim3(kGroup), 0,
+                     s, nbins, bmin, bmax);
+  // one thread per row: the outward search is a chain of dependent loads, so
+  // many rows in flight hide its latency
+  hipLaunchKernelGGL(k_row_bound, dim3(blocks_for(N, 4096)), dim3(256), 0, s, row_mean, N, n, range,
                      nbins, bmin, bmax, lb);
 }
 

@@ -126,6 +126,12 @@ unsigned row_pass_blocks(int64_t N) {
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>(kRowPassBlocks, (N + 255) / 256));
 }
 
+// the witness verification: one row per thread up to 2^21 rows (each row's
+// FP64 sum is a chain of dependent adds, so many rows in flight hide it)
+unsigned verify_blocks(int64_t N) {
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(8192, (N + 255) / 256));
+}
+
 // Rows of the scan: minimum (or abandon distance) and its column; a row is
 // abandoned when its bit in the group's alive mask was cleared.
 __global__ __launch_bounds__(256) void k_unpack_best(const uint64_t* __restrict__ best, int64_t N,
@@ -420,10 +426,10 @@ void launch_verify(const float* Tp, int n, int64_t N, ZStats z, const int32_t* n
                    const float* nn_approx, const Exact* ex, int64_t* uncertain,
                    uint32_t* uncertain_count, uint32_t* max_rel_err_bits, hipStream_t s) {
   if (z.sg)
-    hipLaunchKernelGGL(k_verify<true>, dim3(row_pass_blocks(N)), dim3(256), 0, s, Tp, n, N, z,
+    hipLaunchKernelGGL(k_verify<true>, dim3(verify_blocks(N)), dim3(256), 0, s, Tp, n, N, z,
                        nn_witness, nn_approx, ex, uncertain, uncertain_count, max_rel_err_bits);
   else
-    hipLaunchKernelGGL(k_verify<false>, dim3(row_pass_blocks(N)), dim3(256), 0, s, Tp, n, N, z,
+    hipLaunchKernelGGL(k_verify<false>, dim3(verify_blocks(N)), dim3(256), 0, s, Tp, n, N, z,
                        nn_witness, nn_approx, ex, uncertain, uncertain_count, max_rel_err_bits);
 }
 

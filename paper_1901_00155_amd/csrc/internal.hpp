@@ -24,7 +24,7 @@ constexpr int kWave = 64;
 
 constexpr int kMaxWords = 256;       // |A|^w limit (eq. 9 hash fits a byte)
 constexpr int kStatBlocks = 1024;    // fixed grid of the FP64 reductions (deterministic)
-constexpr int kFp64Cols = 2048;      // columns per block of the FP64 row rescan
+constexpr int kFp64Cols = 256;       // columns per block of the FP64 row rescan (one per thread)
 constexpr int kFp64BatchRows = 64;   // rows per launch of the FP64 row rescan
 
 // Packed (distance, index) keys.  Non-negative IEEE floats order like their bit

@@ -79,6 +79,19 @@ __global__ __launch_bounds__(256) void k_finish(const double* __restrict__ parti
   }
 }
 
+// The 256 rows of a workgroup, i0 .. i0 + 255, read the values t_{i0} ..
+// t_{i0 + 254 + n}: they are copied to LDS once (coalesced), and each thread
+// reads its window from there.  Rows past the series read the zero pad after
+// it (the caller ignores them).  Returns this thread's window.
+__device__ __forceinline__ const float* stage_windows(const float* __restrict__ T, int64_t i0,
+                                                      int n, float* __restrict__ sh) {
+  for (int k = threadIdx.x; k < 255 + n; k += 256) sh[k] = T[i0 + k];
+  __syncthreads();
+  return sh + threadIdx.x;
+}
+
+size_t stage_bytes(int n) { return sizeof(float) * (size_t)(255 + n); }
+
 // Mean and centred squared norm of every row (FP64, sequential two-pass sums,
 // each multiply and add rounded on its own) and, for per-window normalisation,
 // the row's standard deviation sqrt(cnorm / n): eq. (2) over the window alone.
@@ -87,9 +100,11 @@ __global__ __launch_bounds__(256) void k_row_stats(const float* __restrict__ T, 
                                                    double* __restrict__ cnorm,
                                                    double* __restrict__ sigma) {
 #pragma clang fp contract(off)
-  const int64_t i = blockIdx.x * 256ll + threadIdx.x;
+  extern __shared__ float stage[];
+  const int64_t i0 = blockIdx.x * 256ll;
+  const int64_t i = i0 + threadIdx.x;
+  const float* x = stage_windows(T, i0, n, stage);
   if (i >= N) return;
-  const float* x = T + i;
   double s = 0.0;
   for (int k = 0; k < n; ++k) s = s + (double)x[k];
   const double mu = s / (double)n;
@@ -103,20 +118,16 @@ __global__ __launch_bounds__(256) void k_row_stats(const float* __restrict__ T, 
   if (sigma) sigma[i] = sqrt(q / (double)n);
 }
 
-// FP32 row statistics of the split-BF16 scan.  The centre of row i is
-// c_i = fp32(mean_i); the scan centres with exactly c_i, so the centred norm is
-// taken about c_i (FP64), while the mean term uses the exact mean:
-//   d^2 = |a - c_a|^2 + |b - c_b|^2 - 2 (a - c_a).(b - c_b) + n (mu_a - mu_b)^2
-//         - n ((mu_a - c_a) - (mu_b - c_b))^2,
-// whose last term (below n * ulp(mu)^2) is dropped.  smu = sqrt(n) (mu - mu_T)
-// with mu_T the series mean.  Entries N .. N+pad-1 are zero.
+// FP32 row statistics of the split-BF16 scan (scan_mfma.hip) and of the
+// normalised FP32 scan.  c_i = fp32(mean_i) is row i's centre; cnorm is the
+// squared norm about c_i (FP64, rounded once), which differs from the norm
+// about the exact mean by n (mu_i - c_i)^2, below n ulp(mu)^2; smu =
+// sqrt(n) (mu - mu_T) with mu_T the series mean.  Entries N .. N+pad-1 are zero.
 //
-// Per-window normalisation (sigma != nullptr): the operands are the centred
-// windows scaled by r_i = fp32(1 / sigma_i) (0 for a flat window), i.e. the
-// normalised windows up to the rounding of c_i and r_i; the mean term is gone
-// (every normalised window has mean 0), so smu = 0, and cnorm is the squared
-// norm of the FP32 operand values x_k = (t_{i+k} - c_i) * r_i, computed with
-// the same FP32 operations the split uses.  Both scans read c and r.
+// Per-window normalisation (sigma != nullptr): r_i = fp32(1 / sigma_i) (0 for
+// a flat window); the normalised operand values are x_k = (t_{i+k} - c_i) r_i,
+// cnorm is their squared norm, computed with the FP32 operations the FP32
+// scan uses, and smu = 0 (normalised windows have mean 0).
 __global__ __launch_bounds__(256) void k_row_stats32(const float* __restrict__ T, int64_t N, int n,
                                                      int64_t padded,
                                                      const double* __restrict__ mean,
@@ -126,7 +137,10 @@ __global__ __launch_bounds__(256) void k_row_stats32(const float* __restrict__ T
                                                      float* __restrict__ smu32,
                                                      float* __restrict__ cn32,
                                                      float* __restrict__ r32) {
-  const int64_t i = blockIdx.x * 256ll + threadIdx.x;
+  extern __shared__ float stage[];
+  const int64_t i0 = blockIdx.x * 256ll;
+  const int64_t i = i0 + threadIdx.x;
+  const float* x = stage_windows(T, i0, n, stage);
   if (i >= padded) return;
   if (i >= N) {
     c32[i] = 0.0f;
@@ -142,15 +156,15 @@ __global__ __launch_bounds__(256) void k_row_stats32(const float* __restrict__ T
     const double sg = sigma[i];
     const float r = sg > 0.0 ? (float)(1.0 / sg) : 0.0f;
     for (int k = 0; k < n; ++k) {
-      const float x = (T[i + k] - c) * r;
-      q += (double)x * (double)x;
+      const float v = (x[k] - c) * r;
+      q += (double)v * (double)v;
     }
     r32[i] = r;
     smu32[i] = 0.0f;
   } else {
     const double cd = (double)c;
     for (int k = 0; k < n; ++k) {
-      const double d = (double)T[i + k] - cd;
+      const double d = (double)x[k] - cd;
       q += d * d;
     }
     smu32[i] = (float)(sqrt((double)n) * (mu - stats[0]));
@@ -175,12 +189,13 @@ __global__ __launch_bounds__(256) void k_sax(const float* __restrict__ T, int64_
                                              int32_t* __restrict__ words,
                                              int32_t* __restrict__ hist) {
   __shared__ int32_t lh[kMaxWords];
+  extern __shared__ float stage[];
   for (int b = threadIdx.x; b < kMaxWords; b += 256) lh[b] = 0;
-  __syncthreads();
-  const int64_t i = blockIdx.x * 256ll + threadIdx.x;
+  const int64_t i0 = blockIdx.x * 256ll;
+  const int64_t i = i0 + threadIdx.x;
+  const float* x = stage_windows(T, i0, n, stage);   // (its barrier also covers lh)
   if (i < N) {
     const double mu = Z ? zmu[i] : stats[0], sigma = Z ? zsg[i] : stats[1];
-    const float* x = T + i;
     int32_t code = 0;
     for (int s = 0; s < w; ++s) {
       const int a = (int)(((int64_t)s * n) / w), e = (int)(((int64_t)(s + 1) * n) / w);
@@ -396,27 +411,47 @@ __global__ __launch_bounds__(64) void k_csr_count(const int32_t* __restrict__ wo
 }
 
 // offsets = exclusive scan of hist; seg_counts[s][w] -> base of segment s for word w
+// One workgroup per word w: offsets[w] = sum of the frequencies of the words
+// before it, then the exclusive scan of w's per-segment counts (segment s at
+// seg_counts[s * dict + w]) on top of it, 256 segments at a time.
 __global__ __launch_bounds__(256) void k_csr_scan(const int32_t* __restrict__ hist, int dict,
                                                   int64_t nseg, int32_t* __restrict__ seg_counts,
                                                   int32_t* __restrict__ offsets) {
-  __shared__ int32_t off[kMaxWords + 1];
+  __shared__ int32_t wsum[4];
+  const int w = blockIdx.x;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  // sum over the block of one value per thread, returned to every thread
+  auto block_sum = [&](int32_t v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    __syncthreads();                       // wsum free again
+    if (lane == 0) wsum[wv] = v;
+    __syncthreads();
+    return wsum[0] + wsum[1] + wsum[2] + wsum[3];
+  };
+  int32_t part = 0;
+  for (int k = threadIdx.x; k < w; k += 256) part += hist[k];
+  int32_t carry = block_sum(part);
   if (threadIdx.x == 0) {
-    int32_t run = 0;
-    for (int w = 0; w < dict; ++w) {
-      off[w] = run;
-      run += hist[w];
-    }
-    off[dict] = run;
+    offsets[w] = carry;
+    if (w == dict - 1) offsets[dict] = carry + hist[w];
   }
-  __syncthreads();
-  for (int w = threadIdx.x; w <= dict; w += 256) offsets[w] = off[w];
-  for (int w = threadIdx.x; w < dict; w += 256) {
-    int32_t run = off[w];
-    for (int64_t s = 0; s < nseg; ++s) {
-      const int32_t c = seg_counts[s * dict + w];
-      seg_counts[s * dict + w] = run;
-      run += c;
+  for (int64_t s0 = 0; s0 < nseg; s0 += 256) {
+    const int64_t sg = s0 + threadIdx.x;
+    const int32_t v = sg < nseg ? seg_counts[sg * dict + w] : 0;
+    // inclusive scan within the wave, then the wave totals
+    int32_t x = v;
+    for (int off = 1; off < 64; off <<= 1) {
+      const int32_t y = __shfl_up(x, off, 64);
+      if (lane >= off) x += y;
     }
+    __syncthreads();                       // wsum free again
+    if (lane == 63) wsum[wv] = x;
+    __syncthreads();
+    int32_t before = 0;
+    for (int k = 0; k < wv; ++k) before += wsum[k];
+    const int32_t total = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    if (sg < nseg) seg_counts[sg * dict + w] = carry + before + x - v;
+    carry += total;
   }
 }
 
@@ -465,16 +500,16 @@ void launch_stats(const float* Tp, int64_t m, double* partials, double* stats, i
 void launch_row_stats(const float* Tp, int64_t N, int n, double* row_mean, double* row_cnorm,
                       double* row_sigma, hipStream_t s) {
   const int64_t blocks = (N + 255) / 256;
-  hipLaunchKernelGGL(k_row_stats, dim3((unsigned)blocks), dim3(256), 0, s, Tp, N, n, row_mean,
-                     row_cnorm, row_sigma);
+  hipLaunchKernelGGL(k_row_stats, dim3((unsigned)blocks), dim3(256), stage_bytes(n), s, Tp, N, n,
+                     row_mean, row_cnorm, row_sigma);
 }
 
 void launch_row_stats32(const float* Tp, int64_t N, int n, int64_t padded, const double* row_mean,
                         const double* row_sigma, const double* stats, float* c32, float* smu32,
                         float* cn32, float* r32, hipStream_t s) {
   const int64_t blocks = (padded + 255) / 256;
-  hipLaunchKernelGGL(k_row_stats32, dim3((unsigned)blocks), dim3(256), 0, s, Tp, N, n, padded,
-                     row_mean, row_sigma, stats, c32, smu32, cn32, r32);
+  hipLaunchKernelGGL(k_row_stats32, dim3((unsigned)blocks), dim3(256), stage_bytes(n), s, Tp, N, n,
+                     padded, row_mean, row_sigma, stats, c32, smu32, cn32, r32);
 }
 
 // Breakpoints of eq. (4): beta_k = Phi^{-1}(k / alpha), computed on the host by
@@ -488,11 +523,11 @@ void launch_sax(const float* Tp, int64_t N, int n, int w, int alpha, const doubl
   sax_breakpoints(alpha, bp.b);
   const int64_t blocks = (N + 255) / 256;
   if (zsg)
-    hipLaunchKernelGGL(k_sax<true>, dim3((unsigned)blocks), dim3(256), 0, s, Tp, N, n, w, alpha,
-                       bp, stats, zmu, zsg, words, hist);
+    hipLaunchKernelGGL(k_sax<true>, dim3((unsigned)blocks), dim3(256), stage_bytes(n), s, Tp, N, n,
+                       w, alpha, bp, stats, zmu, zsg, words, hist);
   else
-    hipLaunchKernelGGL(k_sax<false>, dim3((unsigned)blocks), dim3(256), 0, s, Tp, N, n, w, alpha,
-                       bp, stats, zmu, zsg, words, hist);
+    hipLaunchKernelGGL(k_sax<false>, dim3((unsigned)blocks), dim3(256), stage_bytes(n), s, Tp, N,
+                       n, w, alpha, bp, stats, zmu, zsg, words, hist);
 }
 
 void launch_cand(const int32_t* words, const int32_t* hist, int64_t N, int dict,
@@ -541,7 +576,8 @@ void launch_csr(const int32_t* words, const int32_t* hist, int64_t N, int dict,
   const int64_t nseg = csr_waves(N);
   hipLaunchKernelGGL(k_csr_count, dim3((unsigned)nseg), dim3(64), 0, s, words, N, dict,
                      seg_counts);
-  hipLaunchKernelGGL(k_csr_scan, dim3(1), dim3(256), 0, s, hist, dict, nseg, seg_counts, offsets);
+  hipLaunchKernelGGL(k_csr_scan, dim3((unsigned)dict), dim3(256), 0, s, hist, dict, nseg, seg_counts,
+                     offsets);
   hipLaunchKernelGGL(k_csr_scatter, dim3((unsigned)nseg), dim3(64), 0, s, words, N, dict,
                      seg_counts, members);
 }
