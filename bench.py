@@ -165,11 +165,12 @@ def cpu_baseline(series, n, budget_s=15.0):
 
 
 def serving(dd, workloads, precision="bf16x3", slots=4, budget=8 << 30, count=4096, speed=1.0,
-            reqs=None):
-    """The request stream of the serving configuration (Poisson arrivals at
-    200 req/s, m log-uniform in [2^12, 2^18], n in {64, 128, 256}, one planted
-    anomaly each), replayed open-loop through the serving loop, at its own
-    rate (speed 1) or compressed in time (speed > 1) to saturate the server."""
+            reqs=None, label=None):
+    """A request stream (by default the serving configuration's: Poisson
+    arrivals at 200 req/s, m log-uniform in [2^12, 2^18], n in {64, 128, 256},
+    one planted anomaly each) replayed open-loop through the serving loop, at
+    its own rate (speed 1) or compressed in time (speed > 1) to saturate the
+    server."""
     from paper_1901_00155_amd import serve
     t = time.perf_counter()
     if reqs is None:
@@ -186,9 +187,14 @@ def serving(dd, workloads, precision="bf16x3", slots=4, budget=8 << 30, count=40
     recs = list(out["records"].values())
     ok = [c for c in recs if c["status"] == 0]
     assert sm["failed"] == 0 and all(c["result"]["certified"] == 1 for c in ok)
+    modes = [c["result"]["graph"] for c in ok]
     return {
-        "workload": f"{count} requests, Poisson 200 req/s, m log-uniform [2^12, 2^18], "
-                    "n in {64,128,256}, random walk + 1 planted anomaly each (seed 4)",
+        "workload": label or (f"{count} requests, Poisson 200 req/s, m log-uniform [2^12, 2^18], "
+                              "n in {64,128,256}, random walk + 1 planted anomaly each (seed 4)"),
+        # how each completed request was launched: ordinary launches, captured
+        # into a HIP graph, or a replay of its slot's graph
+        "launch_modes": {"ordinary": modes.count(0), "captured": modes.count(1),
+                         "graph_replay": modes.count(2)},
         "speed": speed, "precision": precision, "slots": slots, "hbm_budget_bytes": budget,
         "p50_ms": sm["p50_ms"], "p99_ms": sm["p99_ms"], "mean_ms": sm["mean_ms"],
         "max_ms": sm["max_ms"], "throughput_rps": sm["throughput_rps"],
@@ -393,7 +399,8 @@ def main():
             "precision": other, "time_to_discord_ms": s2 * 1e3, "pairs_per_s": p2 / s2,
             "brute_force_equiv_pairs_per_s": P / s2, "speedup_vs_step": sec / s2,
             "max_rel_err_of_approx_nn": float(x.max_rel_err),
-            "roofline": roofline(n, other, p2, sm2, traffic_for(other, w.name, mode, n))}
+            "roofline": roofline(n, other, p2, sm2, traffic_for(other, w.name, mode, n),
+                                 launches=int(np.mean([y.scan_launches for y in rr])))}
         print(f"# {other} step {s2 * 1e3:.2f} ms", file=sys.stderr, flush=True)
         if abandon:
             # the paper's visiting order (PhiDD: Cand first, same-word columns first)
@@ -449,12 +456,21 @@ def main():
             out["long_windows"] = long_window_block(dd, workloads)
     if not args.no_serve:
         reqs = workloads.serve_requests(count=4096)
-        for key, speed in (("serving", 1.0), ("serving_saturated", 8.0)):
-            out[key] = serving(dd, workloads, speed=speed, reqs=reqs)
+        # one shape (a monitor re-searching a fixed-length window of a stream):
+        # every slot replays its captured graph after two requests
+        fixed = workloads.serve_requests(seed=6, count=2048, log2_min=14, log2_max=14,
+                                         windows=(128,))
+        fixed_label = ("2048 requests, Poisson 200 req/s, m = 2^14, n = 128, random walk + 1 "
+                       "planted anomaly each (seed 6)")
+        for key, speed, rq, label in (("serving", 1.0, reqs, None),
+                                      ("serving_saturated", 8.0, reqs, None),
+                                      ("serving_fixed_shape", 8.0, fixed, fixed_label)):
+            out[key] = serving(dd, workloads, speed=speed, reqs=rq, label=label,
+                               count=len(rq))
             sv = out[key]
             print(f"# {key} (x{speed:g}): p50 {sv['p50_ms']:.2f} ms p99 {sv['p99_ms']:.2f} ms "
-                  f"{sv['throughput_rps']:.1f} req/s, mean concurrency {sv['mean_concurrency']:.2f}",
-                  file=sys.stderr, flush=True)
+                  f"{sv['throughput_rps']:.1f} req/s, mean concurrency {sv['mean_concurrency']:.2f}, "
+                  f"launches {sv['launch_modes']}", file=sys.stderr, flush=True)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w.series, n, args.cpu_budget)
         out["cpu_baseline"]["config1_full"] = cpu_config1(dd, workloads)

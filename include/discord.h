@@ -39,7 +39,7 @@ extern "C" {
 
 /* 2: discord_opts lost its unused `topk` field (the certification rescores
  * every row's witness in FP64 instead of the k best candidates of some rows). */
-#define DISCORD_ABI_VERSION 2
+#define DISCORD_ABI_VERSION 3
 
 /* ---- status codes ------------------------------------------------------- */
 #define DISCORD_OK        0
@@ -120,6 +120,11 @@ typedef struct {
     uint64_t scan_launches;   /* scan launches enqueued (the device-decided search
                                  enqueues a fixed number; those past the end of its
                                  loop find no work)                                 */
+    int32_t  graph;           /* how the work was launched: 0 ordinary launches, 1
+                                 captured into a HIP graph and launched, 2 a replay
+                                 of a graph captured by an earlier call (see
+                                 discord_search_graph and the serving loop)          */
+    int32_t  reserved;        /* 0                                                   */
 } discord_result;
 
 typedef struct discord_plan_s* discord_plan;
@@ -287,6 +292,11 @@ int discord_stream_destroy(void* stream);
  * request completes.  A request's result depends only on its own series: the
  * requests share no device state besides the arena, whose blocks are disjoint.
  * A failing request completes with its status and never disturbs the others.
+ * A slot that serves requests of one shape keeps its arena block (a request
+ * whose footprint equals the slot's previous one gets that block back when it
+ * is free) and replays its preparation and search as one captured HIP graph:
+ * the second request of a shape on a slot is captured, later ones are replays
+ * (result.graph = 1, 2; 0 for ordinary launches, and always for order = 1).
  * All server functions are thread-safe. */
 typedef struct discord_server_s* discord_server;
 

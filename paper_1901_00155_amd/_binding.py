@@ -27,7 +27,7 @@ LIB_PATH = os.path.join(_HERE, "lib", "libdiscord.so")
 PREC_FP32 = 0
 PREC_BF16X3 = 1
 MIXED_MAX_N = 2048  # DISCORD_MIXED_MAX_N: longest window of the split-BF16 scan
-ABI_VERSION = 2     # DISCORD_ABI_VERSION of the header these structures mirror
+ABI_VERSION = 3     # DISCORD_ABI_VERSION of the header these structures mirror
 NOALLOC_MAX_BYTES = 32 << 20  # DISCORD_NOALLOC_MAX_BYTES: static workspace per device
 _PREC = {"fp32": PREC_FP32, "bf16x3": PREC_BF16X3, PREC_FP32: PREC_FP32, PREC_BF16X3: PREC_BF16X3}
 
@@ -71,7 +71,8 @@ class Result(ctypes.Structure):
                 ("pairs_evaluated", ctypes.c_uint64), ("rows_rescored", ctypes.c_uint64),
                 ("rows_abandoned", ctypes.c_uint64), ("cand_rows", ctypes.c_uint64),
                 ("ms_prepare", ctypes.c_double), ("ms_search", ctypes.c_double),
-                ("ms_scan", ctypes.c_double), ("scan_launches", ctypes.c_uint64)]
+                ("ms_scan", ctypes.c_double), ("scan_launches", ctypes.c_uint64),
+                ("graph", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -981,6 +981,7 @@ int discord_search_graph(discord_plan p, discord_result* out) {
     p->hout = h;
   }
   HostOut* h = static_cast<HostOut*>(p->hout);
+  const bool captured = !p->gexec;
   if (!p->gexec) {
     // capture once: the sequence depends only on the plan, and every launch's
     // work is decided on the device, so the same graph serves every search
@@ -1017,7 +1018,9 @@ int discord_search_graph(discord_plan p, discord_result* out) {
   run.h = h;
   run.events = false;
   run.launches = p->glaunches;
-  return search_finish(p, run, ev, out);
+  const int st = search_finish(p, run, ev, out);
+  if (st == DISCORD_OK) out->graph = captured ? 1 : 2;
+  return st;
 }
 
 void discord_release(discord_plan p) {
@@ -1222,6 +1225,123 @@ int search_series_in_arena(const float* T, int64_t m, int32_t n, const discord_o
       st = search_finish(p, run, none, out);
     }
   }
+  if (st != DISCORD_OK && err && err_len) std::snprintf(err, err_len, "%s", p->err);
+  return st;
+}
+
+struct RequestGraph {
+  discord_plan_s plan;            // host fields of the plan bound to the workspace
+  const float* T = nullptr;       // the key: series pointer, sizes, options, memory, stream
+  int64_t m = 0;
+  int32_t n = 0;
+  discord_opts opts{};
+  void* arena = nullptr;
+  hipStream_t stream = nullptr;
+  HostOut* h = nullptr;           // pinned block the graph's copies land in
+  hipGraphExec_t exec = nullptr;
+  int launches = 0;
+};
+
+void request_graph_free(RequestGraph* g) {
+  if (!g) return;
+  if (g->stream) (void)hipStreamSynchronize(g->stream);
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->h) (void)hipHostFree(g->h);
+  delete g;
+}
+
+int search_series_graph(RequestGraph** cache, bool capture, const float* T, int64_t m, int32_t n,
+                        const discord_opts* opts, void* arena, size_t arena_bytes,
+                        hipStream_t stream, discord_result* out, char* err, size_t err_len) {
+  if (err && err_len) err[0] = 0;
+  discord_opts o;
+  int st = check_prepare_args(T, m, n, opts, &o);
+  if (st != DISCORD_OK) return st;
+  RequestGraph* g = *cache;
+  const bool hit = g && g->exec && g->T == T && g->m == m && g->n == n && g->arena == arena &&
+                   g->stream == stream && std::memcmp(&g->opts, &o, sizeof(o)) == 0;
+  if (!hit) {
+    request_graph_free(g);
+    *cache = nullptr;
+    if (!capture || o.order == 1) {
+      st = search_series_in_arena(T, m, n, &o, arena, arena_bytes, stream, out, err, err_len);
+      if (st == DISCORD_OK) out->graph = 0;
+      return st;
+    }
+    g = new (std::nothrow) RequestGraph();
+    if (!g) return DISCORD_ENOMEM;
+    discord_plan p = &g->plan;
+    init_plan(p, m, n, o);
+    auto give_up = [&](int code) {
+      if (err && err_len) std::snprintf(err, err_len, "%s", p->err);
+      request_graph_free(g);
+      return code;
+    };
+    if (!arena || p->L.total > arena_bytes || ((uintptr_t)arena % kAlign) != 0)
+      return give_up(DISCORD_ERANGE);
+    if (hipGetDevice(&p->device) != hipSuccess) return give_up(DISCORD_EDEVICE);
+    p->stream = stream;
+    p->arena = static_cast<char*>(arena);
+    p->timed = false;
+    void* hb = nullptr;
+    if (hipHostMalloc(&hb, sizeof(HostOut), hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      return give_up(DISCORD_ENOMEM);
+    }
+    g->h = static_cast<HostOut*>(hb);
+    // the request's whole sequence, as the ordinary one-sequence path runs it
+    SearchRun cap;
+    cap.h = g->h;
+    cap.events = false;
+    if (hipStreamBeginCapture(stream, hipStreamCaptureModeRelaxed) != hipSuccess) {
+      (void)hipGetLastError();
+      return give_up(fail(p, DISCORD_EDEVICE, "hipStreamBeginCapture failed"));
+    }
+    st = prepare_enqueue(p, T);
+    if (st == DISCORD_OK) st = search_enqueue(p, cap);
+    if (st == DISCORD_OK) st = prepare_readback(p, g->h);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(stream, &graph);
+    if (st != DISCORD_OK || e != hipSuccess || !graph) {
+      if (graph) (void)hipGraphDestroy(graph);
+      (void)hipGetLastError();
+      return give_up(st != DISCORD_OK ? st
+                                      : fail(p, DISCORD_EDEVICE, "stream capture failed: %s",
+                                             hipGetErrorString(e)));
+    }
+    const hipError_t ei = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) {
+      g->exec = nullptr;
+      (void)hipGetLastError();
+      return give_up(fail(p, DISCORD_EDEVICE, "hipGraphInstantiate failed: %s",
+                          hipGetErrorString(ei)));
+    }
+    g->launches = cap.launches;
+    g->T = T;
+    g->m = m;
+    g->n = n;
+    g->opts = o;
+    g->arena = arena;
+    g->stream = stream;
+    *cache = g;
+  }
+  discord_plan p = &g->plan;
+  if (hipGraphLaunch(g->exec, stream) != hipSuccess ||
+      hipStreamSynchronize(stream) != hipSuccess) {
+    (void)hipGetLastError();
+    st = fail(p, DISCORD_EDEVICE, "graph launch failed");
+  }
+  if (st == DISCORD_OK) st = prepare_check(p, *g->h);
+  if (st == DISCORD_OK) {
+    SearchRun run;
+    run.h = g->h;
+    run.events = false;
+    run.launches = g->launches;
+    EventPair none(0, false);
+    st = search_finish(p, run, none, out);
+  }
+  if (st == DISCORD_OK) out->graph = hit ? 2 : 1;
   if (st != DISCORD_OK && err && err_len) std::snprintf(err, err_len, "%s", p->err);
   return st;
 }

@@ -329,4 +329,20 @@ int search_series_in_arena(const float* T, int64_t m, int32_t n, const discord_o
                            discord_result* out, char* err, size_t err_len);
 // Sets the calling thread's error text (discord_plan_error(NULL)).
 void set_thread_error(const char* fmt, ...);
+
+// The same request run as one HIP graph: preparation and search (every
+// decision of the search is taken on the device) captured from `stream` into
+// a graph that `*cache` keeps, together with the plan and a pinned readback
+// block.  A later call with the same series pointer, (m, n), options,
+// workspace and stream replays the graph (one launch, one synchronisation);
+// any other call drops the cached graph and either captures a new one
+// (capture = true) or runs the request with ordinary launches.  The PhiDD
+// order (its sequences need host-side sizes) always runs with ordinary
+// launches.  out->graph tells which happened (0 ordinary, 1 captured now,
+// 2 replayed).  The caller owns *cache and frees it with request_graph_free.
+struct RequestGraph;
+int search_series_graph(RequestGraph** cache, bool capture, const float* T, int64_t m, int32_t n,
+                        const discord_opts* opts, void* arena, size_t arena_bytes,
+                        hipStream_t stream, discord_result* out, char* err, size_t err_len);
+void request_graph_free(RequestGraph* g);
 }  // namespace dd

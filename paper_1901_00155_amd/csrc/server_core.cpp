@@ -47,6 +47,22 @@ size_t ArenaAllocator::alloc(size_t bytes) {
   return kNone;
 }
 
+size_t ArenaAllocator::alloc_at(size_t off, size_t bytes) {
+  const size_t b = std::max(round(bytes), kAlign);
+  if (off % kAlign || off > capacity_ || b > capacity_ - off) return kNone;
+  auto& fb = impl_->free_blocks;
+  auto it = fb.upper_bound(off);            // first free block starting after off
+  if (it == fb.begin()) return kNone;
+  --it;                                      // the free block starting at or before off
+  const size_t s = it->first, e = it->first + it->second;
+  if (off + b > e) return kNone;
+  fb.erase(it);
+  if (off > s) fb.emplace(s, off - s);
+  if (off + b < e) fb.emplace(off + b, e - off - b);
+  in_use_ += b;
+  return off;
+}
+
 void ArenaAllocator::release(size_t offset, size_t bytes) {
   const size_t b = std::max(round(bytes), kAlign);
   auto& fb = impl_->free_blocks;
@@ -117,11 +133,17 @@ struct discord_server_s {
 
 void discord_server_s::worker(int slot) {
   std::unique_lock<std::mutex> lk(mu);
+  // the block of this slot's previous request: a request of the same footprint
+  // gets it back when it is free, so a slot that serves one shape keeps its
+  // device addresses (and can replay its captured graph)
+  size_t last_off = dd::ArenaAllocator::kNone, last_bytes = 0;
   for (;;) {
     size_t off = dd::ArenaAllocator::kNone;
     while (!stop) {
       if (!queue.empty()) {
-        off = alloc.alloc(queue.front().bytes);
+        const size_t want = queue.front().bytes;
+        if (want == last_bytes) off = alloc.alloc_at(last_off, want);
+        if (off == dd::ArenaAllocator::kNone) off = alloc.alloc(want);
         if (off != dd::ArenaAllocator::kNone) break;
       }
       cv_work.wait(lk);
@@ -130,6 +152,8 @@ void discord_server_s::worker(int slot) {
 
     Pending rq = std::move(queue.front());
     queue.pop_front();
+    last_off = off;
+    last_bytes = rq.bytes;
     ++running;
     peak_running = std::max(peak_running, running);
     peak_bytes = std::max(peak_bytes, alloc.in_use());

@@ -22,6 +22,8 @@ class ArenaAllocator {
   ArenaAllocator(const ArenaAllocator&) = delete;
   ArenaAllocator& operator=(const ArenaAllocator&) = delete;
   size_t alloc(size_t bytes);            // offset, or kNone when no free block fits
+  // [off, off + bytes) if that range is free (off a multiple of kAlign), else kNone
+  size_t alloc_at(size_t off, size_t bytes);
   void release(size_t offset, size_t bytes);
   size_t capacity() const { return capacity_; }
   size_t in_use() const { return in_use_; }

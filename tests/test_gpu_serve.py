@@ -169,3 +169,52 @@ def test_concurrent_submitters_many_slots(gpu):
         assert c["status"] == 0, c["detail"]
         got = (c["result"]["index"], c["result"]["nn_index"], c["result"]["d2"])
         assert got == alone[r.tag], (r.tag, got, alone[r.tag])
+
+
+@pytest.mark.parametrize("precision", PRECS)
+def test_repeated_shape_replays_a_graph(gpu, precision):
+    """Requests of one shape: on each slot the first runs with ordinary
+    launches, the second is captured into a HIP graph and later ones replay it
+    (result.graph 0, 1, 2).  Every result equals a plan's own search bit for
+    bit, the first equals the FP64 oracle, and a failing request (NaN) in the
+    stream neither breaks the replays after it nor changes their results."""
+    dd = gpu
+    m, n = 6000, 64
+    series = [workloads.random_walk(m, seed=900 + k) for k in range(14)]
+    bad = series[7].copy()
+    bad[100] = np.nan
+    series[7] = bad
+    alone = {}
+    for k, T in enumerate(series):
+        if k == 7:
+            continue
+        with dd.Plan(T, n, precision=precision) as p:
+            alone[k] = p.search().as_dict()
+    o = oracle.discord(series[0], n)
+    assert (alone[0]["index"], alone[0]["nn_index"]) == (o["index"], o["nn_index"])
+    with dd.Server(1 << 30, slots=2, precision=precision) as s:
+        for k, T in enumerate(series):
+            assert s.submit(T, n, k) == 0
+        done = _drain(s, len(series))
+    assert done[7]["status"] == -1, done[7]["detail"]          # EINVAL: NaN in the series
+    modes = [done[k]["result"]["graph"] for k in alone]
+    print(precision, "graph modes", modes, flush=True)
+    assert modes.count(2) >= 6 and modes.count(1) >= 1 and set(modes) <= {0, 1, 2}
+    for k, a in alone.items():
+        c = done[k]
+        assert c["status"] == 0, c["detail"]
+        b = c["result"]
+        assert b["certified"] == 1
+        assert (b["index"], b["nn_index"]) == (a["index"], a["nn_index"]), k
+        assert b["d2"] == a["d2"] and b["distance"] == a["distance"], k
+
+
+def test_plan_graph_reports_capture_then_replay(gpu):
+    dd = gpu
+    w = workloads.small()
+    with dd.Plan(w.series, w.n) as p:
+        r0 = p.search()
+        r1 = p.search_graph()
+        r2 = p.search_graph()
+    assert (r0.graph, r1.graph, r2.graph) == (0, 1, 2)
+    assert r0.index == r1.index == r2.index and r0.d2 == r1.d2 == r2.d2

@@ -101,6 +101,32 @@ def test_slots_bind_when_memory_is_plentiful(dd):
     assert not ex.errors
 
 
+def test_slot_keeps_its_block_for_one_shape(dd):
+    """A slot serving requests of one footprint gets its previous arena block
+    back (so a captured graph of the request keeps its device addresses), even
+    where first-fit would hand it another free block."""
+    m, n = 8192, 64
+    fp = (dd.workspace_bytes(m, n) + 255) // 256 * 256
+    seen = {}
+    lock = threading.Lock()
+
+    def ex(req, opts, res):
+        with lock:
+            seen.setdefault(req.slot, []).append(req.ws_offset)
+        time.sleep(0.002 * (1 + req.slot))    # the slots drift apart
+        res.index = 0
+        return 0
+
+    with dd.Server(4 * fp, slots=3, executor=ex) as s:
+        for t in range(30):
+            assert s.submit(np.arange(m, dtype=np.float32), n, t) == 0
+        _drain(s, 30)
+    assert sum(len(v) for v in seen.values()) == 30 and len(seen) == 3
+    for slot, offs in seen.items():
+        assert len(set(offs)) == 1, (slot, offs)
+    assert len({offs[0] for offs in seen.values()}) == 3   # disjoint blocks
+
+
 def test_strict_fifo_admission(dd):
     """A request at the head that does not fit yet is not overtaken by smaller
     ones behind it (no starvation); admission order equals submission order."""
