@@ -163,7 +163,10 @@ __device__ __forceinline__ bf16x8 mask_bf16(bf16x8 x, uint4 m) {
   return __builtin_bit_cast(bf16x8, u);
 }
 
-template <bool Z>
+// PFE > 0: the stretch has at most PFE * 256 entries, and each thread holds
+// the values of its PFE entries (and a column's statistics) for the next step
+// in registers: they are loaded while the current step's MFMAs run.
+template <bool Z, int PFE>
 __device__ __forceinline__ void scan_item(const ScanJob& J, const MixedRows& R, int64_t wi,
                                           bf16x8* smem) {
   __shared__ uint32_t wave_live[2 * W];
@@ -245,10 +248,69 @@ __device__ __forceinline__ void scan_item(const ScanJob& J, const MixedRows& R, 
   for (int w = 0; w < W; ++w) wg_live |= wave_live[w] != 0;
   if (!wg_live) steps = 0;
 
+  const int32_t jlim = (int32_t)N;   // N < 2^31 (checked at prepare)
+
+  // ---- a step's column data: the stretch values, the centre and the columns'
+  // statistics (prefetched one step ahead when PFE > 0) ---------------------------
+  constexpr int PFN = PFE > 0 ? PFE : 1;
+  float4 pa[PFN], pb[PFN];
+  float pcc = 0.0f, pcn = 0.0f, pmu = 0.0f, px = 0.0f;
+  int32_t pj0 = 0;
+  auto fetch_cols = [&](int64_t st) {
+    pj0 = (int32_t)(block_of(st) * TC);
+    pcc = R.mu[min<int64_t>(pj0 + TC / 2, N - 1)];
+#pragma unroll
+    for (int r = 0; r < PFN; ++r) {
+      const int p = threadIdx.x + THREADS * r;
+      if (p < L) {
+        const float* src = J.Tp + pj0 + p;
+        __builtin_memcpy(&pa[r], src, 16);
+        __builtin_memcpy(&pb[r], src + 4, 16);
+      }
+    }
+    if (threadIdx.x < TC) {
+      const int32_t j = pj0 + threadIdx.x;
+      const bool in = j < jlim;
+      pcn = in ? R.cnorm[j] : 0.0f;
+      pmu = in ? R.mu[j] : 0.0f;
+      px = in ? (Z ? R.r[j] : R.smu[j]) : 0.0f;
+    }
+  };
+  // the prefetched step into LDS: hi/lo entries, norm-step operands, values
+  auto store_cols = [&]() {
+#pragma unroll
+    for (int r = 0; r < PFN; ++r) {
+      const int p = threadIdx.x + THREADS * r;
+      if (p < L) {
+        const float v[8] = {pa[r].x - pcc, pa[r].y - pcc, pa[r].z - pcc, pa[r].w - pcc,
+                            pb[r].x - pcc, pb[r].y - pcc, pb[r].z - pcc, pb[r].w - pcc};
+        bf16x8 hi, lo;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const __bf16 x = (__bf16)v[e];
+          hi[e] = x;
+          lo[e] = (__bf16)(v[e] - (float)x);
+        }
+        cEh[p] = hi;
+        cEl[p] = lo;
+      }
+    }
+    if (threadIdx.x < TC) {
+      const bool in = pj0 + (int32_t)threadIdx.x < jlim;
+      norm_col(Z ? 0.0f : pcn, in ? pmu - pcc : 0.0f, cN[2 * threadIdx.x], cN[2 * threadIdx.x + 1]);
+      cst[threadIdx.x] = px;
+      if (Z) cst[TC + threadIdx.x] = pcn;
+    }
+  };
+
   // ---- the row stretch and the per-row terms -----------------------------------
-  // the row stretch carries the factor -2 of -2 P (exact in bf16)
+  // the row stretch carries the factor -2 of -2 P (exact in bf16); the first
+  // step's column loads are issued first, so that both are in flight together
   const float CR = R.mu[min<int64_t>(r_first + TR / 2, N - 1)];
-  if (steps > 0) build_stretch(J.Tp, r_first, CR, -2.0f, L, rEh, rEl);
+  if (steps > 0) {
+    if constexpr (PFE > 0) fetch_cols(0);
+    build_stretch(J.Tp, r_first, CR, -2.0f, L, rEh, rEl);
+  }
   const int64_t irow = min<int64_t>(r0 + rl, N - 1);
   const float ci = R.cnorm[irow];
   const float mi = R.mu[irow] - CR;
@@ -271,7 +333,6 @@ __device__ __forceinline__ void scan_item(const ScanJob& J, const MixedRows& R, 
   int32_t rj = -1;
   uint32_t cnt = 0;
   const int32_t i = (int32_t)(r0 + rl);
-  const int32_t jlim = (int32_t)N;   // N < 2^31 (checked at prepare)
 
   for (int64_t s = 0; s < steps; ++s) {
     // every wavefront has finished reading the previous step's columns (and
@@ -284,22 +345,34 @@ __device__ __forceinline__ void scan_item(const ScanJob& J, const MixedRows& R, 
       for (int w = 0; w < W; ++w) any |= flags[w] != 0;
       if (!any) break;
     }
-    const int64_t q = block_of(s);
-    const int32_t j0 = (int32_t)(q * TC);
-    const float CC = R.mu[min<int64_t>(j0 + TC / 2, N - 1)];
-    build_stretch(J.Tp, j0, CC, 1.0f, L, cEh, cEl);
-    if (threadIdx.x < TC) {
-      const int32_t j = j0 + threadIdx.x;
-      const bool in = j < jlim;
-      const float cn = in ? R.cnorm[j] : 0.0f;
-      norm_col(Z ? 0.0f : cn, in ? R.mu[j] - CC : 0.0f, cN[2 * threadIdx.x],
-               cN[2 * threadIdx.x + 1]);
-      cst[threadIdx.x] = in ? (Z ? R.r[j] : R.smu[j]) : 0.0f;
-      if (Z) cst[TC + threadIdx.x] = cn;
+    int32_t j0;
+    if constexpr (PFE > 0) {
+      j0 = pj0;
+      store_cols();
+    } else {
+      j0 = (int32_t)(block_of(s) * TC);
+      const float CC = R.mu[min<int64_t>(j0 + TC / 2, N - 1)];
+      build_stretch(J.Tp, j0, CC, 1.0f, L, cEh, cEl);
+      if (threadIdx.x < TC) {
+        const int32_t j = j0 + threadIdx.x;
+        const bool in = j < jlim;
+        const float cn = in ? R.cnorm[j] : 0.0f;
+        norm_col(Z ? 0.0f : cn, in ? R.mu[j] - CC : 0.0f, cN[2 * threadIdx.x],
+                 cN[2 * threadIdx.x + 1]);
+        cst[threadIdx.x] = in ? (Z ? R.r[j] : R.smu[j]) : 0.0f;
+        if (Z) cst[TC + threadIdx.x] = cn;
+      }
     }
     __syncthreads();
+    // the next step's column loads run while this step's MFMAs do
+    if constexpr (PFE > 0) {
+      if (s + 1 < steps) fetch_cols(s + 1);
+    }
 
     if (live) {
+      // the best-so-far for this step's abandon test, read before the MFMAs so
+      // that its latency overlaps them (a value read earlier is never larger)
+      const float bsf_now = J.abandon ? __builtin_bit_cast(float, load_relaxed(J.bsf)) : 0.0f;
       // ---- the norm step, then -2 P for 32 rows x 128 columns ----------------------
       floatx16 acc[CB];
       {
@@ -419,9 +492,8 @@ __device__ __forceinline__ void scan_item(const ScanJob& J, const MixedRows& R, 
       }
       // ---- early abandon ----------------------------------------------------------
       if (J.abandon) {
-        const float bsf = __builtin_bit_cast(float, load_relaxed(J.bsf));
         const float m = fminf(rmin, __shfl_xor(rmin, 32, 64));
-        const uint32_t dead = (uint32_t)(__ballot(m < bsf && h == 0) & 0xFFFFFFFFull) & live;
+        const uint32_t dead = (uint32_t)(__ballot(m < bsf_now && h == 0) & 0xFFFFFFFFull) & live;
         if (dead) {
           uint64_t key = rj < 0 ? kEmptyMin : pack_min(fmaxf(rmin, 0.0f), (uint32_t)rj);
           const uint64_t o = __shfl_xor(key, 32, 64);
@@ -494,19 +566,19 @@ __device__ __forceinline__ void scan_item(const ScanJob& J, const MixedRows& R, 
 
 // One workgroup per work item (item, chunk), striding by the grid size.  Every
 // wavefront finishes its LDS reads before the next item rebuilds the stretches.
-template <bool Z>
+template <bool Z, int PFE>
 __global__ __launch_bounds__(THREADS, 2) void k_scan_mfma(ScanJob Jarg, MixedRows R) {
   extern __shared__ bf16x8 smem[];
   ScanJob J = Jarg;
   apply_win(J);
   const int64_t total = J.n_groups * J.chunks;
   for (int64_t wi = blockIdx.x; wi < total; wi += gridDim.x) {
-    scan_item<Z>(J, R, wi, smem);
+    scan_item<Z, PFE>(J, R, wi, smem);
     if (wi + gridDim.x < total) __syncthreads();
   }
 }
 
-template <bool Z>
+template <bool Z, int PFE>
 void launch_scan(const ScanJob& J, const MixedRows& R, hipStream_t s) {
   const int64_t blocks = J.win ? J.max_work : J.n_groups * J.chunks;
   if (blocks <= 0) return;
@@ -514,23 +586,32 @@ void launch_scan(const ScanJob& J, const MixedRows& R, hipStream_t s) {
   // the LDS opt-in is per kernel and set once per process, to the largest
   // window's need; the initialisation of a function-local static is thread-safe
   static const bool attr_set = [] {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_scan_mfma<Z>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_scan_mfma<Z, PFE>),
                               hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds_bytes(kMixedMaxN / 16));
     return true;
   }();
   (void)attr_set;
-  hipLaunchKernelGGL(k_scan_mfma<Z>, dim3((unsigned)blocks), dim3(THREADS), lds, s, J, R);
+  hipLaunchKernelGGL((k_scan_mfma<Z, PFE>), dim3((unsigned)blocks), dim3(THREADS), lds, s, J, R);
 }
 
 }  // namespace
 
 bool launch_scan_mfma(const ScanJob& J, const MixedRows& R, hipStream_t s) {
   if (J.n < 1 || J.n > kMixedMaxN) return false;
-  if (R.r)
-    launch_scan<true>(J, R, s);
-  else
-    launch_scan<false>(J, R, s);
+  // stretches of up to 512 entries (windows up to 384) prefetch a step ahead
+  const bool pf = stretch_entries((J.n + 15) / 16) <= 2 * THREADS;
+  if (R.r) {
+    if (pf)
+      launch_scan<true, 2>(J, R, s);
+    else
+      launch_scan<true, 0>(J, R, s);
+  } else {
+    if (pf)
+      launch_scan<false, 2>(J, R, s);
+    else
+      launch_scan<false, 0>(J, R, s);
+  }
   return true;
 }
 
