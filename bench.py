@@ -85,19 +85,30 @@ def traffic_for(precision: str, workload: str, mode: str, n: int):
     return rec.get("bytes_per_search")
 
 
-def time_steps(dd, Td, n, precision, abandon, steps, warmup, order=2, znorm=False):
+def time_steps(dd, Td, n, precision, abandon, steps, warmup, order=2, znorm=False,
+               per_step=None):
+    """Mean seconds per step over `steps` timed steps after `warmup` untimed
+    ones, and the steps' results.  Each step returns once its result is on the
+    host, so `per_step` (a list, if given) receives every timed step's own
+    duration in ms as well."""
     import torch
     results = []
     stream = torch.cuda.current_stream()
+    t_prev = 0.0
     for it in range(warmup + steps):
         if it == warmup:
             torch.cuda.synchronize()
             t0 = time.perf_counter()
+            t_prev = t0
         with dd.Plan(Td, n, precision=precision, abandon=abandon, order=order, stream=stream,
                      torch_workspace=True, znorm=znorm) as p:
             r = p.search()
         if it >= warmup:
             results.append(r)
+            if per_step is not None:
+                t_now = time.perf_counter()
+                per_step.append((t_now - t_prev) * 1e3)
+                t_prev = t_now
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     return (t1 - t0) / max(steps, 1), results
@@ -350,7 +361,9 @@ def main():
     mode = "abandon" if abandon else "full"
 
     print(f"# workload {w.name}: m={m} n={n} N={N} P={P:.4e}", file=sys.stderr, flush=True)
-    sec, res = time_steps(dd, Td, n, args.precision, abandon, args.steps, args.warmup, args.order)
+    step_ms = []
+    sec, res = time_steps(dd, Td, n, args.precision, abandon, args.steps, args.warmup, args.order,
+                          per_step=step_ms)
     r = res[-1]
     assert len({int(x.index) for x in res}) == 1, "steps disagree"
     pairs = float(np.mean([x.pairs_evaluated for x in res]))
@@ -376,6 +389,8 @@ def main():
                    "precision": args.precision, "abandon": abandon,
                    "order": {0: "matrix", 1: "phidd", 2: "cand+near-first"}[args.order]},
         "time_to_discord_ms": sec * 1e3,
+        "time_to_discord_median_ms": float(np.median(step_ms)),
+        "time_to_discord_p90_ms": float(np.percentile(step_ms, 90)),
         "brute_force_equiv_pairs_per_s": P / sec,
         "pairs_evaluated": pairs,
         "discord": {"index": int(r.index), "nn_index": int(r.nn_index),
@@ -389,6 +404,18 @@ def main():
         "paper_context": PAPER_CONTEXT,
     }
     if not args.no_extras:
+        # the same step from the host series: the 4 MB host-to-device copy of T
+        # (and the readback, in every step anyway) inside the timed region
+        hs = {}
+        for prec in ("fp32", "bf16x3"):
+            hms = []
+            sh, _ = time_steps(dd, w.series, n, prec, abandon, args.steps, args.warmup, args.order,
+                               per_step=hms)
+            hs[prec] = {"time_to_discord_ms": sh * 1e3,
+                        "time_to_discord_median_ms": float(np.median(hms))}
+        out["host_series"] = hs
+        print(f"# host series: fp32 {hs['fp32']['time_to_discord_ms']:.2f} ms, "
+              f"bf16x3 {hs['bf16x3']['time_to_discord_ms']:.2f} ms", file=sys.stderr, flush=True)
         other = "bf16x3" if args.precision == "fp32" else "fp32"
         s2, rr = time_steps(dd, Td, n, other, abandon, args.steps, args.warmup, args.order)
         x = rr[-1]
