@@ -529,10 +529,12 @@ __device__ __forceinline__ void scan_item(const ScanJob& J, const MixedRows& R, 
 
   // the item's last chunk to finish decides: complete rows raise the
   // best-so-far with their minimum over all launches; rows still live after a
-  // non-final launch make the item a survivor
-  __threadfence();
-  __syncthreads();                              // every wavefront has published
+  // non-final launch make the item a survivor.  With one chunk each wavefront
+  // decides on its own rows (it reads back only what it published itself), so
+  // only several chunks need the fence and the barrier.
   if (J.chunks > 1) {
+    __threadfence();
+    __syncthreads();                            // every wavefront has published
     if (threadIdx.x == 0) {
       const uint32_t prev = atomicAdd(&J.done[item], 1u);
       const bool last = prev + 1 == (uint32_t)J.chunks;
