@@ -18,20 +18,24 @@
 // min_c <= i - n, so the first such bin at distance d from row i's own bin
 // bounds the nearest non-self mean below by (d - 1) bin widths.  With bins
 // that dense, a row leaves the outward search after a bin or two unless its
-// level is rare, which is what the bound is for.  Groups of 256 bins keep the
-// smallest and largest row index of their bins as well, so the search crosses
-// a group without a match in one step: a row at a rare level checks at most
-// a few hundred bins and groups on either side instead of tens of thousands
-// of bins.
+// level is rare, which is what the bound is for.  Groups of 16 bins and
+// supergroups of 256 keep the smallest and largest row index of their bins as
+// well, so the search crosses a (super)group without a match in one step: a
+// row at a rare level checks a few dozen slots on either side instead of
+// hundreds or thousands of bins.
 #include "internal.hpp"
 
 namespace dd {
 namespace {
 
 constexpr int kBoundBins = 65536;   // most bins
-constexpr int kGroup = 256;         // bins per group
-// scratch arrays: the bins, then their groups from index kBoundBins on
-constexpr int kBoundSlots = kBoundBins + kBoundBins / kGroup;
+constexpr int kG1 = 16;             // bins per group
+constexpr int kG2 = 256;            // bins per supergroup (kG2 / kG1 groups)
+// scratch arrays (smallest / largest row index): the bins, then their groups
+// from kBoundBins on, then their supergroups
+constexpr int kGroupBase = kBoundBins;
+constexpr int kSuperBase = kBoundBins + kBoundBins / kG1;
+constexpr int kBoundSlots = kSuperBase + kBoundBins / kG2;
 
 // order-preserving map of doubles to unsigned integers
 __device__ __forceinline__ uint64_t ordered(double x) {
@@ -105,14 +109,24 @@ __global__ __launch_bounds__(256) void k_bin_rows(const double* __restrict__ mu,
   }
 }
 
-// group g's smallest / largest row index over its bins (one workgroup each;
-// the last group may be partial, and fewer than kGroup bins make one group)
-__global__ __launch_bounds__(kGroup) void k_bin_groups(int nbins, int32_t* __restrict__ bmin,
-                                                       int32_t* __restrict__ bmax) {
-  __shared__ int32_t lo_s[kGroup / 64], hi_s[kGroup / 64];
-  const int c = blockIdx.x * kGroup + threadIdx.x;
+// the smallest / largest row index of every group (level 1) or supergroup
+// (level 2) over its bins: one workgroup of kG2 threads per supergroup, whose
+// threads are its bins (bins past nbins count as empty)
+__global__ __launch_bounds__(kG2) void k_bin_groups(int nbins, int32_t* __restrict__ bmin,
+                                                    int32_t* __restrict__ bmax) {
+  __shared__ int32_t lo_s[kG2 / 64], hi_s[kG2 / 64];
+  const int c = blockIdx.x * kG2 + threadIdx.x;
   int32_t lo = c < nbins ? bmin[c] : 0x7FFFFFFF, hi = c < nbins ? bmax[c] : -1;
-  for (int off = 32; off > 0; off >>= 1) {
+  // groups of kG1 bins: kG1 consecutive lanes
+  for (int off = 1; off < kG1; off <<= 1) {
+    lo = min(lo, __shfl_xor(lo, off, 64));
+    hi = max(hi, __shfl_xor(hi, off, 64));
+  }
+  if ((threadIdx.x & (kG1 - 1)) == 0 && c < nbins) {
+    bmin[kGroupBase + c / kG1] = lo;
+    bmax[kGroupBase + c / kG1] = hi;
+  }
+  for (int off = kG1; off < 64; off <<= 1) {
     lo = min(lo, __shfl_xor(lo, off, 64));
     hi = max(hi, __shfl_xor(hi, off, 64));
   }
@@ -122,47 +136,69 @@ __global__ __launch_bounds__(kGroup) void k_bin_groups(int nbins, int32_t* __res
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    for (int w = 1; w < kGroup / 64; ++w) {
+    for (int w = 1; w < kG2 / 64; ++w) {
       lo = min(lo, lo_s[w]);
       hi = max(hi, hi_s[w]);
     }
-    bmin[kBoundBins + blockIdx.x] = lo;
-    bmax[kBoundBins + blockIdx.x] = hi;
+    bmin[kSuperBase + blockIdx.x] = lo;
+    bmax[kSuperBase + blockIdx.x] = hi;
   }
 }
 
-// Does slot c (a bin, or a group at kBoundBins + g) hold a non-self row?
+// Does slot c (a bin, a group or a supergroup) hold a non-self row?
 __device__ __forceinline__ bool holds_match(const int32_t* __restrict__ bmin,
                                             const int32_t* __restrict__ bmax, int c,
                                             int64_t lo_row, int64_t hi_row) {
   return bmax[c] >= hi_row || bmin[c] <= lo_row;
 }
 
-// The nearest bin at distance < limit from bin k (going down if dir < 0, up
-// otherwise) holding a non-self row: its distance, or `limit` if none.
+// The nearest bin at distance < limit from bin k, going down (dir < 0) or up,
+// that holds a non-self row: its distance, or `limit` if none.  Bins of k's
+// group one by one, then groups of k's supergroup, then supergroups; a
+// (super)group that holds a match is entered (the match is in it).
 __device__ int nearest_match(const int32_t* __restrict__ bmin, const int32_t* __restrict__ bmax,
                              int nbins, int k, int dir, int limit, int64_t lo_row,
                              int64_t hi_row) {
-  int c = k;
-  // the rest of k's group, bin by bin
-  const int gedge = dir < 0 ? k / kGroup * kGroup : min(nbins, (k / kGroup + 1) * kGroup) - 1;
-  for (;; c += dir) {
-    const int d = dir < 0 ? k - c : c - k;
-    if (d >= limit) return limit;
-    if (holds_match(bmin, bmax, c, lo_row, hi_row)) return d;
-    if (c == gedge) break;
-  }
-  // whole groups; the first that holds a match is searched bin by bin
-  const int ngroups = (nbins + kGroup - 1) / kGroup;
-  for (int g = k / kGroup + dir; g >= 0 && g < ngroups; g += dir) {
-    const int first = dir < 0 ? (g + 1) * kGroup - 1 : g * kGroup;
-    if ((dir < 0 ? k - first : first - k) >= limit) return limit;
-    if (!holds_match(bmin, bmax, kBoundBins + g, lo_row, hi_row)) continue;
-    for (c = first;; c += dir) {
-      const int d = dir < 0 ? k - c : c - k;
-      if (d >= limit) return limit;
-      if (holds_match(bmin, bmax, c, lo_row, hi_row)) return d;
+  auto dist = [&](int c) { return dir < 0 ? k - c : c - k; };
+  // bins from c on (towards dir) until the edge of their group; -1 if none matches
+  auto scan_bins = [&](int c) -> int {
+    const int edge = dir < 0 ? c / kG1 * kG1 : min(nbins, (c / kG1 + 1) * kG1) - 1;
+    for (;; c += dir) {
+      if (dist(c) >= limit) return limit;
+      if (holds_match(bmin, bmax, c, lo_row, hi_row)) return dist(c);
+      if (c == edge) return -1;
     }
+  };
+  // groups from g on until the edge of their supergroup, entering the first
+  // that matches; -1 if none does
+  const int ngroups = (nbins + kG1 - 1) / kG1;
+  auto scan_groups = [&](int g) -> int {
+    const int edge = dir < 0 ? g / (kG2 / kG1) * (kG2 / kG1)
+                             : min(ngroups, (g / (kG2 / kG1) + 1) * (kG2 / kG1)) - 1;
+    for (;; g += dir) {
+      const int first = dir < 0 ? (g + 1) * kG1 - 1 : g * kG1;   // its bin nearest to k
+      if (dist(first) >= limit) return limit;
+      if (holds_match(bmin, bmax, kGroupBase + g, lo_row, hi_row)) {
+        const int d = scan_bins(first);
+        return d >= 0 ? d : limit;   // (a matching group holds a matching bin)
+      }
+      if (g == edge) return -1;
+    }
+  };
+  int d = scan_bins(k);
+  if (d >= 0) return d;
+  const int g = k / kG1 + dir;
+  if (g >= 0 && g < ngroups && g / (kG2 / kG1) == k / kG2) {
+    d = scan_groups(g);
+    if (d >= 0) return d;
+  }
+  const int nsuper = (nbins + kG2 - 1) / kG2;
+  for (int sg = k / kG2 + dir; sg >= 0 && sg < nsuper; sg += dir) {
+    const int first = dir < 0 ? (sg + 1) * kG2 - 1 : sg * kG2;
+    if (dist(first) >= limit) return limit;
+    if (!holds_match(bmin, bmax, kSuperBase + sg, lo_row, hi_row)) continue;
+    d = scan_groups(first / kG1);
+    return d >= 0 ? d : limit;
   }
   return limit;
 }
@@ -238,8 +274,8 @@ void launch_row_bound(const double* row_mean, int64_t N, int n, uint64_t* range,
   hipLaunchKernelGGL(k_mean_range, dim3(blocks_for(N)), dim3(256), 0, s, row_mean, N, range);
   hipLaunchKernelGGL(k_bin_rows, dim3(blocks_for(N, 4096)), dim3(256), 0, s, row_mean, N, range, nbins,
                      bmin, bmax);
-  hipLaunchKernelGGL(k_bin_groups, dim3((unsigned)((nbins + kGroup - 1) / kGroup)), dim3(kGroup), 0,
-                     s, nbins, bmin, bmax);
+  hipLaunchKernelGGL(k_bin_groups, dim3((unsigned)((nbins + kG2 - 1) / kG2)), dim3(kG2), 0, s,
+                     nbins, bmin, bmax);
   // one thread per row: the outward search is a chain of dependent loads, so
   // many rows in flight hide its latency
   hipLaunchKernelGGL(k_row_bound, dim3(blocks_for(N, 4096)), dim3(256), 0, s, row_mean, N, n, range,

@@ -50,13 +50,13 @@ def test_opts_defaults_and_workspace(dd):
 def test_znorm_option_workspace(dd):
     """Per-window normalisation adds the FP64 row standard deviations and the
     FP32 row scales (N + 64 entries) to the plan and drops the mean-gap bound
-    arrays of global normalisation (4 B per row, 2 x (65536 bins + 256 bin
-    groups), the range); other values are refused."""
+    arrays of global normalisation (4 B per row, 2 x (65536 bins + 4096 groups
+    + 256 supergroups), the range); other values are refused."""
     m, n = 4096, 64
     N = m - n + 1
     base = dd.workspace_bytes(m, n)
     z = dd.workspace_bytes(m, n, znorm=1)
-    bound = 4 * N + 16 + 2 * 4 * (65536 + 256)
+    bound = 4 * N + 16 + 2 * 4 * (65536 + 4096 + 256)
     assert z >= base - bound - 4 * 256 + 8 * N + 4 * (N + 64)
     assert z <= base - bound + 8 * N + 4 * (N + 64) + 4 * 256
     assert dd.workspace_bytes(m, n, znorm=2) == 0
