@@ -26,9 +26,28 @@ namespace {
 
 #pragma clang fp contract(off)
 
+// The two windows' values are loaded kPairBatch at a time ahead of the sum, so
+// a thread has that many loads in flight instead of waiting on each one; the
+// additions keep their sequential order.
+constexpr int kPairBatch = 16;
+
 __device__ inline double d2_fp64(const float* __restrict__ T, int64_t i, int64_t j, int n) {
   double s = 0.0;
-  for (int k = 0; k < n; ++k) {
+  int k = 0;
+  for (; k + kPairBatch <= n; k += kPairBatch) {
+    float x[kPairBatch], y[kPairBatch];
+#pragma unroll
+    for (int u = 0; u < kPairBatch; ++u) {
+      x[u] = T[i + k + u];
+      y[u] = T[j + k + u];
+    }
+#pragma unroll
+    for (int u = 0; u < kPairBatch; ++u) {
+      const double d = (double)x[u] - (double)y[u];
+      s = s + d * d;
+    }
+  }
+  for (; k < n; ++k) {
     const double d = (double)T[i + k] - (double)T[j + k];
     s = s + d * d;
   }
@@ -46,7 +65,22 @@ __device__ inline double d2_fp64_z(const float* __restrict__ T, int64_t i, int64
                                    ZStats z) {
   const double mi = z.mu[i], si = z.sg[i], mj = z.mu[j], sj = z.sg[j];
   double s = 0.0;
-  for (int k = 0; k < n; ++k) {
+  int k = 0;
+  for (; k + kPairBatch <= n; k += kPairBatch) {
+    float x[kPairBatch], y[kPairBatch];
+#pragma unroll
+    for (int u = 0; u < kPairBatch; ++u) {
+      x[u] = T[i + k + u];
+      y[u] = T[j + k + u];
+    }
+#pragma unroll
+    for (int u = 0; u < kPairBatch; ++u) {
+      const double d = (si > 0.0 ? ((double)x[u] - mi) / si : 0.0) -
+                       (sj > 0.0 ? ((double)y[u] - mj) / sj : 0.0);
+      s = s + d * d;
+    }
+  }
+  for (; k < n; ++k) {
     const double d = zval(T, i, k, mi, si) - zval(T, j, k, mj, sj);
     s = s + d * d;
   }
