@@ -64,11 +64,30 @@ struct SearchScalars {
 };
 static_assert(sizeof(SearchScalars) % 4 == 0, "filled as 32-bit words");
 
+// What a plan reads back to the host: the preparation's statistics and
+// counts, and the search's counters and certified answer.  The arena holds
+// one block with this same layout, so each readback is a single copy (a copy
+// into pageable memory waits on the host before the next one can start).
+struct HostOut {
+  SearchScalars sc;
+  Exact ex;
+  double stats[8];   // eq. (2): mean, sigma (as laid out on the device) ...
+  int32_t bad[4];    // ... followed by the NaN/Inf flag
+  int32_t cand[8];   // |Cand| at [0], the longest bucket at [4]
+};
+static_assert(offsetof(HostOut, sc) == 0, "the search's readback starts at the block");
+static_assert(offsetof(HostOut, bad) == offsetof(HostOut, stats) + sizeof(double) * 8 &&
+                  offsetof(HostOut, cand) == offsetof(HostOut, bad) + sizeof(int32_t) * 4,
+              "the statistics, the flag and the counts are copied as one");
+constexpr size_t kPrepareOut = offsetof(HostOut, stats);   // the preparation's part
+constexpr size_t kPrepareOutBytes = sizeof(HostOut) - kPrepareOut;
+constexpr size_t kSearchOutBytes = offsetof(HostOut, ex) + sizeof(Exact);
+
 struct Layout {
-  // stats: 8 doubles (eq. (2)) followed by the NaN/Inf flag (`bad`); cand_count:
-  // |Cand| followed by the longest bucket (`max_bucket`): each pair is read back
-  // with one copy
-  size_t T, stats, partials, bad, words, hist, minfreq, cand, cand_count, seg, csr_off, csr_mem,
+  // out: the block laid out as HostOut; stats (8 doubles of eq. (2)), the
+  // NaN/Inf flag (`bad`), cand_count (|Cand| followed by the longest bucket,
+  // `max_bucket`), srch and exact are its fields
+  size_t T, out, stats, partials, bad, words, hist, minfreq, cand, cand_count, seg, csr_off, csr_mem,
       best, nn_approx, nn_wit, row_state, row_mean, row_cnorm, rows, part_d, part_j, out_d,
       out_j, exact, unc, srch, pair_slots, alive, done, survivors, survivors2, score, rank_hist, gflags,
       cand_groups, bgrp_cnt, bgrp_off, bgrp, max_bucket, mu32, smu32, cn32, r32, row_sigma,
@@ -92,15 +111,18 @@ Layout make_layout(int64_t m, int32_t n, int dict, bool mixed, bool znorm) {
     return o;
   };
   L.T = take(sizeof(float) * (size_t)(kFrontPad + m + kBackPad));
-  L.stats = take(sizeof(double) * 8 + sizeof(int32_t) * 4);
-  L.bad = L.stats + sizeof(double) * 8;
+  L.out = take(sizeof(HostOut));
+  L.srch = L.out + offsetof(HostOut, sc);
+  L.exact = L.out + offsetof(HostOut, ex);
+  L.stats = L.out + offsetof(HostOut, stats);
+  L.bad = L.out + offsetof(HostOut, bad);
+  L.cand_count = L.out + offsetof(HostOut, cand);
+  L.max_bucket = L.cand_count + sizeof(int32_t) * 4;
   L.partials = take(sizeof(double) * kStatBlocks);
   L.words = take(sizeof(int32_t) * N);
   L.hist = take(sizeof(int32_t) * kMaxWords);
   L.minfreq = take(sizeof(int32_t) * 4);
   L.cand = take(sizeof(int32_t) * N);
-  L.cand_count = take(sizeof(int32_t) * 8);
-  L.max_bucket = L.cand_count + sizeof(int32_t) * 4;
   L.seg = take(sizeof(int32_t) * seg);
   L.csr_off = take(sizeof(int32_t) * (kMaxWords + 1));
   L.csr_mem = take(sizeof(int32_t) * N);
@@ -115,10 +137,8 @@ Layout make_layout(int64_t m, int32_t n, int dict, bool mixed, bool znorm) {
   L.part_j = take(sizeof(int64_t) * kFp64BatchRows * nchunks);
   L.out_d = take(sizeof(double) * kFp64BatchRows);
   L.out_j = take(sizeof(int64_t) * kFp64BatchRows);
-  L.exact = take(sizeof(Exact));
   L.unc = take(sizeof(int64_t) * N);
   const int64_t G = (N + kRowGroup - 1) / kRowGroup;
-  L.srch = take(sizeof(SearchScalars));
   L.ctl = take(sizeof(SearchCtl));
   L.wins = take(sizeof(WinDesc) * kMaxWins);
   L.pair_slots = take(sizeof(uint64_t) * kPairSlots * kPairStride);
@@ -248,7 +268,13 @@ bool is_device_pointer(const void* p) {
 // lives until the process ends (a serving worker times every request with the
 // same events instead of creating and destroying them per call).  A search or
 // preparation synchronises its stream before it returns, so the events are idle
-// whenever the next call on the thread takes them.
+// whenever the next call on the thread takes them.  Pair 0 brackets a whole
+// preparation or search and keeps the default system-scope release; the pairs
+// around the scan launches only time device work, so they release to the
+// device, and their interval holds the kernel rather than a system-scope
+// write-back.  Each record is still a packet of its own in the queue, a few us
+// between the kernels it separates; untimed searches (graphs, the
+// allocation-free entry point) take none.
 struct EventPool {
   int device = -1;
   std::vector<hipEvent_t> ev;
@@ -261,7 +287,8 @@ struct EventPool {
     }
     while (ev.size() <= k) {
       hipEvent_t e = nullptr;
-      if (hipEventCreate(&e) != hipSuccess) {
+      const unsigned flags = ev.size() >= 2 ? hipEventReleaseToDevice : hipEventDefault;
+      if (hipEventCreateWithFlags(&e, flags) != hipSuccess) {
         (void)hipGetLastError();
         return nullptr;
       }
@@ -389,17 +416,6 @@ void init_plan(discord_plan p, int64_t m, int32_t n, const discord_opts& o) {
   p->L = make_layout(m, n, p->dict, o.precision == DISCORD_PREC_BF16X3, o.znorm != 0);
 }
 
-// What a plan reads back to the host: the preparation's statistics and
-// counts, and the search's counters and certified answer.
-struct HostOut {
-  SearchScalars sc;
-  Exact ex;
-  double stats[8];   // eq. (2): mean, sigma (as laid out on the device) ...
-  int32_t bad[4];    // ... followed by the NaN/Inf flag
-  int32_t cand[8];   // |Cand| at [0], the longest bucket at [4]
-};
-static_assert(offsetof(HostOut, bad) == offsetof(HostOut, stats) + sizeof(double) * 8,
-              "the statistics block and the flag are copied as one");
 
 // The preparation kernels on a plan whose arena and stream are set, with no
 // host synchronisation: on a series with NaN/Inf or sigma = 0 they run on
@@ -471,11 +487,8 @@ int prepare_enqueue(discord_plan p, const float* T) {
 
 // Copies of the preparation's statistics and counts into h.
 int prepare_readback(discord_plan p, HostOut* h) {
-  hipStream_t s = p->stream;
-  HIP_TRY(p, hipMemcpyAsync(h->stats, p->at<double>(p->L.stats),
-                            sizeof(double) * 8 + sizeof(int32_t) * 4, hipMemcpyDeviceToHost, s));
-  HIP_TRY(p, hipMemcpyAsync(h->cand, p->at<int32_t>(p->L.cand_count), sizeof(h->cand),
-                            hipMemcpyDeviceToHost, s));
+  HIP_TRY(p, hipMemcpyAsync(reinterpret_cast<char*>(h) + kPrepareOut, p->arena + p->L.out +
+                            kPrepareOut, kPrepareOutBytes, hipMemcpyDeviceToHost, p->stream));
   return DISCORD_OK;
 }
 
@@ -569,6 +582,7 @@ constexpr int64_t kDevRows = 8;   // uncertain rows rescanned before the readbac
 struct SearchRun {
   HostOut* h = nullptr;
   bool events = true;
+  bool with_prepare = false;   // the readback also carries the preparation's part
   int timed = 0;
   int launches = 0;   // scan launches enqueued
 };
@@ -882,8 +896,11 @@ int search_enqueue(discord_plan p, SearchRun& run) {
   launch_merge_exact(unc, p->at<double>(p->L.out_d), p->at<int64_t>(p->L.out_j), kDevRows, ex,
                      nn_wit, s, unc_count);
   LAUNCH_OK(p, "rescan");
-  HIP_TRY(p, hipMemcpyAsync(&run.h->sc, sc, sizeof(SearchScalars), hipMemcpyDeviceToHost, s));
-  HIP_TRY(p, hipMemcpyAsync(&run.h->ex, ex, sizeof(Exact), hipMemcpyDeviceToHost, s));
+  // the counters and the answer (HostOut.sc, .ex), with the preparation's
+  // statistics and counts behind them when the caller has not read those yet
+  HIP_TRY(p, hipMemcpyAsync(run.h, p->arena + p->L.out,
+                            run.with_prepare ? sizeof(HostOut) : kSearchOutBytes,
+                            hipMemcpyDeviceToHost, s));
   return DISCORD_OK;
 }
 
@@ -1214,9 +1231,9 @@ int search_series_in_arena(const float* T, int64_t m, int32_t n, const discord_o
     SearchRun run;
     run.h = &h;
     run.events = false;
+    run.with_prepare = true;
     st = prepare_enqueue(p, T);
     if (st == DISCORD_OK) st = search_enqueue(p, run);
-    if (st == DISCORD_OK) st = prepare_readback(p, &h);
     if (st == DISCORD_OK && hipStreamSynchronize(stream) != hipSuccess)
       st = fail(p, DISCORD_EDEVICE, "hipStreamSynchronize failed");
     if (st == DISCORD_OK) st = prepare_check(p, h);
@@ -1293,13 +1310,13 @@ int search_series_graph(RequestGraph** cache, bool capture, const float* T, int6
     SearchRun cap;
     cap.h = g->h;
     cap.events = false;
+    cap.with_prepare = true;
     if (hipStreamBeginCapture(stream, hipStreamCaptureModeRelaxed) != hipSuccess) {
       (void)hipGetLastError();
       return give_up(fail(p, DISCORD_EDEVICE, "hipStreamBeginCapture failed"));
     }
     st = prepare_enqueue(p, T);
     if (st == DISCORD_OK) st = search_enqueue(p, cap);
-    if (st == DISCORD_OK) st = prepare_readback(p, g->h);
     hipGraph_t graph = nullptr;
     const hipError_t e = hipStreamEndCapture(stream, &graph);
     if (st != DISCORD_OK || e != hipSuccess || !graph) {
