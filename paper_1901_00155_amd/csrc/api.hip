@@ -610,11 +610,15 @@ int search_enqueue(discord_plan p, SearchRun& run) {
   int item_shift = 0;
   while ((int64_t{1} << item_shift) < item_rows) ++item_shift;
   const int64_t n_items = (N + item_rows - 1) / item_rows;
-  const int64_t target_items = mixed ? 1024 : 4096;   // ~4 wavefronts per SIMD
+  // work items a window launch aims at: about 4 wavefronts per SIMD, FP32
+  // 1.5x that under global normalisation (2^22 series n = 512 47.9 -> 44.7
+  // ms, noisy 2^20 walk 7.52 -> 7.41 ms, 2^20 walk unchanged; per-window
+  // normalisation 9.5 -> 10.1 ms, so it keeps 4096)
+  const int64_t target_items = mixed ? 1024 : (p->opts.znorm ? 4096 : 6144);
   // The launch that completes the bound-ranked items holds few items with
-  // long sequences, so it is split finer: 4x the work items (FP32), 2x
+  // long sequences, so it is split finer: 16384 work items (FP32), 2048
   // (split-BF16).
-  const int64_t seed_items = (mixed ? 2 : 4) * target_items;
+  const int64_t seed_items = mixed ? 2048 : 16384;
   const bool abandon = p->opts.abandon != 0;
   const bool order = p->opts.order != 0;          // Cand first (Algorithm 3)
   const bool buckets = p->opts.order == 1;        // same-word columns first
@@ -760,7 +764,14 @@ int search_enqueue(discord_plan p, SearchRun& run) {
     // ranked rounds: items completed after each ranking (split-BF16: 16
     // workgroup items; FP32 groups: more for longer windows)
     const int64_t seeds = mixed ? 16 : (n >= 1024 ? 512 : (n >= 512 ? 256 : 128));
-    const CtlParams P{seq_max, gran, target_items, seed_items, growth, seeds, near_first ? 1 : 0};
+    // shortest chunk of the launches that complete whole sequences, in 512
+    // columns: FP32 4 (2^20 walk 5.86 -> 5.60 ms, noisy walk 7.82 -> 7.53 ms,
+    // 2^22 series 47.7 -> 47.2 ms: the bound-ranked launch had 2 steps per
+    // wavefront); split-BF16 1 (2 and 4 were no better across the workloads);
+    // a minimum on the windows or the ranked completions did not help either
+    const int64_t min_full = mixed ? 1 : 4;
+    const CtlParams P{seq_max, gran, target_items, seed_items, growth, seeds, near_first ? 1 : 0,
+                      min_full * gran, 0, 0};
     // A launch whose work is decided on the device gets a grid sized for the
     // most work its descriptor can hold, at most `cap` work items (beyond, its
     // wavefronts or workgroups stride over the work).

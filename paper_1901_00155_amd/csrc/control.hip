@@ -18,12 +18,18 @@ namespace {
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // the split of entries [begin, end) of `items` items into chunks (a multiple of
-// the granule each) so that the launch holds about `target` work items
+// the granule each) so that the launch holds about `target` work items, no
+// chunk shorter than `min_chunk` entries (0: one granule) unless the window is
 __host__ __device__ inline void set_window(WinDesc* w, int64_t items, int64_t begin, int64_t end,
-                                           int64_t target, int64_t gran, int64_t list_off) {
+                                           int64_t target, int64_t gran, int64_t list_off,
+                                           int64_t min_chunk = 0) {
   const int64_t it = items > 1 ? items : 1;
   const int64_t width = end - begin > 1 ? end - begin : 1;
-  const int64_t maxc = ceil_div(width, gran);
+  int64_t maxc = ceil_div(width, gran);
+  if (min_chunk > gran) {
+    const int64_t m = width / min_chunk;
+    maxc = m < 1 ? 1 : (m < maxc ? m : maxc);
+  }
   int64_t c = ceil_div(target, it);
   c = c < 1 ? 1 : c;
   c = c < maxc ? c : maxc;
@@ -46,15 +52,17 @@ __global__ void k_ctl_start(SearchCtl* ctl, int64_t count, int64_t width,
   ctl->in_off = 0;
   ctl->end = 0;
   ctl->k = 0;
-  if (cand_win) set_window(cand_win, go ? *cand_count : 0, 0, P.seq_max, P.target, P.gran, 0);
+  if (cand_win)
+    set_window(cand_win, go ? *cand_count : 0, 0, P.seq_max, P.target, P.gran, 0, P.min_chunk_full);
   if (bound_win)
-    set_window(bound_win, go ? bound_items : 0, 0, P.seq_max, P.seed_target, P.gran, 0);
+    set_window(bound_win, go ? bound_items : 0, 0, P.seq_max, P.seed_target, P.gran, 0,
+               P.min_chunk_full);
 }
 
 __global__ void k_ctl_window(SearchCtl* ctl, WinDesc* win, uint32_t* n_surv, CtlParams P) {
   const int64_t c = ctl->count;
   const int64_t end = ctl->covered + ctl->width < P.seq_max ? ctl->covered + ctl->width : P.seq_max;
-  set_window(win, c, ctl->covered, end, P.target, P.gran, ctl->in_off);
+  set_window(win, c, ctl->covered, end, P.target, P.gran, ctl->in_off, P.min_chunk_win);
   ctl->end = end;
   *n_surv = 0;
 }
@@ -77,7 +85,7 @@ __global__ void k_ctl_after(SearchCtl* ctl, const uint32_t* n_surv, CtlParams P)
 __global__ void k_ctl_seeds(SearchCtl* ctl, WinDesc* win, CtlParams P) {
   const int64_t c = ctl->count;
   const int64_t k = c < P.seeds ? c : P.seeds;
-  set_window(win, k, ctl->covered, P.seq_max, P.seed_target, P.gran, 0);
+  set_window(win, k, ctl->covered, P.seq_max, P.seed_target, P.gran, 0, P.min_chunk_seeds);
   ctl->k = k;
 }
 

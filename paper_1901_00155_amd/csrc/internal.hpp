@@ -213,6 +213,12 @@ struct CtlParams {
   int64_t growth;       // window growth per round
   int64_t seeds;        // ranked rounds: best-ranked items completed after each window
   int32_t near_first;   // 1: windows grow by `growth`; 0: the second window ends the sequences
+  // shortest chunk (entries) of the launches that complete whole sequences
+  // (Cand, bound-ranked items), of the growing windows and of the ranked
+  // rounds' completions (0: one granule)
+  int64_t min_chunk_full;
+  int64_t min_chunk_win;
+  int64_t min_chunk_seeds;
 };
 // entries [begin, end) of `items` items, split into chunks so that the launch
 // holds about `target` work items (the host computes the same split for the
