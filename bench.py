@@ -86,9 +86,12 @@ def traffic_for(precision: str, workload: str, mode: str, n: int):
 
 
 def time_steps(dd, Td, n, precision, abandon, steps, warmup, order=2, znorm=False,
-               per_step=None):
+               per_step=None, plan=False):
     """Mean seconds per step over `steps` timed steps after `warmup` untimed
-    ones, and the steps' results.  Each step returns once its result is on the
+    ones, and the steps' results.  A step is one discord_search_once call
+    (preparation and search as one device sequence, one synchronisation), or
+    with `plan` discord_prepare + discord_search on a new plan (a
+    synchronisation after each).  Each step returns once its result is on the
     host, so `per_step` (a list, if given) receives every timed step's own
     duration in ms as well."""
     import torch
@@ -100,9 +103,13 @@ def time_steps(dd, Td, n, precision, abandon, steps, warmup, order=2, znorm=Fals
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             t_prev = t0
-        with dd.Plan(Td, n, precision=precision, abandon=abandon, order=order, stream=stream,
-                     torch_workspace=True, znorm=znorm) as p:
-            r = p.search()
+        if plan:
+            with dd.Plan(Td, n, precision=precision, abandon=abandon, order=order, stream=stream,
+                         torch_workspace=True, znorm=znorm) as p:
+                r = p.search()
+        else:
+            r = dd.search_once(Td, n, precision=precision, abandon=abandon, order=order,
+                               stream=stream, znorm=znorm)
         if it >= warmup:
             results.append(r)
             if per_step is not None:
@@ -310,8 +317,7 @@ def scalability_block(dd, Td, w, cu_counts=(8, 16, 32, 64, 128, 256)):
                 ts = []
                 for it in range(3):
                     t = time.perf_counter()
-                    with dd.Plan(Td, w.n, precision=prec, stream=cs) as p:
-                        r = p.search()
+                    r = dd.search_once(Td, w.n, precision=prec, stream=cs)
                     ts.append(time.perf_counter() - t)
             rows.append({"cus": k, "time_to_discord_ms": min(ts[1:]) * 1e3, "index": int(r.index),
                          "pairs_evaluated": float(r.pairs_evaluated)})
@@ -414,6 +420,16 @@ def main():
             hs[prec] = {"time_to_discord_ms": sh * 1e3,
                         "time_to_discord_median_ms": float(np.median(hms))}
         out["host_series"] = hs
+        # the same step as discord_prepare + discord_search on a new plan: one
+        # synchronisation after the preparation and one after the search
+        pp = {}
+        for prec in ("fp32", "bf16x3"):
+            sp, _ = time_steps(dd, Td, n, prec, abandon, args.steps, args.warmup, args.order,
+                               plan=True)
+            pp[prec] = {"time_to_discord_ms": sp * 1e3}
+        out["plan_path"] = pp
+        print(f"# plan path: fp32 {pp['fp32']['time_to_discord_ms']:.2f} ms, "
+              f"bf16x3 {pp['bf16x3']['time_to_discord_ms']:.2f} ms", file=sys.stderr, flush=True)
         print(f"# host series: fp32 {hs['fp32']['time_to_discord_ms']:.2f} ms, "
               f"bf16x3 {hs['bf16x3']['time_to_discord_ms']:.2f} ms", file=sys.stderr, flush=True)
         other = "bf16x3" if args.precision == "fp32" else "fp32"

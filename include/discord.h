@@ -39,7 +39,7 @@ extern "C" {
 
 /* 2: discord_opts lost its unused `topk` field (the certification rescores
  * every row's witness in FP64 instead of the k best candidates of some rows). */
-#define DISCORD_ABI_VERSION 3
+#define DISCORD_ABI_VERSION 4
 
 /* ---- status codes ------------------------------------------------------- */
 #define DISCORD_OK        0
@@ -170,6 +170,29 @@ int discord_search(discord_plan plan, discord_result* out);
  * discord_search). */
 int discord_search_graph(discord_plan plan, discord_result* out);
 
+/* One call from a series to its certified discord: the computation and result
+ * of discord_prepare + discord_search with `opts`, enqueued as one sequence on
+ * the device with one host synchronisation (the statistics of eq. (2) are
+ * checked from the same readback as the answer), and no plan left behind.
+ * The PhiDD order (opts.order = 1) synchronises once more, after the
+ * preparation (its sequences need the bucket sizes on the host).
+ *   T          m float32 values, host or device pointer.
+ *   opts       NULL for defaults.
+ *   workspace  a device buffer of ws_bytes >= discord_workspace_bytes(m, n,
+ *              opts), 256-byte aligned, owned by the caller and free for the
+ *              duration of the call; NULL: the call allocates and frees one.
+ *   stream     hipStream_t to run on (NULL: the null stream); synchronised
+ *              before the call returns.
+ *   out        receives the result.  ms_scan sums the scan launches (HIP
+ *              events); ms_search spans preparation and search and ms_prepare
+ *              is 0, except in the PhiDD order, whose two stages are timed
+ *              apart as in discord_prepare and discord_search.
+ * Errors: those of discord_prepare and discord_search (ENOMEM also for a
+ * workspace that is too small or misaligned); the text is in
+ * discord_plan_error(NULL). */
+int discord_search_once(const float* T, int64_t m, int32_t n, const discord_opts* opts,
+                        void* workspace, size_t ws_bytes, void* stream, discord_result* out);
+
 /* Frees the plan and the device memory it owns.  NULL is ignored. */
 void discord_release(discord_plan plan);
 
@@ -177,8 +200,8 @@ void discord_release(discord_plan plan);
 const char* discord_strerror(int status);
 
 /* Detail of the last error on this plan ("" if none).  With plan == NULL: the
- * detail of the calling thread's last failed discord_prepare or
- * discord_search_series_noalloc. */
+ * detail of the calling thread's last failed discord_prepare,
+ * discord_search_once or discord_search_series_noalloc. */
 const char* discord_plan_error(discord_plan plan);
 
 /* The inner breakpoints beta_1..beta_{alpha-1} of eq. (4) (N(0,1) quantiles

@@ -15,7 +15,7 @@ import numpy as np
 __all__ = [
     "load", "DiscordError", "Opts", "Result", "Plan", "search", "default_opts",
     "workspace_bytes", "strerror", "sax_breakpoints", "search_series",
-    "search_series_noalloc", "NOALLOC_MAX_BYTES",
+    "search_series_noalloc", "search_once", "NOALLOC_MAX_BYTES",
     "FIELD", "PREC_FP32", "PREC_BF16X3", "MIXED_MAX_N", "ABI_VERSION", "LIB_PATH", "EXPORTED", "Server",
     "ServerConfig", "cu_mask", "CULimitedStream",
     "Request", "Completion", "ServerStats", "EXECUTOR_FN",
@@ -27,7 +27,7 @@ LIB_PATH = os.path.join(_HERE, "lib", "libdiscord.so")
 PREC_FP32 = 0
 PREC_BF16X3 = 1
 MIXED_MAX_N = 2048  # DISCORD_MIXED_MAX_N: longest window of the split-BF16 scan
-ABI_VERSION = 3     # DISCORD_ABI_VERSION of the header these structures mirror
+ABI_VERSION = 4     # DISCORD_ABI_VERSION of the header these structures mirror
 NOALLOC_MAX_BYTES = 32 << 20  # DISCORD_NOALLOC_MAX_BYTES: static workspace per device
 _PREC = {"fp32": PREC_FP32, "bf16x3": PREC_BF16X3, PREC_FP32: PREC_FP32, PREC_BF16X3: PREC_BF16X3}
 
@@ -43,7 +43,7 @@ FIELD = {
 EXPORTED = [
     "discord_default_opts", "discord_abi_version", "discord_workspace_bytes", "discord_prepare", "discord_search",
     "discord_release", "discord_search_graph", "discord_strerror", "discord_plan_error", "discord_sax_breakpoints",
-    "discord_search_series", "discord_search_series_noalloc", "discord_plan_count", "discord_plan_copy", "discord_rows_nn_fp64",
+    "discord_search_series", "discord_search_series_noalloc", "discord_search_once", "discord_plan_count", "discord_plan_copy", "discord_rows_nn_fp64",
     "discord_server_create", "discord_server_create_with_executor", "discord_server_submit",
     "discord_server_poll", "discord_server_get_stats", "discord_server_destroy",
     "discord_cu_mask", "discord_stream_create_cu_limited", "discord_stream_destroy",
@@ -166,6 +166,9 @@ def load():
     lib.discord_search_series_noalloc.argtypes = [vp, i64, i32, ctypes.POINTER(Opts), vp,
                                                   ctypes.POINTER(Result)]
     lib.discord_search_series_noalloc.restype = ctypes.c_int
+    lib.discord_search_once.argtypes = [vp, i64, i32, ctypes.POINTER(Opts), vp, ctypes.c_size_t,
+                                        vp, ctypes.POINTER(Result)]
+    lib.discord_search_once.restype = ctypes.c_int
     lib.discord_plan_count.argtypes = [vp, i32]
     lib.discord_plan_count.restype = i64
     lib.discord_plan_copy.argtypes = [vp, i32, vp, ctypes.c_size_t]
@@ -370,11 +373,44 @@ class Plan:
         self.release()
 
 
+def search_once(T, n: int, precision="fp32", stream=None, torch_workspace=True,
+                **opts) -> Result:
+    """discord_search_once: preparation and search of one series as one device
+    sequence with one synchronisation.  torch_workspace: the workspace is a
+    torch tensor (from torch's caching allocator); else the library allocates
+    and frees one per call."""
+    lib = load()
+    o = default_opts(precision=precision, **opts)
+    ptr, m, keep, tstream = _series_ptr(T)
+    if stream is None:
+        stream = tstream
+    elif hasattr(stream, "cuda_stream"):
+        stream = stream.cuda_stream
+    elif isinstance(stream, CULimitedStream):
+        stream = stream.handle
+    ws, ws_ptr, ws_bytes = None, None, 0
+    if torch_workspace:
+        import torch
+        ws_bytes = lib.discord_workspace_bytes(m, n, ctypes.byref(o))
+        if ws_bytes == 0:
+            _check(-1)
+        ws = torch.empty(ws_bytes + 256, dtype=torch.uint8, device="cuda")
+        ws_ptr = (ws.data_ptr() + 255) // 256 * 256
+    r = Result()
+    st = lib.discord_search_once(ctypes.c_void_p(ptr), m, n, ctypes.byref(o), ws_ptr, ws_bytes,
+                                 stream, ctypes.byref(r))
+    del ws   # the call has synchronised its stream
+    if st != 0:
+        detail = lib.discord_plan_error(None).decode()
+        raise DiscordError(st, strerror(st) + (f": {detail}" if detail else ""))
+    return r
+
+
 def search(T, n: int, precision="fp32", **kw):
-    """One prepared search: returns (index, distance, result-dict)."""
-    with Plan(T, n, precision=precision, **kw) as p:
-        r = p.search()
-        return int(r.index), float(r.distance), r.as_dict()
+    """One search of one series (discord_search_once): returns (index,
+    distance, result-dict)."""
+    r = search_once(T, n, precision=precision, **kw)
+    return int(r.index), float(r.distance), r.as_dict()
 
 
 def search_series(T, n: int):

@@ -1075,6 +1075,40 @@ int discord_search_series(const float* T, int64_t m, int32_t n, int64_t* index, 
   return DISCORD_OK;
 }
 
+int discord_search_once(const float* T, int64_t m, int32_t n, const discord_opts* opts,
+                        void* workspace, size_t ws_bytes, void* stream, discord_result* out) {
+  g_prepare_err[0] = 0;
+  if (!out) return DISCORD_EINVAL;
+  discord_opts o;
+  const int bad = check_prepare_args(T, m, n, opts, &o);
+  if (bad != DISCORD_OK) return bad;
+  const size_t need = discord_workspace_bytes(m, n, &o);
+  void* arena = workspace;
+  size_t bytes = ws_bytes;
+  if (arena) {
+    if (ws_bytes < need || ((uintptr_t)arena % kAlign) != 0) {
+      std::snprintf(g_prepare_err, sizeof(g_prepare_err),
+                    "workspace of %zu bytes at %p: the plan needs %zu, 256-byte aligned", ws_bytes,
+                    arena, need);
+      return DISCORD_ENOMEM;
+    }
+  } else {
+    if (hipMalloc(&arena, need) != hipSuccess) {
+      (void)hipGetLastError();
+      return DISCORD_ENOMEM;
+    }
+    bytes = need;
+  }
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  const int st = dd::search_series_in_arena(T, m, n, &o, arena, bytes, s, out, g_prepare_err,
+                                            sizeof(g_prepare_err), true);
+  if (!workspace) {
+    (void)hipStreamSynchronize(s);   // nothing of this call is left in flight on the buffer
+    (void)hipFree(arena);
+  }
+  return st;
+}
+
 int64_t discord_plan_count(discord_plan p, int32_t field) {
   if (!p) return DISCORD_EINVAL;
   switch (field) {
@@ -1216,7 +1250,7 @@ namespace dd {
 
 int search_series_in_arena(const float* T, int64_t m, int32_t n, const discord_opts* opts,
                            void* arena, size_t arena_bytes, hipStream_t stream,
-                           discord_result* out, char* err, size_t err_len) {
+                           discord_result* out, char* err, size_t err_len, bool timed) {
   if (err && err_len) err[0] = 0;
   discord_opts o;
   int st = check_prepare_args(T, m, n, opts, &o);
@@ -1230,7 +1264,7 @@ int search_series_in_arena(const float* T, int64_t m, int32_t n, const discord_o
   if (hipGetDevice(&p->device) != hipSuccess) return DISCORD_EDEVICE;
   p->stream = stream;
   p->arena = static_cast<char*>(arena);
-  p->timed = false;
+  p->timed = timed;
   if (o.order == 1) {
     // the PhiDD order's sequences need the bucket sizes on the host first
     st = prepare_run(p, T);
@@ -1241,17 +1275,20 @@ int search_series_in_arena(const float* T, int64_t m, int32_t n, const discord_o
     HostOut h;
     SearchRun run;
     run.h = &h;
-    run.events = false;
+    run.events = timed;
     run.with_prepare = true;
-    st = prepare_enqueue(p, T);
+    EventPair ev(0, timed);
+    if (!ev.ready()) st = fail(p, DISCORD_EDEVICE, "hipEventCreate failed");
+    if (st == DISCORD_OK && ev.start(stream) != hipSuccess)
+      st = fail(p, DISCORD_EDEVICE, "hipEventRecord failed");
+    if (st == DISCORD_OK) st = prepare_enqueue(p, T);
     if (st == DISCORD_OK) st = search_enqueue(p, run);
+    if (st == DISCORD_OK && ev.stop(stream) != hipSuccess)
+      st = fail(p, DISCORD_EDEVICE, "hipEventRecord failed");
     if (st == DISCORD_OK && hipStreamSynchronize(stream) != hipSuccess)
       st = fail(p, DISCORD_EDEVICE, "hipStreamSynchronize failed");
     if (st == DISCORD_OK) st = prepare_check(p, h);
-    if (st == DISCORD_OK) {
-      EventPair none(0, false);
-      st = search_finish(p, run, none, out);
-    }
+    if (st == DISCORD_OK) st = search_finish(p, run, ev, out);
   }
   if (st != DISCORD_OK && err && err_len) std::snprintf(err, err_len, "%s", p->err);
   return st;

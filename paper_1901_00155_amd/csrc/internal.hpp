@@ -329,10 +329,12 @@ namespace dd {
 // synchronises before returning (once: preparation and search are enqueued as
 // one sequence, except for the PhiDD order, whose sequences need the bucket
 // sizes on the host).  Creates no stream, event, heap object or device
-// allocation.  ERANGE if the plan does not fit in arena_bytes.
+// allocation; with `timed`, it takes the calling thread's pooled HIP events
+// (ms_search brackets the whole sequence, ms_scan sums the scan launches).
+// ERANGE if the plan does not fit in arena_bytes.
 int search_series_in_arena(const float* T, int64_t m, int32_t n, const discord_opts* opts,
                            void* arena, size_t arena_bytes, hipStream_t stream,
-                           discord_result* out, char* err, size_t err_len);
+                           discord_result* out, char* err, size_t err_len, bool timed = false);
 // Sets the calling thread's error text (discord_plan_error(NULL)).
 void set_thread_error(const char* fmt, ...);
 

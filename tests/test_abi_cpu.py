@@ -40,7 +40,7 @@ def test_every_declared_symbol_is_exported(dd):
 def test_opts_defaults_and_workspace(dd):
     o = dd.default_opts()
     assert (o.precision, o.abandon, o.order, o.paa_w, o.alphabet) == (0, 1, 2, 4, 4)
-    assert dd.load().discord_abi_version() == dd.ABI_VERSION == 3
+    assert dd.load().discord_abi_version() == dd.ABI_VERSION == 4
     assert dd.workspace_bytes(4096, 64) > 4 * 4096
     assert dd.workspace_bytes(100, 64) == 0            # m < 2n
     assert dd.workspace_bytes(4096, 64, paa_w=9) == 0  # bad option
