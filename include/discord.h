@@ -116,7 +116,10 @@ typedef struct {
     uint64_t cand_rows;       /* |Cand| (eq. 7)                                       */
     double   ms_prepare;      /* device time of discord_prepare (HIP events)         */
     double   ms_search;       /* device time of discord_search (HIP events)          */
-    double   ms_scan;         /* of which: the approximate scan launches, summed     */
+    double   ms_scan;         /* of which: the approximate scan launches, one event
+                                 span from the first to the end of the last (the
+                                 few-us window-decision kernels between them
+                                 included)                                        */
     uint64_t scan_launches;   /* scan launches enqueued (the device-decided search
                                  enqueues a fixed number; those past the end of its
                                  loop find no work)                                 */
@@ -183,7 +186,7 @@ int discord_search_graph(discord_plan plan, discord_result* out);
  *              duration of the call; NULL: the call allocates and frees one.
  *   stream     hipStream_t to run on (NULL: the null stream); synchronised
  *              before the call returns.
- *   out        receives the result.  ms_scan sums the scan launches (HIP
+ *   out        receives the result.  ms_scan spans the scan launches (HIP
  *              events); ms_search spans preparation and search and ms_prepare
  *              is 0, except in the PhiDD order, whose two stages are timed
  *              apart as in discord_prepare and discord_search.

@@ -576,9 +576,9 @@ namespace {
 
 constexpr int64_t kDevRows = 8;   // uncertain rows rescanned before the readback
 
-// One search in flight.  timed: scan launches timed so far (event pairs 1,
-// 2, ...: their sum is ms_scan); events are taken only if the plan is timed
-// and the search is not being captured into a graph.
+// One search in flight.  timed: event pairs taken for ms_scan (0, or 1: pair 1
+// spans the scan launches); events are taken only if the plan is timed and the
+// search is not being captured into a graph.
 struct SearchRun {
   HostOut* h = nullptr;
   bool events = true;
@@ -595,7 +595,6 @@ int search_enqueue(discord_plan p, SearchRun& run) {
   const int64_t N = p->N;
   const int n = p->n;
   int& timed = run.timed;
-  constexpr int kMaxTimed = 256;
   HIP_TRY(p, hipSetDevice(p->device));
 
   const bool mixed = p->opts.precision == DISCORD_PREC_BF16X3;
@@ -682,22 +681,27 @@ int search_enqueue(discord_plan p, SearchRun& run) {
     // best-so-far by that lower bound keeps it <= the discord's NN.
     J.raise_scale = (float)(1.0 - ((n + 3) * std::ldexp(1.0, -24) * 1.01 + std::ldexp(1.0, -22)));
   }
+  // The scan launches are timed as one span, from an event before the first
+  // to one after the last.  An event record is a packet of its own in the
+  // queue and costs a few us between the kernels it separates: a pair per
+  // launch cost about 0.1 ms of a search of the 2^20 walk.  The span also
+  // holds the small kernels between the scans (the one-thread window
+  // decisions, a few us each; the rankings of per-window normalisation).
+  EventPair span(1, run.events);
+  if (!span.ready()) return fail(p, DISCORD_EDEVICE, "hipEventCreate failed");
+  bool span_open = false;
   auto launch = [&](const char* what) -> int {
-    const bool timing = run.events && timed < kMaxTimed;
     ++run.launches;
-    EventPair t(1 + timed, timing);
-    if (!t.ready()) return fail(p, DISCORD_EDEVICE, "hipEventCreate failed");
-    if (timing) HIP_TRY(p, hipEventRecord(t.a, s));
+    if (run.events && !span_open) {
+      HIP_TRY(p, span.start(s));
+      span_open = true;
+    }
     if (mixed) {
       if (!launch_scan_mfma(J, R, s)) return fail(p, DISCORD_ERANGE, "window too long for bf16x3");
     } else {
       launch_scan_fp32(J, s);
     }
     LAUNCH_OK(p, what);
-    if (timing) {
-      HIP_TRY(p, hipEventRecord(t.b, s));
-      ++timed;
-    }
     return DISCORD_OK;
   };
   // Sequence entries are column groups of 8 (FP32) or blocks of 128 (MFMA); a
@@ -876,6 +880,10 @@ int search_enqueue(discord_plan p, SearchRun& run) {
       }
     }
     J.win = nullptr;
+  }
+  if (span_open) {
+    HIP_TRY(p, span.stop(s));
+    timed = 1;
   }
 
   // ---- certification in FP64 ---------------------------------------------------
