@@ -833,8 +833,7 @@ int search_enqueue(discord_plan p, SearchRun& run) {
       J.skip = nullptr;
       J.precheck = 0;
       if ((st = launch("scan (bound seeds)"))) return st;
-      launch_flag_items(spare, bound_seeds, bound_win, gflags, s);
-      launch_flag_items(spare, bound_seeds, bound_win, bflags, s);
+      launch_flag_items(spare, bound_seeds, bound_win, gflags, bflags, s);
     }
     if (cand) {
       // Algorithm 3: the items holding Cand rows, each over its whole sequence
@@ -850,7 +849,12 @@ int search_enqueue(discord_plan p, SearchRun& run) {
       const int64_t end = std::min<int64_t>(seq_max, covered + width);
       if (nw + 2 > kMaxWins) return fail(p, DISCORD_EDEVICE, "search needs too many rounds");
       WinDesc* w = &wins[nw++];
-      launch_ctl_window(ctl, w, n_surv, P, s);
+      // the first window, or the next one after a ranking; else the decision
+      // after the previous window and this window's description in one launch
+      if (round == 0 || ranked)
+        launch_ctl_window(ctl, w, n_surv, P, s);
+      else
+        launch_ctl_next(ctl, w, n_surv, P, s);
       J.win = w;
       // lists: ranked rounds read the ranked list (`spare`, past its completed
       // head) and always list survivors in lists[0]; otherwise the lists alternate
@@ -861,7 +865,7 @@ int search_enqueue(discord_plan p, SearchRun& run) {
       J.max_work = grid_work(n_items, end - covered, target_items);
       if ((st = launch("scan (window)"))) return st;
       if (end >= seq_max) break;                  // final for every item
-      launch_ctl_after(ctl, n_surv, P, s);
+      if (ranked) launch_ctl_after(ctl, n_surv, P, s);
       covered = end;
       width = near_first ? width * growth : seq_max;
       if (ranked) {

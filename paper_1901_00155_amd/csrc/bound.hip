@@ -102,10 +102,21 @@ __global__ __launch_bounds__(256) void k_bin_rows(const double* __restrict__ mu,
                                                   int32_t* __restrict__ bmin,
                                                   int32_t* __restrict__ bmax) {
   const Bins b = bins_of(range, nbins);
-  for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < N; i += (int64_t)gridDim.x * 256) {
-    const int k = bin_of(b, mu[i]);
-    atomicMin(&bmin[k], (int32_t)i);
-    atomicMax(&bmax[k], (int32_t)i);
+  const int lane = threadIdx.x & 63;
+  // the loop bound is uniform across the block (base steps by whole blocks), so
+  // every lane of a wavefront takes each iteration and the shuffles see all 64
+  for (int64_t base = blockIdx.x * 256ll; base < N; base += (int64_t)gridDim.x * 256) {
+    const int64_t i = base + threadIdx.x;
+    const int k = i < N ? bin_of(b, mu[i]) : -1;
+    // a wavefront's rows ascend with the lane, and neighbouring windows have
+    // nearly equal means: a run of lanes in one bin sends only its first row
+    // (the run's smallest index) to atomicMin and its last (the largest) to
+    // atomicMax, instead of every lane hitting the same address
+    const int kp = __shfl_up(k, 1, 64), kn = __shfl_down(k, 1, 64);
+    if (k >= 0) {
+      if (lane == 0 || kp != k) atomicMin(&bmin[k], (int32_t)i);
+      if (lane == 63 || kn != k) atomicMax(&bmax[k], (int32_t)i);
+    }
   }
 }
 
@@ -244,10 +255,15 @@ __global__ __launch_bounds__(256) void k_item_bound(const float* __restrict__ lb
 // (none when the device loop stopped before it began)
 __global__ __launch_bounds__(256) void k_flag_items(const int32_t* __restrict__ list, int64_t count,
                                                     const WinDesc* __restrict__ win,
-                                                    int32_t* __restrict__ flags) {
+                                                    int32_t* __restrict__ flags,
+                                                    int32_t* __restrict__ flags2) {
   const int64_t t = blockIdx.x * 256ll + threadIdx.x;
   const int64_t c = win->n_groups < count ? win->n_groups : count;
-  if (t < c) flags[list[t]] = 1;
+  if (t < c) {
+    const int32_t g = list[t];
+    flags[g] = 1;
+    if (flags2) flags2[g] = 1;
+  }
 }
 
 // blocks of 256 threads for `count` items, at most `cap` (threads then stride)
@@ -271,7 +287,9 @@ void launch_row_bound(const double* row_mean, int64_t N, int n, uint64_t* range,
       {bmax, nbins, 0xFFFFFFFFu, 0},
   };
   launch_fill_many(fills, 4, s);
-  hipLaunchKernelGGL(k_mean_range, dim3(blocks_for(N)), dim3(256), 0, s, row_mean, N, range);
+  // few workgroups: each ends with two atomics on the same two words, which the
+  // memory system serialises (1024 workgroups took 26 us on 2^20 rows)
+  hipLaunchKernelGGL(k_mean_range, dim3(blocks_for(N, 256)), dim3(256), 0, s, row_mean, N, range);
   hipLaunchKernelGGL(k_bin_rows, dim3(blocks_for(N, 4096)), dim3(256), 0, s, row_mean, N, range, nbins,
                      bmin, bmax);
   hipLaunchKernelGGL(k_bin_groups, dim3((unsigned)((nbins + kG2 - 1) / kG2)), dim3(kG2), 0, s,
@@ -289,10 +307,10 @@ void launch_item_bound(const float* lb, int64_t N, int64_t item_rows, int64_t n_
 }
 
 void launch_flag_items(const int32_t* list, int64_t count, const WinDesc* win, int32_t* flags,
-                       hipStream_t s) {
+                       int32_t* flags2, hipStream_t s) {
   if (count > 0)
     hipLaunchKernelGGL(k_flag_items, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, list,
-                       count, win, flags);
+                       count, win, flags, flags2);
 }
 
 }  // namespace dd

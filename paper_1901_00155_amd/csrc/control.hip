@@ -59,7 +59,7 @@ __global__ void k_ctl_start(SearchCtl* ctl, int64_t count, int64_t width,
                P.min_chunk_full);
 }
 
-__global__ void k_ctl_window(SearchCtl* ctl, WinDesc* win, uint32_t* n_surv, CtlParams P) {
+__device__ void ctl_window(SearchCtl* ctl, WinDesc* win, uint32_t* n_surv, const CtlParams& P) {
   const int64_t c = ctl->count;
   const int64_t end = ctl->covered + ctl->width < P.seq_max ? ctl->covered + ctl->width : P.seq_max;
   set_window(win, c, ctl->covered, end, P.target, P.gran, ctl->in_off, P.min_chunk_win);
@@ -67,7 +67,7 @@ __global__ void k_ctl_window(SearchCtl* ctl, WinDesc* win, uint32_t* n_surv, Ctl
   *n_surv = 0;
 }
 
-__global__ void k_ctl_after(SearchCtl* ctl, const uint32_t* n_surv, CtlParams P) {
+__device__ void ctl_after(SearchCtl* ctl, const uint32_t* n_surv, const CtlParams& P) {
   if (ctl->count == 0) return;
   const int64_t hs = *n_surv;
   if (ctl->end >= P.seq_max || hs == 0) {   // every sequence done, or no live row left
@@ -80,6 +80,20 @@ __global__ void k_ctl_after(SearchCtl* ctl, const uint32_t* n_surv, CtlParams P)
   // near-first: the next window `growth` times longer; else the survivors
   // finish in one more window
   ctl->width = P.near_first ? ctl->width * P.growth : P.seq_max;
+}
+
+__global__ void k_ctl_window(SearchCtl* ctl, WinDesc* win, uint32_t* n_surv, CtlParams P) {
+  ctl_window(ctl, win, n_surv, P);
+}
+
+__global__ void k_ctl_after(SearchCtl* ctl, const uint32_t* n_surv, CtlParams P) {
+  ctl_after(ctl, n_surv, P);
+}
+
+// the two decisions between consecutive windows in one launch
+__global__ void k_ctl_next(SearchCtl* ctl, WinDesc* win, uint32_t* n_surv, CtlParams P) {
+  ctl_after(ctl, n_surv, P);
+  ctl_window(ctl, win, n_surv, P);
 }
 
 __global__ void k_ctl_seeds(SearchCtl* ctl, WinDesc* win, CtlParams P) {
@@ -121,6 +135,11 @@ void launch_ctl_window(SearchCtl* ctl, WinDesc* win, uint32_t* n_surv, const Ctl
 
 void launch_ctl_after(SearchCtl* ctl, const uint32_t* n_surv, const CtlParams& P, hipStream_t s) {
   hipLaunchKernelGGL(k_ctl_after, dim3(1), dim3(1), 0, s, ctl, n_surv, P);
+}
+
+void launch_ctl_next(SearchCtl* ctl, WinDesc* win, uint32_t* n_surv, const CtlParams& P,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_ctl_next, dim3(1), dim3(1), 0, s, ctl, win, n_surv, P);
 }
 
 void launch_ctl_seeds(SearchCtl* ctl, WinDesc* win, const CtlParams& P, hipStream_t s) {

@@ -240,6 +240,9 @@ void launch_ctl_window(SearchCtl* ctl, WinDesc* win, uint32_t* n_surv, const Ctl
 // after a window: the loop ends when the sequences are done or no item has a
 // live row; else the survivors are the next list and the window grows
 void launch_ctl_after(SearchCtl* ctl, const uint32_t* n_surv, const CtlParams& P, hipStream_t s);
+// launch_ctl_after, then launch_ctl_window, as one launch
+void launch_ctl_next(SearchCtl* ctl, WinDesc* win, uint32_t* n_surv, const CtlParams& P,
+                     hipStream_t s);
 // ranked rounds: after the survivors were ranked, the best-ranked
 // min(count, seeds) items are completed over the rest of their sequences ...
 void launch_ctl_seeds(SearchCtl* ctl, WinDesc* win, const CtlParams& P, hipStream_t s);
@@ -256,11 +259,11 @@ void launch_row_bound(const double* row_mean, int64_t N, int n, uint64_t* range,
 // score[t] = bits of the largest lb over item t's rows (item_rows rows each)
 void launch_item_bound(const float* lb, int64_t N, int64_t item_rows, int64_t n_items,
                        uint32_t* score, hipStream_t s);
-// flags[list[t]] = 1 for t < min(count, win->n_groups): the items a launch
-// described by `win` covered (the list may hold fewer valid entries than
-// count when the device decided on less work)
+// flags[list[t]] = 1 (and flags2[list[t]] = 1, if given) for t < min(count,
+// win->n_groups): the items a launch described by `win` covered (the list may
+// hold fewer valid entries than count when the device decided on less work)
 void launch_flag_items(const int32_t* list, int64_t count, const WinDesc* win, int32_t* flags,
-                       hipStream_t s);
+                       int32_t* flags2, hipStream_t s);
 
 // ---- rank.hip -----------------------------------------------------------------
 // A descending counting sort of the *count entries of `list` (nullptr: 0, 1,
