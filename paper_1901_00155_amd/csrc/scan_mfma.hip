@@ -41,8 +41,12 @@
 // four 32x32 accumulators.  At K-step s, column block c needs the column
 // operand at offset 16 (s + 2c), so one operand serves 4 (block, step) pairs.
 // Each K-step reads one new column operand and one row operand (hi and lo)
-// for 12 MFMAs.  Steps visit 128-column super-blocks: the item's word bucket
-// first (same-word columns, Algorithm 4), then outward from the item's rows
+// for 12 MFMAs.  In an early-abandon search a step in which only one row block
+// is still live would leave three wavefronts idle; there the four wavefronts
+// take one column block of the live row block each, and the row minima of the
+// four tiles are merged through LDS by the block's own wavefront, in column
+// order.  Steps visit 128-column super-blocks: the item's word bucket first
+// (same-word columns, Algorithm 4), then outward from the item's rows
 // (spiral.hpp), or in matrix order.
 //
 // Early abandon (Algorithms 3 and 4): after every step, rows whose running
@@ -171,6 +175,8 @@ __device__ __forceinline__ void scan_item(const ScanJob& J, const MixedRows& R, 
                                           bf16x8* smem) {
   __shared__ uint32_t wave_live[2 * W];
   __shared__ uint32_t tail[W + 1];
+  __shared__ float part_d[W * 64];     // one-live-block steps: each tile's row minima
+  __shared__ int32_t part_j[W * 64];
 
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
@@ -338,12 +344,18 @@ __device__ __forceinline__ void scan_item(const ScanJob& J, const MixedRows& R, 
     // every wavefront has finished reading the previous step's columns (and
     // the row stretch is complete before the first step)
     __syncthreads();
-    if (s > 0) {
+    // the row blocks live in this step (uniform over the workgroup)
+    int n_live = 0, one = 0;
+    {
       const uint32_t* flags = wave_live + (s & 1) * W;
-      bool any = false;
 #pragma unroll
-      for (int w = 0; w < W; ++w) any |= flags[w] != 0;
-      if (!any) break;
+      for (int w = 0; w < W; ++w) {
+        if (flags[w] != 0) {
+          ++n_live;
+          one = w;
+        }
+      }
+      if (n_live == 0) break;
     }
     int32_t j0;
     if constexpr (PFE > 0) {
@@ -369,7 +381,124 @@ __device__ __forceinline__ void scan_item(const ScanJob& J, const MixedRows& R, 
       if (s + 1 < steps) fetch_cols(s + 1);
     }
 
-    if (live) {
+    if (J.abandon && n_live == 1) {
+      // ---- one live row block: the 4 wavefronts share its 4 column blocks ----
+      // Wavefront w computes the 32x32 tile of the live block `one` and column
+      // block w, with the same operands and MFMA order as the owner would (so
+      // the distances are the same bits); the owner then merges the 4 tiles'
+      // row minima in column order and takes the abandon decision.
+      const bool owner = wv == one;
+      const float bsf_now = owner ? __builtin_bit_cast(float, load_relaxed(J.bsf)) : 0.0f;
+      const int64_t q0 = (item * W + one) * BM;     // the live block's first row
+      const uint32_t qvalid =
+          N - q0 >= BM ? 0xFFFFFFFFu : ((1u << (uint32_t)(N - q0)) - 1u);
+      const int64_t qrow = min<int64_t>(q0 + rl, N - 1);
+      const float qc = R.cnorm[qrow];
+      const bf16x8 qnrow = norm_row(Z ? 0.0f : qc, 2.0f * (float)n * (R.mu[qrow] - CR), h);
+      const float qx = Z ? R.r[qrow] : R.smu[qrow];
+      floatx16 a1;
+      {
+        floatx16 z;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) z[v] = 0.0f;
+        a1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(cN[2 * (32 * wv + rl) + h], qnrow, z, 0, 0, 0);
+      }
+      // column block wv at K-step k: entry 16 k + 32 wv; row block `one`: 16 k + 32 one
+      const bf16x8* ph = cEh + rl + 8 * h + 32 * wv;
+      const bf16x8* pl = cEl + rl + 8 * h + 32 * wv;
+      const bf16x8* qh = rEh + 32 * one + rl + 8 * h;
+      const bf16x8* ql = rEl + 32 * one + rl + 8 * h;
+      bf16x8 oh0 = ph[0], ol0 = pl[0], bh0 = qh[0], bl0 = ql[0];
+#pragma unroll 1
+      for (int k = 0; k < KS; ++k) {
+        const int kn = min(k + 1, KS - 1);   // the next K-step's reads, clamped
+        const bf16x8 oh1 = ph[16 * kn], ol1 = pl[16 * kn], bh1 = qh[16 * kn], bl1 = ql[16 * kn];
+        if (k == KS - 1) {
+          bh0 = mask_bf16(bh0, tail_mask);
+          bl0 = mask_bf16(bl0, tail_mask);
+        }
+        a1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(oh0, bh0, a1, 0, 0, 0);
+        a1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(oh0, bl0, a1, 0, 0, 0);
+        a1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ol0, bh0, a1, 0, 0, 0);
+        oh0 = oh1;
+        ol0 = ol1;
+        bh0 = bh1;
+        bl0 = bl1;
+      }
+      // the tile's distances, as in the epilogue below for column block wv
+      const int32_t jb = j0 + 32 * wv;
+      const int32_t qi = (int32_t)(q0 + rl);
+      const bool clean = (jb + BM <= jlim) && ((jb >= (int32_t)q0 + BM - 1 + n) ||
+                                               (jb + BM - 1 + n <= (int32_t)q0));
+      float d[16];
+#pragma unroll
+      for (int qd = 0; qd < 4; ++qd) {
+        const int lc = 32 * wv + 8 * qd + 4 * h;
+        const float4 xj = *reinterpret_cast<const float4*>(cst + lc);
+        const float xjv[4] = {xj.x, xj.y, xj.z, xj.w};
+        if (Z) {
+          const float4 cn = *reinterpret_cast<const float4*>(cst + TC + lc);
+          const float cnv[4] = {cn.x, cn.y, cn.z, cn.w};
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            d[4 * qd + e] = __builtin_fmaf(qx * xjv[e], a1[4 * qd + e], qc + cnv[e]);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const float u = qx - xjv[e];
+            d[4 * qd + e] = __builtin_fmaf(u, u, a1[4 * qd + e]);
+          }
+        }
+      }
+      if (!clean) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int32_t j = jb + 8 * (v >> 2) + 4 * h + (v & 3);
+          const int32_t dij = qi > j ? qi - j : j - qi;
+          if (!(j < jlim && dij >= n)) d[v] = __builtin_inff();
+        }
+      }
+      float tmin = d[0];
+#pragma unroll
+      for (int v = 1; v < 16; ++v) tmin = fminf(tmin, d[v]);
+      int32_t jj = -1;
+#pragma unroll
+      for (int v = 15; v >= 0; --v)
+        if (d[v] == tmin) jj = jb + 8 * (v >> 2) + 4 * h + (v & 3);
+      if ((qvalid >> rl) & 1u) {
+        if (clean) {
+          cnt += 16;
+        } else {
+#pragma unroll
+          for (int v = 0; v < 16; ++v) cnt += d[v] < __builtin_inff();
+        }
+      }
+      part_d[64 * wv + lane] = tmin;
+      part_j[64 * wv + lane] = jj;
+      __syncthreads();
+      if (owner) {
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+          const float pd = part_d[64 * c + lane];
+          if (pd < rmin) {
+            rmin = pd;
+            rj = part_j[64 * c + lane];
+          }
+        }
+        const float m = fminf(rmin, __shfl_xor(rmin, 32, 64));
+        const uint32_t dead = (uint32_t)(__ballot(m < bsf_now && h == 0) & 0xFFFFFFFFull) & live;
+        if (dead) {
+          uint64_t key = rj < 0 ? kEmptyMin : pack_min(fmaxf(rmin, 0.0f), (uint32_t)rj);
+          const uint64_t o = __shfl_xor(key, 32, 64);
+          key = o < key ? o : key;
+          if (h == 0 && ((dead >> rl) & 1u))
+            atomicMin((unsigned long long*)&J.best[r0 + rl], (unsigned long long)key);
+          if (lane == 0) atomicAnd(&J.alive[g], ~dead);
+          live &= ~dead;
+        }
+        if (J.chunks > 1) live &= __builtin_amdgcn_readfirstlane(load_relaxed(&J.alive[g]));
+      }
+    } else if (live) {
       // the best-so-far for this step's abandon test, read before the MFMAs so
       // that its latency overlaps them (a value read earlier is never larger)
       const float bsf_now = J.abandon ? __builtin_bit_cast(float, load_relaxed(J.bsf)) : 0.0f;
