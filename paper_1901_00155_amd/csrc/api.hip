@@ -211,6 +211,9 @@ struct discord_plan_s {
   double ms_prepare = 0.0;
   bool searched = false;
   bool timed = true;          // false: no HIP events (the allocation-free entry point)
+  // false: the preparation skips Index_Word (eq. (10)), which only the PhiDD
+  // order's sequences and the introspection of a kept plan read
+  bool index_word = true;
   hipGraphExec_t gexec = nullptr;   // the search captured by discord_search_graph
   int glaunches = 0;                // scan launches in that graph
   void* hout = nullptr;             // pinned block the captured search reads back into
@@ -459,9 +462,10 @@ int prepare_enqueue(discord_plan p, const float* T) {
   launch_cand(p->at<int32_t>(p->L.words), p->at<int32_t>(p->L.hist), p->N, p->dict,
               p->at<int32_t>(p->L.minfreq), p->at<int32_t>(p->L.seg), p->at<int32_t>(p->L.cand),
               p->at<int32_t>(p->L.cand_count), s);
-  launch_csr(p->at<int32_t>(p->L.words), p->at<int32_t>(p->L.hist), p->N, p->dict,
-             p->at<int32_t>(p->L.seg), p->at<int32_t>(p->L.csr_off),
-             p->at<int32_t>(p->L.csr_mem), s);
+  if (p->index_word)
+    launch_csr(p->at<int32_t>(p->L.words), p->at<int32_t>(p->L.hist), p->N, p->dict,
+               p->at<int32_t>(p->L.seg), p->at<int32_t>(p->L.csr_off),
+               p->at<int32_t>(p->L.csr_mem), s);
   const bool mixed = o.precision == DISCORD_PREC_BF16X3;
   // FP32 centres and scales: the split-BF16 operands, and under per-window
   // normalisation also the FP32 scan's
@@ -1293,6 +1297,7 @@ int search_series_in_arena(const float* T, int64_t m, int32_t n, const discord_o
     if (!ev.ready()) st = fail(p, DISCORD_EDEVICE, "hipEventCreate failed");
     if (st == DISCORD_OK && ev.start(stream) != hipSuccess)
       st = fail(p, DISCORD_EDEVICE, "hipEventRecord failed");
+    p->index_word = false;   // no plan is kept, and the sequences need no bucket
     if (st == DISCORD_OK) st = prepare_enqueue(p, T);
     if (st == DISCORD_OK) st = search_enqueue(p, run);
     if (st == DISCORD_OK && ev.stop(stream) != hipSuccess)
@@ -1375,6 +1380,7 @@ int search_series_graph(RequestGraph** cache, bool capture, const float* T, int6
       (void)hipGetLastError();
       return give_up(fail(p, DISCORD_EDEVICE, "hipStreamBeginCapture failed"));
     }
+    p->index_word = o.order == 1;   // the served request keeps no plan to inspect
     st = prepare_enqueue(p, T);
     if (st == DISCORD_OK) st = search_enqueue(p, cap);
     hipGraph_t graph = nullptr;

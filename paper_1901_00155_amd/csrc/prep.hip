@@ -82,15 +82,24 @@ __global__ __launch_bounds__(256) void k_finish(const double* __restrict__ parti
 // The 256 rows of a workgroup, i0 .. i0 + 255, read the values t_{i0} ..
 // t_{i0 + 254 + n}: they are copied to LDS once (coalesced), and each thread
 // reads its window from there.  Rows past the series read the zero pad after
-// it (the caller ignores them).  Returns this thread's window.
+// it (the caller ignores them).  Returns this thread's window.  Windows longer
+// than kStageMaxN values are read from the series itself (the copy would not
+// fit in a workgroup's LDS); the barrier is taken either way, so callers may
+// rely on it.
+constexpr int kStageMaxN = 8192;   // 255 + n floats: at most 33.8 KB
+
 __device__ __forceinline__ const float* stage_windows(const float* __restrict__ T, int64_t i0,
                                                       int n, float* __restrict__ sh) {
+  if (n > kStageMaxN) {
+    __syncthreads();
+    return T + i0 + threadIdx.x;
+  }
   for (int k = threadIdx.x; k < 255 + n; k += 256) sh[k] = T[i0 + k];
   __syncthreads();
   return sh + threadIdx.x;
 }
 
-size_t stage_bytes(int n) { return sizeof(float) * (size_t)(255 + n); }
+size_t stage_bytes(int n) { return n > kStageMaxN ? 0 : sizeof(float) * (size_t)(255 + n); }
 
 // Mean and centred squared norm of every row (FP64, sequential two-pass sums,
 // each multiply and add rounded on its own) and, for per-window normalisation,

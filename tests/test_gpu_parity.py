@@ -393,3 +393,22 @@ def test_row_bound_below_exact_nn(gpu, m, n, seed):
     top = np.argsort(-lb)[:16]
     assert np.max(prof[top]) >= np.quantile(prof[has], 0.75)
     assert r.index == ref["index"]
+
+
+@pytest.mark.parametrize("znorm", [False, True])
+def test_fp32_window_longer_than_lds_stage(gpu, znorm):
+    """Windows of more than 8192 values: the preparation reads them from the
+    series instead of staging 255 + n values of a workgroup's rows in LDS; the
+    result is the oracle's."""
+    m, n = 19000, 9000
+    T = workloads.random_walk(m, seed=9)
+    ref = oracle.discord(T, n, znorm=znorm)
+    r = gpu.search_once(T, n, znorm=znorm)
+    assert (r.index, r.nn_index) == (ref["index"], ref["nn_index"])
+    assert abs(r.d2 - ref["d2"]) <= 1e-9 * ref["d2"]
+    with gpu.Plan(T, n, znorm=znorm) as p:
+        words = p.copy("words")
+        mean = p.copy("row_mean")
+    assert np.array_equal(words, oracle.sax_words(T, n, znorm=znorm))
+    mu = np.lib.stride_tricks.sliding_window_view(T.astype(np.float64), n).mean(axis=1)
+    assert np.allclose(mean, mu, rtol=1e-12, atol=1e-9)
