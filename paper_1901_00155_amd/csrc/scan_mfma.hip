@@ -389,6 +389,10 @@ __device__ __forceinline__ void scan_item(const ScanJob& J, const MixedRows& R, 
       // row minima in column order and takes the abandon decision.
       const bool owner = wv == one;
       const float bsf_now = owner ? __builtin_bit_cast(float, load_relaxed(J.bsf)) : 0.0f;
+      // this path's LDS addresses are formed here, not hoisted out of the step
+      // loop, where they would hold registers through the 4-block K-loop
+      int cw = wv;
+      asm volatile("" : "+v"(cw));
       const int64_t q0 = (item * W + one) * BM;     // the live block's first row
       const uint32_t qvalid =
           N - q0 >= BM ? 0xFFFFFFFFu : ((1u << (uint32_t)(N - q0)) - 1u);
@@ -401,11 +405,11 @@ __device__ __forceinline__ void scan_item(const ScanJob& J, const MixedRows& R, 
         floatx16 z;
 #pragma unroll
         for (int v = 0; v < 16; ++v) z[v] = 0.0f;
-        a1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(cN[2 * (32 * wv + rl) + h], qnrow, z, 0, 0, 0);
+        a1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(cN[2 * (32 * cw + rl) + h], qnrow, z, 0, 0, 0);
       }
       // column block wv at K-step k: entry 16 k + 32 wv; row block `one`: 16 k + 32 one
-      const bf16x8* ph = cEh + rl + 8 * h + 32 * wv;
-      const bf16x8* pl = cEl + rl + 8 * h + 32 * wv;
+      const bf16x8* ph = cEh + rl + 8 * h + 32 * cw;
+      const bf16x8* pl = cEl + rl + 8 * h + 32 * cw;
       const bf16x8* qh = rEh + 32 * one + rl + 8 * h;
       const bf16x8* ql = rEl + 32 * one + rl + 8 * h;
       bf16x8 oh0 = ph[0], ol0 = pl[0], bh0 = qh[0], bl0 = ql[0];
@@ -426,14 +430,14 @@ __device__ __forceinline__ void scan_item(const ScanJob& J, const MixedRows& R, 
         bl0 = bl1;
       }
       // the tile's distances, as in the epilogue below for column block wv
-      const int32_t jb = j0 + 32 * wv;
+      const int32_t jb = j0 + 32 * cw;
       const int32_t qi = (int32_t)(q0 + rl);
       const bool clean = (jb + BM <= jlim) && ((jb >= (int32_t)q0 + BM - 1 + n) ||
                                                (jb + BM - 1 + n <= (int32_t)q0));
       float d[16];
 #pragma unroll
       for (int qd = 0; qd < 4; ++qd) {
-        const int lc = 32 * wv + 8 * qd + 4 * h;
+        const int lc = 32 * cw + 8 * qd + 4 * h;
         const float4 xj = *reinterpret_cast<const float4*>(cst + lc);
         const float xjv[4] = {xj.x, xj.y, xj.z, xj.w};
         if (Z) {
@@ -473,8 +477,8 @@ __device__ __forceinline__ void scan_item(const ScanJob& J, const MixedRows& R, 
           for (int v = 0; v < 16; ++v) cnt += d[v] < __builtin_inff();
         }
       }
-      part_d[64 * wv + lane] = tmin;
-      part_j[64 * wv + lane] = jj;
+      part_d[64 * cw + lane] = tmin;
+      part_j[64 * cw + lane] = jj;
       __syncthreads();
       if (owner) {
 #pragma unroll
