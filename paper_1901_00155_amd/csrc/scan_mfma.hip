@@ -169,14 +169,17 @@ __device__ __forceinline__ bf16x8 mask_bf16(bf16x8 x, uint4 m) {
 
 // PFE > 0: the stretch has at most PFE * 256 entries, and each thread holds
 // the values of its PFE entries (and a column's statistics) for the next step
-// in registers: they are loaded while the current step's MFMAs run.
-template <bool Z, int PFE>
+// in registers: they are loaded while the current step's MFMAs run.  SHARE:
+// the early-abandon instance, with the one-live-block steps (full scans never
+// have a dead row block, and keep the code without them).
+template <bool Z, int PFE, bool SHARE>
 __device__ __forceinline__ void scan_item(const ScanJob& J, const MixedRows& R, int64_t wi,
                                           bf16x8* smem) {
   __shared__ uint32_t wave_live[2 * W];
   __shared__ uint32_t tail[W + 1];
-  __shared__ float part_d[W * 64];     // one-live-block steps: each tile's row minima
-  __shared__ int32_t part_j[W * 64];
+  // one-live-block steps: each tile's row minima (early-abandon instance only)
+  __shared__ float part_d[SHARE ? W * 64 : 1];
+  __shared__ int32_t part_j[SHARE ? W * 64 : 1];
 
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
@@ -346,7 +349,7 @@ __device__ __forceinline__ void scan_item(const ScanJob& J, const MixedRows& R, 
     __syncthreads();
     // the row blocks live in this step (uniform over the workgroup)
     int n_live = 0, one = 0;
-    {
+    if constexpr (SHARE) {
       const uint32_t* flags = wave_live + (s & 1) * W;
 #pragma unroll
       for (int w = 0; w < W; ++w) {
@@ -356,6 +359,12 @@ __device__ __forceinline__ void scan_item(const ScanJob& J, const MixedRows& R, 
         }
       }
       if (n_live == 0) break;
+    } else if (s > 0) {
+      const uint32_t* flags = wave_live + (s & 1) * W;
+      bool any = false;
+#pragma unroll
+      for (int w = 0; w < W; ++w) any |= flags[w] != 0;
+      if (!any) break;
     }
     int32_t j0;
     if constexpr (PFE > 0) {
@@ -381,7 +390,7 @@ __device__ __forceinline__ void scan_item(const ScanJob& J, const MixedRows& R, 
       if (s + 1 < steps) fetch_cols(s + 1);
     }
 
-    if (J.abandon && n_live == 1) {
+    if (SHARE && n_live == 1) {
       // ---- one live row block: the 4 wavefronts share its 4 column blocks ----
       // Wavefront w computes the 32x32 tile of the live block `one` and column
       // block w, with the same operands and MFMA order as the owner would (so
@@ -701,19 +710,19 @@ __device__ __forceinline__ void scan_item(const ScanJob& J, const MixedRows& R, 
 
 // One workgroup per work item (item, chunk), striding by the grid size.  Every
 // wavefront finishes its LDS reads before the next item rebuilds the stretches.
-template <bool Z, int PFE>
+template <bool Z, int PFE, bool SHARE>
 __global__ __launch_bounds__(THREADS, 2) void k_scan_mfma(ScanJob Jarg, MixedRows R) {
   extern __shared__ bf16x8 smem[];
   ScanJob J = Jarg;
   apply_win(J);
   const int64_t total = J.n_groups * J.chunks;
   for (int64_t wi = blockIdx.x; wi < total; wi += gridDim.x) {
-    scan_item<Z, PFE>(J, R, wi, smem);
+    scan_item<Z, PFE, SHARE>(J, R, wi, smem);
     if (wi + gridDim.x < total) __syncthreads();
   }
 }
 
-template <bool Z, int PFE>
+template <bool Z, int PFE, bool SHARE>
 void launch_scan(const ScanJob& J, const MixedRows& R, hipStream_t s) {
   const int64_t blocks = J.win ? J.max_work : J.n_groups * J.chunks;
   if (blocks <= 0) return;
@@ -721,13 +730,14 @@ void launch_scan(const ScanJob& J, const MixedRows& R, hipStream_t s) {
   // the LDS opt-in is per kernel and set once per process, to the largest
   // window's need; the initialisation of a function-local static is thread-safe
   static const bool attr_set = [] {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_scan_mfma<Z, PFE>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_scan_mfma<Z, PFE, SHARE>),
                               hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds_bytes(kMixedMaxN / 16));
     return true;
   }();
   (void)attr_set;
-  hipLaunchKernelGGL((k_scan_mfma<Z, PFE>), dim3((unsigned)blocks), dim3(THREADS), lds, s, J, R);
+  hipLaunchKernelGGL((k_scan_mfma<Z, PFE, SHARE>), dim3((unsigned)blocks), dim3(THREADS), lds, s,
+                     J, R);
 }
 
 }  // namespace
@@ -736,16 +746,17 @@ bool launch_scan_mfma(const ScanJob& J, const MixedRows& R, hipStream_t s) {
   if (J.n < 1 || J.n > kMixedMaxN) return false;
   // stretches of up to 512 entries (windows up to 384) prefetch a step ahead
   const bool pf = stretch_entries((J.n + 15) / 16) <= 2 * THREADS;
+  const bool ab = J.abandon != 0;
   if (R.r) {
     if (pf)
-      launch_scan<true, 2>(J, R, s);
+      ab ? launch_scan<true, 2, true>(J, R, s) : launch_scan<true, 2, false>(J, R, s);
     else
-      launch_scan<true, 0>(J, R, s);
+      ab ? launch_scan<true, 0, true>(J, R, s) : launch_scan<true, 0, false>(J, R, s);
   } else {
     if (pf)
-      launch_scan<false, 2>(J, R, s);
+      ab ? launch_scan<false, 2, true>(J, R, s) : launch_scan<false, 2, false>(J, R, s);
     else
-      launch_scan<false, 0>(J, R, s);
+      ab ? launch_scan<false, 0, true>(J, R, s) : launch_scan<false, 0, false>(J, R, s);
   }
   return true;
 }
