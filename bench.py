@@ -415,8 +415,8 @@ def main():
         hs = {}
         for prec in ("fp32", "bf16x3"):
             hms = []
-            sh, _ = time_steps(dd, w.series, n, prec, abandon, args.steps, args.warmup, args.order,
-                               per_step=hms)
+            sh, _ = time_steps(dd, w.series, n, prec, abandon, max(args.steps, 5), args.warmup,
+                               args.order, per_step=hms)
             hs[prec] = {"time_to_discord_ms": sh * 1e3,
                         "time_to_discord_median_ms": float(np.median(hms))}
         out["host_series"] = hs
