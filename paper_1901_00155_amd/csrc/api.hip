@@ -476,9 +476,10 @@ int prepare_enqueue(discord_plan p, const float* T) {
                        p->at<float>(p->L.smu32), p->at<float>(p->L.cn32), r32, s);
   // the bucket column blocks serve only the PhiDD order (same-word columns first)
   if (o.order == 1) {
-    // (bucket entries are the scan's column blocks: 8 or 128 columns)
+    // (bucket entries are the scan's column blocks: 128 columns, or 4 (FP32
+    // early abandon) or 8 (FP32 full scan))
     launch_bucket_groups(p->at<int32_t>(p->L.csr_off), p->at<int32_t>(p->L.csr_mem), p->dict,
-                         mixed ? 7 : 3,
+                         mixed ? 7 : (o.abandon ? 2 : 3),
                          p->at<int32_t>(p->L.bgrp_cnt), p->at<int32_t>(p->L.bgrp_off),
                          p->at<int32_t>(p->L.bgrp), s);
     launch_max_bucket(p->at<int32_t>(p->L.bgrp_off), p->dict, p->at<int32_t>(p->L.max_bucket), s);
@@ -710,7 +711,7 @@ int search_enqueue(discord_plan p, SearchRun& run) {
   };
   // Sequence entries are column groups of 8 (FP32) or blocks of 128 (MFMA); a
   // sequence is at most the word bucket plus every column block.
-  const int64_t col_w = mixed ? kMixedCols : kColBlock;
+  const int64_t col_w = mixed ? kMixedCols : (abandon ? kColBlockSearch : kColBlock);
   const int64_t nq = (N + col_w - 1) / col_w;
   if (buckets && p->max_bucket < 0) return fail(p, DISCORD_EDEVICE, "bucket sizes not read back");
   const int64_t seq_max = nq + (buckets ? p->max_bucket : 0);
@@ -768,7 +769,9 @@ int search_enqueue(discord_plan p, SearchRun& run) {
     // with the bound-ranked items completed first: FP32 2^20 walk 6.6 -> 6.2
     // ms with 4x; FP32 10^7-point walk n = 1024 613 -> 559 ms with 2x); in
     // ranked rounds 2x from 2^15 entries
-    const int64_t growth = seq_max >= (int64_t{1} << (ranked ? 15 : 20)) ? 2 : 4;
+    // (sequence lengths counted in blocks of 8 FP32 or 128 split-BF16 columns)
+    const int64_t seq_units = mixed ? seq_max : seq_max * col_w / kColBlock;
+    const int64_t growth = seq_units >= (int64_t{1} << (ranked ? 15 : 20)) ? 2 : 4;
     // ranked rounds: items completed after each ranking (split-BF16: 16
     // workgroup items; FP32 groups: more for longer windows)
     const int64_t seeds = mixed ? 16 : (n >= 1024 ? 512 : (n >= 512 ? 256 : 128));

@@ -24,13 +24,17 @@ namespace dd {
 namespace {
 
 constexpr int TM = kRowGroup;   // 8 rows per wave
-constexpr int TN = kColBlock;   // 8 columns per lane
-static_assert(TM == 8 && TN == 8, "the micro-tile below is written for 8 x 8");
+// TN columns per lane: kColBlock (8) in full scans; kColBlockSearch (4) in
+// early-abandon searches, whose rows can leave only at the end of a step of
+// 64 lanes x TN columns (most rows of a search leave within its first 256
+// columns, so 512-column steps did twice the work needed)
+static_assert(TM == 8 && kColBlock == 8 && kColBlockSearch == 4,
+              "the micro-tiles below are written for 8 x 8 and 8 x 4");
 
 // One position p: all 64 pairs of the block that are active at p take
 // acc += D^2 with D = x[p] - y[p + (c - r)].  yw[g + 7] = y[p + g].
 // PRED: apply the activity test 0 <= p - r < n (first and last 7 positions).
-template <bool PRED>
+template <bool PRED, int TN>
 __device__ __forceinline__ void step(float (&acc)[TM][TN], float xp, const float* yw, int p,
                                      int n) {
   float D[TM + TN - 1];
@@ -52,12 +56,13 @@ __device__ __forceinline__ void step(float (&acc)[TM][TN], float xp, const float
   }
 }
 
-// y loads for positions [p0, p0+8): y[p0-8 .. p0+15] (24 floats, 16-byte aligned
-// when y and p0 are multiples of 4 floats).
-__device__ __forceinline__ void load_y(const float* __restrict__ y, int p0, float (&yb)[24]) {
+// y loads for positions [p0, p0+8): y[p0-8 .. p0+TN+7] (TN + 16 floats, 16-byte
+// aligned when y and p0 are multiples of 4 floats).
+template <int TN>
+__device__ __forceinline__ void load_y(const float* __restrict__ y, int p0, float (&yb)[TN + 16]) {
   const float4* v = reinterpret_cast<const float4*>(y + p0 - 8);
 #pragma unroll
-  for (int q = 0; q < 6; ++q) {
+  for (int q = 0; q < (TN + 16) / 4; ++q) {
     const float4 f = v[q];
     yb[4 * q + 0] = f.x;
     yb[4 * q + 1] = f.y;
@@ -73,27 +78,28 @@ __device__ __forceinline__ void load_x(const float* __restrict__ x, int p0, floa
   xb[4] = b.x; xb[5] = b.y; xb[6] = b.z; xb[7] = b.w;
 }
 
-template <bool PRED>
+template <bool PRED, int TN>
 __device__ __forceinline__ void steps8(float (&acc)[TM][TN], const float* __restrict__ x,
                                        const float* __restrict__ y, int p0, int n) {
-  float xb[8], yb[24];
+  float xb[8], yb[TN + 16];
   load_x(x, p0, xb);
-  load_y(y, p0, yb);
+  load_y<TN>(y, p0, yb);
 #pragma unroll
-  for (int u = 0; u < 8; ++u) step<PRED>(acc, xb[u], &yb[u + 1], p0 + u, n);
+  for (int u = 0; u < 8; ++u) step<PRED, TN>(acc, xb[u], &yb[u + 1], p0 + u, n);
 }
 
-// acc[r][c] = sum_{k<n} (x[r+k] - y[c+k])^2 for the 8 x 8 block at x, y.
+// acc[r][c] = sum_{k<n} (x[r+k] - y[c+k])^2 for the 8 x TN block at x, y.
+template <int TN>
 __device__ __forceinline__ void block8x8(const float* __restrict__ x, const float* __restrict__ y,
                                          int n, float (&acc)[TM][TN]) {
 #pragma unroll
   for (int r = 0; r < TM; ++r)
 #pragma unroll
     for (int c = 0; c < TN; ++c) acc[r][c] = 0.0f;
-  steps8<true>(acc, x, y, 0, n);            // positions 0..7: rows r > p not started
+  steps8<true, TN>(acc, x, y, 0, n);            // positions 0..7: rows r > p not started
   int p0 = 8;
-  for (; p0 + 8 <= n; p0 += 8) steps8<false>(acc, x, y, p0, n);   // every row active
-  for (; p0 < n + TM - 1; p0 += 8) steps8<true>(acc, x, y, p0, n);  // rows finishing
+  for (; p0 + 8 <= n; p0 += 8) steps8<false, TN>(acc, x, y, p0, n);   // every row active
+  for (; p0 < n + TM - 1; p0 += 8) steps8<true, TN>(acc, x, y, p0, n);  // rows finishing
 }
 
 // Per-window normalisation.  With x_{i,k} = (t_{i+k} - mu_i) / sigma_i, the
@@ -118,7 +124,7 @@ __device__ __forceinline__ void load16(const float* __restrict__ p, float (&v)[1
 }
 
 // positions k0 .. k0 + kn - 1 (kn <= 8, wave-uniform)
-template <bool TAIL>
+template <bool TAIL, int TN>
 __device__ __forceinline__ void zsteps8(float (&acc)[TM][TN], const float* __restrict__ x,
                                         const float* __restrict__ y, int k0, int kn,
                                         const float (&cx)[TM], const float (&cy)[TN]) {
@@ -141,8 +147,9 @@ __device__ __forceinline__ void zsteps8(float (&acc)[TM][TN], const float* __res
 }
 
 // acc[r][c] = approximate d^2 between normalised rows x + r and columns y + c.
-// x, y: 8-float aligned windows of the padded series; zx, zy: the same rows'
+// x, y: TN-float aligned windows of the padded series; zx, zy: the same rows'
 // and columns' entries of the centre (zc) and scale (zr) arrays.
+template <int TN>
 __device__ __forceinline__ void block8x8_z(const float* __restrict__ x, const float* __restrict__ y,
                                            int n, const float* __restrict__ zcx,
                                            const float* __restrict__ zrx,
@@ -157,19 +164,20 @@ __device__ __forceinline__ void block8x8_z(const float* __restrict__ x, const fl
   {
     const float4* pc = reinterpret_cast<const float4*>(zcy);
     const float4* ps = reinterpret_cast<const float4*>(zry);
-    const float4 c0 = pc[0], c1 = pc[1], s0 = ps[0], s1 = ps[1];
-    cy[0] = c0.x; cy[1] = c0.y; cy[2] = c0.z; cy[3] = c0.w;
-    cy[4] = c1.x; cy[5] = c1.y; cy[6] = c1.z; cy[7] = c1.w;
-    sy[0] = s0.x; sy[1] = s0.y; sy[2] = s0.z; sy[3] = s0.w;
-    sy[4] = s1.x; sy[5] = s1.y; sy[6] = s1.z; sy[7] = s1.w;
+#pragma unroll
+    for (int h = 0; h < TN / 4; ++h) {
+      const float4 c4 = pc[h], s4 = ps[h];
+      cy[4 * h + 0] = c4.x; cy[4 * h + 1] = c4.y; cy[4 * h + 2] = c4.z; cy[4 * h + 3] = c4.w;
+      sy[4 * h + 0] = s4.x; sy[4 * h + 1] = s4.y; sy[4 * h + 2] = s4.z; sy[4 * h + 3] = s4.w;
+    }
   }
 #pragma unroll
   for (int r = 0; r < TM; ++r)
 #pragma unroll
     for (int c = 0; c < TN; ++c) acc[r][c] = 0.0f;
   int k0 = 0;
-  for (; k0 + 8 <= n; k0 += 8) zsteps8<false>(acc, x, y, k0, 8, cx, cy);
-  if (k0 < n) zsteps8<true>(acc, x, y, k0, n - k0, cx, cy);
+  for (; k0 + 8 <= n; k0 += 8) zsteps8<false, TN>(acc, x, y, k0, 8, cx, cy);
+  if (k0 < n) zsteps8<true, TN>(acc, x, y, k0, n - k0, cx, cy);
   const float fn = (float)n;
 #pragma unroll
   for (int r = 0; r < TM; ++r) {
@@ -211,7 +219,7 @@ __device__ __forceinline__ uint64_t load_relaxed64(const uint64_t* p) {
 // each live row compares its running minimum with the device best-so-far and
 // leaves as soon as it is below (Algorithms 3-4); the leaving row keeps that
 // column as its witness.
-template <bool Z>
+template <bool Z, int TN>
 __device__ __forceinline__ void scan_item(const ScanJob& J, int64_t item, int lane) {
   const int64_t li = item / J.chunks;
   const int64_t ch = item - li * J.chunks;
@@ -274,9 +282,9 @@ __device__ __forceinline__ void scan_item(const ScanJob& J, int64_t item, int la
     const int32_t j0 = (int32_t)(q * TN);   // N < 2^31 (checked at prepare)
     float acc[TM][TN];
     if constexpr (Z)
-      block8x8_z(x, J.Tp + j0, n, J.zc + i0, J.zr + i0, J.zc + j0, J.zr + j0, acc);
+      block8x8_z<TN>(x, J.Tp + j0, n, J.zc + i0, J.zr + i0, J.zc + j0, J.zr + j0, acc);
     else
-      block8x8(x, J.Tp + j0, n, acc);
+      block8x8<TN>(x, J.Tp + j0, n, acc);
     // blocks inside the matrix and clear of the exclusion band need no mask:
     // each row's minimum over the 8 columns first, its column only on improvement
     const bool clean = in_seq && valid == 0xFFu && j0 + TN <= N &&
@@ -378,7 +386,7 @@ __device__ __forceinline__ void scan_item(const ScanJob& J, int64_t item, int la
 // strides by the grid's wavefront count: a grid sized for the work gives every
 // work item its own wavefront, a smaller one (the device-decided launches,
 // sized for the most work they can hold) takes several per wavefront.
-template <bool Z>
+template <bool Z, int TN>
 __global__ __launch_bounds__(256) void k_scan_fp32(ScanJob Jarg) {
   ScanJob J = Jarg;
   apply_win(J);
@@ -386,7 +394,7 @@ __global__ __launch_bounds__(256) void k_scan_fp32(ScanJob Jarg) {
   const int64_t total = J.n_groups * J.chunks;
   for (int64_t item = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); item < total;
        item += (int64_t)gridDim.x * 4)
-    scan_item<Z>(J, item, lane);
+    scan_item<Z, TN>(J, item, lane);
 }
 
 }  // namespace
@@ -395,10 +403,23 @@ void launch_scan_fp32(const ScanJob& J, hipStream_t s) {
   const int64_t items = J.win ? J.max_work : J.n_groups * J.chunks;
   if (items <= 0) return;
   const int64_t blocks = (items + 3) / 4;
-  if (J.zc)
-    hipLaunchKernelGGL(k_scan_fp32<true>, dim3((unsigned)blocks), dim3(256), 0, s, J);
-  else
-    hipLaunchKernelGGL(k_scan_fp32<false>, dim3((unsigned)blocks), dim3(256), 0, s, J);
+  // the column width must match the one the host split the sequences with
+  // (kColBlockSearch with early abandon, else kColBlock)
+  if (J.zc) {
+    if (J.abandon)
+      hipLaunchKernelGGL((k_scan_fp32<true, kColBlockSearch>), dim3((unsigned)blocks), dim3(256),
+                         0, s, J);
+    else
+      hipLaunchKernelGGL((k_scan_fp32<true, kColBlock>), dim3((unsigned)blocks), dim3(256), 0, s,
+                         J);
+  } else {
+    if (J.abandon)
+      hipLaunchKernelGGL((k_scan_fp32<false, kColBlockSearch>), dim3((unsigned)blocks), dim3(256),
+                         0, s, J);
+    else
+      hipLaunchKernelGGL((k_scan_fp32<false, kColBlock>), dim3((unsigned)blocks), dim3(256), 0,
+                         s, J);
+  }
 }
 
 }  // namespace dd
