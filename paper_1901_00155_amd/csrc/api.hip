@@ -614,11 +614,14 @@ int search_enqueue(discord_plan p, SearchRun& run) {
   int item_shift = 0;
   while ((int64_t{1} << item_shift) < item_rows) ++item_shift;
   const int64_t n_items = (N + item_rows - 1) / item_rows;
-  // work items a window launch aims at: about 4 wavefronts per SIMD, FP32
-  // 1.5x that under global normalisation (2^22 series n = 512 47.9 -> 44.7
-  // ms, noisy 2^20 walk 7.52 -> 7.41 ms, 2^20 walk unchanged; per-window
-  // normalisation 9.5 -> 10.1 ms, so it keeps 4096)
-  const int64_t target_items = mixed ? 1024 : (p->opts.znorm ? 4096 : 6144);
+  // work items a window launch aims at: about 4 wavefronts per SIMD (split-
+  // BF16 workgroups, FP32 under per-window normalisation); FP32 searches under
+  // global normalisation, in 256-column steps, gain from more: 10240 below
+  // 2^21 rows, 16384 from there (against 6144: 2^20 walk 4.60 -> 4.49 ms,
+  // noisy walk 5.69 -> 5.56 ms; 2^22 series 35.7 -> 32.1 ms, 10^7-point walk
+  // n = 1024 509 -> 430 ms; per-window normalisation 8.5 -> 8.6 ms at 10240)
+  const int64_t target_items =
+      mixed ? 1024 : (p->opts.znorm ? 4096 : (N >= (int64_t{1} << 21) ? 16384 : 10240));
   // The launch that completes the bound-ranked items holds few items with
   // long sequences, so it is split finer: 16384 work items (FP32), 2048
   // (split-BF16).
