@@ -476,10 +476,9 @@ int prepare_enqueue(discord_plan p, const float* T) {
                        p->at<float>(p->L.smu32), p->at<float>(p->L.cn32), r32, s);
   // the bucket column blocks serve only the PhiDD order (same-word columns first)
   if (o.order == 1) {
-    // (bucket entries are the scan's column blocks: 128 columns, or 4 (FP32
-    // early abandon) or 8 (FP32 full scan))
+    // (bucket entries are the scan's column blocks: 8 or 128 columns)
     launch_bucket_groups(p->at<int32_t>(p->L.csr_off), p->at<int32_t>(p->L.csr_mem), p->dict,
-                         mixed ? 7 : (o.abandon ? 2 : 3),
+                         mixed ? 7 : 3,
                          p->at<int32_t>(p->L.bgrp_cnt), p->at<int32_t>(p->L.bgrp_off),
                          p->at<int32_t>(p->L.bgrp), s);
     launch_max_bucket(p->at<int32_t>(p->L.bgrp_off), p->dict, p->at<int32_t>(p->L.max_bucket), s);
@@ -620,8 +619,14 @@ int search_enqueue(discord_plan p, SearchRun& run) {
   // 2^21 rows, 16384 from there (against 6144: 2^20 walk 4.60 -> 4.49 ms,
   // noisy walk 5.69 -> 5.56 ms; 2^22 series 35.7 -> 32.1 ms, 10^7-point walk
   // n = 1024 509 -> 430 ms; per-window normalisation 8.5 -> 8.6 ms at 10240)
+  // FP32 early abandon in the near-first order: 256-column steps (most rows
+  // meet a neighbour below the best-so-far within their first 256 columns);
+  // the PhiDD and matrix orders keep 512 (2^20 walk 164 -> 183 and 718 -> 762
+  // ms with 256)
+  const bool fine = !mixed && p->opts.abandon && p->opts.order == 2;
   const int64_t target_items =
-      mixed ? 1024 : (p->opts.znorm ? 4096 : (N >= (int64_t{1} << 21) ? 16384 : 10240));
+      mixed ? 1024
+            : (p->opts.znorm ? 4096 : (fine ? (N >= (int64_t{1} << 21) ? 16384 : 10240) : 6144));
   // The launch that completes the bound-ranked items holds few items with
   // long sequences, so it is split finer: 16384 work items (FP32), 2048
   // (split-BF16).
@@ -714,7 +719,7 @@ int search_enqueue(discord_plan p, SearchRun& run) {
   };
   // Sequence entries are column groups of 8 (FP32) or blocks of 128 (MFMA); a
   // sequence is at most the word bucket plus every column block.
-  const int64_t col_w = mixed ? kMixedCols : (abandon ? kColBlockSearch : kColBlock);
+  const int64_t col_w = mixed ? kMixedCols : (fine ? kColBlockSearch : kColBlock);
   const int64_t nq = (N + col_w - 1) / col_w;
   if (buckets && p->max_bucket < 0) return fail(p, DISCORD_EDEVICE, "bucket sizes not read back");
   const int64_t seq_max = nq + (buckets ? p->max_bucket : 0);

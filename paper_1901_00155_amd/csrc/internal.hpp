@@ -20,7 +20,7 @@ constexpr int64_t kBackPad = 2048;   // floats after t_{m-1}
 
 constexpr int kRowGroup = 8;         // rows sharing one FP32 scan micro-tile
 constexpr int kColBlock = 8;         // columns per lane in the FP32 scan micro-tile
-constexpr int kColBlockSearch = 4;   // ... in an early-abandon FP32 search (256-column steps)
+constexpr int kColBlockSearch = 4;   // ... in a near-first early-abandon search (256-column steps)
 constexpr int kWave = 64;
 
 constexpr int kMaxWords = 256;       // |A|^w limit (eq. 9 hash fits a byte)

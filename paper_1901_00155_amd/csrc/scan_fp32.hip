@@ -24,9 +24,9 @@ namespace dd {
 namespace {
 
 constexpr int TM = kRowGroup;   // 8 rows per wave
-// TN columns per lane: kColBlock (8) in full scans; kColBlockSearch (4) in
-// early-abandon searches, whose rows can leave only at the end of a step of
-// 64 lanes x TN columns (most rows of a search leave within its first 256
+// TN columns per lane: kColBlock (8), or kColBlockSearch (4) in early-abandon
+// searches in the near-first order, whose rows can leave only at the end of a
+// step of 64 lanes x TN columns (most rows there leave within their first 256
 // columns, so 512-column steps did twice the work needed)
 static_assert(TM == 8 && kColBlock == 8 && kColBlockSearch == 4,
               "the micro-tiles below are written for 8 x 8 and 8 x 4");
@@ -404,16 +404,18 @@ void launch_scan_fp32(const ScanJob& J, hipStream_t s) {
   if (items <= 0) return;
   const int64_t blocks = (items + 3) / 4;
   // the column width must match the one the host split the sequences with
-  // (kColBlockSearch with early abandon, else kColBlock)
+  // (kColBlockSearch with early abandon in the near-first order, else
+  // kColBlock)
+  const bool fine = J.abandon && J.near_first;
   if (J.zc) {
-    if (J.abandon)
+    if (fine)
       hipLaunchKernelGGL((k_scan_fp32<true, kColBlockSearch>), dim3((unsigned)blocks), dim3(256),
                          0, s, J);
     else
       hipLaunchKernelGGL((k_scan_fp32<true, kColBlock>), dim3((unsigned)blocks), dim3(256), 0, s,
                          J);
   } else {
-    if (J.abandon)
+    if (fine)
       hipLaunchKernelGGL((k_scan_fp32<false, kColBlockSearch>), dim3((unsigned)blocks), dim3(256),
                          0, s, J);
     else
