@@ -6,18 +6,22 @@
 // column attaining it.
 //
 // Layout of the work: one wavefront owns a group of 8 consecutive rows
-// (i0..i0+7); each of its 64 lanes owns 8 consecutive columns (j0..j0+7) per
-// step, so a wave covers 8 x 512 pairs per step.  The subsequences are read
-// straight from the series (Hankel structure: row i is t[i..i+n-1]), so no
-// subsequence matrix is streamed; the row window is wave-uniform.
+// (i0..i0+7); each of its 64 lanes owns TN consecutive columns (j0..j0+TN-1)
+// per step, so a wave covers 8 x 64 TN pairs per step: TN = 8 (512-column
+// steps) in full scans and the PhiDD and matrix orders, TN = 4 (256-column
+// steps) in near-first early-abandon searches, whose rows can leave only at
+// the end of a step.  The subsequences are read straight from the series
+// (Hankel structure: row i is t[i..i+n-1]), so no subsequence matrix is
+// streamed; the row window is wave-uniform.
 //
 // Arithmetic reuse: the difference t_{i+k} - t_{j+k} depends only on the
-// diagonal g = j - i and the position p = i + k, so inside an 8 x 8 block the
-// 64 pairs at position p need only the 15 differences D_g(p), g in [-7, 7].
-// Each pair's sum is still the plain sequential sum over k = 0..n-1 of its own
+// diagonal g = j - i and the position p = i + k, so inside an 8 x TN block the
+// 8 TN pairs at position p need only the 7 + TN differences D_g(p).  Each
+// pair's sum is still the plain sequential sum over k = 0..n-1 of its own
 // squared differences (one fused multiply-add per term), so the arithmetic per
-// pair is exactly the direct form; only the subtractions are shared.  Cost:
-// 64 FMA + 15 SUB per 64 (pair, k) terms, about 1.23 VALU ops per term.
+// pair is exactly the direct form; only the subtractions are shared.  Cost per
+// (pair, k) term: 64 FMA + 15 SUB per 64 (about 1.23 VALU ops) at TN = 8,
+// 32 FMA + 11 SUB per 32 (about 1.34) at TN = 4.
 #include "internal.hpp"
 
 namespace dd {
@@ -90,7 +94,7 @@ __device__ __forceinline__ void steps8(float (&acc)[TM][TN], const float* __rest
 
 // acc[r][c] = sum_{k<n} (x[r+k] - y[c+k])^2 for the 8 x TN block at x, y.
 template <int TN>
-__device__ __forceinline__ void block8x8(const float* __restrict__ x, const float* __restrict__ y,
+__device__ __forceinline__ void block_tile(const float* __restrict__ x, const float* __restrict__ y,
                                          int n, float (&acc)[TM][TN]) {
 #pragma unroll
   for (int r = 0; r < TM; ++r)
@@ -150,7 +154,7 @@ __device__ __forceinline__ void zsteps8(float (&acc)[TM][TN], const float* __res
 // x, y: TN-float aligned windows of the padded series; zx, zy: the same rows'
 // and columns' entries of the centre (zc) and scale (zr) arrays.
 template <int TN>
-__device__ __forceinline__ void block8x8_z(const float* __restrict__ x, const float* __restrict__ y,
+__device__ __forceinline__ void block_tile_z(const float* __restrict__ x, const float* __restrict__ y,
                                            int n, const float* __restrict__ zcx,
                                            const float* __restrict__ zrx,
                                            const float* __restrict__ zcy,
@@ -282,9 +286,9 @@ __device__ __forceinline__ void scan_item(const ScanJob& J, int64_t item, int la
     const int32_t j0 = (int32_t)(q * TN);   // N < 2^31 (checked at prepare)
     float acc[TM][TN];
     if constexpr (Z)
-      block8x8_z<TN>(x, J.Tp + j0, n, J.zc + i0, J.zr + i0, J.zc + j0, J.zr + j0, acc);
+      block_tile_z<TN>(x, J.Tp + j0, n, J.zc + i0, J.zr + i0, J.zc + j0, J.zr + j0, acc);
     else
-      block8x8<TN>(x, J.Tp + j0, n, acc);
+      block_tile<TN>(x, J.Tp + j0, n, acc);
     // blocks inside the matrix and clear of the exclusion band need no mask:
     // each row's minimum over the 8 columns first, its column only on improvement
     const bool clean = in_seq && valid == 0xFFu && j0 + TN <= N &&
