@@ -790,7 +790,7 @@ int search_enqueue(discord_plan p, SearchRun& run) {
     // a minimum on the windows or the ranked completions did not help either
     const int64_t min_full = mixed ? 1 : 4;
     const CtlParams P{seq_max, gran, target_items, seed_items, growth, seeds, near_first ? 1 : 0,
-                      min_full * gran, 0, 0};
+                      min_full * gran};
     // A launch whose work is decided on the device gets a grid sized for the
     // most work its descriptor can hold, at most `cap` work items (beyond, its
     // wavefronts or workgroups stride over the work).

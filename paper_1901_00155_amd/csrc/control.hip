@@ -15,14 +15,15 @@
 namespace dd {
 namespace {
 
-__host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+__device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // the split of entries [begin, end) of `items` items into chunks (a multiple of
-// the granule each) so that the launch holds about `target` work items, no
-// chunk shorter than `min_chunk` entries (0: one granule) unless the window is
-__host__ __device__ inline void set_window(WinDesc* w, int64_t items, int64_t begin, int64_t end,
-                                           int64_t target, int64_t gran, int64_t list_off,
-                                           int64_t min_chunk = 0) {
+// the granule each) so that the launch holds about `target` work items, with
+// no chunk shorter than `min_chunk` entries (0: one granule) unless the whole
+// window is
+__device__ inline void set_window(WinDesc* w, int64_t items, int64_t begin, int64_t end,
+                                  int64_t target, int64_t gran, int64_t list_off,
+                                  int64_t min_chunk = 0) {
   const int64_t it = items > 1 ? items : 1;
   const int64_t width = end - begin > 1 ? end - begin : 1;
   int64_t maxc = ceil_div(width, gran);
@@ -62,7 +63,7 @@ __global__ void k_ctl_start(SearchCtl* ctl, int64_t count, int64_t width,
 __device__ void ctl_window(SearchCtl* ctl, WinDesc* win, uint32_t* n_surv, const CtlParams& P) {
   const int64_t c = ctl->count;
   const int64_t end = ctl->covered + ctl->width < P.seq_max ? ctl->covered + ctl->width : P.seq_max;
-  set_window(win, c, ctl->covered, end, P.target, P.gran, ctl->in_off, P.min_chunk_win);
+  set_window(win, c, ctl->covered, end, P.target, P.gran, ctl->in_off);
   ctl->end = end;
   *n_surv = 0;
 }
@@ -99,7 +100,7 @@ __global__ void k_ctl_next(SearchCtl* ctl, WinDesc* win, uint32_t* n_surv, CtlPa
 __global__ void k_ctl_seeds(SearchCtl* ctl, WinDesc* win, CtlParams P) {
   const int64_t c = ctl->count;
   const int64_t k = c < P.seeds ? c : P.seeds;
-  set_window(win, k, ctl->covered, P.seq_max, P.seed_target, P.gran, 0, P.min_chunk_seeds);
+  set_window(win, k, ctl->covered, P.seq_max, P.seed_target, P.gran, 0);
   ctl->k = k;
 }
 
@@ -115,11 +116,6 @@ __global__ void k_ctl_post(SearchCtl* ctl) {
 }
 
 }  // namespace
-
-void set_window_host(WinDesc* w, int64_t items, int64_t begin, int64_t end, int64_t target,
-                     int64_t gran) {
-  set_window(w, items, begin, end, target, gran, 0);
-}
 
 void launch_ctl_start(SearchCtl* ctl, int64_t count, int64_t width, const int32_t* cand_count,
                       WinDesc* cand_win, int64_t bound_items, WinDesc* bound_win,

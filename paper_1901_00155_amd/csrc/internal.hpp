@@ -215,17 +215,9 @@ struct CtlParams {
   int64_t seeds;        // ranked rounds: best-ranked items completed after each window
   int32_t near_first;   // 1: windows grow by `growth`; 0: the second window ends the sequences
   // shortest chunk (entries) of the launches that complete whole sequences
-  // (Cand, bound-ranked items), of the growing windows and of the ranked
-  // rounds' completions (0: one granule)
+  // (Cand, bound-ranked items; 0: one granule)
   int64_t min_chunk_full;
-  int64_t min_chunk_win;
-  int64_t min_chunk_seeds;
 };
-// entries [begin, end) of `items` items, split into chunks so that the launch
-// holds about `target` work items (the host computes the same split for the
-// launches whose counts it knows)
-void set_window_host(WinDesc* w, int64_t items, int64_t begin, int64_t end, int64_t target,
-                     int64_t gran);
 // ctl := (count, 0, width, 0); cand_win (if given): the Cand launch covers the
 // whole sequence of *cand_count items; bound_win (if given): the launch that
 // completes bound_items items.  A series that eq. (2) rejects (bad[0] set, or
