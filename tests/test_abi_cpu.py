@@ -180,3 +180,38 @@ def test_noalloc_refuses_plans_beyond_its_static_workspace(dd):
     with pytest.raises(dd.DiscordError) as e:
         dd.search_series_noalloc(T, n, precision="bf16x3")
     assert e.value.status == -6
+
+
+def test_search_once_refuses_bad_arguments_before_any_device_call(dd):
+    """discord_search_once checks its arguments and the caller's workspace
+    (size against discord_workspace_bytes, 256-byte alignment) before it makes
+    any device call, so each refusal is visible here without a GPU."""
+    import ctypes
+    lib = dd.load()
+    m, n = 4096, 64
+    T = np.zeros(m, dtype=np.float32)
+    tp = ctypes.c_void_p(T.ctypes.data)
+    opts = dd.default_opts()
+    need = lib.discord_workspace_bytes(m, n, ctypes.byref(opts))
+    assert need > 0
+    r = dd.Result()
+    fake = ctypes.c_void_p(1 << 20)   # never dereferenced: every call below is refused first
+    # no result struct; window too long (2n > m); empty window
+    assert lib.discord_search_once(tp, m, n, ctypes.byref(opts), fake, need, None, None) == -1
+    assert lib.discord_search_once(tp, m, m // 2 + 1, ctypes.byref(opts), fake, need, None,
+                                   ctypes.byref(r)) == -1
+    assert lib.discord_search_once(tp, m, 0, ctypes.byref(opts), fake, need, None,
+                                   ctypes.byref(r)) == -1
+    # split-BF16 beyond its longest window
+    big = dd.MIXED_MAX_N + 1
+    ob = dd.default_opts(precision="bf16x3")
+    Tb = np.zeros(2 * big, dtype=np.float32)
+    assert lib.discord_search_once(ctypes.c_void_p(Tb.ctypes.data), Tb.size, big,
+                                   ctypes.byref(ob), fake, need, None, ctypes.byref(r)) == -6
+    # a workspace one granule short, and a misaligned one
+    for ptr, size in ((1 << 20, need - 256), ((1 << 20) + 4, need)):
+        st = lib.discord_search_once(tp, m, n, ctypes.byref(opts), ctypes.c_void_p(ptr), size,
+                                     None, ctypes.byref(r))
+        assert st == -3, st
+        msg = lib.discord_plan_error(None).decode()
+        assert "needs" in msg and str(need) in msg
